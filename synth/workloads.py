@@ -1,0 +1,44 @@
+"""Named workloads: lattice, fillings, couplings, precision, step budget, seed.
+
+These are the five synthetic configurations the benchmarks and parity tests use.
+Nothing here computes anything of the method.
+"""
+
+from dataclasses import dataclass, field
+from typing import List, Tuple
+
+from .lattice import ring_bonds, torus_bonds
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    n_sites: int
+    bonds: Tuple[Tuple[int, int], ...]
+    n_up: int
+    n_dn: int
+    t: float
+    U: float
+    steps: int
+    seed: int
+    note: str = ""
+
+
+def _wl(name, n_sites, bonds, n, t, U, steps, seed, note=""):
+    return Workload(name, n_sites, tuple(bonds), n, n, t, U, steps, seed, note)
+
+
+WORKLOADS = {
+    "ring8_4x4": _wl("ring8_4x4", 8, ring_bonds(8), 4, 1.0, 4.0, 100, 1,
+                     "1-D periodic 8-site Hubbard chain, 4 up + 4 down, dim 4900"),
+    "torus4x4_5x5": _wl("torus4x4_5x5", 16, torus_bonds(4, 4), 5, 1.0, 4.0, 200, 2,
+                        "4x4 periodic Hubbard, 5 up + 5 down, dim 19,079,424"),
+    "torus6x6_3x3": _wl("torus6x6_3x3", 36, torus_bonds(6, 6), 3, 1.0, 0.0, 300, 3,
+                        "6x6 periodic tight binding (U=0), 3 up + 3 down, dim 50,979,600"),
+    "torus4x4_8x8": _wl("torus4x4_8x8", 16, torus_bonds(4, 4), 8, 1.0, 4.0, 300, 5,
+                        "4x4 periodic Hubbard at half filling, 8 up + 8 down, dim 165,636,900"),
+}
+
+
+def workload(name: str) -> Workload:
+    return WORKLOADS[name]
