@@ -1,0 +1,168 @@
+"""Benchmark: Lanczos steps/s and H.v bandwidth on one MI355X.
+
+A "step" is one Lanczos iteration (Alg. 1 loop body): the up-part kernel, the
+down-part/diagonal/recurrence kernel with its partial dot products, the scalar
+reduction and the vector update.  The default workload is the 4x4 periodic
+Hubbard model at half filling (8 up + 8 down, dim 165,636,900, t=1, U=4) from a
+seeded uniform(-1,1) start vector, float64 (the plain method); the mixed form
+(float32 vectors, float64 scalars) is timed beside it.  Inputs are resident in
+HBM before the timed region; as in the paper's protocol no transfer is timed.
+
+Prints ONE JSON line.  Options: --steps K --warmup W (timed / untimed steps),
+--gpus N (only 1 is supported: the method runs on one GPU), --no-cpu-baseline.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "Lanczos steps/s + H·v HBM GB/s, 4x4 Hubbard 8↑8↓, plain vs mixed/learned"
+KERNELS = ("k_up", "k_down", "k_reduce", "k_update", "k_norm")
+
+
+def kernel_bytes(h, es):
+    """Algorithmic HBM bytes per launch of each step kernel (every operand moved once).
+
+    k_up reads x and writes the up part: 2 p D plus the up table.
+    k_down reads x, the up part and f_{j-1}, writes q: 4 p D plus the down table
+    and both bases.  k_update reads q and f_j (and f_{j-1} in the mixed form)
+    and writes f_{j+1}.  k_reduce and k_norm read a few hundred KB of partial sums."""
+    D = h.dim
+    tab_up = h.dim_up * h.up.width * 2
+    tab_dn = h.dim_dn * h.dn.width * 2
+    states = 8 * (h.dim_up + h.dim_dn)
+    upd = (4 if es == 4 else 3) * es * D
+    return {"k_up": 2 * es * D + tab_up, "k_down": 4 * es * D + tab_dn + states,
+            "k_reduce": 8 * 8 * h.dim_up, "k_update": upd, "k_norm": 8 * 8192}
+
+
+def time_run(h, x, warmup, steps, n_kernel_samples):
+    import torch
+    total = warmup + steps + n_kernel_samples + 2
+    run = h.lanczos(total)
+    run.init(x)
+    for _ in range(warmup):
+        run.step()
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        run.step()
+    end.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / steps
+    import numpy as np
+    per = np.zeros(5)
+    for _ in range(n_kernel_samples):
+        per += run.step_timed()
+    per /= max(n_kernel_samples, 1)
+    st = run.read()
+    if st["steps"] != warmup + steps + n_kernel_samples or st["status"] not in (0,):
+        raise RuntimeError("run did not complete every step: %r" % ({k: st[k] for k in ("steps", "status")},))
+    return ms, dict(zip(KERNELS, per.tolist())), st
+
+
+def cpu_baseline(wl, n_steps):
+    """The oracle's float64 matrix-free Lanczos steps (NumPy/SciPy, single thread) on a sample."""
+    import numpy as np
+    from oracle.hamiltonian import Model
+    from oracle.lanczos import lanczos
+    from synth import start_vector
+    m = Model(wl.n_sites, wl.bonds, wl.n_up, wl.n_dn, wl.t, wl.U)
+    x = start_vector(wl.seed, m.dim)
+    t0 = time.perf_counter()
+    lanczos(m.hv, x, n_steps)
+    dt = time.perf_counter() - t0
+    return {"value": n_steps / dt, "unit": "steps/s", "cores": 1, "kind": "oracle",
+            "sample": "%d float64 Lanczos steps of the oracle on the full %s workload (dim %d), "
+                      "%.1f s; SciPy sparse-times-dense and NumPy elementwise run on one thread"
+                      % (n_steps, wl.name, m.dim, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="torus4x4_8x8")
+    ap.add_argument("--kernel-samples", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this method runs on one GPU; --gpus %d is not supported (use --gpus 1)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1511_00863_amd as ed
+    from synth import start_vector, workload
+
+    wl = workload(args.workload)
+    dev = "cuda:0"
+    x64 = start_vector(wl.seed, 1)  # seed check (cheap); the full vector is drawn below
+    del x64
+    up = ed.SpinTables(wl.n_sites, wl.bonds, wl.n_up, dev)
+    dn = up if wl.n_dn == wl.n_up else ed.SpinTables(wl.n_sites, wl.bonds, wl.n_dn, dev)
+    x_host = start_vector(wl.seed, up.dim * dn.dim)
+
+    results = {}
+    for dtype in (("f64",) if args.no_mixed else ("f64", "f32")):
+        h = ed.Hamiltonian(up, dn, wl.t, wl.U, dtype)
+        x = torch.from_numpy(x_host).to(dev, h.torch_dtype)
+        ms, per, st = time_run(h, x, args.warmup, args.steps, args.kernel_samples)
+        es = 8 if dtype == "f64" else 4
+        kb = kernel_bytes(h, es)
+        hv_bytes = 2 * es * h.dim + h.dim_up * h.up.width * 2 + h.dim_dn * h.dn.width * 2
+        results[dtype] = {"ms_per_step": ms, "steps_per_s": 1000.0 / ms, "kernel_ms": per, "kernel_bytes": kb,
+                          "hv_alg_GBps": hv_bytes / ((per["k_up"] + per["k_down"]) * 1e-3) / 1e9,
+                          "step_floor_GBps": 3 * es * h.dim / (ms * 1e-3) / 1e9}
+        del x, h
+        torch.cuda.empty_cache()
+
+    r64 = results["f64"]
+    dom = max(KERNELS, key=lambda k: r64["kernel_ms"][k])
+    achieved = r64["kernel_bytes"][dom] / (r64["kernel_ms"][dom] * 1e-3) / 1e9
+    line = {
+        "metric": METRIC,
+        "value": r64["steps_per_s"],
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r64["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "lattice": "4x4 periodic square" if wl.n_sites == 16 else wl.name,
+                   "n_up": wl.n_up, "n_dn": wl.n_dn, "dim": up.dim * dn.dim, "t": wl.t, "U": wl.U,
+                   "start": "uniform(-1,1), seed %d" % wl.seed},
+        "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None},
+        "hv_alg_GBps": r64["hv_alg_GBps"],
+        "step_floor_frac": r64["step_floor_GBps"] / HBM_PEAK_GBPS,
+        "kernel_ms": r64["kernel_ms"],
+    }
+    if "f32" in results:
+        r32 = results["f32"]
+        line["mixed"] = {"dtype": "f32 vectors, f64 scalars", "steps_per_s": r32["steps_per_s"],
+                         "ms_per_step": r32["ms_per_step"], "hv_alg_GBps": r32["hv_alg_GBps"],
+                         "kernel_ms": r32["kernel_ms"], "step_floor_frac": r32["step_floor_GBps"] / HBM_PEAK_GBPS}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

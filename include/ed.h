@@ -1,0 +1,210 @@
+/*
+ * ed.h -- C ABI of the MI355X exact-diagonalisation library.
+ *
+ * Ground-state energies of two-species lattice models H = -t sum_<ij>,sigma
+ * (c+_i,s c_j,s + h.c.) + U sum_i n_i,up n_i,dn  (Eq. 1 and the on-site term of
+ * Sec. 1) by the Lanczos iteration (Alg. 1) over the fixed-(N_up, N_dn)
+ * occupation-bitstring basis (Sec. 2.1), with H applied matrix-free as
+ * H_up x I + I x H_dn + diag(U n_up n_dn)  (Eq. 3, 4, 5).
+ *
+ * Conventions shared by every call:
+ *  - Return value: ED_OK (0), a positive informational code, or a negative
+ *    error code.  Nothing throws across this boundary.  On error,
+ *    ed_last_error() gives a text for the calling thread.
+ *  - "host" pointers are CPU memory, "device" pointers are GPU memory on the
+ *    current HIP device.  Every buffer is allocated and owned by the caller;
+ *    the library keeps no state between calls and never frees a caller
+ *    buffer.  Device calls are asynchronous on `stream` (a hipStream_t passed
+ *    as void*, NULL = the default stream) unless stated otherwise.
+ *  - Basis states are uint64 bitmasks, bit i = site i (N_s <= 64).  Per-spin
+ *    states are in ascending integer order; a two-species state has index
+ *    i_up * dim_dn + i_dn, i.e. a vector is dim_up subvectors of length
+ *    dim_dn (Sec. 4, Eq. 4-5).
+ *  - Fermion signs: operators ordered by site index within a species, all up
+ *    operators before all down operators.  A hop i <- j in state s carries
+ *    (-1)^(number of occupied sites strictly between i and j); the two
+ *    species then decouple exactly as Eq. 3 states.
+ */
+#ifndef ED_H
+#define ED_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+enum {
+    ED_OK = 0,
+    ED_BREAKDOWN = 1,      /* b_{j+1} vanished (Alg. 1 stop): T_j is exact on an invariant subspace */
+    ED_NOT_CONVERGED = 2,  /* max_steps reached before the convergence test passed */
+    ED_EINVAL = -1,        /* bad argument (null pointer, bad size, zero/non-finite start vector...) */
+    ED_ECAPACITY = -2,     /* caller buffer too small; the needed size is returned where stated */
+    ED_EOVERFLOW = -3,     /* sizes beyond what the representation holds (N_s > 64, dims > 2^31-1 ...) */
+    ED_EDEVICE = -4        /* a HIP runtime error; text via ed_last_error() */
+};
+
+/* Vector storage and H.v arithmetic.  Scalars (dots, norms, a_j, b_j, T) are float64 in both. */
+enum { ED_F64 = 0, ED_F32 = 1 };
+
+/* Flattening order of an exported ELL table (Fig. 2): row-major as the paper's
+ * CPU code, column-major as its GPU code. */
+enum { ED_ROW_MAJOR = 0, ED_COL_MAJOR = 1 };
+
+/* Text of the last error on this thread; valid until the next ed_* call on it. */
+const char *ed_last_error(void);
+
+/* Library version string (static storage). */
+const char *ed_version(void);
+
+/* ---- host: basis and hopping tables ------------------------------------ */
+
+/* Per-spin basis (Sec. 2.1, Eq. 2): every n_part-subset of n_sites sites as a
+ * bitmask, in ascending order; *dim = C(n_sites, n_part).
+ * states: host, capacity `cap` entries; states == NULL with cap == 0 only
+ * queries *dim.  cap < dim -> ED_ECAPACITY (with *dim set).  n_sites > 64 or
+ * dim > 2^31-1 -> ED_EOVERFLOW.  0 <= n_part <= n_sites, else ED_EINVAL. */
+int ed_build_basis(int n_sites, int n_part, uint64_t *states, int64_t cap, int64_t *dim);
+
+/* Index of each state in the ascending per-spin basis, by its colex rank
+ * sum_k C(p_k, k+1) over the set bits p_0 < p_1 < ...  states/ranks: host,
+ * n entries.  A state with the wrong popcount or bits >= n_sites -> ED_EINVAL. */
+int ed_state_rank(int n_sites, int n_part, const uint64_t *states, int64_t n, int64_t *ranks);
+
+/* Per-spin hopping matrix H_sigma for t = 1 (Sec. 2.1), exported in ELL form
+ * (Fig. 2): row r holds, in ascending column order, the columns and values
+ * of its nonzeros, then zero padding (value 0, index 0) up to the width.
+ * bonds: host, n_bonds pairs (i, j), 0 <= i, j < n_sites, i != j, unordered
+ * duplicates rejected (ED_EINVAL).  states: host, the basis of ed_build_basis.
+ * Values are -sign in {-1, +1}; t scales them at H.v time.
+ * layout: ED_ROW_MAJOR (entry [r * width + k]) or ED_COL_MAJOR ([k * dim + r]).
+ * cols/vals: host, cap_width * dim entries each; nnz: host, dim entries.
+ * *width gets the ELL width (max nonzeros in a row); cap_width < width ->
+ * ED_ECAPACITY with *width set and nothing else written.  Pass cols == vals ==
+ * nnz == NULL with cap_width == 0 to query the width. */
+int ed_build_hopping(int n_sites, const int32_t *bonds, int n_bonds, const uint64_t *states,
+                     int64_t dim, int layout, int32_t cap_width, int32_t *cols, double *vals,
+                     int32_t *nnz, int32_t *width);
+
+/* Convert an exported ELL table into the device table format: uint16
+ * entries, column-major ([k * dim + r]), e = (col << 1) | (val < 0), padding
+ * 0xFFFF after the last nonzero of a row (ascending columns as exported).
+ * Input values must be exactly +-1 for k < nnz[r] (ED_EINVAL otherwise);
+ * dim > 32767 -> ED_EOVERFLOW.  packed: host, width * dim entries.  Copy it
+ * to device memory for ed_ham. */
+int ed_pack_tables(const int32_t *cols, const double *vals, const int32_t *nnz, int64_t dim,
+                   int32_t width, int layout, uint16_t *packed);
+
+/* Lowest eigenvalue of the m-by-m symmetric tridiagonal T (Sec. 2.2) with
+ * diagonal a[0..m-1] = a_1..a_m and off-diagonal b[0..m-2] = b_2..b_m, by
+ * Sturm-sequence bisection in float64 to full precision.  host pointers. */
+int ed_tridiag_lowest(const double *a, const double *b, int m, double *e0);
+
+/* Lowest eigenvector y (unit norm, y[0] >= 0 unless it vanishes) of the same
+ * T, by inverse iteration at the bisection eigenvalue.  y: host, m entries. */
+int ed_tridiag_lowest_vector(const double *a, const double *b, int m, double *e0, double *y);
+
+/* ---- device: the Hamiltonian and H.v ----------------------------------- */
+
+/* One instance (lattice, fillings, t, U).  All pointers are device memory.
+ * tab_up/tab_dn: ed_pack_tables output for H_up (dim_up x w_up) and H_dn
+ * (dim_dn x w_dn).  st_up/st_dn: the per-spin bases (for the U term).
+ * dtype: ED_F64 or ED_F32 (vectors and H.v).  tile: 0 = default launch
+ * configuration, else an id returned by ed_tune.  dim_up, dim_dn <= 32767
+ * (the table format; ED_EOVERFLOW otherwise). */
+typedef struct ed_ham {
+    int64_t dim_up, dim_dn;
+    int32_t w_up, w_dn;
+    const uint16_t *tab_up, *tab_dn;
+    const uint64_t *st_up, *st_dn;
+    double t, U;
+    int32_t dtype;
+    int32_t tile;
+} ed_ham;
+
+/* Bytes of device workspace (`ws` below) the calls on this instance need
+ * for runs of up to max_steps Lanczos steps.  Pass a 256-byte aligned buffer;
+ * its contents are scratch between calls. */
+int ed_workspace_size(const ed_ham *h, int32_t max_steps, int64_t *bytes);
+
+/* y = H x (Eq. 3-5 plus the diagonal U term).  x, y: device, dim_up*dim_dn
+ * elements of h->dtype, distinct buffers.  ws: device workspace. */
+int ed_hv(const ed_ham *h, const void *x, void *y, void *ws, void *stream);
+
+/* ---- device: the Lanczos iteration (Alg. 1) ---------------------------- */
+
+/* Lanczos state.  f_prev, f_cur, f_next: device vectors (h->dtype, dim
+ * elements, distinct); a: device, >= max_steps doubles (a[j-1] = a_j);
+ * b: device, >= max_steps + 1 doubles (b[j-1] = b_j, b[0] = b_1 = 0).
+ * j: steps launched so far (host side).  The library rotates the three
+ * vector pointers after every step, so f_cur always holds the newest vector.
+ * Vectors are stored unnormalised: after j steps f_cur = b_{j+1} f_{j+1}
+ * (that is Alg. 1's q_j after its line 6), and right after init f_cur is a
+ * copy of f1, i.e. |f1| f_1; the kernels apply the scale on the fly, which is
+ * what lets b_{j+1} be the norm of the stored vector itself. */
+typedef struct ed_lanczos {
+    void *f_prev, *f_cur, *f_next;
+    double *a, *b;
+    int32_t j;
+    int32_t max_steps;
+} ed_lanczos;
+
+/* Start the iteration (Alg. 1 requires a start vector of norm 1): f_cur =
+ * f1 / |f1| with the norm accumulated in float64, b_1 = 0, j = 0.
+ * f1: device, h->dtype, dim elements (it may alias f_prev or f_next, not
+ * f_cur).  Synchronises `stream`; a zero or non-finite norm -> ED_EINVAL. */
+int ed_lanczos_init(const ed_ham *h, ed_lanczos *st, const void *f1, void *ws, void *stream);
+
+/* One iteration of Alg. 1, asynchronous:
+ *   q = H f_j - b_j f_{j-1};  a_j = q.f_j;  q -= a_j f_j;  b_{j+1} = |q|;
+ *   f_{j+1} = q / b_{j+1}  (the division is deferred, see ed_lanczos).
+ * ED_F64 follows that order in float64.  ED_F32 stores vectors in float32
+ * and adds local re-orthogonalisation: q is projected off both f_j and
+ * f_{j-1} with float64 coefficients from their Gram matrix, the f_j
+ * coefficient is a_j and b_{j+1} is the norm of the projected q.
+ * All scalars stay on the device.  A vanishing b_{j+1} (<= 64 eps max|a|,b,
+ * eps = 2^-52 or 2^-24) or j == max_steps freezes the state: further steps are
+ * no-ops.  ed_lanczos_read reports it. */
+int ed_lanczos_step(const ed_ham *h, ed_lanczos *st, void *ws, void *stream);
+
+/* ed_lanczos_step with a HIP event recorded before each of its five kernels
+ * and after the last: ms[0..4] = durations in milliseconds of the up-part
+ * kernel (Eq. 4), the down-part/diagonal/recurrence kernel (Eq. 5 and Alg. 1
+ * line 4, with the partial dot products), the a_j reduction (line 5), the
+ * vector update with its partial norms (line 6) and the b_{j+1} reduction
+ * (lines 7-8).  Synchronises on the last event.  ms: host, 5 doubles. */
+int ed_lanczos_step_timed(const ed_ham *h, ed_lanczos *st, void *ws, void *stream, double *ms);
+
+/* Synchronise `stream` and report the device-side state: *steps = number of
+ * completed steps j, *status = ED_OK (running), ED_BREAKDOWN or
+ * ED_NOT_CONVERGED (max_steps reached).  a_host (steps doubles) and b_host
+ * (steps + 1 doubles, b_host[0] = b_1 = 0) may be NULL. */
+int ed_lanczos_read(const ed_ham *h, const ed_lanczos *st, void *ws, void *stream, int32_t *steps,
+                    int32_t *status, double *a_host, double *b_host);
+
+/* The whole ground-state-energy run: init from f1, then Alg. 1 steps (launched
+ * `check_every` at a time from a captured HIP graph) until
+ *   tol > 0: |E0(j) - E0(j-1)| < tol at two consecutive j, where E0(j) is the
+ *            lowest eigenvalue of T_j (Sec. 2.2, host bisection), or
+ *   tol <= 0: exactly st->max_steps steps (the paper's fixed-m protocol),
+ * or a breakdown.  Synchronises.  *e0 = E0 at the stopping step, *steps = j.
+ * a_host/b_host as in ed_lanczos_read (may be NULL).  Returns ED_OK,
+ * ED_BREAKDOWN (E0 exact on the invariant subspace) or ED_NOT_CONVERGED. */
+int ed_ground_energy(const ed_ham *h, ed_lanczos *st, const void *f1, double tol,
+                     int32_t check_every, void *ws, void *stream, double *e0, int32_t *steps,
+                     double *a_host, double *b_host);
+
+/* Ground-state vector by two passes: pass 1 runs m steps from f1 (as
+ * ed_ground_energy with tol <= 0), the lowest eigenvector y of T_m is found on
+ * the host, pass 2 replays the identical steps and accumulates
+ * v = sum_k y_k f_k, then v is normalised (float64 norm).  v: device, h->dtype,
+ * dim elements, distinct from the three Lanczos vectors.  ws must hold
+ * ed_workspace_size(h, m).  *e0 = lowest eigenvalue of T_m. */
+int ed_ground_state(const ed_ham *h, ed_lanczos *st, const void *f1, int32_t m, void *v,
+                    void *ws, void *stream, double *e0, int32_t *steps);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -42,7 +42,13 @@ class Model:
         self.h_up = hopping_matrix(n_sites, self.bonds, self.st_up, self.t)
         self.h_dn = (self.h_up if (n_dn == n_up) else
                      hopping_matrix(n_sites, self.bonds, self.st_dn, self.t))
-        self.docc = double_occupancy(self.st_up, self.st_dn)
+        self._docc = None
+
+    @property
+    def docc(self) -> np.ndarray:
+        if self._docc is None:
+            self._docc = double_occupancy(self.st_up, self.st_dn)
+        return self._docc
 
     @property
     def dim_up(self):
@@ -69,7 +75,8 @@ class Model:
         rows = np.asarray(rows)
         up = self.h_up[rows] @ X
         dn = (self.h_dn @ X[rows].T).T
-        return up + dn + self.U * self.docc[rows] * X[rows]
+        docc = double_occupancy(self.st_up[rows], self.st_dn)
+        return up + dn + self.U * docc * X[rows]
 
     def full_sparse(self) -> sp.csr_matrix:
         """The plain definition: kron(H_up, I) + kron(I, H_dn) + diag(U * Docc)."""

@@ -1,0 +1,16 @@
+"""MI355X (gfx950) exact diagonalisation of two-species lattice models.
+
+The Lanczos ground-state method of Siro and Harju (Alg. 1) with a matrix-free
+H.v over the fixed-(N_up, N_dn) occupation basis (Eq. 3-5), as a C-ABI library
+of hand-written HIP kernels (include/ed.h).  This package is its thin Python
+binding; torch supplies device memory and streams.
+"""
+
+from ._ffi import (ED_BREAKDOWN, ED_COL_MAJOR, ED_F32, ED_F64, ED_NOT_CONVERGED, ED_OK, ED_ROW_MAJOR, EdError,
+                   lib)
+from .api import (Hamiltonian, LanczosRun, SpinTables, build_basis, build_hopping, pack_tables, state_rank,
+                  tridiag_lowest, tridiag_lowest_vector)
+
+__all__ = ["Hamiltonian", "LanczosRun", "SpinTables", "build_basis", "build_hopping", "pack_tables",
+           "state_rank", "tridiag_lowest", "tridiag_lowest_vector", "EdError", "lib",
+           "ED_OK", "ED_BREAKDOWN", "ED_NOT_CONVERGED", "ED_F64", "ED_F32", "ED_ROW_MAJOR", "ED_COL_MAJOR"]

@@ -1,0 +1,275 @@
+"""Python face of the C ABI: host arrays via numpy, device memory and streams via torch.
+
+Every computation happens in the library (host C++ or gfx950 kernels); this
+module only allocates buffers, fills the C structs and maps error codes to
+exceptions.  Names follow the C entry points of include/ed.h.
+"""
+
+import ctypes
+from ctypes import POINTER, byref, c_double, c_int32, c_int64, c_uint16, c_uint64
+
+import numpy as np
+import torch
+
+from . import _ffi
+from ._ffi import (ED_COL_MAJOR, ED_F32, ED_F64, ED_ROW_MAJOR, EdHam, EdLanczos, check, lib)
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(POINTER(ctype))
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+# ---------------------------------------------------------------- host calls
+def build_basis(n_sites: int, n_part: int) -> np.ndarray:
+    d = c_int64(0)
+    check(lib().ed_build_basis(n_sites, n_part, None, 0, byref(d)))
+    st = np.zeros(d.value, dtype=np.uint64)
+    check(lib().ed_build_basis(n_sites, n_part, _ptr(st, c_uint64), d.value, byref(d)))
+    return st
+
+
+def state_rank(n_sites: int, n_part: int, states) -> np.ndarray:
+    st = np.ascontiguousarray(states, dtype=np.uint64)
+    out = np.zeros(st.size, dtype=np.int64)
+    check(lib().ed_state_rank(n_sites, n_part, _ptr(st, c_uint64), st.size, _ptr(out, c_int64)))
+    return out
+
+
+def _bond_array(bonds) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(bonds, dtype=np.int32).reshape(-1, 2))
+
+
+def build_hopping(n_sites: int, bonds, states, layout: int = ED_COL_MAJOR):
+    """Exported ELL table of H_sigma for t=1: dict(cols, vals, nnz, width) (Fig. 2 layout)."""
+    st = np.ascontiguousarray(states, dtype=np.uint64)
+    b = _bond_array(bonds)
+    w = c_int32(0)
+    check(lib().ed_build_hopping(n_sites, _ptr(b, c_int32), b.shape[0], _ptr(st, c_uint64), st.size, layout, 0,
+                                 None, None, None, byref(w)))
+    width = w.value
+    cols = np.zeros(max(width, 1) * st.size, dtype=np.int32)
+    vals = np.zeros(max(width, 1) * st.size, dtype=np.float64)
+    nnz = np.zeros(st.size, dtype=np.int32)
+    check(lib().ed_build_hopping(n_sites, _ptr(b, c_int32), b.shape[0], _ptr(st, c_uint64), st.size, layout,
+                                 max(width, 1), _ptr(cols, c_int32), _ptr(vals, c_double), _ptr(nnz, c_int32),
+                                 byref(w)))
+    cap = max(width, 1)
+    cols, vals = cols[:width * st.size], vals[:width * st.size]
+    if cap != width and width == 0:
+        cols, vals = cols[:0], vals[:0]
+    return {"cols": cols, "vals": vals, "nnz": nnz, "width": width, "layout": layout}
+
+
+def pack_tables(table, dim: int) -> np.ndarray:
+    width = table["width"]
+    out = np.zeros(max(width * dim, 1), dtype=np.uint16)
+    if width == 0:
+        return out[:0]
+    check(lib().ed_pack_tables(_ptr(table["cols"], c_int32), _ptr(table["vals"], c_double),
+                               _ptr(table["nnz"], c_int32), dim, width, table["layout"], _ptr(out, c_uint16)))
+    return out
+
+
+def tridiag_lowest(a, b_off) -> float:
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    b = np.ascontiguousarray(b_off, dtype=np.float64)
+    e = c_double(0)
+    check(lib().ed_tridiag_lowest(_ptr(a, c_double), _ptr(b, c_double) if b.size else None, a.size, byref(e)))
+    return e.value
+
+
+def tridiag_lowest_vector(a, b_off):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    b = np.ascontiguousarray(b_off, dtype=np.float64)
+    y = np.zeros(a.size)
+    e = c_double(0)
+    check(lib().ed_tridiag_lowest_vector(_ptr(a, c_double), _ptr(b, c_double) if b.size else None, a.size,
+                                         byref(e), _ptr(y, c_double)))
+    return e.value, y
+
+
+# ---------------------------------------------------------------- device side
+class SpinTables:
+    """Basis and packed hopping table of one species, on the host and on the device."""
+
+    def __init__(self, n_sites: int, bonds, n_part: int, device=None):
+        self.n_sites, self.n_part = n_sites, n_part
+        self.bonds = [tuple(int(v) for v in b) for b in bonds]
+        self.states = build_basis(n_sites, n_part)
+        self.dim = int(self.states.size)
+        self.table = build_hopping(n_sites, self.bonds, self.states, ED_COL_MAJOR)
+        self.width = self.table["width"]
+        self.packed = pack_tables(self.table, self.dim)
+        self.device = torch.device(device if device is not None else "cuda")
+        self.dev_states = torch.from_numpy(self.states.view(np.int64).copy()).to(self.device)
+        self.dev_tab = (torch.from_numpy(self.packed.view(np.int16).copy()).to(self.device)
+                        if self.width else torch.zeros(1, dtype=torch.int16, device=self.device))
+
+
+class Hamiltonian:
+    """One (lattice, N_up, N_dn, t, U) instance with device tables; float64 or float32 vectors."""
+
+    def __init__(self, up: SpinTables, dn: SpinTables, t: float = 1.0, U: float = 0.0, dtype: str = "f64",
+                 tile: int = 0):
+        self.up, self.dn, self.t, self.U = up, dn, float(t), float(U)
+        self.dtype = ED_F64 if dtype in ("f64", torch.float64) else ED_F32
+        self.tile = int(tile)
+        self.device = up.device
+
+    @classmethod
+    def from_lattice(cls, n_sites, bonds, n_up, n_dn, t=1.0, U=0.0, dtype="f64", device=None, tile=0):
+        up = SpinTables(n_sites, bonds, n_up, device)
+        dn = up if n_dn == n_up else SpinTables(n_sites, bonds, n_dn, device)
+        return cls(up, dn, t, U, dtype, tile)
+
+    @property
+    def dim_up(self):
+        return self.up.dim
+
+    @property
+    def dim_dn(self):
+        return self.dn.dim
+
+    @property
+    def dim(self):
+        return self.up.dim * self.dn.dim
+
+    @property
+    def torch_dtype(self):
+        return torch.float64 if self.dtype == ED_F64 else torch.float32
+
+    def c_struct(self) -> EdHam:
+        return EdHam(self.dim_up, self.dim_dn, self.up.width, self.dn.width,
+                     self.up.dev_tab.data_ptr(), self.dn.dev_tab.data_ptr(),
+                     self.up.dev_states.data_ptr(), self.dn.dev_states.data_ptr(),
+                     self.t, self.U, self.dtype, self.tile)
+
+    def workspace_bytes(self, max_steps: int = 1) -> int:
+        n = c_int64(0)
+        h = self.c_struct()
+        check(lib().ed_workspace_size(byref(h), max_steps, byref(n)))
+        return n.value
+
+    def workspace(self, max_steps: int = 1) -> torch.Tensor:
+        return torch.empty(self.workspace_bytes(max_steps), dtype=torch.uint8, device=self.device)
+
+    def empty_vec(self) -> torch.Tensor:
+        return torch.empty(self.dim, dtype=self.torch_dtype, device=self.device)
+
+    def _vec(self, x) -> torch.Tensor:
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == self.torch_dtype and x.is_contiguous()
+                and x.numel() == self.dim):
+            raise ValueError("expected a contiguous %s device vector of %d elements" % (self.torch_dtype, self.dim))
+        return x
+
+    def hv(self, x, y=None, ws=None, stream=None):
+        """y = H x (Eq. 3-5 plus the U term)."""
+        x = self._vec(x)
+        y = self.empty_vec() if y is None else self._vec(y)
+        h = self.c_struct()
+        check(lib().ed_hv(byref(h), _dptr(x), _dptr(y), _dptr(ws), _stream(stream)))
+        return y
+
+    def lanczos(self, max_steps: int) -> "LanczosRun":
+        return LanczosRun(self, max_steps)
+
+    def ground_energy(self, f1, max_steps: int, tol: float = 0.0, check_every: int = 10, stream=None):
+        """Alg. 1 from f1 until |dE0| < tol twice (tol > 0) or exactly max_steps steps (tol <= 0)."""
+        run = LanczosRun(self, max_steps)
+        return run.ground_energy(f1, tol, check_every, stream)
+
+    def ground_state(self, f1, m: int, stream=None):
+        """Two-pass ground-state vector: returns (E0, steps, v) with |v| = 1."""
+        run = LanczosRun(self, m)
+        return run.ground_state(f1, m, stream)
+
+
+class LanczosRun:
+    """Buffers of one Lanczos run (three vectors, a, b, workspace) and the calls on them."""
+
+    def __init__(self, ham: Hamiltonian, max_steps: int):
+        self.ham = ham
+        self.max_steps = int(max_steps)
+        dev = ham.device
+        self.vecs = [ham.empty_vec() for _ in range(3)]
+        self.a = torch.zeros(max(self.max_steps, 1), dtype=torch.float64, device=dev)
+        self.b = torch.zeros(self.max_steps + 1, dtype=torch.float64, device=dev)
+        self.ws = ham.workspace(self.max_steps)
+        self.st = EdLanczos(self.vecs[2].data_ptr(), self.vecs[0].data_ptr(), self.vecs[1].data_ptr(),
+                            self.a.data_ptr(), self.b.data_ptr(), 0, self.max_steps)
+        self._h = ham.c_struct()
+
+    def _by_ptr(self, p):
+        for v in self.vecs:
+            if v.data_ptr() == p:
+                return v
+        raise RuntimeError("unknown vector pointer")
+
+    @property
+    def f_cur(self) -> torch.Tensor:
+        return self._by_ptr(self.st.f_cur)
+
+    @property
+    def f_prev(self) -> torch.Tensor:
+        return self._by_ptr(self.st.f_prev)
+
+    @property
+    def f_next(self) -> torch.Tensor:
+        return self._by_ptr(self.st.f_next)
+
+    def init(self, f1, stream=None):
+        f1 = self.ham._vec(f1)
+        if f1.data_ptr() == self.st.f_cur:
+            raise ValueError("f1 must not be the run's current vector")
+        check(lib().ed_lanczos_init(byref(self._h), byref(self.st), _dptr(f1), _dptr(self.ws), _stream(stream)))
+
+    def step(self, stream=None):
+        check(lib().ed_lanczos_step(byref(self._h), byref(self.st), _dptr(self.ws), _stream(stream)))
+
+    def step_timed(self, stream=None):
+        """One step; returns the five kernel durations in ms (up, down, reduce, update, norm)."""
+        ms = np.zeros(5)
+        check(lib().ed_lanczos_step_timed(byref(self._h), byref(self.st), _dptr(self.ws), _stream(stream),
+                                          _ptr(ms, c_double)))
+        return ms
+
+    def read(self, stream=None):
+        steps, status = c_int32(0), c_int32(0)
+        a = np.zeros(self.max_steps)
+        b = np.zeros(self.max_steps + 1)
+        check(lib().ed_lanczos_read(byref(self._h), byref(self.st), _dptr(self.ws), _stream(stream), byref(steps), byref(status),
+                                    _ptr(a, c_double), _ptr(b, c_double)))
+        k = steps.value
+        return {"steps": k, "status": status.value, "a": a[:k], "b": b[:k + 1]}
+
+    def ground_energy(self, f1, tol=0.0, check_every=10, stream=None):
+        f1 = self.ham._vec(f1)
+        e0, steps = c_double(0), c_int32(0)
+        a = np.zeros(self.max_steps)
+        b = np.zeros(self.max_steps + 1)
+        if f1.data_ptr() == self.st.f_cur:
+            raise ValueError("f1 must not be the run's current vector")
+        rc = check(lib().ed_ground_energy(byref(self._h), byref(self.st), _dptr(f1), float(tol), int(check_every),
+                                          _dptr(self.ws), _stream(stream), byref(e0), byref(steps),
+                                          _ptr(a, c_double), _ptr(b, c_double)))
+        k = steps.value
+        return {"e0": e0.value, "steps": k, "status": rc, "a": a[:k], "b": b[:k + 1]}
+
+    def ground_state(self, f1, m, stream=None):
+        f1 = self.ham._vec(f1)
+        v = self.ham.empty_vec()
+        e0, steps = c_double(0), c_int32(0)
+        if f1.data_ptr() == self.st.f_cur:
+            raise ValueError("f1 must not be the run's current vector")
+        check(lib().ed_ground_state(byref(self._h), byref(self.st), _dptr(f1), int(m), _dptr(v), _dptr(self.ws),
+                                    _stream(stream), byref(e0), byref(steps)))
+        return e0.value, steps.value, v

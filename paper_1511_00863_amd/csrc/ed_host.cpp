@@ -1,0 +1,333 @@
+// Host side of the library: per-spin basis and ranking, hopping tables in ELL
+// form, the device table packer, and the tridiagonal eigensolver.
+//
+// Basis and ELL: Sec. 2.1 and Fig. 2.  Tridiagonal T: Sec. 2.2.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <set>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/ed.h"
+#include "ed_internal.h"
+
+namespace ed {
+
+static thread_local std::string g_last_error;
+
+int set_error(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+struct BinomTable {
+    uint64_t c[65][66];
+    BinomTable() {
+        std::memset(c, 0, sizeof c);
+        for (int n = 0; n <= 64; ++n) {
+            c[n][0] = 1;
+            for (int k = 1; k <= n; ++k) c[n][k] = c[n - 1][k - 1] + (k <= n - 1 ? c[n - 1][k] : 0);
+        }
+    }
+};
+static const BinomTable g_binom;
+
+uint64_t binom(int n, int k) {
+    if (n < 0 || n > 64 || k < 0 || k > n) return 0;
+    return g_binom.c[n][k];
+}
+
+// Colex rank of a bitmask with set bits p_0 < p_1 < ...: sum_k C(p_k, k+1).
+static inline int64_t colex_rank(uint64_t s) {
+    int64_t r = 0;
+    int k = 0;
+    while (s) {
+        int p = __builtin_ctzll(s);
+        r += (int64_t)g_binom.c[p][k + 1];
+        ++k;
+        s &= s - 1;
+    }
+    return r;
+}
+
+// Number of negative pivots of T - x I (= eigenvalues below x).
+static int sturm_count(const double *a, const double *b2, int m, double x, double pivmin) {
+    int cnt = 0;
+    double d = a[0] - x;
+    if (std::fabs(d) < pivmin) d = -pivmin;
+    if (d < 0) ++cnt;
+    for (int k = 1; k < m; ++k) {
+        d = (a[k] - x) - b2[k - 1] / d;
+        if (std::fabs(d) < pivmin) d = -pivmin;
+        if (d < 0) ++cnt;
+    }
+    return cnt;
+}
+
+double tridiag_lowest(const double *a, const double *b, int m) {
+    if (m == 1) return a[0];
+    std::vector<double> b2(m - 1);
+    double lo = INFINITY, hi = -INFINITY, bmax2 = 0.0;
+    for (int k = 0; k < m; ++k) {
+        double r = (k > 0 ? std::fabs(b[k - 1]) : 0.0) + (k < m - 1 ? std::fabs(b[k]) : 0.0);
+        lo = std::min(lo, a[k] - r);
+        hi = std::max(hi, a[k] + r);
+        if (k < m - 1) {
+            b2[k] = b[k] * b[k];
+            bmax2 = std::max(bmax2, b2[k]);
+        }
+    }
+    const double eps = std::ldexp(1.0, -53);
+    const double pivmin = std::max(std::numeric_limits<double>::min() * std::max(1.0, bmax2), 1e-300);
+    double scale = std::max(std::fabs(lo), std::fabs(hi));
+    lo -= 2.0 * eps * scale + pivmin;
+    hi += 2.0 * eps * scale + pivmin;
+    for (int it = 0; it < 400; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (sturm_count(a, b2.data(), m, mid, pivmin) >= 1) hi = mid; else lo = mid;
+        if (hi - lo <= 2.0 * eps * std::max(std::fabs(lo), std::fabs(hi))) break;
+    }
+    return 0.5 * (lo + hi);
+}
+
+}  // namespace ed
+
+using namespace ed;
+
+extern "C" {
+
+const char *ed_last_error(void) { return g_last_error.c_str(); }
+
+const char *ed_version(void) { return "ed-mi355x 0.1 (gfx950)"; }
+
+int ed_build_basis(int n_sites, int n_part, uint64_t *states, int64_t cap, int64_t *dim) {
+    clear_error();
+    if (!dim) return set_error(ED_EINVAL, "ed_build_basis: dim is NULL");
+    if (n_sites > 64) return set_error(ED_EOVERFLOW, "ed_build_basis: n_sites=%d > 64", n_sites);
+    if (n_sites < 1 || n_part < 0 || n_part > n_sites)
+        return set_error(ED_EINVAL, "ed_build_basis: need 0 <= n_part (%d) <= n_sites (%d), n_sites >= 1",
+                         n_part, n_sites);
+    uint64_t d = binom(n_sites, n_part);
+    if (d > 0x7fffffffULL) return set_error(ED_EOVERFLOW, "ed_build_basis: dim %llu > 2^31-1",
+                                            (unsigned long long)d);
+    *dim = (int64_t)d;
+    if (states == nullptr && cap == 0) return ED_OK;
+    if (!states) return set_error(ED_EINVAL, "ed_build_basis: states is NULL");
+    if (cap < (int64_t)d) return set_error(ED_ECAPACITY, "ed_build_basis: cap %lld < dim %llu",
+                                           (long long)cap, (unsigned long long)d);
+    // Ascending integers with n_part set bits (next-larger-same-popcount step).
+    uint64_t s = n_part == 0 ? 0ULL : (n_part == 64 ? ~0ULL : ((1ULL << n_part) - 1ULL));
+    for (uint64_t k = 0; k < d; ++k) {
+        states[k] = s;
+        if (n_part == 0 || k + 1 == d) break;
+        uint64_t c = s & (~s + 1ULL);
+        uint64_t r = s + c;
+        s = (((r ^ s) >> 2) / c) | r;
+    }
+    return ED_OK;
+}
+
+int ed_state_rank(int n_sites, int n_part, const uint64_t *states, int64_t n, int64_t *ranks) {
+    clear_error();
+    if (n_sites < 1 || n_sites > 64 || n_part < 0 || n_part > n_sites)
+        return set_error(ED_EINVAL, "ed_state_rank: bad n_sites/n_part");
+    if (n < 0 || (n > 0 && (!states || !ranks))) return set_error(ED_EINVAL, "ed_state_rank: bad buffers");
+    const uint64_t allowed = n_sites == 64 ? ~0ULL : ((1ULL << n_sites) - 1ULL);
+    for (int64_t k = 0; k < n; ++k) {
+        uint64_t s = states[k];
+        if ((s & ~allowed) || __builtin_popcountll(s) != n_part)
+            return set_error(ED_EINVAL, "ed_state_rank: state %lld (0x%llx) not in the basis",
+                             (long long)k, (unsigned long long)s);
+        ranks[k] = colex_rank(s);
+    }
+    return ED_OK;
+}
+
+int ed_build_hopping(int n_sites, const int32_t *bonds, int n_bonds, const uint64_t *states,
+                     int64_t dim, int layout, int32_t cap_width, int32_t *cols, double *vals,
+                     int32_t *nnz, int32_t *width) {
+    clear_error();
+    if (!width) return set_error(ED_EINVAL, "ed_build_hopping: width is NULL");
+    if (n_sites < 1 || n_sites > 64) return set_error(ED_EINVAL, "ed_build_hopping: n_sites=%d", n_sites);
+    if (n_bonds < 0 || (n_bonds > 0 && !bonds)) return set_error(ED_EINVAL, "ed_build_hopping: bad bonds");
+    if (dim < 1 || !states) return set_error(ED_EINVAL, "ed_build_hopping: bad states/dim");
+    if (dim > 0x3fffffffLL) return set_error(ED_EOVERFLOW, "ed_build_hopping: dim too large");
+    if (layout != ED_ROW_MAJOR && layout != ED_COL_MAJOR)
+        return set_error(ED_EINVAL, "ed_build_hopping: bad layout %d", layout);
+    std::set<std::pair<int, int>> seen;
+    std::vector<uint64_t> bmask(n_bonds), between(n_bonds);
+    for (int k = 0; k < n_bonds; ++k) {
+        int i = bonds[2 * k], j = bonds[2 * k + 1];
+        if (i < 0 || j < 0 || i >= n_sites || j >= n_sites || i == j)
+            return set_error(ED_EINVAL, "ed_build_hopping: bond %d = (%d, %d) invalid", k, i, j);
+        int lo = std::min(i, j), hi = std::max(i, j);
+        if (!seen.insert({lo, hi}).second)
+            return set_error(ED_EINVAL, "ed_build_hopping: duplicate bond (%d, %d)", lo, hi);
+        bmask[k] = (1ULL << lo) | (1ULL << hi);
+        // sites strictly between lo and hi
+        uint64_t below_hi = (1ULL << hi) - 1ULL;
+        uint64_t upto_lo = (lo == 63) ? ~0ULL : ((1ULL << (lo + 1)) - 1ULL);
+        between[k] = below_hi & ~upto_lo;
+    }
+    const int popc = __builtin_popcountll(states[0]);
+    // first pass: width and validation
+    int32_t w = 0;
+    for (int64_t r = 0; r < dim; ++r) {
+        uint64_t s = states[r];
+        if (__builtin_popcountll(s) != popc || (n_sites < 64 && (s >> n_sites)))
+            return set_error(ED_EINVAL, "ed_build_hopping: state %lld not in a fixed-N basis", (long long)r);
+        if (r > 0 && states[r] <= states[r - 1])
+            return set_error(ED_EINVAL, "ed_build_hopping: states not strictly ascending at %lld", (long long)r);
+        int c = 0;
+        for (int k = 0; k < n_bonds; ++k) {
+            uint64_t m = s & bmask[k];
+            if (m && m != bmask[k]) ++c;
+        }
+        w = std::max(w, c);
+    }
+    if ((int64_t)binom(n_sites, popc) != dim)
+        return set_error(ED_EINVAL, "ed_build_hopping: dim %lld is not C(%d,%d)", (long long)dim, n_sites, popc);
+    *width = w;
+    if (cols == nullptr && vals == nullptr && nnz == nullptr && cap_width == 0) return ED_OK;
+    if (!cols || !vals || !nnz) return set_error(ED_EINVAL, "ed_build_hopping: NULL output buffer");
+    if (cap_width < w) return set_error(ED_ECAPACITY, "ed_build_hopping: cap_width %d < width %d", cap_width, w);
+    std::vector<std::pair<int32_t, double>> row;
+    row.reserve(n_bonds);
+    const int64_t W = cap_width;
+    for (int64_t r = 0; r < dim; ++r) {
+        uint64_t s = states[r];
+        row.clear();
+        for (int k = 0; k < n_bonds; ++k) {
+            uint64_t m = s & bmask[k];
+            if (!m || m == bmask[k]) continue;      // both empty or both occupied: no hop
+            uint64_t t = s ^ bmask[k];
+            int sign = (__builtin_popcountll(s & between[k]) & 1) ? -1 : 1;
+            row.push_back({(int32_t)colex_rank(t), -1.0 * sign});
+        }
+        std::sort(row.begin(), row.end());
+        nnz[r] = (int32_t)row.size();
+        for (int64_t k = 0; k < W; ++k) {
+            int32_t c = k < (int64_t)row.size() ? row[k].first : 0;
+            double v = k < (int64_t)row.size() ? row[k].second : 0.0;
+            int64_t at = layout == ED_ROW_MAJOR ? r * W + k : k * dim + r;
+            cols[at] = c;
+            vals[at] = v;
+        }
+    }
+    return ED_OK;
+}
+
+int ed_pack_tables(const int32_t *cols, const double *vals, const int32_t *nnz, int64_t dim,
+                   int32_t width, int layout, uint16_t *packed) {
+    clear_error();
+    if (!cols || !vals || !nnz || !packed || dim < 1 || width < 0)
+        return set_error(ED_EINVAL, "ed_pack_tables: bad arguments");
+    if (dim > 32767) return set_error(ED_EOVERFLOW, "ed_pack_tables: dim %lld > 32767", (long long)dim);
+    if (layout != ED_ROW_MAJOR && layout != ED_COL_MAJOR)
+        return set_error(ED_EINVAL, "ed_pack_tables: bad layout %d", layout);
+    for (int64_t r = 0; r < dim; ++r) {
+        if (nnz[r] < 0 || nnz[r] > width)
+            return set_error(ED_EINVAL, "ed_pack_tables: nnz[%lld] = %d out of range", (long long)r, nnz[r]);
+        int32_t last = -1;
+        for (int64_t k = 0; k < width; ++k) {
+            int64_t at = layout == ED_ROW_MAJOR ? r * width + k : k * dim + r;
+            uint16_t e = 0xFFFF;
+            if (k < nnz[r]) {
+                if (cols[at] < 0 || cols[at] >= dim)
+                    return set_error(ED_EINVAL, "ed_pack_tables: column %d out of range", cols[at]);
+                if (cols[at] <= last)
+                    return set_error(ED_EINVAL, "ed_pack_tables: row %lld not in ascending column order", (long long)r);
+                if (vals[at] != 1.0 && vals[at] != -1.0)
+                    return set_error(ED_EINVAL, "ed_pack_tables: value %g is not +-1", vals[at]);
+                last = cols[at];
+                e = (uint16_t)((cols[at] << 1) | (vals[at] < 0 ? 1 : 0));
+            }
+            packed[k * dim + r] = e;
+        }
+    }
+    return ED_OK;
+}
+
+int ed_tridiag_lowest(const double *a, const double *b, int m, double *e0) {
+    clear_error();
+    if (!a || !e0 || m < 1 || (m > 1 && !b)) return set_error(ED_EINVAL, "ed_tridiag_lowest: bad arguments");
+    for (int k = 0; k < m; ++k)
+        if (!std::isfinite(a[k]) || (k < m - 1 && !std::isfinite(b[k])))
+            return set_error(ED_EINVAL, "ed_tridiag_lowest: non-finite entry at %d", k);
+    *e0 = tridiag_lowest(a, b, m);
+    return ED_OK;
+}
+
+int ed_tridiag_lowest_vector(const double *a, const double *b, int m, double *e0, double *y) {
+    int rc = ed_tridiag_lowest(a, b, m, e0);
+    if (rc) return rc;
+    if (!y) return set_error(ED_EINVAL, "ed_tridiag_lowest_vector: y is NULL");
+    if (m == 1) { y[0] = 1.0; return ED_OK; }
+    // Inverse iteration on (T - lambda I) with partial pivoting (tridiagonal
+    // elimination with row swaps, so the factor has two super-diagonals).
+    double tn = 0.0;
+    for (int k = 0; k < m; ++k) tn = std::max(tn, std::fabs(a[k]) + (k ? std::fabs(b[k - 1]) : 0) + (k < m - 1 ? std::fabs(b[k]) : 0));
+    const double tiny = std::ldexp(1.0, -52) * std::max(tn, 1e-300);
+    const double lam = *e0;
+    std::vector<double> d(m), du(m), du2(m), dl(m), x(m);
+    std::vector<int> swp(m, 0);
+    for (int k = 0; k < m; ++k) { d[k] = a[k] - lam; du[k] = k < m - 1 ? b[k] : 0.0; dl[k] = k < m - 1 ? b[k] : 0.0; du2[k] = 0.0; }
+    for (int k = 0; k < m - 1; ++k) {
+        if (std::fabs(d[k]) >= std::fabs(dl[k])) {
+            if (d[k] == 0.0) d[k] = tiny;
+            double f = dl[k] / d[k];
+            dl[k] = f;
+            d[k + 1] -= f * du[k];
+            swp[k] = 0;
+        } else {
+            double f = d[k] / dl[k];
+            d[k] = dl[k];
+            dl[k] = f;
+            double tmp = du[k];
+            du[k] = d[k + 1];
+            d[k + 1] = tmp - f * d[k + 1];
+            if (k < m - 2) { du2[k] = du[k + 1]; du[k + 1] = -f * du[k + 1]; }
+            swp[k] = 1;
+        }
+    }
+    if (d[m - 1] == 0.0) d[m - 1] = tiny;
+    for (int k = 0; k < m; ++k) x[k] = 1.0 / std::sqrt((double)m);
+    for (int it = 0; it < 4; ++it) {
+        // forward: apply L^{-1} with the recorded swaps
+        for (int k = 0; k < m - 1; ++k) {
+            if (swp[k]) { double t = x[k]; x[k] = x[k + 1]; x[k + 1] = t - dl[k] * x[k]; }
+            else x[k + 1] -= dl[k] * x[k];
+        }
+        // back substitution with U (diag d, super du, second super du2)
+        for (int k = m - 1; k >= 0; --k) {
+            double s = x[k];
+            if (k + 1 < m) s -= du[k] * x[k + 1];
+            if (k + 2 < m) s -= du2[k] * x[k + 2];
+            if (std::fabs(d[k]) < tiny) d[k] = d[k] < 0 ? -tiny : tiny;
+            x[k] = s / d[k];
+        }
+        double nrm = 0.0;
+        for (int k = 0; k < m; ++k) nrm += x[k] * x[k];
+        nrm = std::sqrt(nrm);
+        if (!(nrm > 0.0) || !std::isfinite(nrm)) return set_error(ED_EINVAL, "ed_tridiag_lowest_vector: inverse iteration failed");
+        for (int k = 0; k < m; ++k) x[k] /= nrm;
+    }
+    double sgn = x[0] < 0 ? -1.0 : 1.0;
+    for (int k = 0; k < m; ++k) y[k] = sgn * x[k];
+    return ED_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,164 @@
+"""Host-side library calls (no GPU): basis, ranks, ELL export, packer, tridiagonal
+solver, error paths, and the exported symbol set of include/ed.h."""
+
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import paper_1511_00863_amd as ed
+from paper_1511_00863_amd import _ffi
+from oracle.basis import basis_states
+from oracle.hopping import hopping_matrix, to_ell
+from synth import ring_bonds, torus_bonds, two_site_bonds
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "ed.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ed_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_every_declared_symbol_is_exported():
+    decl = _declared()
+    assert len(decl) >= 10
+    out = subprocess.run(["nm", "-D", "--defined-only", _ffi.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (ed_[a-z0-9_]+)", out))
+    missing = [d for d in decl if d not in exported]
+    assert not missing, missing
+    lib = ed.lib()
+    for d in decl:
+        assert hasattr(lib, d)
+    assert set(decl) == set(_ffi.exported_names())
+
+
+@pytest.mark.parametrize("ns,n", [(1, 0), (1, 1), (2, 1), (8, 4), (16, 5), (16, 8), (36, 3), (20, 10)])
+def test_basis_matches_oracle(ns, n):
+    st = ed.build_basis(ns, n)
+    if ns <= 20:
+        assert np.array_equal(st, basis_states(ns, n))
+    assert np.all(np.diff(st.astype(np.float64)) > 0) if st.size > 1 else True
+    assert np.array_equal(ed.state_rank(ns, n, st), np.arange(st.size))
+
+
+def test_basis_errors():
+    with pytest.raises(ed.EdError) as e:
+        ed.build_basis(65, 3)
+    assert e.value.code == _ffi.ED_EOVERFLOW
+    with pytest.raises(ed.EdError) as e:
+        ed.build_basis(8, 9)
+    assert e.value.code == _ffi.ED_EINVAL
+    with pytest.raises(ed.EdError) as e:
+        ed.build_basis(40, 20)          # C(40,20) > 2^31
+    assert e.value.code == _ffi.ED_EOVERFLOW
+    import ctypes
+    d = ctypes.c_int64(0)
+    buf = np.zeros(3, dtype=np.uint64)
+    rc = ed.lib().ed_build_basis(8, 4, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), 3, ctypes.byref(d))
+    assert rc == _ffi.ED_ECAPACITY and d.value == 70
+
+
+def test_rank_rejects_foreign_state():
+    with pytest.raises(ed.EdError):
+        ed.state_rank(8, 4, np.array([0b111], dtype=np.uint64))
+
+
+CASES = [("two_site", 2, two_site_bonds(), 1), ("ring8_n4", 8, ring_bonds(8), 4), ("ring8_n3", 8, ring_bonds(8), 3),
+         ("t44_n3", 16, torus_bonds(4, 4), 3), ("t44_n5", 16, torus_bonds(4, 4), 5),
+         ("t66_n3", 36, torus_bonds(6, 6), 3), ("ring6_n0", 6, ring_bonds(6), 0), ("ring6_n6", 6, ring_bonds(6), 6)]
+
+
+@pytest.mark.parametrize("name,ns,bonds,n", CASES)
+def test_hopping_ell_bit_exact_vs_oracle(name, ns, bonds, n):
+    st = basis_states(ns, n)
+    data, ind, width = to_ell(hopping_matrix(ns, bonds, st))
+    for layout, order in ((ed.ED_ROW_MAJOR, "C"), (ed.ED_COL_MAJOR, "F")):
+        t = ed.build_hopping(ns, bonds, st, layout)
+        assert t["width"] == width
+        if width:
+            assert np.array_equal(t["cols"], ind.flatten(order=order).astype(np.int32))
+            assert np.array_equal(t["vals"], data.flatten(order=order))
+        assert np.array_equal(t["nnz"], (data != 0).sum(axis=1)) if width else True
+
+
+def test_hopping_half_filling_4x4_vs_oracle():
+    st = basis_states(16, 8)
+    data, ind, width = to_ell(hopping_matrix(16, torus_bonds(4, 4), st))
+    t = ed.build_hopping(16, torus_bonds(4, 4), st, ed.ED_ROW_MAJOR)
+    assert width == 32 and t["width"] == 32
+    assert np.array_equal(t["cols"], ind.ravel().astype(np.int32))
+    assert np.array_equal(t["vals"], data.ravel())
+    assert int(t["nnz"].sum()) == 219648
+
+
+def test_pack_tables_roundtrip():
+    st = ed.build_basis(16, 5)
+    t = ed.build_hopping(16, torus_bonds(4, 4), st, ed.ED_ROW_MAJOR)
+    p = ed.pack_tables(t, st.size).reshape(t["width"], st.size)     # [k, r]
+    cols = t["cols"].reshape(st.size, t["width"])
+    vals = t["vals"].reshape(st.size, t["width"])
+    for r in range(0, st.size, 37):
+        for k in range(t["width"]):
+            e = int(p[k, r])
+            if k < t["nnz"][r]:
+                assert e >> 1 == cols[r, k] and ((e & 1) == 1) == (vals[r, k] < 0)
+            else:
+                assert e == 0xFFFF
+
+
+def test_hopping_errors():
+    st = ed.build_basis(4, 2)
+    with pytest.raises(ed.EdError):
+        ed.build_hopping(4, [(0, 1), (1, 0)], st)       # duplicate unordered bond
+    with pytest.raises(ed.EdError):
+        ed.build_hopping(4, [(0, 4)], st)               # site out of range
+    with pytest.raises(ed.EdError):
+        ed.build_hopping(4, [(2, 2)], st)
+
+
+def test_pack_rejects_non_unit_values():
+    t = {"cols": np.array([0, 1], dtype=np.int32), "vals": np.array([2.0, 1.0]),
+         "nnz": np.array([1, 1], dtype=np.int32), "width": 1, "layout": ed.ED_ROW_MAJOR}
+    with pytest.raises(ed.EdError):
+        ed.pack_tables(t, 2)
+
+
+def test_tridiag_closed_forms():
+    assert ed.tridiag_lowest([2.5], []) == 2.5
+    a1, a2, b = 1.3, -0.4, 0.9
+    ref = ((a1 + a2) - np.sqrt((a1 - a2) ** 2 + 4 * b * b)) / 2
+    assert abs(ed.tridiag_lowest([a1, a2], [b]) - ref) < 1e-15 * 4
+
+
+@pytest.mark.parametrize("m", [3, 17, 100, 300])
+def test_tridiag_vs_lapack(m):
+    rng = np.random.default_rng(m)
+    for _ in range(5):
+        a, b = rng.normal(size=m) * 10, rng.uniform(0.01, 3.0, m - 1)
+        ref = sla.eigh_tridiagonal(a, b, eigvals_only=True)[0]
+        nrm = np.abs(a).max() + 2 * b.max()
+        assert abs(ed.tridiag_lowest(a, b) - ref) <= 1e-13 * nrm
+        e, y = ed.tridiag_lowest_vector(a, b)
+        T = np.diag(a) + np.diag(b, 1) + np.diag(b, -1)
+        assert abs(np.linalg.norm(y) - 1) < 1e-12
+        assert np.linalg.norm(T @ y - e * y) < 1e-10 * nrm
+
+
+def test_tridiag_near_degenerate_vector():
+    # tiny off-diagonal coupling between two blocks: eigenvector still accurate
+    a = np.array([1.0, 1.0, -3.0, 0.5])
+    b = np.array([0.5, 1e-9, 0.2])
+    e, y = ed.tridiag_lowest_vector(a, b)
+    T = np.diag(a) + np.diag(b, 1) + np.diag(b, -1)
+    w, v = np.linalg.eigh(T)
+    assert abs(e - w[0]) < 1e-14 and abs(abs(y @ v[:, 0]) - 1) < 1e-12
+
+
+def test_tridiag_rejects_nan():
+    with pytest.raises(ed.EdError):
+        ed.tridiag_lowest([1.0, np.nan], [0.5])
