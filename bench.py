@@ -96,6 +96,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="use the built-in default tile instead of ed_tune")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this method runs on one GPU; --gpus %d is not supported (use --gpus 1)" % args.gpus,
@@ -119,11 +120,14 @@ def main():
     for dtype in (("f64",) if args.no_mixed else ("f64", "f32")):
         h = ed.Hamiltonian(up, dn, wl.t, wl.U, dtype)
         x = torch.from_numpy(x_host).to(dev, h.torch_dtype)
+        if not args.no_tune:
+            h.tune(x, reps=3)          # the project's autotuner; outside the timed region
         ms, per, st = time_run(h, x, args.warmup, args.steps, args.kernel_samples)
         es = 8 if dtype == "f64" else 4
         kb = kernel_bytes(h, es)
         hv_bytes = 2 * es * h.dim + h.dim_up * h.up.width * 2 + h.dim_dn * h.dn.width * 2
         results[dtype] = {"ms_per_step": ms, "steps_per_s": 1000.0 / ms, "kernel_ms": per, "kernel_bytes": kb,
+                          "tile": h.tile, "tile_params": h.tile_params(),
                           "hv_alg_GBps": hv_bytes / ((per["k_up"] + per["k_down"]) * 1e-3) / 1e9,
                           "step_floor_GBps": 3 * es * h.dim / (ms * 1e-3) / 1e9}
         del x, h
@@ -153,12 +157,14 @@ def main():
         "hv_alg_GBps": r64["hv_alg_GBps"],
         "step_floor_frac": r64["step_floor_GBps"] / HBM_PEAK_GBPS,
         "kernel_ms": r64["kernel_ms"],
+        "tile": {"id": r64["tile"], **r64["tile_params"]},
     }
     if "f32" in results:
         r32 = results["f32"]
         line["mixed"] = {"dtype": "f32 vectors, f64 scalars", "steps_per_s": r32["steps_per_s"],
                          "ms_per_step": r32["ms_per_step"], "hv_alg_GBps": r32["hv_alg_GBps"],
-                         "kernel_ms": r32["kernel_ms"], "step_floor_frac": r32["step_floor_GBps"] / HBM_PEAK_GBPS}
+                         "kernel_ms": r32["kernel_ms"], "step_floor_frac": r32["step_floor_GBps"] / HBM_PEAK_GBPS,
+                         "tile": {"id": r32["tile"], **r32["tile_params"]}}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
     print(json.dumps(line), flush=True)

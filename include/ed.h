@@ -88,11 +88,18 @@ int ed_build_hopping(int n_sites, const int32_t *bonds, int n_bonds, const uint6
                      int32_t *nnz, int32_t *width);
 
 /* Convert an exported ELL table into the device table format: uint16
- * entries, column-major ([k * dim + r]), e = (col << 1) | (val < 0), padding
- * 0xFFFF after the last nonzero of a row (ascending columns as exported).
+ * entries e = (col << 1) | (val < 0) in ascending column order with padding
+ * 0xFFFF after the last nonzero of a row; the row stride W8 is the width
+ * rounded up to a multiple of 8 (whole 16-byte chunks).  The table is stored
+ * twice, one layout after the other:
+ *   [0, dim*W8):       row-major, entry k of row r at [r*W8 + k]
+ *                      (read by the up-part kernel, one row per wavefront);
+ *   [dim*W8, 2*dim*W8): 8-interleaved, entry k of row r at
+ *                      [dim*W8 + ((k/8)*dim + r)*8 + k%8]
+ *                      (read by the down-part kernel, one row per lane).
  * Input values must be exactly +-1 for k < nnz[r] (ED_EINVAL otherwise);
- * dim > 32767 -> ED_EOVERFLOW.  packed: host, width * dim entries.  Copy it
- * to device memory for ed_ham. */
+ * dim > 32767 -> ED_EOVERFLOW.  packed: host, 2 * dim * W8 entries.  Copy it
+ * to 16-byte aligned device memory for ed_ham, whose w_up/w_dn are then W8. */
 int ed_pack_tables(const int32_t *cols, const double *vals, const int32_t *nnz, int64_t dim,
                    int32_t width, int layout, uint16_t *packed);
 
@@ -108,8 +115,8 @@ int ed_tridiag_lowest_vector(const double *a, const double *b, int m, double *e0
 /* ---- device: the Hamiltonian and H.v ----------------------------------- */
 
 /* One instance (lattice, fillings, t, U).  All pointers are device memory.
- * tab_up/tab_dn: ed_pack_tables output for H_up (dim_up x w_up) and H_dn
- * (dim_dn x w_dn).  st_up/st_dn: the per-spin bases (for the U term).
+ * tab_up/tab_dn: ed_pack_tables output for H_up and H_dn, with row strides
+ * w_up/w_dn (multiples of 8; 0 when a species cannot hop).  st_up/st_dn: the per-spin bases (for the U term).
  * dtype: ED_F64 or ED_F32 (vectors and H.v).  tile: 0 = default launch
  * configuration, else an id returned by ed_tune.  dim_up, dim_dn <= 32767
  * (the table format; ED_EOVERFLOW otherwise). */
@@ -129,8 +136,34 @@ typedef struct ed_ham {
 int ed_workspace_size(const ed_ham *h, int32_t max_steps, int64_t *bytes);
 
 /* y = H x (Eq. 3-5 plus the diagonal U term).  x, y: device, dim_up*dim_dn
- * elements of h->dtype, distinct buffers.  ws: device workspace. */
+ * elements of h->dtype, distinct buffers.  ws: device workspace of
+ * ed_workspace_size(h, 0) bytes (work-queue counters of the up-part kernel). */
 int ed_hv(const ed_ham *h, const void *x, void *y, void *ws, void *stream);
+
+/* Launch-configuration autotuner (the paper tuned its CPU blocking and GPU
+ * block size by experiment, Sec. 4-5; this searches the kernels' tiles).
+ * Times every candidate tile of the up-part kernel (stripe width, rows per
+ * tile, workgroup-to-XCD mapping) and of the down-part kernel (workgroup size,
+ * rows per workgroup) on y = H x with h's sizes, `reps` timed launches each
+ * after one warm-up, and returns in *tile the id of the fastest combination,
+ * to be stored in ed_ham.tile.  The down-part kernel is timed as in a
+ * Lanczos step.  x, y: as for ed_hv (y is overwritten); ws: device
+ * workspace of ed_workspace_size(h, 2) bytes.
+ * ms_up (n_up doubles) / ms_dn (n_dn doubles), may be NULL: average ms per
+ * candidate index, -1 where a candidate does not apply (see ed_tile_count).
+ * Synchronises `stream`. */
+int ed_tune(const ed_ham *h, const void *x, void *y, void *ws, void *stream, int32_t reps, int32_t *tile,
+            double *ms_up, double *ms_dn);
+
+/* Number of up-part and down-part tile candidates; a tile id is
+ * up_index | (down_index << 8), index 0 = built-in default. */
+int ed_tile_count(int32_t *n_up, int32_t *n_dn);
+
+/* The launch parameters a tile id resolves to for instance h: params[0..5] =
+ * stripe width, rows per up tile, up workgroup size, up mapping (0 XCD
+ * round-robin, 1 linear, 2 per-XCD work queues), down workgroup size, rows
+ * per down workgroup.  params: host, 6 ints. */
+int ed_tile_params(int32_t tile, const ed_ham *h, int32_t *params);
 
 /* ---- device: the Lanczos iteration (Alg. 1) ---------------------------- */
 

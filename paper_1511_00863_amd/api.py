@@ -69,9 +69,16 @@ def build_hopping(n_sites: int, bonds, states, layout: int = ED_COL_MAJOR):
     return {"cols": cols, "vals": vals, "nnz": nnz, "width": width, "layout": layout}
 
 
+def table_stride(width: int) -> int:
+    """Row stride of the device table: the ELL width rounded up to a multiple of 8."""
+    return (int(width) + 7) & ~7
+
+
 def pack_tables(table, dim: int) -> np.ndarray:
+    """Device table (uint16; row-major then 8-interleaved, stride table_stride(width))."""
     width = table["width"]
-    out = np.zeros(max(width * dim, 1), dtype=np.uint16)
+    stride = table_stride(width)
+    out = np.zeros(max(2 * stride * dim, 1), dtype=np.uint16)
     if width == 0:
         return out[:0]
     check(lib().ed_pack_tables(_ptr(table["cols"], c_int32), _ptr(table["vals"], c_double),
@@ -108,6 +115,7 @@ class SpinTables:
         self.dim = int(self.states.size)
         self.table = build_hopping(n_sites, self.bonds, self.states, ED_COL_MAJOR)
         self.width = self.table["width"]
+        self.stride = table_stride(self.width)
         self.packed = pack_tables(self.table, self.dim)
         self.device = torch.device(device if device is not None else "cuda")
         self.dev_states = torch.from_numpy(self.states.view(np.int64).copy()).to(self.device)
@@ -148,7 +156,7 @@ class Hamiltonian:
         return torch.float64 if self.dtype == ED_F64 else torch.float32
 
     def c_struct(self) -> EdHam:
-        return EdHam(self.dim_up, self.dim_dn, self.up.width, self.dn.width,
+        return EdHam(self.dim_up, self.dim_dn, self.up.stride, self.dn.stride,
                      self.up.dev_tab.data_ptr(), self.dn.dev_tab.data_ptr(),
                      self.up.dev_states.data_ptr(), self.dn.dev_states.data_ptr(),
                      self.t, self.U, self.dtype, self.tile)
@@ -175,9 +183,38 @@ class Hamiltonian:
         """y = H x (Eq. 3-5 plus the U term)."""
         x = self._vec(x)
         y = self.empty_vec() if y is None else self._vec(y)
+        if ws is None:
+            ws = self.workspace(0)
         h = self.c_struct()
         check(lib().ed_hv(byref(h), _dptr(x), _dptr(y), _dptr(ws), _stream(stream)))
         return y
+
+    def tile_params(self, tile=None):
+        p = np.zeros(6, dtype=np.int32)
+        h = self.c_struct()
+        check(lib().ed_tile_params(self.tile if tile is None else int(tile), byref(h), _ptr(p, c_int32)))
+        keys = ("stripe_width", "up_rows", "up_block", "up_map", "dn_block", "dn_rows")
+        return dict(zip(keys, p.tolist()))
+
+    def tune(self, x=None, reps: int = 3, stream=None, apply: bool = True):
+        """Time every tile candidate on y = H x and (apply=True) adopt the fastest.
+
+        Returns dict(tile, up_ms, dn_ms) with per-candidate times (-1 = not applicable)."""
+        if x is None:
+            x = torch.ones(self.dim, dtype=self.torch_dtype, device=self.device)
+        x = self._vec(x)
+        y = self.empty_vec()
+        ws = self.workspace(2)
+        nu, nd = c_int32(0), c_int32(0)
+        check(lib().ed_tile_count(byref(nu), byref(nd)))
+        mu, md = np.full(nu.value, -1.0), np.full(nd.value, -1.0)
+        tile = c_int32(0)
+        h = self.c_struct()
+        check(lib().ed_tune(byref(h), _dptr(x), _dptr(y), _dptr(ws), _stream(stream), int(reps), byref(tile),
+                            _ptr(mu, c_double), _ptr(md, c_double)))
+        if apply:
+            self.tile = tile.value
+        return {"tile": tile.value, "up_ms": mu, "dn_ms": md}
 
     def lanczos(self, max_steps: int) -> "LanczosRun":
         return LanczosRun(self, max_steps)

@@ -47,7 +47,8 @@ namespace ed {
 //   k_norm   b_{j+1} = |F_{j+1}| (line 7), breakdown test (line 8)
 // so b_{j+1} is the norm of the vector actually stored, with no cancellation.
 //
-// workspace layout: [Hdr: 256 B][y: max_steps doubles][part: P x 8][part2: 8192]
+// workspace layout: [Hdr: 256 B][queue counters: 256 B][y: max_steps doubles]
+//                   [part: P x 8 doubles][part2: 8192 doubles]
 struct Hdr {
     double sig_cur;    // 1 / s_j of the current vector
     double sig_prev;   // 1 / s_{j-1}
@@ -67,6 +68,7 @@ static inline int64_t align256(int64_t b) { return (b + 255) & ~int64_t(255); }
 
 struct WsLayout {
     Hdr *hdr;
+    int *ctr;
     double *y;
     double *part;
     double *part2;
@@ -75,7 +77,7 @@ struct WsLayout {
 static int64_t n_partial_slots(const ed_ham *h) { return std::max<int64_t>(h->dim_up, 1); }
 
 static int64_t ws_bytes(const ed_ham *h, int32_t max_steps) {
-    return 256 + align256(8 * (int64_t)std::max(max_steps, 1)) + align256(8 * kPartStride * n_partial_slots(h)) +
+    return 512 + align256(8 * (int64_t)std::max(max_steps, 1)) + align256(8 * kPartStride * n_partial_slots(h)) +
            8 * kUpdBlocks;
 }
 
@@ -83,6 +85,8 @@ static WsLayout ws_layout(const ed_ham *h, void *ws, int32_t max_steps) {
     char *p = static_cast<char *>(ws);
     WsLayout l;
     l.hdr = reinterpret_cast<Hdr *>(p);
+    p += 256;
+    l.ctr = reinterpret_cast<int *>(p);
     p += 256;
     l.y = reinterpret_cast<double *>(p);
     p += align256(8 * (int64_t)std::max(max_steps, 1));
@@ -122,49 +126,165 @@ __device__ __forceinline__ bool frozen(const Hdr *hdr, int max_steps) {
 }
 
 // ---------------------------------------------------------------------------
-// k_up: out[r, c] = t * sum_k sgn_k * x[J_up[r,k], c]   (Eq. 4)
-// Workgroup g runs on XCD g % 8 (round-robin dispatch).  Stripe s belongs to
-// XCD s % 8; the n_rc row chunks of a stripe are consecutive workgroups of
-// that XCD.  A wave covers 64/w rows x w columns of a stripe.
-template <typename T>
-__global__ __launch_bounds__(256) void k_up(const T *__restrict__ x, T *__restrict__ out,
-                                            const uint16_t *__restrict__ tab, int Dup, int Ddn, int Wup,
-                                            int w_log2, int rc, int n_stripes, int n_rc, T t,
-                                            const Hdr *__restrict__ hdr, int gate, int max_steps) {
-    if (gate && frozen(hdr, max_steps)) return;
-    const int g = blockIdx.x, xcd = g & 7, local = g >> 3;
-    const int sl = local / n_rc, rci = local - sl * n_rc;
-    const int s = sl * 8 + xcd;
-    if (s >= n_stripes) return;
-    const int w = 1 << w_log2;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
-    const int rpw = 64 >> w_log2;
+// table entries: 8 uint16 per 16-byte chunk, e = (col << 1) | negative, 0xFFFF = pad
+__device__ __forceinline__ unsigned entry(const uint4 &q, int k) {
+    const unsigned w = k < 2 ? q.x : (k < 4 ? q.y : (k < 6 ? q.z : q.w));
+    return (k & 1) ? (w >> 16) : (w & 0xFFFFu);
+}
+
+// Up part (Eq. 4) on one tile = (column stripe s of width w = 64/R, row chunk rci):
+// out[r, c] = t * sum_k sgn_k * x[J_up[r,k], c].  A wave serves R consecutive
+// rows x w columns; the row index is wave-uniform, so each row's table chunks
+// are scalar loads, chunks that are padding for every row of the wave are
+// skipped, and the 8 gathers of a chunk per row are issued back to back
+// (padding inside a chunk re-reads x[0, c] and is multiplied by zero).
+template <typename T, int R>
+__device__ __forceinline__ void up_tile(const T *__restrict__ x, T *__restrict__ out,
+                                        const uint16_t *__restrict__ tab, int Dup, int Ddn, int W8, int rc, int s,
+                                        int rci, T t) {
+    constexpr int w = 64 / R;
+    const int lane = threadIdx.x & 63, nwave = blockDim.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int sub = R == 1 ? 0 : lane / w;
     const int c = s * w + (lane & (w - 1));
-    if (c >= Ddn) return;
+    const bool cok = c < Ddn;
+    const int cc = cok ? c : 0;
+    const T *xc = x + cc;
     const int r1 = min(Dup, (rci + 1) * rc);
-    for (int r = rci * rc + wave * rpw + (lane >> w_log2); r < r1; r += nwave * rpw) {
-        T acc = T(0);
-        for (int k = 0; k < Wup; ++k) {
-            const unsigned e = tab[(int64_t)k * Dup + r];
-            if (e == 0xFFFFu) break;
-            const T v = x[(int64_t)(e >> 1) * Ddn + c];
-            acc += (e & 1u) ? -v : v;
+    const int nch = W8 >> 3;
+    for (int rb = rci * rc + wave * R; rb < r1; rb += nwave * R) {
+        const int r = rb + sub;
+        T acc0 = T(0), acc1 = T(0);
+        for (int k8 = 0; k8 < nch; ++k8) {
+            uint4 q[R];
+            bool any = false;
+#pragma unroll
+            for (int u = 0; u < R; ++u) {
+                const int ru = min(rb + u, Dup - 1);
+                q[u] = *reinterpret_cast<const uint4 *>(tab + (int64_t)ru * W8 + 8 * k8);
+                any = any || (entry(q[u], 0) != 0xFFFFu && rb + u < r1);
+            }
+            if (!any) break;   // ascending columns, padding at the end: the rest is padding too
+            T v[8], sg[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                unsigned e = entry(q[0], k);
+#pragma unroll
+                for (int u = 1; u < R; ++u)
+                    if (sub == u) e = entry(q[u], k);
+                const bool pk = e != 0xFFFFu;
+                sg[k] = pk ? ((e & 1u) ? T(-1) : T(1)) : T(0);
+                v[k] = xc[(int64_t)(pk ? (e >> 1) : 0u) * Ddn];
+            }
+#pragma unroll
+            for (int k = 0; k < 8; k += 2) {
+                acc0 += sg[k] * v[k];
+                acc1 += sg[k + 1] * v[k + 1];
+            }
         }
-        out[(int64_t)r * Ddn + c] = t * acc;
+        if (cok && r < r1) __builtin_nontemporal_store(t * (acc0 + acc1), out + (int64_t)r * Ddn + c);
     }
+}
+
+// k_up, static mapping.  map 0: workgroup g runs on XCD g % 8 under
+// round-robin dispatch; stripe s belongs to XCD s % 8 and its n_rc row chunks
+// are consecutive workgroups of that XCD, so the stripe stays in that XCD's
+// L2 while its chunks run.  map 1: plain stripe-major order.
+template <typename T, int R>
+__global__ __launch_bounds__(512) void k_up(const T *__restrict__ x, T *__restrict__ out,
+                                            const uint16_t *__restrict__ tab, int Dup, int Ddn, int W8, int rc,
+                                            int n_stripes, int n_rc, int map, T t, const Hdr *__restrict__ hdr,
+                                            int gate, int max_steps) {
+    if (gate && frozen(hdr, max_steps)) return;
+    int s, rci;
+    if (map == 0) {
+        const int g = blockIdx.x, xcd = g & 7, local = g >> 3;
+        const int sl = local / n_rc;
+        rci = local - sl * n_rc;
+        s = sl * 8 + xcd;
+    } else {
+        s = blockIdx.x / n_rc;
+        rci = blockIdx.x - s * n_rc;
+    }
+    if (s >= n_stripes) return;
+    up_tile<T, R>(x, out, tab, Dup, Ddn, W8, rc, s, rci, t);
+}
+
+// k_up_q, persistent mapping (map 2): one queue per XCD holding the tiles of
+// the stripes s = q (mod 8).  A workgroup reads the XCD it runs on from the
+// XCC_ID hardware register, drains that XCD's queue (integer atomics), then
+// helps the other queues, so every tile is processed whatever the dispatch.
+template <typename T, int R>
+__global__ __launch_bounds__(512) void k_up_q(const T *__restrict__ x, T *__restrict__ out,
+                                              const uint16_t *__restrict__ tab, int Dup, int Ddn, int W8, int rc,
+                                              int n_stripes, int n_rc, T t, int *__restrict__ ctr,
+                                              const Hdr *__restrict__ hdr, int gate, int max_steps) {
+    if (gate && frozen(hdr, max_steps)) return;
+    __shared__ int tile_sh;
+    const int mine = (int)(__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 7u);
+    for (int qi = 0; qi < 8; ++qi) {
+        const int q = (mine + qi) & 7;
+        const int ntiles = (q < n_stripes ? (n_stripes - q + 7) / 8 : 0) * n_rc;
+        while (true) {
+            if (threadIdx.x == 0) tile_sh = atomicAdd(&ctr[q], 1);
+            __syncthreads();
+            const int tq = tile_sh;
+            __syncthreads();
+            if (tq >= ntiles) break;
+            const int sl = tq / n_rc;
+            up_tile<T, R>(x, out, tab, Dup, Ddn, W8, rc, q + 8 * sl, tq - sl * n_rc, t);
+        }
+    }
+}
+
+__global__ void k_ctr_reset(int *ctr, const Hdr *hdr, int gate, int max_steps) {
+    if (gate && frozen(hdr, max_steps)) return;
+    if (threadIdx.x < 8) ctr[threadIdx.x] = 0;
 }
 
 // ---------------------------------------------------------------------------
 // k_down: q[r, c] = sig * (io[r, c] + t * sum_k sgn_k x[r, J_dn[c,k]] + U*Docc[r,c]*x[r,c])
 //                   (- b_j sig_prev p[r, c] in a Lanczos step)          (Eq. 5)
-// io holds the up part on entry and q on exit.
+// io holds the up part on entry and q on exit.  The rows of the block are
+// staged in LDS with 16-byte loads; lane c reads its table row from the
+// 8-interleaved layout (16 bytes per chunk, contiguous across lanes).  The
+// column loop is software pipelined: the next column's table chunks, up
+// part and f_{j-1} value are loaded while the current column gathers from LDS
+// (branch-free: padding reads the lane's own element times zero).
+// NCH = largest number of table chunks per row (W8 / 8 <= NCH) the
+// instantiation handles; LDS = rows staged in LDS (else the gathers read
+// global memory).
 // MODE 0: plain H.v (sig = 1).  MODE 1: Lanczos, partial q.x.
 // MODE 2: Lanczos mixed form, partials (q.x, q.p, x.x, x.p, p.p).
-template <typename T, int MODE, bool LDS>
+template <typename T>
+__device__ __forceinline__ void stage_rows(const T *__restrict__ src, T *__restrict__ dst, int n) {
+    // 16-byte pieces, four in flight per thread; the tail element by element
+    constexpr int V = 16 / sizeof(T);
+    const int nv = n / V;
+    const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
+    uint4 *d4 = reinterpret_cast<uint4 *>(dst);
+    const bool aligned = (reinterpret_cast<uintptr_t>(src) & 15) == 0;
+    if (aligned) {
+        int i = threadIdx.x;
+        for (; i + 3 * (int)blockDim.x < nv; i += 4 * blockDim.x) {
+            const uint4 a = s4[i], b = s4[i + blockDim.x], c = s4[i + 2 * blockDim.x], d = s4[i + 3 * blockDim.x];
+            d4[i] = a;
+            d4[i + blockDim.x] = b;
+            d4[i + 2 * blockDim.x] = c;
+            d4[i + 3 * blockDim.x] = d;
+        }
+        for (; i < nv; i += blockDim.x) d4[i] = s4[i];
+        for (int k = nv * V + threadIdx.x; k < n; k += blockDim.x) dst[k] = src[k];
+    } else {
+        for (int k = threadIdx.x; k < n; k += blockDim.x) dst[k] = src[k];
+    }
+}
+
+template <typename T, int MODE, bool LDS, int NCH>
 __global__ __launch_bounds__(1024) void k_down(const T *__restrict__ x, T *__restrict__ io, const T *__restrict__ p,
                                                const uint16_t *__restrict__ tab,
                                                const uint64_t *__restrict__ st_up,
-                                               const uint64_t *__restrict__ st_dn, int Dup, int Ddn, int Wdn,
+                                               const uint64_t *__restrict__ st_dn, int Dup, int Ddn, int W8,
                                                int rpb, T t, T U, const double *__restrict__ bvec,
                                                const Hdr *__restrict__ hdr, double *__restrict__ partials,
                                                int max_steps) {
@@ -184,40 +304,76 @@ __global__ __launch_bounds__(1024) void k_down(const T *__restrict__ x, T *__res
     const int64_t base = (int64_t)r0 * Ddn;
     const int n = nr * Ddn;
     if (LDS) {
-        for (int i = threadIdx.x; i < n; i += blockDim.x) xs[i] = x[base + i];
+        stage_rows<T>(x + base, xs, n);
         __syncthreads();
     }
+    const uint4 *til = reinterpret_cast<const uint4 *>(tab + (int64_t)Ddn * W8);   // 8-interleaved part
+    const int nch = W8 >> 3;
+    const uint4 kPad4 = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
     constexpr int NV = MODE == 2 ? 5 : 1;
     double s[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) s[k] = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        int rr = 0, c = i;
-        if (rpb > 1) { rr = i / Ddn; c = i - rr * Ddn; }
+    const bool use_p = MODE != 0 && has_prev;
+
+    int i = threadIdx.x;
+    uint4 tq[NCH];
+    T iov = T(0), pv = T(0);
+    int c = 0, rr = 0;
+    if (i < n) {
+        if (rpb > 1) { rr = i / Ddn; c = i - rr * Ddn; } else { c = i; }
+#pragma unroll
+        for (int k8 = 0; k8 < NCH; ++k8) tq[k8] = k8 < nch ? til[(int64_t)k8 * Ddn + c] : kPad4;
+        iov = io[base + i];
+        if (use_p) pv = p[base + i];
+    }
+    for (; i < n; i += blockDim.x) {
+        // prefetch the next column of this thread
+        const int in = i + blockDim.x;
+        int cn = 0, rrn = 0;
+        uint4 tqn[NCH];
+        T iovn = T(0), pvn = T(0);
+        if (in < n) {
+            if (rpb > 1) { rrn = in / Ddn; cn = in - rrn * Ddn; } else { cn = in; }
+#pragma unroll
+            for (int k8 = 0; k8 < NCH; ++k8) tqn[k8] = k8 < nch ? til[(int64_t)k8 * Ddn + cn] : kPad4;
+            iovn = io[base + in];
+            if (use_p) pvn = p[base + in];
+        }
         const T *xrow = LDS ? xs + rr * Ddn : x + base + (int64_t)rr * Ddn;
-        T acc = T(0);
-        for (int k = 0; k < Wdn; ++k) {
-            const unsigned e = tab[(int64_t)k * Ddn + c];
-            if (e == 0xFFFFu) break;
-            const T v = xrow[e >> 1];
-            acc += (e & 1u) ? -v : v;
+        T acc0 = T(0), acc1 = T(0);
+#pragma unroll
+        for (int k8 = 0; k8 < NCH; ++k8) {
+            if (k8 >= nch) break;
+            // a chunk whose first entry is padding is padding throughout; skip it
+            // when that holds for every lane of the wave
+            if (!__any(entry(tq[k8], 0) != 0xFFFFu)) break;
+            T v[8], sg[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const unsigned e = entry(tq[k8], k);
+                const bool pk = e != 0xFFFFu;
+                sg[k] = pk ? ((e & 1u) ? T(-1) : T(1)) : T(0);
+                v[k] = xrow[pk ? (int)(e >> 1) : 0];   // padding: one broadcast address
+            }
+#pragma unroll
+            for (int k = 0; k < 8; k += 2) {
+                acc0 += sg[k] * v[k];
+                acc1 += sg[k + 1] * v[k + 1];
+            }
         }
         const T xv = xrow[c];
         const T nd = static_cast<T>(__popcll(st_up[r0 + rr] & st_dn[c]));
-        T q = io[base + i] + t * acc + U * nd * xv;
-        T pv = T(0);
+        T q = iov + t * (acc0 + acc1) + U * nd * xv;
         if (MODE != 0) {
             q *= sig;
-            if (has_prev) {
-                pv = p[base + i];
-                q -= cprev * pv;
-            }
+            if (use_p) q -= cprev * pv;
         }
         io[base + i] = q;
         if (MODE != 0) {
             const double qd = q, xd = xv;
             s[0] += qd * xd;
-            if (MODE == 2) {
+            if constexpr (MODE == 2) {
                 const double pd = pv;
                 s[1] += qd * pd;
                 s[2] += xd * xd;
@@ -225,6 +381,12 @@ __global__ __launch_bounds__(1024) void k_down(const T *__restrict__ x, T *__res
                 s[4] += pd * pd;
             }
         }
+        c = cn;
+        rr = rrn;
+        iov = iovn;
+        pv = pvn;
+#pragma unroll
+        for (int k8 = 0; k8 < NCH; ++k8) tq[k8] = tqn[k8];
     }
     if (MODE != 0) {
         double tot[NV];
@@ -289,11 +451,32 @@ __global__ __launch_bounds__(256) void k_update(T *__restrict__ q, const T *__re
     const double yj = v ? y[hdr->jdev] * hdr->sig_cur : 0.0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     double s[1] = {0.0};
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // four independent elements per trip keep more loads in flight
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        double xv[4], qv[4], pv[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            xv[u] = x[i + u * stride];
+            qv[u] = q[i + u * stride];
+        }
+        if (cp != 0.0) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) pv[u] = p[i + u * stride];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const T st = static_cast<T>(qv[u] - cx * xv[u] - cp * pv[u]);
+            q[i + u * stride] = st;
+            const double sd = st;
+            s[0] += sd * sd;
+            if (v) v[i + u * stride] = static_cast<T>((double)v[i + u * stride] + yj * xv[u]);
+        }
+    }
+    for (; i < n; i += stride) {
         const double xv = x[i];
-        double qv = (double)q[i] - cx * xv;
-        if (cp != 0.0) qv -= cp * (double)p[i];
-        const T st = static_cast<T>(qv);
+        const double pv = cp != 0.0 ? (double)p[i] : 0.0;
+        const T st = static_cast<T>((double)q[i] - cx * xv - cp * pv);
         q[i] = st;
         const double sd = st;
         s[0] += sd * sd;
@@ -383,45 +566,80 @@ __global__ __launch_bounds__(256) void k_fill0(T *__restrict__ out, int64_t n) {
 // ---------------------------------------------------------------------------
 // launch configuration ("tile")
 struct Tile {
-    int up_wlog2;   // stripe width = 2^up_wlog2 columns (<= 64)
-    int up_rc;      // rows per k_up workgroup
+    int up_wlog2;   // stripe width = 2^up_wlog2 columns (8..64)
+    int up_rc;      // rows per k_up tile
     int up_block;   // k_up threads per workgroup
+    int up_map;     // 0 XCD round-robin remap, 1 linear, 2 per-XCD queues
     int dn_block;   // k_down threads per workgroup
-    int dn_rpb;     // rows per k_down workgroup (0 = derive from LDS)
+    int dn_rpb;     // rows per k_down workgroup (0 = derive from LDS and block)
 };
 
-// Candidate tiles searched by ed_tune; id 0 means "heuristic default".
-static const Tile kTiles[] = {
-    {0, 0, 0, 0, 0},
-    {6, 64, 256, 1024, 0}, {5, 64, 256, 1024, 0}, {4, 64, 256, 1024, 0},
-    {6, 128, 256, 1024, 0}, {5, 128, 256, 1024, 0}, {4, 128, 256, 1024, 0},
-    {6, 32, 256, 1024, 0}, {5, 32, 256, 1024, 0},
-    {6, 64, 256, 512, 0}, {5, 64, 256, 512, 0}, {6, 64, 256, 256, 0}, {5, 64, 256, 256, 0},
-    {6, 256, 256, 1024, 0}, {5, 256, 256, 1024, 0},
+struct UpTile { int wlog2, rc, block, map; };
+struct DnTile { int block, rpb; };
+
+// Candidates searched by ed_tune.  A tile id is up_index | (dn_index << 8);
+// index 0 means "heuristic default" for that kernel.
+static const UpTile kUpTiles[] = {
+    {0, 0, 0, 0},
+    {6, 16, 256, 0}, {5, 16, 256, 0}, {4, 16, 256, 0},
+    {6, 32, 256, 0}, {5, 32, 256, 0}, {4, 32, 256, 0},
+    {6, 64, 256, 0}, {5, 64, 256, 0}, {4, 64, 256, 0},
+    {6, 128, 256, 0}, {5, 128, 256, 0}, {4, 128, 256, 0},
+    {6, 256, 256, 0}, {5, 256, 256, 0}, {4, 256, 256, 0},
+    {6, 32, 256, 1}, {5, 32, 256, 1}, {4, 32, 256, 1},
+    {6, 128, 256, 1}, {5, 128, 256, 1}, {4, 128, 256, 1},
+    {6, 32, 256, 2}, {5, 32, 256, 2}, {4, 32, 256, 2},
+    {6, 128, 256, 2}, {5, 128, 256, 2}, {4, 128, 256, 2},
+    {6, 64, 512, 0}, {5, 64, 512, 0}, {6, 128, 512, 0}, {5, 128, 512, 0},
 };
-constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
+static const DnTile kDnTiles[] = {
+    {0, 0}, {1024, 0}, {512, 0}, {256, 0}, {1024, 1}, {512, 1}, {256, 1}, {1024, 2}, {512, 2}, {256, 4},
+};
+constexpr int kNumUp = sizeof(kUpTiles) / sizeof(kUpTiles[0]);
+constexpr int kNumDn = sizeof(kDnTiles) / sizeof(kDnTiles[0]);
 constexpr int kLdsBudget = 152 * 1024;
 
 static int elem_size(const ed_ham *h) { return h->dtype == ED_F64 ? 8 : 4; }
 
-static Tile resolve_tile(const ed_ham *h) {
-    Tile t = (h->tile > 0 && h->tile < kNumTiles) ? kTiles[h->tile] : Tile{0, 0, 0, 0, 0};
+static Tile resolve_tile_id(const ed_ham *h, int id) {
+    const int ui = id & 0xFF, di = (id >> 8) & 0xFF;
     const int es = elem_size(h);
-    if (t.up_block == 0) {
+    Tile t;
+    if (ui > 0 && ui < kNumUp) {
+        t.up_wlog2 = kUpTiles[ui].wlog2;
+        t.up_rc = kUpTiles[ui].rc;
+        t.up_block = kUpTiles[ui].block;
+        t.up_map = kUpTiles[ui].map;
+    } else {
         t.up_wlog2 = es == 8 ? 5 : 6;
         t.up_rc = 64;
         t.up_block = 256;
-        t.dn_block = h->dim_dn >= 1024 ? 1024 : 256;
+        t.up_map = 0;
     }
-    // stripes narrower than the row are pointless
+    if (di > 0 && di < kNumDn) {
+        t.dn_block = kDnTiles[di].block;
+        t.dn_rpb = kDnTiles[di].rpb;
+    } else {
+        t.dn_block = h->dim_dn >= 1024 ? 1024 : 256;
+        t.dn_rpb = 0;
+    }
+    // stripes much wider than the row are pointless
     while (t.up_wlog2 > 4 && (1 << (t.up_wlog2 - 1)) >= h->dim_dn) --t.up_wlog2;
+    if (t.up_wlog2 < 4) t.up_wlog2 = 4;
+    const int64_t row_bytes = h->dim_dn * es;
     if (t.dn_rpb == 0) {
-        const int64_t row_bytes = h->dim_dn * es;
         int64_t by_lds = std::max<int64_t>(1, kLdsBudget / row_bytes);
         int64_t by_fill = std::max<int64_t>(1, (2 * t.dn_block + h->dim_dn - 1) / h->dim_dn);
         t.dn_rpb = (int)std::min<int64_t>(std::min(by_lds, by_fill), h->dim_up);
     }
+    t.dn_rpb = (int)std::max<int64_t>(1, std::min<int64_t>(t.dn_rpb, h->dim_up));
     return t;
+}
+
+static Tile resolve_tile(const ed_ham *h) { return resolve_tile_id(h, h->tile); }
+
+static bool valid_tile_id(int id) {
+    return id >= 0 && (id & 0xFF) < kNumUp && ((id >> 8) & 0xFF) < kNumDn && (id >> 16) == 0;
 }
 
 static int check_ham(const ed_ham *h, const char *who) {
@@ -432,8 +650,10 @@ static int check_ham(const ed_ham *h, const char *who) {
     if (h->w_up < 0 || h->w_dn < 0 || (h->w_up && !h->tab_up) || (h->w_dn && !h->tab_dn) || !h->st_up ||
         !h->st_dn)
         return set_error(ED_EINVAL, "%s: missing tables or states", who);
+    if ((h->w_up & 7) || (h->w_dn & 7)) return set_error(ED_EINVAL, "%s: table strides must be multiples of 8", who);
+    if (h->w_up > 64 || h->w_dn > 64) return set_error(ED_EOVERFLOW, "%s: table strides above 64 unsupported", who);
     if (h->dtype != ED_F64 && h->dtype != ED_F32) return set_error(ED_EINVAL, "%s: bad dtype %d", who, h->dtype);
-    if (h->tile < 0 || h->tile >= kNumTiles) return set_error(ED_EINVAL, "%s: bad tile id %d", who, h->tile);
+    if (!valid_tile_id(h->tile)) return set_error(ED_EINVAL, "%s: bad tile id %d", who, h->tile);
     if (!std::isfinite(h->t) || !std::isfinite(h->U)) return set_error(ED_EINVAL, "%s: non-finite t or U", who);
     return ED_OK;
 }
@@ -460,25 +680,72 @@ static int grid_for(int64_t n, int block, int cap = 4096) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
 }
 
-template <typename T>
-static int launch_up(const ed_ham *h, const Tile &tl, const T *x, T *out, const Hdr *hdr, int gate, int max_steps,
-                     hipStream_t s) {
-    const int w = 1 << tl.up_wlog2;
+static int up_queue_grid(int block) {
+    static int cached = 0;
+    if (cached) return cached;
+    int dev = 0, ncu = 0, occ = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void *>(k_up_q<double, 1>), block,
+                                                     0) != hipSuccess)
+        return 0;
+    cached = std::max(1, ncu * std::max(1, occ));
+    return cached;
+}
+
+template <typename T, int R>
+static int launch_up_r(const ed_ham *h, const Tile &tl, const T *x, T *out, int *ctr, const Hdr *hdr, int gate,
+                       int max_steps, hipStream_t s) {
+    constexpr int w = 64 / R;
     const int n_stripes = (int)((h->dim_dn + w - 1) / w);
     const int n_rc = (int)((h->dim_up + tl.up_rc - 1) / tl.up_rc);
-    const int64_t grid = 8LL * n_rc * ((n_stripes + 7) / 8);
+    const T t = static_cast<T>(h->t);
+    if (tl.up_map == 2) {
+        if (!ctr) return set_error(ED_EINVAL, "k_up_q needs the workspace");
+        const int total = n_stripes * n_rc;
+        int grid = up_queue_grid(tl.up_block);
+        if (grid <= 0) return set_error(ED_EDEVICE, "occupancy query for k_up_q failed");
+        grid = std::min(grid, total);
+        hipLaunchKernelGGL(k_ctr_reset, dim3(1), dim3(64), 0, s, ctr, hdr, gate, max_steps);
+        ED_LAUNCHED("k_ctr_reset");
+        hipLaunchKernelGGL((k_up_q<T, R>), dim3(grid), dim3(tl.up_block), 0, s, x, out, h->tab_up, (int)h->dim_up,
+                           (int)h->dim_dn, h->w_up, tl.up_rc, n_stripes, n_rc, t, ctr, hdr, gate, max_steps);
+        ED_LAUNCHED("k_up_q");
+        return ED_OK;
+    }
+    const int64_t grid = tl.up_map == 0 ? 8LL * n_rc * ((n_stripes + 7) / 8) : (int64_t)n_rc * n_stripes;
     if (grid > 0x7fffffffLL) return set_error(ED_EOVERFLOW, "k_up grid too large");
+    hipLaunchKernelGGL((k_up<T, R>), dim3((unsigned)grid), dim3(tl.up_block), 0, s, x, out, h->tab_up,
+                       (int)h->dim_up, (int)h->dim_dn, h->w_up, tl.up_rc, n_stripes, n_rc, tl.up_map, t, hdr, gate,
+                       max_steps);
+    ED_LAUNCHED("k_up");
+    return ED_OK;
+}
+
+template <typename T>
+static int launch_up(const ed_ham *h, const Tile &tl, const T *x, T *out, int *ctr, const Hdr *hdr, int gate,
+                     int max_steps, hipStream_t s) {
     if (h->w_up == 0) {   // no up hopping: out = 0
         hipLaunchKernelGGL(k_fill0<T>, dim3(grid_for(h->dim_up * h->dim_dn, 256)), dim3(256), 0, s, out,
                            h->dim_up * h->dim_dn);
         ED_LAUNCHED("k_fill0");
         return ED_OK;
     }
-    hipLaunchKernelGGL(k_up<T>, dim3((unsigned)grid), dim3(tl.up_block), 0, s, x, out, h->tab_up, (int)h->dim_up,
-                       (int)h->dim_dn, h->w_up, tl.up_wlog2, tl.up_rc, n_stripes, n_rc, static_cast<T>(h->t), hdr,
-                       gate, max_steps);
-    ED_LAUNCHED("k_up");
-    return ED_OK;
+    switch (tl.up_wlog2) {
+    case 6: return launch_up_r<T, 1>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
+    case 5: return launch_up_r<T, 2>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
+    default: return launch_up_r<T, 4>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
+    }
+}
+
+template <typename T, int MODE, bool LDS, int NCH>
+static void launch_down_k(const ed_ham *h, const Tile &tl, int grid, int rpb, size_t shm, const T *x, T *io,
+                          const T *p, const double *bvec, const Hdr *hdr, double *part, int max_steps,
+                          hipStream_t s) {
+    hipLaunchKernelGGL((k_down<T, MODE, LDS, NCH>), dim3(grid), dim3(tl.dn_block), shm, s, x, io, p, h->tab_dn,
+                       h->st_up, h->st_dn, (int)h->dim_up, (int)h->dim_dn, h->w_dn, rpb, static_cast<T>(h->t),
+                       static_cast<T>(h->U), bvec, hdr, part, max_steps);
 }
 
 template <typename T, int MODE>
@@ -489,16 +756,11 @@ static int launch_down(const ed_ham *h, const Tile &tl, const T *x, T *io, const
     const int rpb = lds ? tl.dn_rpb : 1;
     const int grid = (int)((h->dim_up + rpb - 1) / rpb);
     const size_t shm = lds ? (size_t)(row_bytes * rpb) : 0;
-    const T t = static_cast<T>(h->t), U = static_cast<T>(h->U);
-    if (lds) {
-        hipLaunchKernelGGL((k_down<T, MODE, true>), dim3(grid), dim3(tl.dn_block), shm, s, x, io, p, h->tab_dn,
-                           h->st_up, h->st_dn, (int)h->dim_up, (int)h->dim_dn, h->w_dn, rpb, t, U, bvec, hdr, part,
-                           max_steps);
-    } else {
-        hipLaunchKernelGGL((k_down<T, MODE, false>), dim3(grid), dim3(tl.dn_block), 0, s, x, io, p, h->tab_dn,
-                           h->st_up, h->st_dn, (int)h->dim_up, (int)h->dim_dn, h->w_dn, 1, t, U, bvec, hdr, part,
-                           max_steps);
-    }
+    const int nch = h->w_dn >> 3;
+    if (!lds) launch_down_k<T, MODE, false, 8>(h, tl, grid, 1, 0, x, io, p, bvec, hdr, part, max_steps, s);
+    else if (nch <= 2) launch_down_k<T, MODE, true, 2>(h, tl, grid, rpb, shm, x, io, p, bvec, hdr, part, max_steps, s);
+    else if (nch <= 4) launch_down_k<T, MODE, true, 4>(h, tl, grid, rpb, shm, x, io, p, bvec, hdr, part, max_steps, s);
+    else launch_down_k<T, MODE, true, 8>(h, tl, grid, rpb, shm, x, io, p, bvec, hdr, part, max_steps, s);
     ED_LAUNCHED("k_down");
     return ED_OK;
 }
@@ -512,27 +774,34 @@ static int down_grid(const ed_ham *h, const Tile &tl) {
 
 // Kernels staging rows in LDS may use up to kLdsBudget bytes of it; set once,
 // outside any stream capture.
+template <typename T, int MODE, int NCH>
+static hipError_t set_lds_attr() {
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(k_down<T, MODE, true, NCH>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget);
+}
+
+template <typename T>
+static hipError_t set_lds_attrs_t() {
+    const hipError_t es[] = {set_lds_attr<T, 0, 2>(), set_lds_attr<T, 0, 4>(), set_lds_attr<T, 0, 8>(),
+                             set_lds_attr<T, 1, 2>(), set_lds_attr<T, 1, 4>(), set_lds_attr<T, 1, 8>(),
+                             set_lds_attr<T, 2, 2>(), set_lds_attr<T, 2, 4>(), set_lds_attr<T, 2, 8>()};
+    for (hipError_t e : es)
+        if (e != hipSuccess) return e;
+    return hipSuccess;
+}
+
 static int ensure_attrs() {
     static int rc = -1000;
     if (rc != -1000) return rc;
-    const void *fs[] = {
-        reinterpret_cast<const void *>(k_down<double, 0, true>), reinterpret_cast<const void *>(k_down<double, 1, true>),
-        reinterpret_cast<const void *>(k_down<double, 2, true>), reinterpret_cast<const void *>(k_down<float, 0, true>),
-        reinterpret_cast<const void *>(k_down<float, 1, true>), reinterpret_cast<const void *>(k_down<float, 2, true>)};
-    int r = ED_OK;
-    for (const void *f : fs) {
-        r = hip_check(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget),
-                      "hipFuncSetAttribute(k_down)");
-        if (r) break;
-    }
-    rc = r;
+    hipError_t e = set_lds_attrs_t<double>();
+    if (e == hipSuccess) e = set_lds_attrs_t<float>();
+    rc = hip_check(e, "hipFuncSetAttribute(k_down)");
     return rc;
 }
 
 template <typename T>
-static int hv_impl(const ed_ham *h, const T *x, T *y, hipStream_t s) {
-    const Tile tl = resolve_tile(h);
-    int rc = launch_up<T>(h, tl, x, y, nullptr, 0, 0, s);
+static int hv_impl(const ed_ham *h, const Tile &tl, const T *x, T *y, int *ctr, hipStream_t s) {
+    int rc = launch_up<T>(h, tl, x, y, ctr, nullptr, 0, 0, s);
     if (rc) return rc;
     return launch_down<T, 0>(h, tl, x, y, nullptr, nullptr, nullptr, nullptr, 0, s);
 }
@@ -545,7 +814,7 @@ template <typename T, int MODE>
 static int step_impl(const ed_ham *h, const Tile &tl, const T *f_prev, const T *f_cur, T *f_next, double *a,
                      double *b, T *v, const WsLayout &w, int max_steps, hipStream_t s, hipEvent_t *ev = nullptr) {
     if (ev) ED_HIP(hipEventRecord(ev[0], s));
-    int rc = launch_up<T>(h, tl, f_cur, f_next, w.hdr, 1, max_steps, s);
+    int rc = launch_up<T>(h, tl, f_cur, f_next, w.ctr, w.hdr, 1, max_steps, s);
     if (rc) return rc;
     if (ev) ED_HIP(hipEventRecord(ev[1], s));
     rc = launch_down<T, MODE>(h, tl, f_cur, f_next, f_prev, b, w.hdr, w.part, max_steps, s);
@@ -688,6 +957,67 @@ static int capture_steps(const ed_ham *h, const Tile &tl, ed_lanczos st_copy, co
     return ED_OK;
 }
 
+template <typename T>
+static int tune_impl(const ed_ham *h, const T *x, T *y, const WsLayout &w, int reps, hipStream_t s, int32_t *tile,
+                     double *ms_up, double *ms_dn) {
+    hipEvent_t e0, e1;
+    ED_HIP(hipEventCreate(&e0));
+    ED_HIP(hipEventCreate(&e1));
+    int rc = ED_OK;
+    double best_up = 1e300, best_dn = 1e300;
+    int bu = 0, bd = 0;
+    for (int ui = 1; ui < kNumUp && rc == ED_OK; ++ui) {
+        const Tile tl = resolve_tile_id(h, ui);
+        if (ms_up) ms_up[ui] = -1.0;
+        if (tl.up_wlog2 != kUpTiles[ui].wlog2) continue;   // clamped duplicate of a narrower stripe
+        rc = launch_up<T>(h, tl, x, y, w.ctr, nullptr, 0, 0, s);
+        if (rc) break;
+        rc = hip_check(hipEventRecord(e0, s), "hipEventRecord");
+        for (int r = 0; r < reps && rc == ED_OK; ++r) rc = launch_up<T>(h, tl, x, y, w.ctr, nullptr, 0, 0, s);
+        if (rc == ED_OK) rc = hip_check(hipEventRecord(e1, s), "hipEventRecord");
+        if (rc == ED_OK) rc = hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+        float msf = 0.f;
+        if (rc == ED_OK) rc = hip_check(hipEventElapsedTime(&msf, e0, e1), "hipEventElapsedTime");
+        const double m = msf / reps;
+        if (ms_up) ms_up[ui] = m;
+        if (m < best_up) { best_up = m; bu = ui; }
+    }
+    // k_down is timed as in a Lanczos step (second step: f_{j-1} read, partial
+    // sums written), from a synthetic header; x stands in for f_{j-1}.
+    Hdr fake{};
+    fake.sig_cur = 1.0;
+    fake.sig_prev = 1.0;
+    fake.jdev = 1;
+    fake.status = 0;
+    const double bfake[2] = {0.0, 0.5};
+    if (rc == ED_OK) rc = hip_check(hipMemcpyAsync(w.hdr, &fake, sizeof(Hdr), hipMemcpyHostToDevice, s), "hipMemcpyAsync");
+    if (rc == ED_OK) rc = hip_check(hipMemcpyAsync(w.y, bfake, sizeof bfake, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
+    if (rc == ED_OK) rc = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    constexpr int SM = sizeof(T) == 8 ? 1 : 2;
+    for (int di = 1; di < kNumDn && rc == ED_OK; ++di) {
+        const Tile tl = resolve_tile_id(h, di << 8);
+        if (ms_dn) ms_dn[di] = -1.0;
+        if (kDnTiles[di].rpb > 0 && (int64_t)kDnTiles[di].rpb * h->dim_dn * (int64_t)sizeof(T) > kLdsBudget) continue;
+        if (kDnTiles[di].rpb > h->dim_up) continue;
+        rc = launch_down<T, SM>(h, tl, x, y, x, w.y, w.hdr, w.part, 2, s);
+        if (rc) break;
+        rc = hip_check(hipEventRecord(e0, s), "hipEventRecord");
+        for (int r = 0; r < reps && rc == ED_OK; ++r) rc = launch_down<T, SM>(h, tl, x, y, x, w.y, w.hdr, w.part, 2, s);
+        if (rc == ED_OK) rc = hip_check(hipEventRecord(e1, s), "hipEventRecord");
+        if (rc == ED_OK) rc = hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+        float msf = 0.f;
+        if (rc == ED_OK) rc = hip_check(hipEventElapsedTime(&msf, e0, e1), "hipEventElapsedTime");
+        const double m = msf / reps;
+        if (ms_dn) ms_dn[di] = m;
+        if (m < best_dn) { best_dn = m; bd = di; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    *tile = bu | (bd << 8);
+    return ED_OK;
+}
+
 }  // namespace ed
 
 using namespace ed;
@@ -710,10 +1040,48 @@ int ed_hv(const ed_ham *h, const void *x, void *y, void *ws, void *stream) {
     rc = ensure_attrs();
     if (rc) return rc;
     if (!x || !y || x == y) return set_error(ED_EINVAL, "ed_hv: x and y must be distinct device buffers");
-    (void)ws;
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255)) return set_error(ED_EINVAL, "ed_hv: ws must be a 256-byte aligned workspace");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (h->dtype == ED_F64) return hv_impl<double>(h, (const double *)x, (double *)y, s);
-    return hv_impl<float>(h, (const float *)x, (float *)y, s);
+    const Tile tl = resolve_tile(h);
+    const WsLayout w = ws_layout(h, ws, 0);
+    if (h->dtype == ED_F64) return hv_impl<double>(h, tl, (const double *)x, (double *)y, w.ctr, s);
+    return hv_impl<float>(h, tl, (const float *)x, (float *)y, w.ctr, s);
+}
+
+int ed_tile_params(int32_t tile, const ed_ham *h, int32_t *params) {
+    clear_error();
+    int rc = check_ham(h, "ed_tile_params");
+    if (rc) return rc;
+    if (!params || !valid_tile_id(tile)) return set_error(ED_EINVAL, "ed_tile_params: bad arguments");
+    const Tile t = resolve_tile_id(h, tile);
+    params[0] = 1 << t.up_wlog2;
+    params[1] = t.up_rc;
+    params[2] = t.up_block;
+    params[3] = t.up_map;
+    params[4] = t.dn_block;
+    params[5] = t.dn_rpb;
+    return ED_OK;
+}
+
+int ed_tune(const ed_ham *h, const void *x, void *y, void *ws, void *stream, int32_t reps, int32_t *tile,
+            double *ms_up, double *ms_dn) {
+    clear_error();
+    int rc = check_ham(h, "ed_tune");
+    if (rc) return rc;
+    rc = ensure_attrs();
+    if (rc) return rc;
+    if (!x || !y || x == y || !ws || !tile || reps < 1) return set_error(ED_EINVAL, "ed_tune: bad arguments");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const WsLayout w = ws_layout(h, ws, 2);
+    if (h->dtype == ED_F64) return tune_impl<double>(h, (const double *)x, (double *)y, w, reps, s, tile, ms_up, ms_dn);
+    return tune_impl<float>(h, (const float *)x, (float *)y, w, reps, s, tile, ms_up, ms_dn);
+}
+
+int ed_tile_count(int32_t *n_up, int32_t *n_dn) {
+    if (!n_up || !n_dn) return set_error(ED_EINVAL, "ed_tile_count: NULL");
+    *n_up = kNumUp;
+    *n_dn = kNumDn;
+    return ED_OK;
 }
 
 int ed_lanczos_init(const ed_ham *h, ed_lanczos *st, const void *f1, void *ws, void *stream) {

@@ -238,14 +238,15 @@ int ed_pack_tables(const int32_t *cols, const double *vals, const int32_t *nnz, 
     if (dim > 32767) return set_error(ED_EOVERFLOW, "ed_pack_tables: dim %lld > 32767", (long long)dim);
     if (layout != ED_ROW_MAJOR && layout != ED_COL_MAJOR)
         return set_error(ED_EINVAL, "ed_pack_tables: bad layout %d", layout);
+    const int64_t stride = (width + 7) & ~7;
     for (int64_t r = 0; r < dim; ++r) {
         if (nnz[r] < 0 || nnz[r] > width)
             return set_error(ED_EINVAL, "ed_pack_tables: nnz[%lld] = %d out of range", (long long)r, nnz[r]);
         int32_t last = -1;
-        for (int64_t k = 0; k < width; ++k) {
-            int64_t at = layout == ED_ROW_MAJOR ? r * width + k : k * dim + r;
+        for (int64_t k = 0; k < stride; ++k) {
             uint16_t e = 0xFFFF;
             if (k < nnz[r]) {
+                int64_t at = layout == ED_ROW_MAJOR ? r * width + k : k * dim + r;
                 if (cols[at] < 0 || cols[at] >= dim)
                     return set_error(ED_EINVAL, "ed_pack_tables: column %d out of range", cols[at]);
                 if (cols[at] <= last)
@@ -255,7 +256,8 @@ int ed_pack_tables(const int32_t *cols, const double *vals, const int32_t *nnz, 
                 last = cols[at];
                 e = (uint16_t)((cols[at] << 1) | (vals[at] < 0 ? 1 : 0));
             }
-            packed[k * dim + r] = e;
+            packed[r * stride + k] = e;                                   // row-major part
+            packed[dim * stride + ((k >> 3) * dim + r) * 8 + (k & 7)] = e;  // 8-interleaved part
         }
     }
     return ED_OK;

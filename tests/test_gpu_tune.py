@@ -1,0 +1,50 @@
+"""The launch-configuration autotuner: every candidate tile computes the same H x bit for bit."""
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1511_00863_amd as ed
+from synth import ring_bonds, torus_bonds
+from tests.gpu_util import announce, ham, seeded_start
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("ns,bonds,nu,nd", [(16, torus_bonds(4, 4), 4, 4), (16, torus_bonds(4, 4), 3, 5),
+                                            (8, ring_bonds(8), 4, 4)])
+def test_every_tile_gives_identical_hv(ns, bonds, nu, nd, dtype):
+    h = ham(ns, bonds, nu, nd, 1.0, 3.0, dtype)
+    _, x = seeded_start(21, h.dim, dtype)
+    announce("tune all tiles %d+%d %s" % (nu, nd, dtype))
+    ref = h.hv(x).clone()
+    import ctypes
+    nu_, nd_ = ctypes.c_int32(0), ctypes.c_int32(0)
+    ed.lib().ed_tile_count(ctypes.byref(nu_), ctypes.byref(nd_))
+    for ui in range(nu_.value):
+        for di in ([0] if ui else range(nd_.value)):
+            h.tile = ui | (di << 8)
+            y = h.hv(x)
+            assert torch.equal(y, ref), (ui, di, h.tile_params())
+    h.tile = 0
+    r = h.tune(x, reps=1)
+    assert r["tile"] & 0xFF < nu_.value and (r["tile"] >> 8) < nd_.value
+    assert torch.equal(h.hv(x), ref)
+    assert (r["up_ms"][1:] != 0).all()
+
+
+def test_tuned_lanczos_matches_default():
+    """A tile changes the number of partial-sum slots, hence the order of the float64
+    reductions: coefficients agree to roundoff across tiles and bit for bit for one tile."""
+    h = ham(16, torus_bonds(4, 4), 4, 4, 1.0, 2.0, "f64")
+    _, x = seeded_start(22, h.dim, "f64")
+    announce("tuned lanczos")
+    r0 = h.ground_energy(x, 30)
+    h.tune(x, reps=1)
+    r1 = h.ground_energy(x, 30)
+    r2 = h.ground_energy(x, 30)
+    scale = np.max(np.abs(r0["a"]))
+    assert np.max(np.abs(r0["a"][:20] - r1["a"][:20])) <= 1e-12 * scale
+    assert np.array_equal(r1["a"], r2["a"]) and np.array_equal(r1["b"], r2["b"])
+    assert abs(r0["e0"] - r1["e0"]) <= 1e-12 * abs(r0["e0"])

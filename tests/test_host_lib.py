@@ -99,16 +99,25 @@ def test_hopping_half_filling_4x4_vs_oracle():
 def test_pack_tables_roundtrip():
     st = ed.build_basis(16, 5)
     t = ed.build_hopping(16, torus_bonds(4, 4), st, ed.ED_ROW_MAJOR)
-    p = ed.pack_tables(t, st.size).reshape(t["width"], st.size)     # [k, r]
+    w8 = ed.api.table_stride(t["width"])
+    assert w8 % 8 == 0 and w8 >= t["width"]
+    packed = ed.pack_tables(t, st.size)
+    assert packed.size == 2 * st.size * w8
+    p = packed[:st.size * w8].reshape(st.size, w8)      # [r, k]
+    il = packed[st.size * w8:].reshape(w8 // 8, st.size, 8)
+    assert np.array_equal(il.transpose(1, 0, 2).reshape(st.size, w8), p)
     cols = t["cols"].reshape(st.size, t["width"])
     vals = t["vals"].reshape(st.size, t["width"])
     for r in range(0, st.size, 37):
-        for k in range(t["width"]):
-            e = int(p[k, r])
+        for k in range(w8):
+            e = int(p[r, k])
             if k < t["nnz"][r]:
                 assert e >> 1 == cols[r, k] and ((e & 1) == 1) == (vals[r, k] < 0)
             else:
                 assert e == 0xFFFF
+    # the column-major export packs to the same device table
+    tc = ed.build_hopping(16, torus_bonds(4, 4), st, ed.ED_COL_MAJOR)
+    assert np.array_equal(ed.pack_tables(tc, st.size), packed)
 
 
 def test_hopping_errors():
