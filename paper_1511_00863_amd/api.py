@@ -6,6 +6,8 @@ exceptions.  Names follow the C entry points of include/ed.h.
 """
 
 import ctypes
+import json
+import os
 from ctypes import POINTER, byref, c_double, c_int32, c_int64, c_uint16, c_uint64
 
 import numpy as np
@@ -228,6 +230,36 @@ class Hamiltonian:
         """Two-pass ground-state vector: returns (E0, steps, v) with |v| = 1."""
         run = LanczosRun(self, m)
         return run.ground_state(f1, m, stream)
+
+
+TUNE_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
+
+
+def tune_key(ham: "Hamiltonian") -> str:
+    """Cache key of a tuned tile: architecture, per-spin dims, table strides, dtype."""
+    dt = "f64" if ham.dtype == ED_F64 else "f32"
+    return "gfx950/%dx%d/w%dx%d/%s" % (ham.dim_up, ham.dim_dn, ham.up.stride, ham.dn.stride, dt)
+
+
+def load_tune_cache(path: str = TUNE_CACHE) -> dict:
+    if not os.path.exists(path):
+        return {}
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def apply_tuned_tile(ham: "Hamiltonian", x=None, path: str = TUNE_CACHE, tune_if_missing: bool = True) -> str:
+    """Set ham.tile from the tuning cache, or run ed_tune when the key is absent.
+
+    Returns "cache" or "tuned" (or "default" when missing and tune_if_missing is False)."""
+    entry = load_tune_cache(path).get(tune_key(ham))
+    if entry is not None:
+        ham.tile = int(entry["tile"])
+        return "cache"
+    if tune_if_missing:
+        ham.tune(x, reps=3)
+        return "tuned"
+    return "default"
 
 
 class LanczosRun:

@@ -1,0 +1,44 @@
+"""Run the launch-configuration autotuner on the named workloads and record the
+chosen tiles in tune_cache.json (keyed by architecture, dims, table strides, dtype).
+
+    python -m paper_1511_00863_amd.tune [--out PATH] torus4x4_8x8 torus4x4_5x5 ...
+"""
+
+import json
+import sys
+
+import torch
+
+from . import api
+from synth import start_vector, workload
+
+
+def tune_workloads(names, dtypes=("f64", "f32"), path=api.TUNE_CACHE):
+    cache = api.load_tune_cache(path)
+    for name in names:
+        wl = workload(name)
+        up = api.SpinTables(wl.n_sites, wl.bonds, wl.n_up, "cuda:0")
+        dn = up if wl.n_dn == wl.n_up else api.SpinTables(wl.n_sites, wl.bonds, wl.n_dn, "cuda:0")
+        x_host = start_vector(wl.seed, up.dim * dn.dim)
+        for dt in dtypes:
+            h = api.Hamiltonian(up, dn, wl.t, wl.U, dt)
+            x = torch.from_numpy(x_host).to("cuda:0", h.torch_dtype)
+            r = h.tune(x, reps=5)
+            best_up = float(r["up_ms"][r["tile"] & 0xFF]) if r["tile"] & 0xFF else None
+            best_dn = float(r["dn_ms"][r["tile"] >> 8]) if r["tile"] >> 8 else None
+            cache[api.tune_key(h)] = {"tile": r["tile"], "params": h.tile_params(), "workload": name,
+                                      "up_ms": best_up, "dn_ms": best_dn}
+            print("%s %s -> tile %d %s" % (name, dt, r["tile"], h.tile_params()), flush=True)
+            del x, h
+            torch.cuda.empty_cache()
+    with open(path, "w") as fh:
+        json.dump(cache, fh, indent=1, sort_keys=True)
+    return cache
+
+
+if __name__ == "__main__":
+    args = sys.argv[1:]
+    out = api.TUNE_CACHE
+    if args[:1] == ["--out"]:
+        out, args = args[1], args[2:]
+    tune_workloads(args or ["torus4x4_8x8"], path=out)
