@@ -237,6 +237,43 @@ int ed_ground_energy(const ed_ham *h, ed_lanczos *st, const void *f1, double tol
 int ed_ground_state(const ed_ham *h, ed_lanczos *st, const void *f1, int32_t m, void *v,
                     void *ws, void *stream, double *e0, int32_t *steps);
 
+/* ---- device: batched ground-state runs --------------------------------- */
+
+/* One instance of a batch: its Hamiltonian (dtype must be ED_F32: float32
+ * vectors and H.v, float64 scalars), its start vector f1 (device, dim
+ * floats, any nonzero norm), three device work vectors of dim floats, and
+ * device arrays a (max_steps doubles) and b (max_steps + 1 doubles) that
+ * receive its Lanczos coefficients.  Tables may be shared between items. */
+typedef struct ed_batch_item {
+    ed_ham h;
+    const void *f1;
+    void *vec[3];
+    double *a, *b;
+} ed_batch_item;
+
+/* Device workspace bytes for ed_ground_energy_batch on these items. */
+int ed_batch_workspace_size(const ed_batch_item *items, int32_t n, int32_t max_steps, int64_t *bytes);
+
+/* Run n independent Lanczos ground-state computations (Alg. 1 with the mixed
+ * form of ed_lanczos_step) in ONE persistent cooperative kernel launch, which
+ * is captured in a HIP graph when use_graph != 0 and the runtime accepts the
+ * capture (*graph_used reports it; otherwise the kernel is launched
+ * directly).  The instances may differ in U, t and fillings (uneven
+ * dimensions).  Each instance stops on its own when |E0(j) - E0(j-1)| < tol
+ * at two consecutive steps, E0(j) being the lowest eigenvalue of T_j found
+ * on the device by Sturm-count multisection; or on breakdown; or at
+ * max_steps.  Launch tiles follow each item's h.tile (see ed_tune).
+ * Per item (host arrays of n): e0 = lowest eigenvalue of T at the stopping
+ * step (host bisection of the returned coefficients), steps, status (ED_OK =
+ * converged, ED_BREAKDOWN, ED_NOT_CONVERGED); e0_device (may be NULL) = the
+ * device's value at that step.  ws: ed_batch_workspace_size bytes, 256-byte
+ * aligned.  Synchronises `stream`.  Returns ED_NOT_CONVERGED if any item
+ * did not converge.  Limits: per-spin dims <= 32767, rows of at most 16384
+ * floats, down-table strides <= 32, both species must hop. */
+int ed_ground_energy_batch(const ed_batch_item *items, int32_t n, int32_t max_steps, double tol, void *ws,
+                           int64_t ws_bytes, void *stream, int32_t use_graph, double *e0, int32_t *steps,
+                           int32_t *status, double *e0_device, int32_t *graph_used);
+
 #ifdef __cplusplus
 }
 #endif

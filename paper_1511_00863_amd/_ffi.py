@@ -28,12 +28,20 @@ class EdHam(ctypes.Structure):
                 ("t", c_double), ("U", c_double), ("dtype", c_int32), ("tile", c_int32)]
 
 
+class EdBatchItem(ctypes.Structure):
+    _fields_ = [("h", EdHam), ("f1", c_void_p), ("vec", c_void_p * 3), ("a", c_void_p), ("b", c_void_p)]
+
+
 class EdLanczos(ctypes.Structure):
     _fields_ = [("f_prev", c_void_p), ("f_cur", c_void_p), ("f_next", c_void_p),
                 ("a", c_void_p), ("b", c_void_p), ("j", c_int32), ("max_steps", c_int32)]
 
 
 _PROTOS = {
+    "ed_batch_workspace_size": (c_int, [POINTER(EdBatchItem), c_int32, c_int32, POINTER(c_int64)]),
+    "ed_ground_energy_batch": (c_int, [POINTER(EdBatchItem), c_int32, c_int32, c_double, c_void_p, c_int64,
+                                       c_void_p, c_int32, POINTER(c_double), POINTER(c_int32), POINTER(c_int32),
+                                       POINTER(c_double), POINTER(c_int32)]),
     "ed_last_error": (c_char_p, []),
     "ed_version": (c_char_p, []),
     "ed_build_basis": (c_int, [c_int, c_int, POINTER(c_uint64), c_int64, POINTER(c_int64)]),

@@ -14,7 +14,7 @@ import numpy as np
 import torch
 
 from . import _ffi
-from ._ffi import (ED_COL_MAJOR, ED_F32, ED_F64, ED_ROW_MAJOR, EdHam, EdLanczos, check, lib)
+from ._ffi import (ED_COL_MAJOR, ED_F32, ED_F64, ED_ROW_MAJOR, EdBatchItem, EdHam, EdLanczos, check, lib)
 
 
 def _ptr(a: np.ndarray, ctype):
@@ -342,3 +342,45 @@ class LanczosRun:
         check(lib().ed_ground_state(byref(self._h), byref(self.st), _dptr(f1), int(m), _dptr(v), _dptr(self.ws),
                                     _stream(stream), byref(e0), byref(steps)))
         return e0.value, steps.value, v
+
+
+def ground_energy_batch(hams, f1s, max_steps: int, tol: float = 1e-6, use_graph: bool = True, stream=None):
+    """ed_ground_energy_batch over a list of float32 Hamiltonians and start vectors.
+
+    Returns dict(e0, steps, status, e0_device, graph_used, wall_ms)."""
+    n = len(hams)
+    keep = []
+    items = (EdBatchItem * n)()
+    for i, (h, f) in enumerate(zip(hams, f1s)):
+        if h.dtype != ED_F32:
+            raise ValueError("batched runs use float32 vectors (ED_F32)")
+        f = h._vec(f)
+        vecs = [h.empty_vec() for _ in range(3)]
+        a = torch.zeros(max_steps, dtype=torch.float64, device=h.device)
+        b = torch.zeros(max_steps + 1, dtype=torch.float64, device=h.device)
+        keep += [f, a, b] + vecs
+        items[i].h = h.c_struct()
+        items[i].f1 = f.data_ptr()
+        for k in range(3):
+            items[i].vec[k] = vecs[k].data_ptr()
+        items[i].a = a.data_ptr()
+        items[i].b = b.data_ptr()
+    nb = c_int64(0)
+    check(lib().ed_batch_workspace_size(items, n, int(max_steps), byref(nb)))
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=hams[0].device)
+    e0 = np.zeros(n)
+    e0d = np.zeros(n)
+    steps = np.zeros(n, dtype=np.int32)
+    status = np.zeros(n, dtype=np.int32)
+    used = c_int32(0)
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    rc = check(lib().ed_ground_energy_batch(items, n, int(max_steps), float(tol), _dptr(ws), nb.value,
+                                            _stream(stream), 1 if use_graph else 0, _ptr(e0, c_double),
+                                            _ptr(steps, c_int32), _ptr(status, c_int32), _ptr(e0d, c_double),
+                                            byref(used)))
+    end.record()
+    torch.cuda.synchronize()
+    return {"e0": e0, "steps": steps, "status": status, "e0_device": e0d, "graph_used": bool(used.value),
+            "rc": rc, "wall_ms": start.elapsed_time(end)}

@@ -1,0 +1,565 @@
+// Batched ground-state runs: many independent instances (different U, t and
+// fillings, hence uneven dimensions) taken through the Lanczos iteration
+// (Alg. 1, mixed form: float32 vectors, float64 scalars) by ONE persistent
+// cooperative kernel.  Every step of every live instance is the same five
+// phases as the single-instance path (up part, down part with partial dots,
+// a_j, update with partial norms, b_{j+1}); in each phase the workgroups
+// share out the union of the live instances' tiles, and a grid barrier
+// separates the phases.  Each instance tests its own convergence on the
+// device: E0(j), the lowest eigenvalue of T_j (Sec. 2.2), comes from a
+// 64-way Sturm-count multisection run by one wavefront, and the instance
+// stops when |E0(j) - E0(j-1)| < tol at two consecutive steps.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "../../include/ed.h"
+#include "ed_common.cuh"
+#include "ed_internal.h"
+#include "ed_launch.h"
+
+namespace ed {
+
+constexpr int kBatchBlock = 512;
+constexpr int kBatchLds = 64 * 1024;
+constexpr int64_t kUpdChunk = 65536;         // elements per update tile
+constexpr int kConverged = 10;
+constexpr int kBadStart = 100;
+constexpr unsigned long long kSpinLimit = 1ull << 24;   // about a second of s_sleep(2)
+
+struct BInst {
+    // set by the host
+    int Dup, Ddn, W8u, W8d;
+    int R, rc, n_stripes, n_rc;
+    int up_tiles, rpb, dn_tiles, upd_tiles;
+    int64_t n, part_off, part2_off;
+    const uint16_t *tab_up, *tab_dn;
+    const uint64_t *st_up, *st_dn;
+    const float *f1;
+    float *vec[3];
+    double *a, *b, *e;
+    double t, U;
+    // device state
+    int j, status, rot, conv;
+    double sig_cur, sig_prev, cx, cp, scale, pad;
+};
+
+struct GridBar {
+    unsigned count;
+    unsigned gen;
+    int err;
+    int pad;
+};
+
+__device__ __forceinline__ bool b_live(const BInst &I, int max_steps) { return I.status == 0 && I.j < max_steps; }
+
+// All workgroups wait until all have arrived.  Spins are bounded: a timeout
+// sets gb->err and releases the waiter, so the kernel always ends.
+__device__ void grid_sync(GridBar *gb) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned g = __hip_atomic_load(&gb->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        const unsigned arrived = atomicAdd(&gb->count, 1u) + 1u;
+        if (arrived == gridDim.x) {
+            atomicExch(&gb->count, 0u);
+            __threadfence();
+            atomicAdd(&gb->gen, 1u);
+        } else {
+            unsigned long long spins = 0;
+            while (__hip_atomic_load(&gb->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > kSpinLimit) {
+                    atomicExch(&gb->err, 1);
+                    break;
+                }
+            }
+        }
+        __threadfence();
+    }
+    __syncthreads();
+}
+
+// Walks the instances in order; (ci, cbase) is a cursor that only moves
+// forward because a workgroup visits its tiles in increasing order.
+enum TileKind { kUpT, kDnT, kUpdT, kInitT };
+
+__device__ __forceinline__ int tiles_of(const BInst &I, TileKind k) {
+    return k == kUpT ? I.up_tiles : (k == kDnT ? I.dn_tiles : I.upd_tiles);
+}
+
+__device__ __forceinline__ bool next_tile(const BInst *inst, int ni, int max_steps, TileKind kind, int64_t tg,
+                                          int &ci, int64_t &cbase) {
+    while (ci < ni) {
+        const BInst &I = inst[ci];
+        const bool use = kind == kInitT ? true : b_live(I, max_steps);
+        const int cnt = use ? tiles_of(I, kind) : 0;
+        if (tg < cbase + cnt) return true;
+        cbase += cnt;
+        ++ci;
+    }
+    return false;
+}
+
+__device__ int sturm_count(const double *a, const double *boff, int m, double x, double pivmin) {
+    int cnt = 0;
+    double d = a[0] - x;
+    if (fabs(d) < pivmin) d = -pivmin;
+    if (d < 0) ++cnt;
+    for (int k = 1; k < m; ++k) {
+        d = (a[k] - x) - boff[k - 1] * boff[k - 1] / d;
+        if (fabs(d) < pivmin) d = -pivmin;
+        if (d < 0) ++cnt;
+    }
+    return cnt;
+}
+
+// Lowest eigenvalue of T_m (diag a[0..m-1], off-diagonal boff[0..m-2]) by one
+// wavefront: each round 64 lanes test 64 interior points of the bracket.
+__device__ double ritz_lowest_wave(const double *a, const double *boff, int m) {
+    const int lane = threadIdx.x & 63;
+    double lo = INFINITY, hi = -INFINITY, bmax = 0.0;
+    for (int k = lane; k < m; k += 64) {
+        const double r = (k > 0 ? fabs(boff[k - 1]) : 0.0) + (k < m - 1 ? fabs(boff[k]) : 0.0);
+        lo = fmin(lo, a[k] - r);
+        hi = fmax(hi, a[k] + r);
+        if (k < m - 1) bmax = fmax(bmax, fabs(boff[k]));
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = fmin(lo, __shfl_xor(lo, o, 64));
+        hi = fmax(hi, __shfl_xor(hi, o, 64));
+        bmax = fmax(bmax, __shfl_xor(bmax, o, 64));
+    }
+    const double pivmin = fmax(2.2250738585072014e-308 * fmax(1.0, bmax * bmax), 1e-300);
+    const double pad = 4e-16 * fmax(fabs(lo), fabs(hi)) + pivmin;
+    lo -= pad;
+    hi += pad;
+    for (int round = 0; round < 9; ++round) {
+        const double w = (hi - lo) / 65.0;
+        const double x = lo + w * (lane + 1);
+        const int cnt = sturm_count(a, boff, m, x, pivmin);
+        const unsigned long long mask = __ballot(cnt >= 1);
+        if (mask == 0ull) {
+            lo = lo + 64.0 * w;
+        } else {
+            const int f = __ffsll((long long)mask) - 1;
+            const double nhi = lo + w * (f + 1), nlo = lo + w * f;
+            lo = nlo;
+            hi = nhi;
+        }
+    }
+    return 0.5 * (lo + hi);
+}
+
+__global__ __launch_bounds__(kBatchBlock) void k_batch(BInst *__restrict__ inst, int ni, double *__restrict__ part,
+                                                       double *__restrict__ part2, GridBar *gb, int max_steps,
+                                                       double tol) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    float *xs = reinterpret_cast<float *>(smem);
+    __shared__ int s_any;
+    const int64_t G = gridDim.x;
+
+    // ---- start: F_1 = copy of f1, |f1|^2 partials
+    {
+        int ci = 0;
+        int64_t cb = 0;
+        for (int64_t tg = blockIdx.x; next_tile(inst, ni, max_steps, kInitT, tg, ci, cb); tg += G) {
+            const BInst &I = inst[ci];
+            const int local = (int)(tg - cb);
+            const int64_t lo = (int64_t)local * kUpdChunk, hi = min(I.n, lo + kUpdChunk);
+            double s[1] = {0.0};
+            for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+                const float v = I.f1[k];
+                I.vec[0][k] = v;
+                s[0] += (double)v * (double)v;
+            }
+            double tot[1];
+            block_sum<1>(s, tot);
+            if (threadIdx.x == 0) part2[I.part2_off + local] = tot[0];
+            __syncthreads();
+        }
+    }
+    grid_sync(gb);
+    for (int i = blockIdx.x; i < ni; i += G) {
+        BInst &I = inst[i];
+        double s[1] = {0.0};
+        for (int k = threadIdx.x; k < I.upd_tiles; k += blockDim.x) s[0] += part2[I.part2_off + k];
+        double tot[1];
+        block_sum<1>(s, tot);
+        if (threadIdx.x == 0) {
+            const bool ok = tot[0] > 0.0 && tot[0] < INFINITY;
+            I.sig_cur = ok ? 1.0 / sqrt(tot[0]) : 0.0;
+            I.sig_prev = 0.0;
+            I.cx = I.cp = 0.0;
+            I.scale = 0.0;
+            I.j = 0;
+            I.rot = 0;
+            I.conv = 0;
+            I.status = ok ? 0 : kBadStart;
+            I.b[0] = 0.0;
+        }
+        __syncthreads();
+    }
+    grid_sync(gb);
+
+    for (int step = 0; step < max_steps; ++step) {
+        if (threadIdx.x == 0) {
+            int any = 0;
+            for (int i = 0; i < ni; ++i) any |= b_live(inst[i], max_steps) ? 1 : 0;
+            s_any = any && !__hip_atomic_load(&gb->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+        if (!s_any) break;
+
+        // ---- up part (Eq. 4): T = t * up(F_j) into the next buffer
+        {
+            int ci = 0;
+            int64_t cb = 0;
+            for (int64_t tg = blockIdx.x; next_tile(inst, ni, max_steps, kUpT, tg, ci, cb); tg += G) {
+                const BInst &I = inst[ci];
+                const int local = (int)(tg - cb);
+                const int xcd = local & 7, l2 = local >> 3;
+                const int sl = l2 / I.n_rc, rci = l2 - sl * I.n_rc;
+                const int s = sl * 8 + xcd;
+                if (s >= I.n_stripes) continue;
+                const float *x = I.vec[I.rot];
+                float *out = I.vec[(I.rot + 1) % 3];
+                if (I.R == 1)
+                    up_tile<float, 1>(x, out, I.tab_up, I.Dup, I.Ddn, I.W8u, I.rc, s, rci, (float)I.t);
+                else
+                    up_tile<float, 2>(x, out, I.tab_up, I.Dup, I.Ddn, I.W8u, I.rc, s, rci, (float)I.t);
+            }
+        }
+        grid_sync(gb);
+
+        // ---- down part (Eq. 5) + U term + recurrence, partial dots
+        {
+            int ci = 0;
+            int64_t cb = 0;
+            for (int64_t tg = blockIdx.x; next_tile(inst, ni, max_steps, kDnT, tg, ci, cb); tg += G) {
+                const BInst &I = inst[ci];
+                const int local = (int)(tg - cb);
+                const int r0 = local * I.rpb, nr = min(I.rpb, I.Dup - r0);
+                const int64_t base = (int64_t)r0 * I.Ddn;
+                const float *x = I.vec[I.rot];
+                float *io = I.vec[(I.rot + 1) % 3];
+                const float *p = I.vec[(I.rot + 2) % 3];
+                __syncthreads();
+                stage_rows<float>(x + base, xs, nr * I.Ddn);
+                __syncthreads();
+                double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+                const bool has_prev = I.j > 0;
+                const float sig = (float)I.sig_cur;
+                const float cprev = (float)(I.b[I.j] * I.sig_prev);
+                down_rows<float, 2, 4>(xs, io, p, I.tab_dn, I.st_up + r0, I.st_dn, I.Ddn, I.W8d, nr, base,
+                                       I.rpb > 1, (float)I.t, (float)I.U, sig, cprev, has_prev, s);
+                double tot[5];
+                block_sum<5>(s, tot);
+                if (threadIdx.x == 0)
+                    for (int k = 0; k < 5; ++k) part[I.part_off + (int64_t)local * 5 + k] = tot[k];
+            }
+        }
+        grid_sync(gb);
+
+        // ---- a_j and the update coefficients (Gram projection, float64)
+        for (int i = blockIdx.x; i < ni; i += G) {
+            BInst &I = inst[i];
+            if (!b_live(I, max_steps)) continue;
+            double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+            for (int k = threadIdx.x; k < I.dn_tiles; k += blockDim.x)
+                for (int u = 0; u < 5; ++u) s[u] += part[I.part_off + (int64_t)k * 5 + u];
+            double tot[5];
+            block_sum<5>(s, tot);
+            if (threadIdx.x == 0) {
+                const double sx = I.sig_cur, sp = I.sig_prev;
+                const double qx = sx * tot[0], qp = sp * tot[1];
+                const double xx = sx * sx * tot[2], xp = sx * sp * tot[3], pp = sp * sp * tot[4];
+                double alpha, beta = 0.0;
+                if (I.j > 0) {
+                    const double det = xx * pp - xp * xp;
+                    alpha = (pp * qx - xp * qp) / det;
+                    beta = (xx * qp - xp * qx) / det;
+                } else {
+                    alpha = qx / xx;
+                }
+                I.a[I.j] = alpha;
+                I.cx = alpha * sx;
+                I.cp = I.j > 0 ? beta * sp : 0.0;
+            }
+            __syncthreads();
+        }
+        grid_sync(gb);
+
+        // ---- F_{j+1} = q - cx F_j - cp F_{j-1}, partial norms
+        {
+            int ci = 0;
+            int64_t cb = 0;
+            for (int64_t tg = blockIdx.x; next_tile(inst, ni, max_steps, kUpdT, tg, ci, cb); tg += G) {
+                const BInst &I = inst[ci];
+                const int local = (int)(tg - cb);
+                const int64_t lo = (int64_t)local * kUpdChunk, hi = min(I.n, lo + kUpdChunk);
+                const float *x = I.vec[I.rot];
+                float *q = I.vec[(I.rot + 1) % 3];
+                const float *p = I.vec[(I.rot + 2) % 3];
+                const double cx = I.cx, cp = I.cp;
+                double s[1] = {0.0};
+                for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+                    double qv = (double)q[k] - cx * (double)x[k];
+                    if (cp != 0.0) qv -= cp * (double)p[k];
+                    const float st = (float)qv;
+                    q[k] = st;
+                    s[0] += (double)st * (double)st;
+                }
+                double tot[1];
+                block_sum<1>(s, tot);
+                if (threadIdx.x == 0) part2[I.part2_off + local] = tot[0];
+                __syncthreads();
+            }
+        }
+        grid_sync(gb);
+
+        // ---- b_{j+1}, breakdown, E0(j+1) and the convergence test
+        for (int i = blockIdx.x; i < ni; i += G) {
+            BInst &I = inst[i];
+            if (!b_live(I, max_steps)) continue;
+            double s[1] = {0.0};
+            for (int k = threadIdx.x; k < I.upd_tiles; k += blockDim.x) s[0] += part2[I.part2_off + k];
+            double tot[1];
+            block_sum<1>(s, tot);
+            __shared__ int s_brk;
+            __shared__ int s_m;
+            if (threadIdx.x == 0) {
+                const int j = I.j;
+                const double bn = sqrt(tot[0]);
+                const double scale = fmax(I.scale, fmax(fabs(I.a[j]), bn));
+                I.b[j + 1] = bn;
+                I.scale = scale;
+                const bool brk = !(bn > 64.0 * 5.960464477539063e-08 * scale);
+                I.sig_prev = I.sig_cur;
+                I.sig_cur = brk ? 0.0 : 1.0 / bn;
+                I.j = j + 1;
+                I.rot = (I.rot + 1) % 3;
+                s_brk = brk ? 1 : 0;
+                s_m = j + 1;
+            }
+            __syncthreads();
+            if (threadIdx.x < 64) {
+                const int m = s_m;
+                const double e = ritz_lowest_wave(I.a, I.b + 1, m);
+                if (threadIdx.x == 0) {
+                    I.e[m] = e;
+                    if (m >= 2 && fabs(e - I.e[m - 1]) < tol) I.conv += 1; else I.conv = 0;
+                    if (s_brk) I.status = ED_BREAKDOWN;
+                    else if (I.conv >= 2) I.status = kConverged;
+                }
+            }
+            __syncthreads();
+        }
+        grid_sync(gb);
+    }
+}
+
+static int batch_grid(int *grid) {
+    static int cached = 0;
+    if (!cached) {
+        int dev = 0, ncu = 0, occ = 0;
+        ED_HIP(hipGetDevice(&dev));
+        ED_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+        ED_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k_batch),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, kBatchLds));
+        ED_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void *>(k_batch),
+                                                            kBatchBlock, kBatchLds));
+        if (occ < 1) return set_error(ED_EDEVICE, "k_batch cannot be resident on a CU");
+        cached = ncu * occ;
+    }
+    *grid = cached;
+    return ED_OK;
+}
+
+struct BatchPlan {
+    std::vector<BInst> inst;
+    int64_t part_doubles = 0, part2_doubles = 0;
+};
+
+static int plan_batch(const ed_batch_item *items, int n, int32_t max_steps, BatchPlan &plan, bool fill_ptrs) {
+    plan.inst.assign(n, BInst{});
+    plan.part_doubles = plan.part2_doubles = 0;
+    for (int i = 0; i < n; ++i) {
+        const ed_ham &h = items[i].h;
+        int rc = check_ham(&h, "ed_ground_energy_batch");
+        if (rc) return rc;
+        if (h.dtype != ED_F32) return set_error(ED_EINVAL, "ed_ground_energy_batch: item %d is not ED_F32", i);
+        if (h.w_dn > 32) return set_error(ED_EOVERFLOW, "ed_ground_energy_batch: down table stride above 32");
+        if (h.w_up == 0) return set_error(ED_EINVAL, "ed_ground_energy_batch: item %d has no up-spin hopping", i);
+        if (h.dim_dn * 4 > kBatchLds) return set_error(ED_EOVERFLOW, "ed_ground_energy_batch: rows above 64 KB");
+        if (fill_ptrs) {
+            const ed_batch_item &it = items[i];
+            if (!it.f1 || !it.vec[0] || !it.vec[1] || !it.vec[2] || !it.a || !it.b)
+                return set_error(ED_EINVAL, "ed_ground_energy_batch: item %d has a NULL buffer", i);
+        }
+        const Tile tl = resolve_tile_id(&h, h.tile);
+        BInst &I = plan.inst[i];
+        I.Dup = (int)h.dim_up;
+        I.Ddn = (int)h.dim_dn;
+        I.W8u = h.w_up;
+        I.W8d = h.w_dn;
+        I.R = tl.up_wlog2 >= 6 ? 1 : 2;
+        const int w = 64 / I.R;
+        I.rc = tl.up_rc;
+        I.n_stripes = (I.Ddn + w - 1) / w;
+        I.n_rc = (I.Dup + I.rc - 1) / I.rc;
+        I.up_tiles = h.w_up ? 8 * I.n_rc * ((I.n_stripes + 7) / 8) : 0;
+        const int by_lds = std::max(1, (int)(kBatchLds / (I.Ddn * 4)));
+        const int by_fill = std::max(1, (2 * kBatchBlock + I.Ddn - 1) / I.Ddn);
+        I.rpb = std::max(1, std::min(std::min(by_lds, by_fill), I.Dup));
+        I.dn_tiles = (I.Dup + I.rpb - 1) / I.rpb;
+        I.n = (int64_t)I.Dup * I.Ddn;
+        I.upd_tiles = (int)((I.n + kUpdChunk - 1) / kUpdChunk);
+        I.part_off = plan.part_doubles;
+        I.part2_off = plan.part2_doubles;
+        plan.part_doubles += (int64_t)I.dn_tiles * 5;
+        plan.part2_doubles += I.upd_tiles;
+        I.tab_up = h.tab_up;
+        I.tab_dn = h.tab_dn;
+        I.st_up = h.st_up;
+        I.st_dn = h.st_dn;
+        I.t = h.t;
+        I.U = h.U;
+        if (fill_ptrs) {
+            const ed_batch_item &it = items[i];
+            I.f1 = static_cast<const float *>(it.f1);
+            for (int k = 0; k < 3; ++k) I.vec[k] = static_cast<float *>(it.vec[k]);
+            I.a = it.a;
+            I.b = it.b;
+        }
+    }
+    return ED_OK;
+}
+
+static int64_t batch_ws_bytes(const BatchPlan &plan, int n, int32_t max_steps) {
+    auto al = [](int64_t b) { return (b + 255) & ~int64_t(255); };
+    return al(sizeof(GridBar)) + al((int64_t)n * sizeof(BInst)) + al(8 * plan.part_doubles) +
+           al(8 * plan.part2_doubles) + al(8 * (int64_t)n * (max_steps + 1));
+}
+
+}  // namespace ed
+
+using namespace ed;
+
+extern "C" {
+
+int ed_batch_workspace_size(const ed_batch_item *items, int32_t n, int32_t max_steps, int64_t *bytes) {
+    clear_error();
+    if (!items || n < 1 || max_steps < 1 || !bytes) return set_error(ED_EINVAL, "ed_batch_workspace_size: bad arguments");
+    BatchPlan plan;
+    int rc = plan_batch(items, n, max_steps, plan, false);
+    if (rc) return rc;
+    *bytes = batch_ws_bytes(plan, n, max_steps);
+    return ED_OK;
+}
+
+int ed_ground_energy_batch(const ed_batch_item *items, int32_t n, int32_t max_steps, double tol, void *ws,
+                           int64_t ws_bytes, void *stream, int32_t use_graph, double *e0, int32_t *steps,
+                           int32_t *status, double *e0_device, int32_t *graph_used) {
+    clear_error();
+    if (!items || n < 1 || max_steps < 1 || !ws || !e0 || !steps || !status || !(tol > 0))
+        return set_error(ED_EINVAL, "ed_ground_energy_batch: bad arguments");
+    if (reinterpret_cast<uintptr_t>(ws) & 255) return set_error(ED_EINVAL, "ed_ground_energy_batch: ws not aligned");
+    BatchPlan plan;
+    int rc = plan_batch(items, n, max_steps, plan, true);
+    if (rc) return rc;
+    if (ws_bytes < batch_ws_bytes(plan, n, max_steps))
+        return set_error(ED_ECAPACITY, "ed_ground_energy_batch: workspace too small");
+    auto al = [](int64_t b) { return (b + 255) & ~int64_t(255); };
+    char *p = static_cast<char *>(ws);
+    GridBar *gb = reinterpret_cast<GridBar *>(p);
+    p += al(sizeof(GridBar));
+    BInst *dinst = reinterpret_cast<BInst *>(p);
+    p += al((int64_t)n * sizeof(BInst));
+    double *part = reinterpret_cast<double *>(p);
+    p += al(8 * plan.part_doubles);
+    double *part2 = reinterpret_cast<double *>(p);
+    p += al(8 * plan.part2_doubles);
+    double *ev = reinterpret_cast<double *>(p);
+    for (int i = 0; i < n; ++i) plan.inst[i].e = ev + (int64_t)i * (max_steps + 1);
+
+    int grid = 0;
+    rc = batch_grid(&grid);
+    if (rc) return rc;
+
+    hipStream_t user = static_cast<hipStream_t>(stream);
+    GridBar gb0{};
+    ED_HIP(hipMemcpyAsync(gb, &gb0, sizeof gb0, hipMemcpyHostToDevice, user));
+    ED_HIP(hipMemcpyAsync(dinst, plan.inst.data(), n * sizeof(BInst), hipMemcpyHostToDevice, user));
+
+    int ni = n, ms = max_steps;
+    double tl = tol;
+    void *args[] = {&dinst, &ni, &part, &part2, &gb, &ms, &tl};
+    bool graphed = false;
+    if (use_graph) {
+        // one graph holding the single persistent cooperative launch
+        hipStream_t cs = nullptr;
+        hipEvent_t ev = nullptr;
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ge = nullptr;
+        bool ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess &&
+                  hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess &&
+                  hipEventRecord(ev, user) == hipSuccess && hipStreamWaitEvent(cs, ev, 0) == hipSuccess;
+        if (ok && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+            const hipError_t le = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_batch), dim3(grid),
+                                                             dim3(kBatchBlock), args, kBatchLds, cs);
+            const hipError_t ee = hipStreamEndCapture(cs, &g);
+            ok = le == hipSuccess && ee == hipSuccess && g != nullptr &&
+                 hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) == hipSuccess;
+            if (ok) ok = hipGraphLaunch(ge, cs) == hipSuccess && hipEventRecord(ev, cs) == hipSuccess &&
+                         hipStreamWaitEvent(user, ev, 0) == hipSuccess;
+            graphed = ok;
+        } else {
+            ok = false;
+        }
+        (void)hipGetLastError();   // a refused capture leaves no sticky error
+        if (!graphed && cs) (void)hipStreamSynchronize(cs);
+        if (ge) (void)hipGraphExecDestroy(ge);
+        if (g) (void)hipGraphDestroy(g);
+        if (graphed) ED_HIP(hipStreamSynchronize(user));
+        if (ev) (void)hipEventDestroy(ev);
+        if (cs) (void)hipStreamDestroy(cs);
+    }
+    if (!graphed) {
+        ED_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_batch), dim3(grid), dim3(kBatchBlock),
+                                          args, kBatchLds, user));
+    }
+    if (graph_used) *graph_used = graphed ? 1 : 0;
+    std::vector<BInst> out(n);
+    GridBar gbh{};
+    ED_HIP(hipMemcpyAsync(out.data(), dinst, n * sizeof(BInst), hipMemcpyDeviceToHost, user));
+    ED_HIP(hipMemcpyAsync(&gbh, gb, sizeof gbh, hipMemcpyDeviceToHost, user));
+    ED_HIP(hipStreamSynchronize(user));
+    if (gbh.err) return set_error(ED_EDEVICE, "ed_ground_energy_batch: grid barrier timed out");
+    int result = ED_OK;
+    for (int i = 0; i < n; ++i) {
+        const BInst &I = out[i];
+        if (I.status == kBadStart) return set_error(ED_EINVAL, "ed_ground_energy_batch: item %d has a zero start", i);
+        const int k = I.j;
+        steps[i] = k;
+        status[i] = I.status == kConverged ? ED_OK : (I.status == ED_BREAKDOWN ? ED_BREAKDOWN : ED_NOT_CONVERGED);
+        if (status[i] == ED_NOT_CONVERGED) result = ED_NOT_CONVERGED;
+        std::vector<double> a(k), b(k + 1), e(k + 1);
+        if (k > 0) {
+            ED_HIP(hipMemcpy(a.data(), items[i].a, 8 * (size_t)k, hipMemcpyDeviceToHost));
+            ED_HIP(hipMemcpy(b.data(), items[i].b, 8 * (size_t)(k + 1), hipMemcpyDeviceToHost));
+            ED_HIP(hipMemcpy(e.data(), plan.inst[i].e, 8 * (size_t)(k + 1), hipMemcpyDeviceToHost));
+            e0[i] = tridiag_lowest(a.data(), b.data() + 1, k);
+        } else {
+            e0[i] = NAN;
+        }
+        if (e0_device) e0_device[i] = k > 0 ? e[k] : NAN;
+    }
+    return result;
+}
+
+}  // extern "C"

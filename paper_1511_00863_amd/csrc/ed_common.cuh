@@ -1,0 +1,223 @@
+// Device building blocks shared by the single-instance kernels and the
+// batched persistent kernel: reductions, table decoding, the up-part tile
+// (Eq. 4) and the down-part row block (Eq. 5).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ed {
+
+// ---------------------------------------------------------------------------
+// reductions: wave64 butterfly, then a fixed-order sum over waves.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double *out) {
+    __shared__ double red[16][NV];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] += __shfl_xor(v[k], o, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) red[wave][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double s = 0.0;
+            for (int w = 0; w < nw; ++w) s += red[w][k];
+            out[k] = s;
+        }
+    }
+}
+
+
+// ---------------------------------------------------------------------------
+// table entries: 8 uint16 per 16-byte chunk, e = (col << 1) | negative, 0xFFFF = pad
+__device__ __forceinline__ unsigned entry(const uint4 &q, int k) {
+    const unsigned w = k < 2 ? q.x : (k < 4 ? q.y : (k < 6 ? q.z : q.w));
+    return (k & 1) ? (w >> 16) : (w & 0xFFFFu);
+}
+
+// Up part (Eq. 4) on one tile = (column stripe s of width w = 64/R, row chunk rci):
+// out[r, c] = t * sum_k sgn_k * x[J_up[r,k], c].  A wave serves R consecutive
+// rows x w columns; the row index is wave-uniform, so each row's table chunks
+// are scalar loads, chunks that are padding for every row of the wave are
+// skipped, and the 8 gathers of a chunk per row are issued back to back
+// (padding inside a chunk re-reads x[0, c] and is multiplied by zero).
+template <typename T, int R>
+__device__ __forceinline__ void up_tile(const T *__restrict__ x, T *__restrict__ out,
+                                        const uint16_t *__restrict__ tab, int Dup, int Ddn, int W8, int rc, int s,
+                                        int rci, T t) {
+    constexpr int w = 64 / R;
+    const int lane = threadIdx.x & 63, nwave = blockDim.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int sub = R == 1 ? 0 : lane / w;
+    const int c = s * w + (lane & (w - 1));
+    const bool cok = c < Ddn;
+    const int cc = cok ? c : 0;
+    const T *xc = x + cc;
+    const int r1 = min(Dup, (rci + 1) * rc);
+    const int nch = W8 >> 3;
+    for (int rb = rci * rc + wave * R; rb < r1; rb += nwave * R) {
+        const int r = rb + sub;
+        T acc0 = T(0), acc1 = T(0);
+        for (int k8 = 0; k8 < nch; ++k8) {
+            uint4 q[R];
+            bool any = false;
+#pragma unroll
+            for (int u = 0; u < R; ++u) {
+                const int ru = min(rb + u, Dup - 1);
+                q[u] = *reinterpret_cast<const uint4 *>(tab + (int64_t)ru * W8 + 8 * k8);
+                any = any || (entry(q[u], 0) != 0xFFFFu && rb + u < r1);
+            }
+            if (!any) break;   // ascending columns, padding at the end: the rest is padding too
+            T v[8], sg[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                unsigned e = entry(q[0], k);
+#pragma unroll
+                for (int u = 1; u < R; ++u)
+                    if (sub == u) e = entry(q[u], k);
+                const bool pk = e != 0xFFFFu;
+                sg[k] = pk ? ((e & 1u) ? T(-1) : T(1)) : T(0);
+                v[k] = xc[(int64_t)(pk ? (e >> 1) : 0u) * Ddn];
+            }
+#pragma unroll
+            for (int k = 0; k < 8; k += 2) {
+                acc0 += sg[k] * v[k];
+                acc1 += sg[k + 1] * v[k + 1];
+            }
+        }
+        if (cok && r < r1) __builtin_nontemporal_store(t * (acc0 + acc1), out + (int64_t)r * Ddn + c);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Down part (Eq. 5) on a block of rows:
+//   q[r, c] = sig * (io[r, c] + t * sum_k sgn_k x[r, J_dn[c,k]] + U*Docc[r,c]*x[r,c])
+//             (- cprev * p[r, c] in a Lanczos step, cprev = b_j / s_{j-1})
+// io holds the up part on entry and q on exit.  The rows are staged in LDS
+// with 16-byte loads by the caller; lane c reads its table row from the
+// 8-interleaved layout (16 bytes per chunk, contiguous across lanes).  The
+// column loop is software pipelined: the next column's table chunks, up part
+// and f_{j-1} value are loaded while the current column gathers from the rows
+// (branch-free: padding reads one broadcast address times zero).
+// NCH = largest number of table chunks per row (W8 / 8 <= NCH) handled.
+// MODE 0: plain H.v (sig = 1).  MODE 1: Lanczos, partial q.x.
+// MODE 2: Lanczos mixed form, partials (q.x, q.p, x.x, x.p, p.p).
+template <typename T>
+__device__ __forceinline__ void stage_rows(const T *__restrict__ src, T *__restrict__ dst, int n) {
+    // 16-byte pieces, four in flight per thread; the tail element by element
+    constexpr int V = 16 / sizeof(T);
+    const int nv = n / V;
+    const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
+    uint4 *d4 = reinterpret_cast<uint4 *>(dst);
+    const bool aligned = (reinterpret_cast<uintptr_t>(src) & 15) == 0;
+    if (aligned) {
+        int i = threadIdx.x;
+        for (; i + 3 * (int)blockDim.x < nv; i += 4 * blockDim.x) {
+            const uint4 a = s4[i], b = s4[i + blockDim.x], c = s4[i + 2 * blockDim.x], d = s4[i + 3 * blockDim.x];
+            d4[i] = a;
+            d4[i + blockDim.x] = b;
+            d4[i + 2 * blockDim.x] = c;
+            d4[i + 3 * blockDim.x] = d;
+        }
+        for (; i < nv; i += blockDim.x) d4[i] = s4[i];
+        for (int k = nv * V + threadIdx.x; k < n; k += blockDim.x) dst[k] = src[k];
+    } else {
+        for (int k = threadIdx.x; k < n; k += blockDim.x) dst[k] = src[k];
+    }
+}
+
+// One block of nr rows starting at row r0 of one instance: q = sig * (io + t *
+// down-part + U Docc x) - cprev * p, in place on io; per-thread partial sums
+// added to s[].  xrows: the rows (LDS copy or global); base: offset of row r0
+// in the global vectors.
+template <typename T, int MODE, int NCH>
+__device__ __forceinline__ void down_rows(const T *__restrict__ xrows, T *__restrict__ io, const T *__restrict__ p,
+                                          const uint16_t *__restrict__ tab, const uint64_t *__restrict__ st_up_r0,
+                                          const uint64_t *__restrict__ st_dn, int Ddn, int W8, int nr,
+                                          int64_t base, bool multi_row, T t, T U, T sig, T cprev, bool use_p,
+                                          double (&s)[MODE == 2 ? 5 : 1]) {
+    const uint4 *til = reinterpret_cast<const uint4 *>(tab + (int64_t)Ddn * W8);   // 8-interleaved part
+    const int nch = W8 >> 3;
+    const uint4 kPad4 = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+    const int n = nr * Ddn;
+    int i = threadIdx.x;
+    uint4 tq[NCH];
+    T iov = T(0), pv = T(0);
+    int c = 0, rr = 0;
+    if (i < n) {
+        if (multi_row) { rr = i / Ddn; c = i - rr * Ddn; } else { c = i; }
+#pragma unroll
+        for (int k8 = 0; k8 < NCH; ++k8) tq[k8] = k8 < nch ? til[(int64_t)k8 * Ddn + c] : kPad4;
+        iov = io[base + i];
+        if (use_p) pv = p[base + i];
+    }
+    for (; i < n; i += blockDim.x) {
+        // prefetch the next column of this thread
+        const int in = i + blockDim.x;
+        int cn = 0, rrn = 0;
+        uint4 tqn[NCH];
+        T iovn = T(0), pvn = T(0);
+        if (in < n) {
+            if (multi_row) { rrn = in / Ddn; cn = in - rrn * Ddn; } else { cn = in; }
+#pragma unroll
+            for (int k8 = 0; k8 < NCH; ++k8) tqn[k8] = k8 < nch ? til[(int64_t)k8 * Ddn + cn] : kPad4;
+            iovn = io[base + in];
+            if (use_p) pvn = p[base + in];
+        }
+        const T *xrow = xrows + (int64_t)rr * Ddn;
+        T acc0 = T(0), acc1 = T(0);
+#pragma unroll
+        for (int k8 = 0; k8 < NCH; ++k8) {
+            if (k8 >= nch) break;
+            // a chunk whose first entry is padding is padding throughout; skip it
+            // when that holds for every lane of the wave
+            if (!__any(entry(tq[k8], 0) != 0xFFFFu)) break;
+            T v[8], sg[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const unsigned e = entry(tq[k8], k);
+                const bool pk = e != 0xFFFFu;
+                sg[k] = pk ? ((e & 1u) ? T(-1) : T(1)) : T(0);
+                v[k] = xrow[pk ? (int)(e >> 1) : 0];   // padding: one broadcast address
+            }
+#pragma unroll
+            for (int k = 0; k < 8; k += 2) {
+                acc0 += sg[k] * v[k];
+                acc1 += sg[k + 1] * v[k + 1];
+            }
+        }
+        const T xv = xrow[c];
+        const T nd = static_cast<T>(__popcll(st_up_r0[rr] & st_dn[c]));
+        T q = iov + t * (acc0 + acc1) + U * nd * xv;
+        if (MODE != 0) {
+            q *= sig;
+            if (use_p) q -= cprev * pv;
+        }
+        io[base + i] = q;
+        if (MODE != 0) {
+            const double qd = q, xd = xv;
+            s[0] += qd * xd;
+            if constexpr (MODE == 2) {
+                const double pd = pv;
+                s[1] += qd * pd;
+                s[2] += xd * xd;
+                s[3] += xd * pd;
+                s[4] += pd * pd;
+            }
+        }
+        c = cn;
+        rr = rrn;
+        iov = iovn;
+        pv = pvn;
+#pragma unroll
+        for (int k8 = 0; k8 < NCH; ++k8) tq[k8] = tqn[k8];
+    }
+}
+
+}  // namespace ed

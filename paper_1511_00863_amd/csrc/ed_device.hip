@@ -28,7 +28,9 @@
 #include <vector>
 
 #include "../../include/ed.h"
+#include "ed_common.cuh"
 #include "ed_internal.h"
+#include "ed_launch.h"
 
 namespace ed {
 
@@ -96,100 +98,10 @@ static WsLayout ws_layout(const ed_ham *h, void *ws, int32_t max_steps) {
     return l;
 }
 
-// ---------------------------------------------------------------------------
-// reductions: wave64 butterfly, then a fixed-order sum over waves.
-template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double *out) {
-    __shared__ double red[16][NV];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-#pragma unroll
-        for (int k = 0; k < NV; ++k) v[k] += __shfl_xor(v[k], o, 64);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0)
-#pragma unroll
-        for (int k = 0; k < NV; ++k) red[wave][k] = v[k];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const int nw = (blockDim.x + 63) >> 6;
-#pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            double s = 0.0;
-            for (int w = 0; w < nw; ++w) s += red[w][k];
-            out[k] = s;
-        }
-    }
-}
-
 __device__ __forceinline__ bool frozen(const Hdr *hdr, int max_steps) {
     return hdr->status != 0 || hdr->jdev >= max_steps;
 }
 
-// ---------------------------------------------------------------------------
-// table entries: 8 uint16 per 16-byte chunk, e = (col << 1) | negative, 0xFFFF = pad
-__device__ __forceinline__ unsigned entry(const uint4 &q, int k) {
-    const unsigned w = k < 2 ? q.x : (k < 4 ? q.y : (k < 6 ? q.z : q.w));
-    return (k & 1) ? (w >> 16) : (w & 0xFFFFu);
-}
-
-// Up part (Eq. 4) on one tile = (column stripe s of width w = 64/R, row chunk rci):
-// out[r, c] = t * sum_k sgn_k * x[J_up[r,k], c].  A wave serves R consecutive
-// rows x w columns; the row index is wave-uniform, so each row's table chunks
-// are scalar loads, chunks that are padding for every row of the wave are
-// skipped, and the 8 gathers of a chunk per row are issued back to back
-// (padding inside a chunk re-reads x[0, c] and is multiplied by zero).
-template <typename T, int R>
-__device__ __forceinline__ void up_tile(const T *__restrict__ x, T *__restrict__ out,
-                                        const uint16_t *__restrict__ tab, int Dup, int Ddn, int W8, int rc, int s,
-                                        int rci, T t) {
-    constexpr int w = 64 / R;
-    const int lane = threadIdx.x & 63, nwave = blockDim.x >> 6;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int sub = R == 1 ? 0 : lane / w;
-    const int c = s * w + (lane & (w - 1));
-    const bool cok = c < Ddn;
-    const int cc = cok ? c : 0;
-    const T *xc = x + cc;
-    const int r1 = min(Dup, (rci + 1) * rc);
-    const int nch = W8 >> 3;
-    for (int rb = rci * rc + wave * R; rb < r1; rb += nwave * R) {
-        const int r = rb + sub;
-        T acc0 = T(0), acc1 = T(0);
-        for (int k8 = 0; k8 < nch; ++k8) {
-            uint4 q[R];
-            bool any = false;
-#pragma unroll
-            for (int u = 0; u < R; ++u) {
-                const int ru = min(rb + u, Dup - 1);
-                q[u] = *reinterpret_cast<const uint4 *>(tab + (int64_t)ru * W8 + 8 * k8);
-                any = any || (entry(q[u], 0) != 0xFFFFu && rb + u < r1);
-            }
-            if (!any) break;   // ascending columns, padding at the end: the rest is padding too
-            T v[8], sg[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                unsigned e = entry(q[0], k);
-#pragma unroll
-                for (int u = 1; u < R; ++u)
-                    if (sub == u) e = entry(q[u], k);
-                const bool pk = e != 0xFFFFu;
-                sg[k] = pk ? ((e & 1u) ? T(-1) : T(1)) : T(0);
-                v[k] = xc[(int64_t)(pk ? (e >> 1) : 0u) * Ddn];
-            }
-#pragma unroll
-            for (int k = 0; k < 8; k += 2) {
-                acc0 += sg[k] * v[k];
-                acc1 += sg[k + 1] * v[k + 1];
-            }
-        }
-        if (cok && r < r1) __builtin_nontemporal_store(t * (acc0 + acc1), out + (int64_t)r * Ddn + c);
-    }
-}
-
-// k_up, static mapping.  map 0: workgroup g runs on XCD g % 8 under
-// round-robin dispatch; stripe s belongs to XCD s % 8 and its n_rc row chunks
-// are consecutive workgroups of that XCD, so the stripe stays in that XCD's
-// L2 while its chunks run.  map 1: plain stripe-major order.
 template <typename T, int R>
 __global__ __launch_bounds__(512) void k_up(const T *__restrict__ x, T *__restrict__ out,
                                             const uint16_t *__restrict__ tab, int Dup, int Ddn, int W8, int rc,
@@ -242,44 +154,6 @@ __global__ void k_ctr_reset(int *ctr, const Hdr *hdr, int gate, int max_steps) {
     if (threadIdx.x < 8) ctr[threadIdx.x] = 0;
 }
 
-// ---------------------------------------------------------------------------
-// k_down: q[r, c] = sig * (io[r, c] + t * sum_k sgn_k x[r, J_dn[c,k]] + U*Docc[r,c]*x[r,c])
-//                   (- b_j sig_prev p[r, c] in a Lanczos step)          (Eq. 5)
-// io holds the up part on entry and q on exit.  The rows of the block are
-// staged in LDS with 16-byte loads; lane c reads its table row from the
-// 8-interleaved layout (16 bytes per chunk, contiguous across lanes).  The
-// column loop is software pipelined: the next column's table chunks, up
-// part and f_{j-1} value are loaded while the current column gathers from LDS
-// (branch-free: padding reads the lane's own element times zero).
-// NCH = largest number of table chunks per row (W8 / 8 <= NCH) the
-// instantiation handles; LDS = rows staged in LDS (else the gathers read
-// global memory).
-// MODE 0: plain H.v (sig = 1).  MODE 1: Lanczos, partial q.x.
-// MODE 2: Lanczos mixed form, partials (q.x, q.p, x.x, x.p, p.p).
-template <typename T>
-__device__ __forceinline__ void stage_rows(const T *__restrict__ src, T *__restrict__ dst, int n) {
-    // 16-byte pieces, four in flight per thread; the tail element by element
-    constexpr int V = 16 / sizeof(T);
-    const int nv = n / V;
-    const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
-    uint4 *d4 = reinterpret_cast<uint4 *>(dst);
-    const bool aligned = (reinterpret_cast<uintptr_t>(src) & 15) == 0;
-    if (aligned) {
-        int i = threadIdx.x;
-        for (; i + 3 * (int)blockDim.x < nv; i += 4 * blockDim.x) {
-            const uint4 a = s4[i], b = s4[i + blockDim.x], c = s4[i + 2 * blockDim.x], d = s4[i + 3 * blockDim.x];
-            d4[i] = a;
-            d4[i + blockDim.x] = b;
-            d4[i + 2 * blockDim.x] = c;
-            d4[i + 3 * blockDim.x] = d;
-        }
-        for (; i < nv; i += blockDim.x) d4[i] = s4[i];
-        for (int k = nv * V + threadIdx.x; k < n; k += blockDim.x) dst[k] = src[k];
-    } else {
-        for (int k = threadIdx.x; k < n; k += blockDim.x) dst[k] = src[k];
-    }
-}
-
 template <typename T, int MODE, bool LDS, int NCH>
 __global__ __launch_bounds__(1024) void k_down(const T *__restrict__ x, T *__restrict__ io, const T *__restrict__ p,
                                                const uint16_t *__restrict__ tab,
@@ -302,92 +176,16 @@ __global__ __launch_bounds__(1024) void k_down(const T *__restrict__ x, T *__res
     const int r0 = blockIdx.x * rpb;
     const int nr = min(rpb, Dup - r0);
     const int64_t base = (int64_t)r0 * Ddn;
-    const int n = nr * Ddn;
     if (LDS) {
-        stage_rows<T>(x + base, xs, n);
+        stage_rows<T>(x + base, xs, nr * Ddn);
         __syncthreads();
     }
-    const uint4 *til = reinterpret_cast<const uint4 *>(tab + (int64_t)Ddn * W8);   // 8-interleaved part
-    const int nch = W8 >> 3;
-    const uint4 kPad4 = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
     constexpr int NV = MODE == 2 ? 5 : 1;
     double s[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) s[k] = 0.0;
-    const bool use_p = MODE != 0 && has_prev;
-
-    int i = threadIdx.x;
-    uint4 tq[NCH];
-    T iov = T(0), pv = T(0);
-    int c = 0, rr = 0;
-    if (i < n) {
-        if (rpb > 1) { rr = i / Ddn; c = i - rr * Ddn; } else { c = i; }
-#pragma unroll
-        for (int k8 = 0; k8 < NCH; ++k8) tq[k8] = k8 < nch ? til[(int64_t)k8 * Ddn + c] : kPad4;
-        iov = io[base + i];
-        if (use_p) pv = p[base + i];
-    }
-    for (; i < n; i += blockDim.x) {
-        // prefetch the next column of this thread
-        const int in = i + blockDim.x;
-        int cn = 0, rrn = 0;
-        uint4 tqn[NCH];
-        T iovn = T(0), pvn = T(0);
-        if (in < n) {
-            if (rpb > 1) { rrn = in / Ddn; cn = in - rrn * Ddn; } else { cn = in; }
-#pragma unroll
-            for (int k8 = 0; k8 < NCH; ++k8) tqn[k8] = k8 < nch ? til[(int64_t)k8 * Ddn + cn] : kPad4;
-            iovn = io[base + in];
-            if (use_p) pvn = p[base + in];
-        }
-        const T *xrow = LDS ? xs + rr * Ddn : x + base + (int64_t)rr * Ddn;
-        T acc0 = T(0), acc1 = T(0);
-#pragma unroll
-        for (int k8 = 0; k8 < NCH; ++k8) {
-            if (k8 >= nch) break;
-            // a chunk whose first entry is padding is padding throughout; skip it
-            // when that holds for every lane of the wave
-            if (!__any(entry(tq[k8], 0) != 0xFFFFu)) break;
-            T v[8], sg[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const unsigned e = entry(tq[k8], k);
-                const bool pk = e != 0xFFFFu;
-                sg[k] = pk ? ((e & 1u) ? T(-1) : T(1)) : T(0);
-                v[k] = xrow[pk ? (int)(e >> 1) : 0];   // padding: one broadcast address
-            }
-#pragma unroll
-            for (int k = 0; k < 8; k += 2) {
-                acc0 += sg[k] * v[k];
-                acc1 += sg[k + 1] * v[k + 1];
-            }
-        }
-        const T xv = xrow[c];
-        const T nd = static_cast<T>(__popcll(st_up[r0 + rr] & st_dn[c]));
-        T q = iov + t * (acc0 + acc1) + U * nd * xv;
-        if (MODE != 0) {
-            q *= sig;
-            if (use_p) q -= cprev * pv;
-        }
-        io[base + i] = q;
-        if (MODE != 0) {
-            const double qd = q, xd = xv;
-            s[0] += qd * xd;
-            if constexpr (MODE == 2) {
-                const double pd = pv;
-                s[1] += qd * pd;
-                s[2] += xd * xd;
-                s[3] += xd * pd;
-                s[4] += pd * pd;
-            }
-        }
-        c = cn;
-        rr = rrn;
-        iov = iovn;
-        pv = pvn;
-#pragma unroll
-        for (int k8 = 0; k8 < NCH; ++k8) tq[k8] = tqn[k8];
-    }
+    down_rows<T, MODE, NCH>(LDS ? xs : x + base, io, p, tab, st_up + r0, st_dn, Ddn, W8, nr, base, rpb > 1, t, U,
+                            sig, cprev, MODE != 0 && has_prev, s);
     if (MODE != 0) {
         double tot[NV];
         block_sum<NV>(s, tot);
@@ -565,116 +363,6 @@ __global__ __launch_bounds__(256) void k_fill0(T *__restrict__ out, int64_t n) {
 
 // ---------------------------------------------------------------------------
 // launch configuration ("tile")
-struct Tile {
-    int up_wlog2;   // stripe width = 2^up_wlog2 columns (8..64)
-    int up_rc;      // rows per k_up tile
-    int up_block;   // k_up threads per workgroup
-    int up_map;     // 0 XCD round-robin remap, 1 linear, 2 per-XCD queues
-    int dn_block;   // k_down threads per workgroup
-    int dn_rpb;     // rows per k_down workgroup (0 = derive from LDS and block)
-};
-
-struct UpTile { int wlog2, rc, block, map; };
-struct DnTile { int block, rpb; };
-
-// Candidates searched by ed_tune.  A tile id is up_index | (dn_index << 8);
-// index 0 means "heuristic default" for that kernel.
-static const UpTile kUpTiles[] = {
-    {0, 0, 0, 0},
-    {6, 16, 256, 0}, {5, 16, 256, 0}, {4, 16, 256, 0},
-    {6, 32, 256, 0}, {5, 32, 256, 0}, {4, 32, 256, 0},
-    {6, 64, 256, 0}, {5, 64, 256, 0}, {4, 64, 256, 0},
-    {6, 128, 256, 0}, {5, 128, 256, 0}, {4, 128, 256, 0},
-    {6, 256, 256, 0}, {5, 256, 256, 0}, {4, 256, 256, 0},
-    {6, 32, 256, 1}, {5, 32, 256, 1}, {4, 32, 256, 1},
-    {6, 128, 256, 1}, {5, 128, 256, 1}, {4, 128, 256, 1},
-    {6, 32, 256, 2}, {5, 32, 256, 2}, {4, 32, 256, 2},
-    {6, 128, 256, 2}, {5, 128, 256, 2}, {4, 128, 256, 2},
-    {6, 64, 512, 0}, {5, 64, 512, 0}, {6, 128, 512, 0}, {5, 128, 512, 0},
-};
-static const DnTile kDnTiles[] = {
-    {0, 0}, {1024, 0}, {512, 0}, {256, 0}, {1024, 1}, {512, 1}, {256, 1}, {1024, 2}, {512, 2}, {256, 4},
-};
-constexpr int kNumUp = sizeof(kUpTiles) / sizeof(kUpTiles[0]);
-constexpr int kNumDn = sizeof(kDnTiles) / sizeof(kDnTiles[0]);
-constexpr int kLdsBudget = 152 * 1024;
-
-static int elem_size(const ed_ham *h) { return h->dtype == ED_F64 ? 8 : 4; }
-
-static Tile resolve_tile_id(const ed_ham *h, int id) {
-    const int ui = id & 0xFF, di = (id >> 8) & 0xFF;
-    const int es = elem_size(h);
-    Tile t;
-    if (ui > 0 && ui < kNumUp) {
-        t.up_wlog2 = kUpTiles[ui].wlog2;
-        t.up_rc = kUpTiles[ui].rc;
-        t.up_block = kUpTiles[ui].block;
-        t.up_map = kUpTiles[ui].map;
-    } else {
-        t.up_wlog2 = es == 8 ? 5 : 6;
-        t.up_rc = 64;
-        t.up_block = 256;
-        t.up_map = 0;
-    }
-    if (di > 0 && di < kNumDn) {
-        t.dn_block = kDnTiles[di].block;
-        t.dn_rpb = kDnTiles[di].rpb;
-    } else {
-        t.dn_block = h->dim_dn >= 1024 ? 1024 : 256;
-        t.dn_rpb = 0;
-    }
-    // stripes much wider than the row are pointless
-    while (t.up_wlog2 > 4 && (1 << (t.up_wlog2 - 1)) >= h->dim_dn) --t.up_wlog2;
-    if (t.up_wlog2 < 4) t.up_wlog2 = 4;
-    const int64_t row_bytes = h->dim_dn * es;
-    if (t.dn_rpb == 0) {
-        int64_t by_lds = std::max<int64_t>(1, kLdsBudget / row_bytes);
-        int64_t by_fill = std::max<int64_t>(1, (2 * t.dn_block + h->dim_dn - 1) / h->dim_dn);
-        t.dn_rpb = (int)std::min<int64_t>(std::min(by_lds, by_fill), h->dim_up);
-    }
-    t.dn_rpb = (int)std::max<int64_t>(1, std::min<int64_t>(t.dn_rpb, h->dim_up));
-    return t;
-}
-
-static Tile resolve_tile(const ed_ham *h) { return resolve_tile_id(h, h->tile); }
-
-static bool valid_tile_id(int id) {
-    return id >= 0 && (id & 0xFF) < kNumUp && ((id >> 8) & 0xFF) < kNumDn && (id >> 16) == 0;
-}
-
-static int check_ham(const ed_ham *h, const char *who) {
-    if (!h) return set_error(ED_EINVAL, "%s: ham is NULL", who);
-    if (h->dim_up < 1 || h->dim_dn < 1) return set_error(ED_EINVAL, "%s: bad dims", who);
-    if (h->dim_up > 32767 || h->dim_dn > 32767)
-        return set_error(ED_EOVERFLOW, "%s: per-spin dims must be <= 32767", who);
-    if (h->w_up < 0 || h->w_dn < 0 || (h->w_up && !h->tab_up) || (h->w_dn && !h->tab_dn) || !h->st_up ||
-        !h->st_dn)
-        return set_error(ED_EINVAL, "%s: missing tables or states", who);
-    if ((h->w_up & 7) || (h->w_dn & 7)) return set_error(ED_EINVAL, "%s: table strides must be multiples of 8", who);
-    if (h->w_up > 64 || h->w_dn > 64) return set_error(ED_EOVERFLOW, "%s: table strides above 64 unsupported", who);
-    if (h->dtype != ED_F64 && h->dtype != ED_F32) return set_error(ED_EINVAL, "%s: bad dtype %d", who, h->dtype);
-    if (!valid_tile_id(h->tile)) return set_error(ED_EINVAL, "%s: bad tile id %d", who, h->tile);
-    if (!std::isfinite(h->t) || !std::isfinite(h->U)) return set_error(ED_EINVAL, "%s: non-finite t or U", who);
-    return ED_OK;
-}
-
-static int hip_check(hipError_t e, const char *what) {
-    if (e == hipSuccess) return ED_OK;
-    return set_error(ED_EDEVICE, "%s: %s", what, hipGetErrorString(e));
-}
-
-#define ED_HIP(call)                                          \
-    do {                                                      \
-        int rc_ = hip_check((call), #call);                   \
-        if (rc_) return rc_;                                  \
-    } while (0)
-
-#define ED_LAUNCHED(name)                                     \
-    do {                                                      \
-        int rc_ = hip_check(hipGetLastError(), name);         \
-        if (rc_) return rc_;                                  \
-    } while (0)
-
 static int grid_for(int64_t n, int block, int cap = 4096) {
     int64_t g = (n + block - 1) / block;
     return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));

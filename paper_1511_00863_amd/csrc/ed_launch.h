@@ -1,0 +1,125 @@
+// Host-side launch helpers shared by the device translation units: tile
+// tables and their resolution, argument checks, HIP error mapping.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+
+#include "../../include/ed.h"
+#include "ed_internal.h"
+
+namespace ed {
+
+struct Tile {
+    int up_wlog2;   // stripe width = 2^up_wlog2 columns (8..64)
+    int up_rc;      // rows per k_up tile
+    int up_block;   // k_up threads per workgroup
+    int up_map;     // 0 XCD round-robin remap, 1 linear, 2 per-XCD queues
+    int dn_block;   // k_down threads per workgroup
+    int dn_rpb;     // rows per k_down workgroup (0 = derive from LDS and block)
+};
+
+struct UpTile { int wlog2, rc, block, map; };
+struct DnTile { int block, rpb; };
+
+// Candidates searched by ed_tune.  A tile id is up_index | (dn_index << 8);
+// index 0 means "heuristic default" for that kernel.
+static const UpTile kUpTiles[] = {
+    {0, 0, 0, 0},
+    {6, 16, 256, 0}, {5, 16, 256, 0}, {4, 16, 256, 0},
+    {6, 32, 256, 0}, {5, 32, 256, 0}, {4, 32, 256, 0},
+    {6, 64, 256, 0}, {5, 64, 256, 0}, {4, 64, 256, 0},
+    {6, 128, 256, 0}, {5, 128, 256, 0}, {4, 128, 256, 0},
+    {6, 256, 256, 0}, {5, 256, 256, 0}, {4, 256, 256, 0},
+    {6, 32, 256, 1}, {5, 32, 256, 1}, {4, 32, 256, 1},
+    {6, 128, 256, 1}, {5, 128, 256, 1}, {4, 128, 256, 1},
+    {6, 32, 256, 2}, {5, 32, 256, 2}, {4, 32, 256, 2},
+    {6, 128, 256, 2}, {5, 128, 256, 2}, {4, 128, 256, 2},
+    {6, 64, 512, 0}, {5, 64, 512, 0}, {6, 128, 512, 0}, {5, 128, 512, 0},
+};
+static const DnTile kDnTiles[] = {
+    {0, 0}, {1024, 0}, {512, 0}, {256, 0}, {1024, 1}, {512, 1}, {256, 1}, {1024, 2}, {512, 2}, {256, 4},
+};
+constexpr int kNumUp = sizeof(kUpTiles) / sizeof(kUpTiles[0]);
+constexpr int kNumDn = sizeof(kDnTiles) / sizeof(kDnTiles[0]);
+constexpr int kLdsBudget = 152 * 1024;
+
+static inline int elem_size(const ed_ham *h) { return h->dtype == ED_F64 ? 8 : 4; }
+
+static inline Tile resolve_tile_id(const ed_ham *h, int id) {
+    const int ui = id & 0xFF, di = (id >> 8) & 0xFF;
+    const int es = elem_size(h);
+    Tile t;
+    if (ui > 0 && ui < kNumUp) {
+        t.up_wlog2 = kUpTiles[ui].wlog2;
+        t.up_rc = kUpTiles[ui].rc;
+        t.up_block = kUpTiles[ui].block;
+        t.up_map = kUpTiles[ui].map;
+    } else {
+        t.up_wlog2 = es == 8 ? 5 : 6;
+        t.up_rc = 64;
+        t.up_block = 256;
+        t.up_map = 0;
+    }
+    if (di > 0 && di < kNumDn) {
+        t.dn_block = kDnTiles[di].block;
+        t.dn_rpb = kDnTiles[di].rpb;
+    } else {
+        t.dn_block = h->dim_dn >= 1024 ? 1024 : 256;
+        t.dn_rpb = 0;
+    }
+    // stripes much wider than the row are pointless
+    while (t.up_wlog2 > 4 && (1 << (t.up_wlog2 - 1)) >= h->dim_dn) --t.up_wlog2;
+    if (t.up_wlog2 < 4) t.up_wlog2 = 4;
+    const int64_t row_bytes = h->dim_dn * es;
+    if (t.dn_rpb == 0) {
+        int64_t by_lds = std::max<int64_t>(1, kLdsBudget / row_bytes);
+        int64_t by_fill = std::max<int64_t>(1, (2 * t.dn_block + h->dim_dn - 1) / h->dim_dn);
+        t.dn_rpb = (int)std::min<int64_t>(std::min(by_lds, by_fill), h->dim_up);
+    }
+    t.dn_rpb = (int)std::max<int64_t>(1, std::min<int64_t>(t.dn_rpb, h->dim_up));
+    return t;
+}
+
+static inline Tile resolve_tile(const ed_ham *h) { return resolve_tile_id(h, h->tile); }
+
+static inline bool valid_tile_id(int id) {
+    return id >= 0 && (id & 0xFF) < kNumUp && ((id >> 8) & 0xFF) < kNumDn && (id >> 16) == 0;
+}
+
+static inline int check_ham(const ed_ham *h, const char *who) {
+    if (!h) return set_error(ED_EINVAL, "%s: ham is NULL", who);
+    if (h->dim_up < 1 || h->dim_dn < 1) return set_error(ED_EINVAL, "%s: bad dims", who);
+    if (h->dim_up > 32767 || h->dim_dn > 32767)
+        return set_error(ED_EOVERFLOW, "%s: per-spin dims must be <= 32767", who);
+    if (h->w_up < 0 || h->w_dn < 0 || (h->w_up && !h->tab_up) || (h->w_dn && !h->tab_dn) || !h->st_up ||
+        !h->st_dn)
+        return set_error(ED_EINVAL, "%s: missing tables or states", who);
+    if ((h->w_up & 7) || (h->w_dn & 7)) return set_error(ED_EINVAL, "%s: table strides must be multiples of 8", who);
+    if (h->w_up > 64 || h->w_dn > 64) return set_error(ED_EOVERFLOW, "%s: table strides above 64 unsupported", who);
+    if (h->dtype != ED_F64 && h->dtype != ED_F32) return set_error(ED_EINVAL, "%s: bad dtype %d", who, h->dtype);
+    if (!valid_tile_id(h->tile)) return set_error(ED_EINVAL, "%s: bad tile id %d", who, h->tile);
+    if (!std::isfinite(h->t) || !std::isfinite(h->U)) return set_error(ED_EINVAL, "%s: non-finite t or U", who);
+    return ED_OK;
+}
+
+static inline int hip_check(hipError_t e, const char *what) {
+    if (e == hipSuccess) return ED_OK;
+    return set_error(ED_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+}  // namespace ed
+
+#define ED_HIP(call)                                          \
+    do {                                                      \
+        int rc_ = ::ed::hip_check((call), #call);             \
+        if (rc_) return rc_;                                  \
+    } while (0)
+
+#define ED_LAUNCHED(name)                                     \
+    do {                                                      \
+        int rc_ = ::ed::hip_check(hipGetLastError(), name);   \
+        if (rc_) return rc_;                                  \
+    } while (0)
