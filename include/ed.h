@@ -232,9 +232,11 @@ int ed_ground_energy(const ed_ham *h, ed_lanczos *st, const void *f1, double tol
  * ed_ground_energy with tol <= 0), the lowest eigenvector y of T_m is found on
  * the host, pass 2 replays the identical steps and accumulates
  * v = sum_k y_k f_k, then v is normalised (float64 norm).  v: device, h->dtype,
- * dim elements, distinct from the three Lanczos vectors.  ws must hold
- * ed_workspace_size(h, m).  *e0 = lowest eigenvalue of T_m. */
-int ed_ground_state(const ed_ham *h, ed_lanczos *st, const void *f1, int32_t m, void *v,
+ * dim elements, distinct from the three Lanczos vectors.  gauge_index >= 0
+ * fixes the arbitrary global sign: v[gauge_index] >= 0 afterwards (-1: no
+ * gauge).  ws must hold ed_workspace_size(h, m).  *e0 = lowest eigenvalue
+ * of T_m. */
+int ed_ground_state(const ed_ham *h, ed_lanczos *st, const void *f1, int32_t m, int64_t gauge_index, void *v,
                     void *ws, void *stream, double *e0, int32_t *steps);
 
 /* ---- device: batched ground-state runs --------------------------------- */
@@ -273,6 +275,53 @@ int ed_batch_workspace_size(const ed_batch_item *items, int32_t n, int32_t max_s
 int ed_ground_energy_batch(const ed_batch_item *items, int32_t n, int32_t max_steps, double tol, void *ws,
                            int64_t ws_bytes, void *stream, int32_t use_graph, double *e0, int32_t *steps,
                            int32_t *status, double *e0_device, int32_t *graph_used);
+
+/* ---- device: the start-vector network ---------------------------------- */
+
+/* psi(bits): 32 inputs (bits 0..15 of the up state, then of the down state,
+ * as +-1) -> 128 -> 128 -> 128 (ReLU) -> 1.  It proposes the Lanczos start
+ * vector (Alg. 1 requires only a vector of norm 1).  Parameters: one float32
+ * array of ED_MLP_NPARAM values, W1[128x32] b1[128] W2[128x128] b2 W3[128x128]
+ * b3 W4[1x128] b4, each W row-major [out][in].  Every matrix product runs on
+ * bfloat16 matrix cores (operands rounded to nearest even), accumulating in
+ * float32.  Minibatch calls keep their activations in `ws`
+ * (ed_mlp_workspace_size bytes for n samples, 256-byte aligned). */
+#define ED_MLP_NPARAM 37377
+int ed_mlp_workspace_size(int64_t n, int64_t *bytes);
+
+/* Forward pass on n samples; sample k is the state (st_up[idx[2k]],
+ * st_dn[idx[2k+1]]).  out: device, n floats (may be NULL).  All device
+ * pointers; the activations stay in ws for ed_mlp_backward. */
+int ed_mlp_forward(const float *params, const uint64_t *st_up, const uint64_t *st_dn, const int32_t *idx,
+                   int64_t n, float *out, void *ws, void *stream);
+
+/* Gradient of the mean squared error (1/n) sum_k (psi_k - target_k)^2 of
+ * the last ed_mlp_forward on ws: grad (device, ED_MLP_NPARAM floats) is
+ * overwritten; loss (device double, may be NULL) receives the loss. */
+int ed_mlp_backward(const float *params, const float *target, int64_t n, float *grad, double *loss, void *ws,
+                    void *stream);
+
+/* One Adam step (bias-corrected, step >= 1) on the float32 parameters with
+ * moments m, v (device, ED_MLP_NPARAM floats each, zero before step 1). */
+int ed_mlp_adam(float *params, const float *grad, float *m, float *v, int32_t step, float lr, float beta1,
+                float beta2, float eps, void *stream);
+
+/* psi over every state of instance h: f1[i_up * dim_dn + i_dn] (h->dtype). */
+int ed_mlp_start_vector(const float *params, const ed_ham *h, void *f1, void *stream);
+
+/* Row distribution of a vector psi of instance h for ed_mlp_sample:
+ * cdf[r] = (sum_{r' <= r} sum_c psi[r', c]^2) / |psi|^2 (float64).  cdf: device,
+ * dim_up + 1 doubles (the last receives |psi|^2). */
+int ed_mlp_row_cdf(const void *psi, const ed_ham *h, double *cdf, void *stream);
+
+/* Draw n training samples from a ground-state vector psi of h: with
+ * uniforms[2k] < 1/2 the state is drawn with probability |psi|^2 (the row
+ * through row_cdf from ed_mlp_row_cdf, then the column inside the row),
+ * otherwise uniformly;
+ * uniforms[2k+1] is the position.  idx: device, 2n ints (i_up, i_dn);
+ * target: device, n floats = sqrt(dim) psi[state]. */
+int ed_mlp_sample(const void *psi, const ed_ham *h, const double *row_cdf, const double *uniforms, int32_t n,
+                  int32_t *idx, float *target, void *stream);
 
 #ifdef __cplusplus
 }

@@ -5,7 +5,7 @@ Loading fails loudly when the built library is missing: there is no fallback.
 
 import ctypes
 import os
-from ctypes import POINTER, c_char_p, c_double, c_int, c_int32, c_int64, c_uint16, c_uint64, c_void_p
+from ctypes import POINTER, c_char_p, c_double, c_float, c_int, c_int32, c_int64, c_uint16, c_uint64, c_void_p
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libed_mi355x.so")
@@ -14,6 +14,7 @@ ED_OK, ED_BREAKDOWN, ED_NOT_CONVERGED = 0, 1, 2
 ED_EINVAL, ED_ECAPACITY, ED_EOVERFLOW, ED_EDEVICE = -1, -2, -3, -4
 ED_F64, ED_F32 = 0, 1
 ED_ROW_MAJOR, ED_COL_MAJOR = 0, 1
+ED_MLP_NPARAM = 37377
 
 
 class EdError(RuntimeError):
@@ -67,8 +68,16 @@ _PROTOS = {
     "ed_ground_energy": (c_int, [POINTER(EdHam), POINTER(EdLanczos), c_void_p, c_double, c_int32, c_void_p,
                                  c_void_p, POINTER(c_double), POINTER(c_int32), POINTER(c_double),
                                  POINTER(c_double)]),
-    "ed_ground_state": (c_int, [POINTER(EdHam), POINTER(EdLanczos), c_void_p, c_int32, c_void_p, c_void_p,
-                                c_void_p, POINTER(c_double), POINTER(c_int32)]),
+    "ed_ground_state": (c_int, [POINTER(EdHam), POINTER(EdLanczos), c_void_p, c_int32, c_int64, c_void_p,
+                                c_void_p, c_void_p, POINTER(c_double), POINTER(c_int32)]),
+    "ed_mlp_workspace_size": (c_int, [c_int64, POINTER(c_int64)]),
+    "ed_mlp_forward": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]),
+    "ed_mlp_backward": (c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "ed_mlp_adam": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_float, c_float, c_float, c_float,
+                            c_void_p]),
+    "ed_mlp_start_vector": (c_int, [c_void_p, POINTER(EdHam), c_void_p, c_void_p]),
+    "ed_mlp_row_cdf": (c_int, [c_void_p, POINTER(EdHam), c_void_p, c_void_p]),
+    "ed_mlp_sample": (c_int, [c_void_p, POINTER(EdHam), c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
 }
 
 _lib = None

@@ -322,9 +322,9 @@ __global__ __launch_bounds__(256) void k_sumsq(const T *__restrict__ x, int64_t 
 }
 
 // mode 0: start a Lanczos run: sigma_1 = 1/|f1|, b_1 = 0, counters reset.
-// mode 1: vinv = 1/|v|.
+// mode 1: vinv = +-1/|v|, the sign making gauge_val * vinv >= 0 (gauge fix).
 __global__ __launch_bounds__(1024) void k_init_norm(const double *__restrict__ part2, int n, Hdr *hdr, double *b,
-                                                    int mode) {
+                                                    int mode, double gauge_sign) {
     double s[1] = {0.0};
     for (int i = threadIdx.x; i < n; i += blockDim.x) s[0] += part2[i];
     double tot[1];
@@ -342,7 +342,7 @@ __global__ __launch_bounds__(1024) void k_init_norm(const double *__restrict__ p
         hdr->status = ok ? 0 : kInitBad;
         b[0] = 0.0;
     } else {
-        hdr->vinv = ok ? 1.0 / sqrt(n2) : 0.0;
+        hdr->vinv = ok ? gauge_sign / sqrt(n2) : 0.0;
     }
 }
 
@@ -537,11 +537,12 @@ static int step_dispatch(const ed_ham *h, const Tile &tl, void *f_prev, void *f_
 // |in|^2 in float64 -> mode 0: start a run (sigma_1) / mode 1: vinv; then
 // out = in (mode 0, the stored f_1 is the raw start vector) or in * vinv.
 template <typename T>
-static int norm_launch(const T *in, T *out, int64_t n, const WsLayout &w, double *b, int mode, hipStream_t s) {
+static int norm_launch(const T *in, T *out, int64_t n, const WsLayout &w, double *b, int mode, hipStream_t s,
+                       double gauge_sign = 1.0) {
     const int g = upd_grid(n);
     hipLaunchKernelGGL(k_sumsq<T>, dim3(g), dim3(256), 0, s, in, n, w.part2);
     ED_LAUNCHED("k_sumsq");
-    hipLaunchKernelGGL(k_init_norm, dim3(1), dim3(1024), 0, s, w.part2, g, w.hdr, b, mode);
+    hipLaunchKernelGGL(k_init_norm, dim3(1), dim3(1024), 0, s, w.part2, g, w.hdr, b, mode, gauge_sign);
     ED_LAUNCHED("k_init_norm");
     hipLaunchKernelGGL(k_copy_scaled<T>, dim3(upd_grid(n)), dim3(256), 0, s, in, out, w.hdr, n, mode);
     ED_LAUNCHED("k_copy_scaled");
@@ -919,8 +920,8 @@ int ed_ground_energy(const ed_ham *h, ed_lanczos *st, const void *f1, double tol
     return result;
 }
 
-int ed_ground_state(const ed_ham *h, ed_lanczos *st, const void *f1, int32_t m, void *v, void *ws, void *stream,
-                    double *e0, int32_t *steps) {
+int ed_ground_state(const ed_ham *h, ed_lanczos *st, const void *f1, int32_t m, int64_t gauge_index, void *v,
+                    void *ws, void *stream, double *e0, int32_t *steps) {
     clear_error();
     int rc = check_lanczos(h, st, ws, "ed_ground_state");
     if (rc) return rc;
@@ -960,8 +961,23 @@ int ed_ground_state(const ed_ham *h, ed_lanczos *st, const void *f1, int32_t m, 
         if (rc) return rc;
         rotate(&s2);
     }
-    if (h->dtype == ED_F64) rc = norm_launch<double>((const double *)v, (double *)v, n, w, s2.b, 1, s);
-    else rc = norm_launch<float>((const float *)v, (float *)v, n, w, s2.b, 1, s);
+    double gsign = 1.0;
+    if (gauge_index >= 0) {
+        if (gauge_index >= n) return set_error(ED_EINVAL, "ed_ground_state: gauge index out of range");
+        double gv = 0.0;
+        if (h->dtype == ED_F64) {
+            ED_HIP(hipMemcpyAsync(&gv, (const double *)v + gauge_index, 8, hipMemcpyDeviceToHost, s));
+        } else {
+            float gf = 0.f;
+            ED_HIP(hipMemcpyAsync(&gf, (const float *)v + gauge_index, 4, hipMemcpyDeviceToHost, s));
+            ED_HIP(hipStreamSynchronize(s));
+            gv = gf;
+        }
+        ED_HIP(hipStreamSynchronize(s));
+        gsign = gv < 0.0 ? -1.0 : 1.0;
+    }
+    if (h->dtype == ED_F64) rc = norm_launch<double>((const double *)v, (double *)v, n, w, s2.b, 1, s, gsign);
+    else rc = norm_launch<float>((const float *)v, (float *)v, n, w, s2.b, 1, s, gsign);
     if (rc) return rc;
     ED_HIP(hipStreamSynchronize(s));
     *e0 = e;
