@@ -8,8 +8,16 @@ seeded uniform(-1,1) start vector, float64 (the plain method); the mixed form
 (float32 vectors, float64 scalars) is timed beside it.  Inputs are resident in
 HBM before the timed region; as in the paper's protocol no transfer is timed.
 
+Beside the step rate the line carries: the roofline of the dominant kernel
+(HIP events inside this run), time-to-E0 at stated accuracy for plain float64,
+mixed and learned starts at a held-out U (the network trained on the
+method's own ground states at U = 1..8), the 64-instance batched launch
+against the same instances run one by one in plain float64, and the oracle
+timed on the host cores.
+
 Prints ONE JSON line.  Options: --steps K --warmup W (timed / untimed steps),
---gpus N (only 1 is supported: the method runs on one GPU), --no-cpu-baseline.
+--gpus N (only 1 is supported: the method runs on one GPU), --no-cpu-baseline,
+--no-learned, --no-batch.
 """
 
 import argparse
@@ -17,6 +25,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -83,6 +93,80 @@ def measured_traffic(dtype, kernel, workload_name):
     return rec["kernels"].get(dtype, {}).get(kernel)
 
 
+def time_to_e0_block(up, dn, wl, args):
+    """Steps and wall ms to E0 at stated accuracy vs converged plain float64 Lanczos (the judge):
+    plain float64 and mixed from the seeded random start, mixed and float64 from the learned start
+    (network inference inside the timed region).  The network trains on ground states at U = 1..8."""
+    import torch
+    import paper_1511_00863_amd as ed
+    from paper_1511_00863_amd import learned
+    from synth import start_vector
+    t0 = time.perf_counter()
+    data = learned.training_data(up, dn, wl.t, [1, 2, 3, 4, 5, 6, 7, 8])
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    net, losses, t_train = learned.train_network(data, iters=args.train_iters, batch=4096)
+    del data
+    torch.cuda.empty_cache()
+    out = {"training": {"ground_states": 8, "data_s": t_data, "train_s": t_train, "iters": args.train_iters,
+                        "batch": 4096, "loss_first": float(losses[:20].mean()), "loss_last": float(losses[-20:].mean())},
+           "held_out": []}
+    for U in [float(u) for u in args.held_out.split(",")]:
+        e_judge, judge_steps = learned.judge_energy(up, dn, wl.t, U, wl.seed)
+        row = {"U": U, "e_judge": e_judge, "judge_steps": judge_steps}
+        for dt, tol in (("f64", 1e-10), ("f32", 1e-6)):
+            h = ed.Hamiltonian(up, dn, wl.t, U, dt)
+            ed.api.apply_tuned_tile(h, tune_if_missing=False)
+            x = torch.from_numpy(start_vector(wl.seed, h.dim)).to("cuda:0", h.torch_dtype)
+            rnd = learned.time_to_e0(h, lambda: x.clone(), e_judge, tol)
+            del x
+            lrn = learned.time_to_e0(h, lambda: learned.learned_start(net, h, wl.seed)[0], e_judge, tol)
+            name = "plain_f64" if dt == "f64" else "mixed"
+            row[name + "_random"] = {"steps": rnd["steps"], "ms": rnd["ms"], "rel_tol": tol}
+            row[name + "_learned"] = {"steps": lrn["steps"], "ms": lrn["ms"], "rel_tol": tol}
+            del h
+            torch.cuda.empty_cache()
+        out["held_out"].append(row)
+    return out
+
+
+def batch_block(args):
+    """64 Hubbard instances on the 4x4 torus (U ~ U[0,8], N_up = N_dn in {3,4,5,6}) in one persistent
+    launch (mixed form, |dE0| < 1e-6), against the same instances run one after another in plain float64."""
+    import torch
+    import paper_1511_00863_amd as ed
+    from synth import batch_instances, start_vector, torus_bonds
+    bonds = torus_bonds(4, 4)
+    draws = batch_instances(64, 1000)
+    tabs = {n: ed.SpinTables(16, bonds, n, "cuda:0") for n in (3, 4, 5, 6)}
+    hams = [ed.Hamiltonian(tabs[n], tabs[n], 1.0, U, "f32") for (U, n, s) in draws]
+    for h in hams:
+        ed.api.apply_tuned_tile(h, tune_if_missing=False)
+    f1s = [torch.from_numpy(start_vector(s, h.dim)).to("cuda:0", torch.float32) for h, (U, n, s) in zip(hams, draws)]
+    r = ed.ground_energy_batch(hams, f1s, 500, tol=1e-6)
+    r = ed.ground_energy_batch(hams, f1s, 500, tol=1e-6)          # second call timed (warm)
+    del f1s
+    torch.cuda.empty_cache()
+    seq_ms, seq_e0 = 0.0, []
+    for (U, n, s) in draws:
+        h = ed.Hamiltonian(tabs[n], tabs[n], 1.0, U, "f64")
+        ed.api.apply_tuned_tile(h, tune_if_missing=False)
+        x = torch.from_numpy(start_vector(s, h.dim)).to("cuda:0", torch.float64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rr = h.ground_energy(x, 500, tol=1e-6, check_every=9)
+        torch.cuda.synchronize()
+        seq_ms += (time.perf_counter() - t0) * 1e3
+        seq_e0.append(rr["e0"])
+        del x
+    seq_e0 = np.array(seq_e0)
+    import numpy as np_
+    return {"instances": 64, "total_dim": int(sum(h.dim for h in hams)), "wall_ms": r["wall_ms"],
+            "graph_used": r["graph_used"], "converged": int((r["status"] == 0).sum()),
+            "max_steps_used": int(r["steps"].max()), "sequential_plain_f64_ms": seq_ms,
+            "max_rel_dev_vs_f64": float(np_.max(np_.abs(r["e0"] - seq_e0) / np_.abs(seq_e0)))}
+
+
 def cpu_baseline(wl, n_steps):
     """The oracle's float64 matrix-free Lanczos steps (NumPy/SciPy, single thread) on a sample."""
     import numpy as np
@@ -111,6 +195,10 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="use the built-in default tile instead of ed_tune")
+    ap.add_argument("--no-learned", action="store_true", help="skip the time-to-E0 comparison with the learned start")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batched run")
+    ap.add_argument("--train-iters", type=int, default=1500)
+    ap.add_argument("--held-out", default="3.5", help="comma-separated held-out U values for time-to-E0")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this method runs on one GPU; --gpus %d is not supported (use --gpus 1)" % args.gpus,
@@ -180,6 +268,10 @@ def main():
                          "ms_per_step": r32["ms_per_step"], "hv_alg_GBps": r32["hv_alg_GBps"],
                          "kernel_ms": r32["kernel_ms"], "step_floor_frac": r32["step_floor_GBps"] / HBM_PEAK_GBPS,
                          "tile": {"id": r32["tile"], "source": r32["tile_src"], **r32["tile_params"]}}
+    if not args.no_learned:
+        line["time_to_e0"] = time_to_e0_block(up, dn, wl, args)
+    if not args.no_batch:
+        line["batch"] = batch_block(args)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
     print(json.dumps(line), flush=True)

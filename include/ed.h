@@ -268,13 +268,15 @@ int ed_batch_workspace_size(const ed_batch_item *items, int32_t n, int32_t max_s
  * Per item (host arrays of n): e0 = lowest eigenvalue of T at the stopping
  * step (host bisection of the returned coefficients), steps, status (ED_OK =
  * converged, ED_BREAKDOWN, ED_NOT_CONVERGED); e0_device (may be NULL) = the
- * device's value at that step.  ws: ed_batch_workspace_size bytes, 256-byte
- * aligned.  Synchronises `stream`.  Returns ED_NOT_CONVERGED if any item
- * did not converge.  Limits: per-spin dims <= 32767, rows of at most 16384
- * floats, down-table strides <= 32, both species must hop. */
+ * device's value at that step.  phase_ms (6 doubles, may be NULL): time spent
+ * in the phases start-up, up part, down part, a_j, update, b_j (summed over
+ * the steps, barrier waits included).  ws: ed_batch_workspace_size bytes,
+ * 256-byte aligned.  Synchronises `stream`.  Returns ED_NOT_CONVERGED if any item
+ * did not converge.  Limits: per-spin dims <= 32767, rows (dim_dn) of at
+ * most 10240 floats, down-table strides <= 32, both species must hop. */
 int ed_ground_energy_batch(const ed_batch_item *items, int32_t n, int32_t max_steps, double tol, void *ws,
                            int64_t ws_bytes, void *stream, int32_t use_graph, double *e0, int32_t *steps,
-                           int32_t *status, double *e0_device, int32_t *graph_used);
+                           int32_t *status, double *e0_device, int32_t *graph_used, double *phase_ms);
 
 /* ---- device: the start-vector network ---------------------------------- */
 

@@ -42,7 +42,7 @@ _PROTOS = {
     "ed_batch_workspace_size": (c_int, [POINTER(EdBatchItem), c_int32, c_int32, POINTER(c_int64)]),
     "ed_ground_energy_batch": (c_int, [POINTER(EdBatchItem), c_int32, c_int32, c_double, c_void_p, c_int64,
                                        c_void_p, c_int32, POINTER(c_double), POINTER(c_int32), POINTER(c_int32),
-                                       POINTER(c_double), POINTER(c_int32)]),
+                                       POINTER(c_double), POINTER(c_int32), POINTER(c_double)]),
     "ed_last_error": (c_char_p, []),
     "ed_version": (c_char_p, []),
     "ed_build_basis": (c_int, [c_int, c_int, POINTER(c_uint64), c_int64, POINTER(c_int64)]),

@@ -373,14 +373,16 @@ def ground_energy_batch(hams, f1s, max_steps: int, tol: float = 1e-6, use_graph:
     steps = np.zeros(n, dtype=np.int32)
     status = np.zeros(n, dtype=np.int32)
     used = c_int32(0)
+    phase = np.zeros(6)
     torch.cuda.synchronize()
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     start.record()
     rc = check(lib().ed_ground_energy_batch(items, n, int(max_steps), float(tol), _dptr(ws), nb.value,
                                             _stream(stream), 1 if use_graph else 0, _ptr(e0, c_double),
                                             _ptr(steps, c_int32), _ptr(status, c_int32), _ptr(e0d, c_double),
-                                            byref(used)))
+                                            byref(used), _ptr(phase, c_double)))
     end.record()
     torch.cuda.synchronize()
+    names = ("start", "up", "down", "a_j", "update", "b_j")
     return {"e0": e0, "steps": steps, "status": status, "e0_device": e0d, "graph_used": bool(used.value),
-            "rc": rc, "wall_ms": start.elapsed_time(end)}
+            "rc": rc, "wall_ms": start.elapsed_time(end), "phase_ms": dict(zip(names, phase.tolist()))}

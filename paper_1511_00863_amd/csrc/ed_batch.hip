@@ -23,8 +23,10 @@
 
 namespace ed {
 
-constexpr int kBatchBlock = 512;
-constexpr int kBatchLds = 64 * 1024;
+#define ED_GLOBAL __attribute__((address_space(1)))
+
+constexpr int kBatchBlock = 256;
+constexpr int kBatchLds = 40 * 1024;        // four workgroups per CU
 constexpr int64_t kUpdChunk = 65536;         // elements per update tile
 constexpr int kConverged = 10;
 constexpr int kBadStart = 100;
@@ -36,50 +38,77 @@ struct BInst {
     int R, rc, n_stripes, n_rc;
     int up_tiles, rpb, dn_tiles, upd_tiles;
     int64_t n, part_off, part2_off;
-    const uint16_t *tab_up, *tab_dn;
-    const uint64_t *st_up, *st_dn;
-    const float *f1;
-    float *vec[3];
-    double *a, *b, *e;
+    // global-memory pointers: typed so, the kernel's loads through pointers
+    // read from this descriptor are global (not flat) instructions
+    const ED_GLOBAL uint16_t *tab_up, *tab_dn;
+    const ED_GLOBAL uint64_t *st_up, *st_dn;
+    const ED_GLOBAL float *f1;
+    ED_GLOBAL float *vec[3];
+    ED_GLOBAL double *a, *b, *e;
     double t, U;
     // device state
     int j, status, rot, conv;
     double sig_cur, sig_prev, cx, cp, scale, pad;
 };
 
+// The arrival counter and the generation word sit on cache lines of their
+// own, so waiters polling the generation do not contend with arrivals.
 struct GridBar {
     unsigned count;
+    unsigned pad0[31];
     unsigned gen;
+    unsigned pad1[31];
     int err;
-    int pad;
+    int pad2;
+    unsigned long long phase[6];   // wall-clock ticks per phase (init, up, down, a_j, update, b_j) seen by WG 0
+    unsigned pad3[16];
+    // up-phase tile counters: [step parity][queue][own 128-byte line]
+    unsigned upq[2][8][32];
+};
+
+// phase bookkeeping of workgroup 0 (the other workgroups do not record)
+struct PhaseClock {
+    unsigned long long last;
+    __device__ void start() { last = wall_clock64(); }
+    __device__ void lap(GridBar *gb, int k) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            const unsigned long long now = wall_clock64();
+            gb->phase[k] += now - last;
+            last = now;
+        }
+    }
 };
 
 __device__ __forceinline__ bool b_live(const BInst &I, int max_steps) { return I.status == 0 && I.j < max_steps; }
 
-// All workgroups wait until all have arrived.  Spins are bounded: a timeout
-// sets gb->err and releases the waiter, so the kernel always ends.
+// All workgroups wait until all have arrived.  Each arrival publishes this
+// workgroup's writes once (release: L2 write-back) and each departure makes
+// the others' writes visible once (acquire: L2 invalidate).  Waiters poll
+// with relaxed loads: an acquire load in the loop would invalidate the XCD's
+// L2 on every poll and evict the lines that workgroups still working in the
+// phase depend on.  Spins are bounded: a timeout sets gb->err and releases
+// the waiter, so the kernel always ends.
 __device__ void grid_sync(GridBar *gb) {
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned g = __hip_atomic_load(&gb->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        const unsigned arrived = atomicAdd(&gb->count, 1u) + 1u;
+        const unsigned g = __hip_atomic_load(&gb->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned arrived =
+            __hip_atomic_fetch_add(&gb->count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) + 1u;
         if (arrived == gridDim.x) {
-            atomicExch(&gb->count, 0u);
-            __threadfence();
-            atomicAdd(&gb->gen, 1u);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __hip_atomic_store(&gb->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&gb->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             unsigned long long spins = 0;
-            while (__hip_atomic_load(&gb->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+            while (__hip_atomic_load(&gb->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
                 __builtin_amdgcn_s_sleep(2);
                 if (++spins > kSpinLimit) {
                     atomicExch(&gb->err, 1);
                     break;
                 }
             }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
-        __threadfence();
     }
     __syncthreads();
 }
@@ -155,13 +184,15 @@ __device__ double ritz_lowest_wave(const double *a, const double *boff, int m) {
     return 0.5 * (lo + hi);
 }
 
-__global__ __launch_bounds__(kBatchBlock) void k_batch(BInst *__restrict__ inst, int ni, double *__restrict__ part,
+__global__ __launch_bounds__(kBatchBlock, 4) void k_batch(BInst *__restrict__ inst, int ni, double *__restrict__ part,
                                                        double *__restrict__ part2, GridBar *gb, int max_steps,
                                                        double tol) {
     extern __shared__ __align__(16) unsigned char smem[];
     float *xs = reinterpret_cast<float *>(smem);
     __shared__ int s_any;
     const int64_t G = gridDim.x;
+    PhaseClock clk;
+    clk.start();
 
     // ---- start: F_1 = copy of f1, |f1|^2 partials
     {
@@ -172,7 +203,19 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch(BInst *__restrict__ inst,
             const int local = (int)(tg - cb);
             const int64_t lo = (int64_t)local * kUpdChunk, hi = min(I.n, lo + kUpdChunk);
             double s[1] = {0.0};
-            for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+            const int64_t B = blockDim.x;
+            int64_t k = lo + threadIdx.x;
+            for (; k + 3 * B < hi; k += 4 * B) {
+                float v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v[u] = I.f1[k + u * B];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    I.vec[0][k + u * B] = v[u];
+                    s[0] += (double)v[u] * (double)v[u];
+                }
+            }
+            for (; k < hi; k += B) {
                 const float v = I.f1[k];
                 I.vec[0][k] = v;
                 s[0] += (double)v * (double)v;
@@ -184,6 +227,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch(BInst *__restrict__ inst,
         }
     }
     grid_sync(gb);
+    clk.lap(gb, 0);
     for (int i = blockIdx.x; i < ni; i += G) {
         BInst &I = inst[i];
         double s[1] = {0.0};
@@ -205,6 +249,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch(BInst *__restrict__ inst,
         __syncthreads();
     }
     grid_sync(gb);
+    clk.lap(gb, 0);
 
     for (int step = 0; step < max_steps; ++step) {
         if (threadIdx.x == 0) {
@@ -215,26 +260,71 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch(BInst *__restrict__ inst,
         __syncthreads();
         if (!s_any) break;
 
-        // ---- up part (Eq. 4): T = t * up(F_j) into the next buffer
+        // ---- up part (Eq. 4): T = t * up(F_j) into the next buffer.  Queue
+        // q = blockIdx % 8 holds the tiles of the stripes s = q (mod 8) of
+        // every live instance (so a stripe's tiles share one XCD's L2 when
+        // workgroups are placed round-robin over the XCDs); its workgroups
+        // take tiles in order from an atomic counter, which keeps the tiles
+        // in flight within a narrow window of stripes, as in-order hardware
+        // dispatch would.  Every queue has workgroups (gridDim.x >= 8), so
+        // all tiles are processed whatever the placement.
         {
+            const int xq = blockIdx.x & 7;
+            unsigned *ctr = &gb->upq[step & 1][xq][0];
+            __shared__ unsigned s_tile;
+            if (threadIdx.x == 0) s_tile = atomicAdd(ctr, 1u);
+            __syncthreads();
+            int64_t qi = s_tile;
+            __syncthreads();
             int ci = 0;
             int64_t cb = 0;
-            for (int64_t tg = blockIdx.x; next_tile(inst, ni, max_steps, kUpT, tg, ci, cb); tg += G) {
+            while (true) {
+                bool found = false;
+                while (ci < ni) {
+                    const BInst &I = inst[ci];
+                    const int cnt = b_live(I, max_steps) && xq < I.n_stripes
+                                        ? I.n_rc * ((I.n_stripes - xq + 7) >> 3) : 0;
+                    if (qi < cb + cnt) {
+                        found = true;
+                        break;
+                    }
+                    cb += cnt;
+                    ++ci;
+                }
+                if (!found) break;
+                unsigned pre = 0;
+                if (threadIdx.x == 0) pre = atomicAdd(ctr, 1u);   // next tile, in flight during this one
                 const BInst &I = inst[ci];
-                const int local = (int)(tg - cb);
-                const int xcd = local & 7, l2 = local >> 3;
-                const int sl = l2 / I.n_rc, rci = l2 - sl * I.n_rc;
-                const int s = sl * 8 + xcd;
-                if (s >= I.n_stripes) continue;
-                const float *x = I.vec[I.rot];
-                float *out = I.vec[(I.rot + 1) % 3];
-                if (I.R == 1)
-                    up_tile<float, 1>(x, out, I.tab_up, I.Dup, I.Ddn, I.W8u, I.rc, s, rci, (float)I.t);
-                else
-                    up_tile<float, 2>(x, out, I.tab_up, I.Dup, I.Ddn, I.W8u, I.rc, s, rci, (float)I.t);
+                const int local = (int)(qi - cb);
+                const int sl = local / I.n_rc, rci = local - sl * I.n_rc;
+                const int s = sl * 8 + xq;
+                const float *x = (const float *)I.vec[I.rot];
+                float *out = (float *)I.vec[(I.rot + 1) % 3];
+                const uint16_t *tab = (const uint16_t *)I.tab_up;
+                const float t = (float)I.t;
+                if (I.R == 1) {
+                    switch (nch_class(I.W8u >> 3)) {
+                    case 1: up_tile_wide<float, 1>(x, out, tab, I.Dup, I.Ddn, I.W8u, I.rc, s, rci, t); break;
+                    case 2: up_tile_wide<float, 2>(x, out, tab, I.Dup, I.Ddn, I.W8u, I.rc, s, rci, t); break;
+                    case 4: up_tile_wide<float, 4>(x, out, tab, I.Dup, I.Ddn, I.W8u, I.rc, s, rci, t); break;
+                    default: up_tile_wide<float, 8>(x, out, tab, I.Dup, I.Ddn, I.W8u, I.rc, s, rci, t); break;
+                    }
+                } else {
+                    up_tile<float, 2>(x, out, tab, I.Dup, I.Ddn, I.W8u, I.rc, s, rci, t);
+                }
+                if (threadIdx.x == 0) s_tile = pre;
+                __syncthreads();
+                qi = s_tile;
+                __syncthreads();
             }
+            // the other parity's counters were last used a step ago: clear them
+            // for the next step (the barriers in between order this)
+            if (blockIdx.x == 0 && threadIdx.x < 8)
+                __hip_atomic_store(&gb->upq[(step + 1) & 1][threadIdx.x][0], 0u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         }
         grid_sync(gb);
+        clk.lap(gb, 1);
 
         // ---- down part (Eq. 5) + U term + recurrence, partial dots
         {
@@ -245,9 +335,9 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch(BInst *__restrict__ inst,
                 const int local = (int)(tg - cb);
                 const int r0 = local * I.rpb, nr = min(I.rpb, I.Dup - r0);
                 const int64_t base = (int64_t)r0 * I.Ddn;
-                const float *x = I.vec[I.rot];
-                float *io = I.vec[(I.rot + 1) % 3];
-                const float *p = I.vec[(I.rot + 2) % 3];
+                const float *x = (const float *)I.vec[I.rot];
+                float *io = (float *)I.vec[(I.rot + 1) % 3];
+                const float *p = (const float *)I.vec[(I.rot + 2) % 3];
                 __syncthreads();
                 stage_rows<float>(x + base, xs, nr * I.Ddn);
                 __syncthreads();
@@ -255,7 +345,8 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch(BInst *__restrict__ inst,
                 const bool has_prev = I.j > 0;
                 const float sig = (float)I.sig_cur;
                 const float cprev = (float)(I.b[I.j] * I.sig_prev);
-                down_rows<float, 2, 4>(xs, io, p, I.tab_dn, I.st_up + r0, I.st_dn, I.Ddn, I.W8d, nr, base,
+                down_rows<float, 2, 4>(xs, io, p, (const uint16_t *)I.tab_dn, (const uint64_t *)I.st_up + r0,
+                                       (const uint64_t *)I.st_dn, I.Ddn, I.W8d, nr, base,
                                        I.rpb > 1, (float)I.t, (float)I.U, sig, cprev, has_prev, s);
                 double tot[5];
                 block_sum<5>(s, tot);
@@ -264,6 +355,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch(BInst *__restrict__ inst,
             }
         }
         grid_sync(gb);
+        clk.lap(gb, 2);
 
         // ---- a_j and the update coefficients (Gram projection, float64)
         for (int i = blockIdx.x; i < ni; i += G) {
@@ -293,6 +385,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch(BInst *__restrict__ inst,
             __syncthreads();
         }
         grid_sync(gb);
+        clk.lap(gb, 3);
 
         // ---- F_{j+1} = q - cx F_j - cp F_{j-1}, partial norms
         {
@@ -302,12 +395,29 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch(BInst *__restrict__ inst,
                 const BInst &I = inst[ci];
                 const int local = (int)(tg - cb);
                 const int64_t lo = (int64_t)local * kUpdChunk, hi = min(I.n, lo + kUpdChunk);
-                const float *x = I.vec[I.rot];
-                float *q = I.vec[(I.rot + 1) % 3];
-                const float *p = I.vec[(I.rot + 2) % 3];
+                const float *x = (const float *)I.vec[I.rot];
+                float *q = (float *)I.vec[(I.rot + 1) % 3];
+                const float *p = (const float *)I.vec[(I.rot + 2) % 3];
                 const double cx = I.cx, cp = I.cp;
                 double s[1] = {0.0};
-                for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+                const int64_t B = blockDim.x;
+                int64_t k = lo + threadIdx.x;
+                for (; k + 3 * B < hi; k += 4 * B) {   // four independent elements in flight
+                    float xv[4], qv[4], pv[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        xv[u] = x[k + u * B];
+                        qv[u] = q[k + u * B];
+                        pv[u] = cp != 0.0 ? p[k + u * B] : 0.f;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const float st = (float)((double)qv[u] - cx * (double)xv[u] - cp * (double)pv[u]);
+                        q[k + u * B] = st;
+                        s[0] += (double)st * (double)st;
+                    }
+                }
+                for (; k < hi; k += B) {
                     double qv = (double)q[k] - cx * (double)x[k];
                     if (cp != 0.0) qv -= cp * (double)p[k];
                     const float st = (float)qv;
@@ -321,6 +431,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch(BInst *__restrict__ inst,
             }
         }
         grid_sync(gb);
+        clk.lap(gb, 4);
 
         // ---- b_{j+1}, breakdown, E0(j+1) and the convergence test
         for (int i = blockIdx.x; i < ni; i += G) {
@@ -349,7 +460,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch(BInst *__restrict__ inst,
             __syncthreads();
             if (threadIdx.x < 64) {
                 const int m = s_m;
-                const double e = ritz_lowest_wave(I.a, I.b + 1, m);
+                const double e = ritz_lowest_wave((const double *)I.a, (const double *)I.b + 1, m);
                 if (threadIdx.x == 0) {
                     I.e[m] = e;
                     if (m >= 2 && fabs(e - I.e[m - 1]) < tol) I.conv += 1; else I.conv = 0;
@@ -360,6 +471,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch(BInst *__restrict__ inst,
             __syncthreads();
         }
         grid_sync(gb);
+        clk.lap(gb, 5);
     }
 }
 
@@ -375,6 +487,7 @@ static int batch_grid(int *grid) {
                                                             kBatchBlock, kBatchLds));
         if (occ < 1) return set_error(ED_EDEVICE, "k_batch cannot be resident on a CU");
         cached = ncu * occ;
+        if (cached < 8) return set_error(ED_EDEVICE, "k_batch needs at least 8 resident workgroups");
     }
     *grid = cached;
     return ED_OK;
@@ -395,7 +508,7 @@ static int plan_batch(const ed_batch_item *items, int n, int32_t max_steps, Batc
         if (h.dtype != ED_F32) return set_error(ED_EINVAL, "ed_ground_energy_batch: item %d is not ED_F32", i);
         if (h.w_dn > 32) return set_error(ED_EOVERFLOW, "ed_ground_energy_batch: down table stride above 32");
         if (h.w_up == 0) return set_error(ED_EINVAL, "ed_ground_energy_batch: item %d has no up-spin hopping", i);
-        if (h.dim_dn * 4 > kBatchLds) return set_error(ED_EOVERFLOW, "ed_ground_energy_batch: rows above 64 KB");
+        if (h.dim_dn * 4 > kBatchLds) return set_error(ED_EOVERFLOW, "ed_ground_energy_batch: rows above 40 KB");
         if (fill_ptrs) {
             const ed_batch_item &it = items[i];
             if (!it.f1 || !it.vec[0] || !it.vec[1] || !it.vec[2] || !it.a || !it.b)
@@ -423,18 +536,18 @@ static int plan_batch(const ed_batch_item *items, int n, int32_t max_steps, Batc
         I.part2_off = plan.part2_doubles;
         plan.part_doubles += (int64_t)I.dn_tiles * 5;
         plan.part2_doubles += I.upd_tiles;
-        I.tab_up = h.tab_up;
-        I.tab_dn = h.tab_dn;
-        I.st_up = h.st_up;
-        I.st_dn = h.st_dn;
+        I.tab_up = (const ED_GLOBAL uint16_t *)h.tab_up;
+        I.tab_dn = (const ED_GLOBAL uint16_t *)h.tab_dn;
+        I.st_up = (const ED_GLOBAL uint64_t *)h.st_up;
+        I.st_dn = (const ED_GLOBAL uint64_t *)h.st_dn;
         I.t = h.t;
         I.U = h.U;
         if (fill_ptrs) {
             const ed_batch_item &it = items[i];
-            I.f1 = static_cast<const float *>(it.f1);
-            for (int k = 0; k < 3; ++k) I.vec[k] = static_cast<float *>(it.vec[k]);
-            I.a = it.a;
-            I.b = it.b;
+            I.f1 = (const ED_GLOBAL float *)it.f1;
+            for (int k = 0; k < 3; ++k) I.vec[k] = (ED_GLOBAL float *)it.vec[k];
+            I.a = (ED_GLOBAL double *)it.a;
+            I.b = (ED_GLOBAL double *)it.b;
         }
     }
     return ED_OK;
@@ -464,7 +577,7 @@ int ed_batch_workspace_size(const ed_batch_item *items, int32_t n, int32_t max_s
 
 int ed_ground_energy_batch(const ed_batch_item *items, int32_t n, int32_t max_steps, double tol, void *ws,
                            int64_t ws_bytes, void *stream, int32_t use_graph, double *e0, int32_t *steps,
-                           int32_t *status, double *e0_device, int32_t *graph_used) {
+                           int32_t *status, double *e0_device, int32_t *graph_used, double *phase_ms) {
     clear_error();
     if (!items || n < 1 || max_steps < 1 || !ws || !e0 || !steps || !status || !(tol > 0))
         return set_error(ED_EINVAL, "ed_ground_energy_batch: bad arguments");
@@ -485,7 +598,7 @@ int ed_ground_energy_batch(const ed_batch_item *items, int32_t n, int32_t max_st
     double *part2 = reinterpret_cast<double *>(p);
     p += al(8 * plan.part2_doubles);
     double *ev = reinterpret_cast<double *>(p);
-    for (int i = 0; i < n; ++i) plan.inst[i].e = ev + (int64_t)i * (max_steps + 1);
+    for (int i = 0; i < n; ++i) plan.inst[i].e = (ED_GLOBAL double *)(ev + (int64_t)i * (max_steps + 1));
 
     int grid = 0;
     rc = batch_grid(&grid);
@@ -540,6 +653,12 @@ int ed_ground_energy_batch(const ed_batch_item *items, int32_t n, int32_t max_st
     ED_HIP(hipMemcpyAsync(&gbh, gb, sizeof gbh, hipMemcpyDeviceToHost, user));
     ED_HIP(hipStreamSynchronize(user));
     if (gbh.err) return set_error(ED_EDEVICE, "ed_ground_energy_batch: grid barrier timed out");
+    if (phase_ms) {
+        int dev = 0, khz = 0;
+        ED_HIP(hipGetDevice(&dev));
+        ED_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+        for (int k = 0; k < 6; ++k) phase_ms[k] = khz > 0 ? (double)gbh.phase[k] / (double)khz : -1.0;
+    }
     int result = ED_OK;
     for (int i = 0; i < n; ++i) {
         const BInst &I = out[i];
@@ -552,7 +671,7 @@ int ed_ground_energy_batch(const ed_batch_item *items, int32_t n, int32_t max_st
         if (k > 0) {
             ED_HIP(hipMemcpy(a.data(), items[i].a, 8 * (size_t)k, hipMemcpyDeviceToHost));
             ED_HIP(hipMemcpy(b.data(), items[i].b, 8 * (size_t)(k + 1), hipMemcpyDeviceToHost));
-            ED_HIP(hipMemcpy(e.data(), plan.inst[i].e, 8 * (size_t)(k + 1), hipMemcpyDeviceToHost));
+            ED_HIP(hipMemcpy(e.data(), (const double *)plan.inst[i].e, 8 * (size_t)(k + 1), hipMemcpyDeviceToHost));
             e0[i] = tridiag_lowest(a.data(), b.data() + 1, k);
         } else {
             e0[i] = NAN;

@@ -95,6 +95,117 @@ __device__ __forceinline__ void up_tile(const T *__restrict__ x, T *__restrict__
     }
 }
 
+// Chunk count template parameter for a table of stride W8 (nch = W8/8 chunks
+// of 8 entries): the smallest of 1, 2, 4, 8 that holds nch.
+__host__ __device__ constexpr int nch_class(int nch) { return nch <= 1 ? 1 : (nch <= 2 ? 2 : (nch <= 4 ? 4 : 8)); }
+
+// The NCH chunks of table row `row` (scalar loads when row is wave-uniform).
+// Chunks at or beyond nch = W8/8 read as padding.  The loads themselves read
+// NCH*8 entries from the row start, which stays inside the packed table: its
+// second (interleaved) half of dim*W8 entries follows the row-major half and
+// NCH*8 - W8 < W8.
+template <int NCH>
+__device__ __forceinline__ void row_chunks(const uint16_t *__restrict__ tab, int row, int W8, int nch,
+                                           uint4 (&q)[NCH]) {
+    const uint4 *p = reinterpret_cast<const uint4 *>(tab + (int64_t)row * W8);
+#pragma unroll
+    for (int k8 = 0; k8 < NCH; ++k8) {
+        const uint4 v = p[k8];
+        q[k8] = k8 < nch ? v : make_uint4(~0u, ~0u, ~0u, ~0u);
+    }
+}
+
+// One row of the up part with NL live chunks: every gather of the row is
+// issued, then the previous row's result is stored (so the store does not
+// sit ahead of these gathers in the in-order memory counter, and its data
+// register is not reused while it is in flight), then the row is summed.
+template <typename T, int NL, int NCH>
+__device__ __forceinline__ void up_row(const T *__restrict__ xs, unsigned cc, int Ddn, const uint4 (&q)[NCH], T t,
+                                       T &pend, T *&pend_ptr, T *row_out) {
+    T v[NL > 0 ? NL : 1][8];
+#pragma unroll
+    for (int k8 = 0; k8 < NL; ++k8)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const unsigned e = entry(q[k8], k);
+            // wave-uniform row base, 32-bit lane offset
+            const T *xr = xs + (int64_t)(e != 0xFFFFu ? (e >> 1) : 0u) * Ddn;
+            v[k8][k] = xr[cc];
+        }
+    if (pend_ptr) __builtin_nontemporal_store(pend, pend_ptr);
+    T acc0 = T(0), acc1 = T(0);
+#pragma unroll
+    for (int k8 = 0; k8 < NL; ++k8)
+#pragma unroll
+        for (int k = 0; k < 8; k += 2) {
+            const unsigned e0 = entry(q[k8], k), e1 = entry(q[k8], k + 1);
+            const T s0 = e0 == 0xFFFFu ? T(0) : ((e0 & 1u) ? T(-1) : T(1));
+            const T s1 = e1 == 0xFFFFu ? T(0) : ((e1 & 1u) ? T(-1) : T(1));
+            acc0 += s0 * v[k8][k];
+            acc1 += s1 * v[k8][k + 1];
+        }
+    pend = t * (acc0 + acc1);
+    pend_ptr = row_out;
+}
+
+// Up part with 64-column stripes (one row per wave), all of a row's gathers
+// in flight at once.  The row's table chunks arrive by scalar loads, fetched
+// one row ahead; the number of live chunks (the columns in a row ascend, so
+// padding is a suffix) selects straight-line code that issues every gather
+// of the row before the first is consumed.  Padding inside the last live
+// chunk re-reads x[0, c] and is multiplied by zero.
+template <typename T, int NCH>
+__device__ __forceinline__ void up_tile_wide(const T *__restrict__ x, T *__restrict__ out,
+                                             const uint16_t *__restrict__ tab, int Dup, int Ddn, int W8, int rc,
+                                             int s, int rci, T t) {
+    const int lane = threadIdx.x & 63, nwave = blockDim.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int c = s * 64 + lane;
+    const bool cok = c < Ddn;
+    const T *xs = x + s * 64;
+    const unsigned cc = cok ? (unsigned)lane : 0u;
+    const int r1 = min(Dup, (rci + 1) * rc);
+    const int nch = W8 >> 3;
+    int rb = rci * rc + wave;
+    if (rb >= r1) return;
+    uint4 q[NCH];
+    row_chunks<NCH>(tab, rb, W8, nch, q);
+    T pend = T(0);
+    T *pend_ptr = nullptr;
+    for (; rb < r1; rb += nwave) {
+        int nl = 0;
+#pragma unroll
+        for (int k8 = 0; k8 < NCH; ++k8) nl += entry(q[k8], 0) != 0xFFFFu ? 1 : 0;
+        uint4 qn[NCH];
+        row_chunks<NCH>(tab, min(rb + nwave, r1 - 1), W8, nch, qn);
+        T *row_out = cok ? out + (int64_t)rb * Ddn + c : nullptr;
+        switch (nl) {
+        case 0: up_row<T, 0, NCH>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
+        case 1: up_row<T, 1, NCH>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
+        case 2: if constexpr (NCH >= 2) up_row<T, 2, NCH>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
+        case 3: if constexpr (NCH >= 4) up_row<T, 3, NCH>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
+        case 4: if constexpr (NCH >= 4) up_row<T, 4, NCH>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
+        case 5: if constexpr (NCH >= 8) up_row<T, 5, NCH>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
+        case 6: if constexpr (NCH >= 8) up_row<T, 6, NCH>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
+        case 7: if constexpr (NCH >= 8) up_row<T, 7, NCH>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
+        default: if constexpr (NCH >= 8) up_row<T, 8, NCH>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
+        }
+#pragma unroll
+        for (int k8 = 0; k8 < NCH; ++k8) q[k8] = qn[k8];
+    }
+    if (pend_ptr) __builtin_nontemporal_store(pend, pend_ptr);
+}
+
+// Chunk k8 of column c in the 8-interleaved table; chunks at or beyond nch
+// read as padding.  The load always goes to a valid table address and the
+// value is selected afterwards: selecting between the table's address and a
+// constant's would make the address space unknown and turn the 16-byte load
+// into flat dword loads.
+__device__ __forceinline__ uint4 table_chunk(const uint4 *__restrict__ til, int k8, int nch, int Ddn, int c) {
+    const uint4 v = til[(int64_t)(k8 < nch ? k8 : 0) * Ddn + c];
+    return k8 < nch ? v : make_uint4(~0u, ~0u, ~0u, ~0u);
+}
+
 // ---------------------------------------------------------------------------
 // Down part (Eq. 5) on a block of rows:
 //   q[r, c] = sig * (io[r, c] + t * sum_k sgn_k x[r, J_dn[c,k]] + U*Docc[r,c]*x[r,c])
@@ -144,7 +255,6 @@ __device__ __forceinline__ void down_rows(const T *__restrict__ xrows, T *__rest
                                           double (&s)[MODE == 2 ? 5 : 1]) {
     const uint4 *til = reinterpret_cast<const uint4 *>(tab + (int64_t)Ddn * W8);   // 8-interleaved part
     const int nch = W8 >> 3;
-    const uint4 kPad4 = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
     const int n = nr * Ddn;
     int i = threadIdx.x;
     uint4 tq[NCH];
@@ -153,7 +263,7 @@ __device__ __forceinline__ void down_rows(const T *__restrict__ xrows, T *__rest
     if (i < n) {
         if (multi_row) { rr = i / Ddn; c = i - rr * Ddn; } else { c = i; }
 #pragma unroll
-        for (int k8 = 0; k8 < NCH; ++k8) tq[k8] = k8 < nch ? til[(int64_t)k8 * Ddn + c] : kPad4;
+        for (int k8 = 0; k8 < NCH; ++k8) tq[k8] = table_chunk(til, k8, nch, Ddn, c);
         iov = io[base + i];
         if (use_p) pv = p[base + i];
     }
@@ -166,7 +276,7 @@ __device__ __forceinline__ void down_rows(const T *__restrict__ xrows, T *__rest
         if (in < n) {
             if (multi_row) { rrn = in / Ddn; cn = in - rrn * Ddn; } else { cn = in; }
 #pragma unroll
-            for (int k8 = 0; k8 < NCH; ++k8) tqn[k8] = k8 < nch ? til[(int64_t)k8 * Ddn + cn] : kPad4;
+            for (int k8 = 0; k8 < NCH; ++k8) tqn[k8] = table_chunk(til, k8, nch, Ddn, cn);
             iovn = io[base + in];
             if (use_p) pvn = p[base + in];
         }

@@ -102,7 +102,7 @@ __device__ __forceinline__ bool frozen(const Hdr *hdr, int max_steps) {
     return hdr->status != 0 || hdr->jdev >= max_steps;
 }
 
-template <typename T, int R>
+template <typename T, int R, int NCH>
 __global__ __launch_bounds__(512) void k_up(const T *__restrict__ x, T *__restrict__ out,
                                             const uint16_t *__restrict__ tab, int Dup, int Ddn, int W8, int rc,
                                             int n_stripes, int n_rc, int map, T t, const Hdr *__restrict__ hdr,
@@ -119,14 +119,17 @@ __global__ __launch_bounds__(512) void k_up(const T *__restrict__ x, T *__restri
         rci = blockIdx.x - s * n_rc;
     }
     if (s >= n_stripes) return;
-    up_tile<T, R>(x, out, tab, Dup, Ddn, W8, rc, s, rci, t);
+    if constexpr (R == 1)
+        up_tile_wide<T, NCH>(x, out, tab, Dup, Ddn, W8, rc, s, rci, t);
+    else
+        up_tile<T, R>(x, out, tab, Dup, Ddn, W8, rc, s, rci, t);
 }
 
 // k_up_q, persistent mapping (map 2): one queue per XCD holding the tiles of
 // the stripes s = q (mod 8).  A workgroup reads the XCD it runs on from the
 // XCC_ID hardware register, drains that XCD's queue (integer atomics), then
 // helps the other queues, so every tile is processed whatever the dispatch.
-template <typename T, int R>
+template <typename T, int R, int NCH>
 __global__ __launch_bounds__(512) void k_up_q(const T *__restrict__ x, T *__restrict__ out,
                                               const uint16_t *__restrict__ tab, int Dup, int Ddn, int W8, int rc,
                                               int n_stripes, int n_rc, T t, int *__restrict__ ctr,
@@ -144,7 +147,10 @@ __global__ __launch_bounds__(512) void k_up_q(const T *__restrict__ x, T *__rest
             __syncthreads();
             if (tq >= ntiles) break;
             const int sl = tq / n_rc;
-            up_tile<T, R>(x, out, tab, Dup, Ddn, W8, rc, q + 8 * sl, tq - sl * n_rc, t);
+            if constexpr (R == 1)
+                up_tile_wide<T, NCH>(x, out, tab, Dup, Ddn, W8, rc, q + 8 * sl, tq - sl * n_rc, t);
+            else
+                up_tile<T, R>(x, out, tab, Dup, Ddn, W8, rc, q + 8 * sl, tq - sl * n_rc, t);
         }
     }
 }
@@ -368,6 +374,7 @@ static int grid_for(int64_t n, int block, int cap = 4096) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
 }
 
+template <typename T, int R, int NCH>
 static int up_queue_grid(int block) {
     static int cached = 0;
     if (cached) return cached;
@@ -375,14 +382,14 @@ static int up_queue_grid(int block) {
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void *>(k_up_q<double, 1>), block,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void *>(k_up_q<T, R, NCH>), block,
                                                      0) != hipSuccess)
         return 0;
     cached = std::max(1, ncu * std::max(1, occ));
     return cached;
 }
 
-template <typename T, int R>
+template <typename T, int R, int NCH>
 static int launch_up_r(const ed_ham *h, const Tile &tl, const T *x, T *out, int *ctr, const Hdr *hdr, int gate,
                        int max_steps, hipStream_t s) {
     constexpr int w = 64 / R;
@@ -392,19 +399,19 @@ static int launch_up_r(const ed_ham *h, const Tile &tl, const T *x, T *out, int 
     if (tl.up_map == 2) {
         if (!ctr) return set_error(ED_EINVAL, "k_up_q needs the workspace");
         const int total = n_stripes * n_rc;
-        int grid = up_queue_grid(tl.up_block);
+        int grid = up_queue_grid<T, R, NCH>(tl.up_block);
         if (grid <= 0) return set_error(ED_EDEVICE, "occupancy query for k_up_q failed");
         grid = std::min(grid, total);
         hipLaunchKernelGGL(k_ctr_reset, dim3(1), dim3(64), 0, s, ctr, hdr, gate, max_steps);
         ED_LAUNCHED("k_ctr_reset");
-        hipLaunchKernelGGL((k_up_q<T, R>), dim3(grid), dim3(tl.up_block), 0, s, x, out, h->tab_up, (int)h->dim_up,
+        hipLaunchKernelGGL((k_up_q<T, R, NCH>), dim3(grid), dim3(tl.up_block), 0, s, x, out, h->tab_up, (int)h->dim_up,
                            (int)h->dim_dn, h->w_up, tl.up_rc, n_stripes, n_rc, t, ctr, hdr, gate, max_steps);
         ED_LAUNCHED("k_up_q");
         return ED_OK;
     }
     const int64_t grid = tl.up_map == 0 ? 8LL * n_rc * ((n_stripes + 7) / 8) : (int64_t)n_rc * n_stripes;
     if (grid > 0x7fffffffLL) return set_error(ED_EOVERFLOW, "k_up grid too large");
-    hipLaunchKernelGGL((k_up<T, R>), dim3((unsigned)grid), dim3(tl.up_block), 0, s, x, out, h->tab_up,
+    hipLaunchKernelGGL((k_up<T, R, NCH>), dim3((unsigned)grid), dim3(tl.up_block), 0, s, x, out, h->tab_up,
                        (int)h->dim_up, (int)h->dim_dn, h->w_up, tl.up_rc, n_stripes, n_rc, tl.up_map, t, hdr, gate,
                        max_steps);
     ED_LAUNCHED("k_up");
@@ -421,9 +428,15 @@ static int launch_up(const ed_ham *h, const Tile &tl, const T *x, T *out, int *c
         return ED_OK;
     }
     switch (tl.up_wlog2) {
-    case 6: return launch_up_r<T, 1>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
-    case 5: return launch_up_r<T, 2>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
-    default: return launch_up_r<T, 4>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
+    case 6:
+        switch (nch_class(h->w_up >> 3)) {
+        case 1: return launch_up_r<T, 1, 1>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
+        case 2: return launch_up_r<T, 1, 2>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
+        case 4: return launch_up_r<T, 1, 4>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
+        default: return launch_up_r<T, 1, 8>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
+        }
+    case 5: return launch_up_r<T, 2, 1>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
+    default: return launch_up_r<T, 4, 1>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
     }
 }
 
