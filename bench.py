@@ -79,13 +79,17 @@ def time_run(h, x, warmup, steps, n_kernel_samples):
     return ms, dict(zip(KERNELS, per.tolist())), st
 
 
+# the step kernels' sources: the traffic record is valid only for these exact bytes
+TRAFFIC_SOURCES = ("ed_device.hip", "ed_common.cuh")
+
+
 def measured_traffic(dtype, kernel, workload_name):
     """HBM bytes per launch from the committed counter record, if it matches this kernel source."""
     import hashlib
     here = os.path.join(ROOT, "paper_1511_00863_amd")
     try:
         rec = json.load(open(os.path.join(here, "measured_traffic.json")))
-        src = open(os.path.join(here, "csrc", "ed_device.hip"), "rb").read()
+        src = b"".join(open(os.path.join(here, "csrc", f), "rb").read() for f in TRAFFIC_SOURCES)
     except OSError:
         return None
     if hashlib.sha256(src).hexdigest()[:16] != rec.get("source_sha256_prefix") or rec.get("workload") != workload_name:
