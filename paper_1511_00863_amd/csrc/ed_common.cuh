@@ -201,7 +201,10 @@ __device__ __forceinline__ void up_tile_wide(const T *__restrict__ x, T *__restr
 // value is selected afterwards: selecting between the table's address and a
 // constant's would make the address space unknown and turn the 16-byte load
 // into flat dword loads.
+// A species without hopping (nch = 0) may pass no table at all: then nothing
+// is loaded (nch is uniform, so this is a scalar branch, not a select).
 __device__ __forceinline__ uint4 table_chunk(const uint4 *__restrict__ til, int k8, int nch, int Ddn, int c) {
+    if (nch == 0) return make_uint4(~0u, ~0u, ~0u, ~0u);
     const uint4 v = til[(int64_t)(k8 < nch ? k8 : 0) * Ddn + c];
     return k8 < nch ? v : make_uint4(~0u, ~0u, ~0u, ~0u);
 }

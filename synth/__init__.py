@@ -7,7 +7,7 @@ Both the oracle (``oracle/``) and the device path read their inputs from here
 and from nowhere else, so neither side can feed the other.
 """
 
-from .lattice import ring_bonds, torus_bonds, two_site_bonds, site_index
+from .lattice import ring_bonds, torus_bonds, two_site_bonds, complete_bonds, site_index
 from .draws import (
     start_vector,
     batch_instances,
@@ -18,7 +18,7 @@ from .draws import (
 from .workloads import WORKLOADS, Workload, workload
 
 __all__ = [
-    "ring_bonds", "torus_bonds", "two_site_bonds", "site_index",
+    "ring_bonds", "torus_bonds", "two_site_bonds", "complete_bonds", "site_index",
     "start_vector", "batch_instances", "mlp_init", "minibatch_uniforms", "MLP_SIZES",
     "WORKLOADS", "Workload", "workload",
 ]

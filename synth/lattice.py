@@ -47,3 +47,10 @@ def torus_bonds(lx: int, ly: int) -> List[Bond]:
 def two_site_bonds() -> List[Bond]:
     """The two-site system with its single bond (0, 1)."""
     return [(0, 1)]
+
+
+def complete_bonds(n_sites: int) -> List[Bond]:
+    """Every pair of sites bonded (all-to-all hopping).  Not a lattice of the
+    paper: it gives the widest hopping tables at a small dimension (a state
+    with N particles has N * (n_sites - N) hops), for edge-case tests."""
+    return [(i, j) for i in range(n_sites) for j in range(i + 1, n_sites)]

@@ -5,7 +5,7 @@ import pytest
 import torch
 
 from oracle.hamiltonian import Model
-from synth import ring_bonds, torus_bonds, two_site_bonds
+from synth import complete_bonds, ring_bonds, torus_bonds, two_site_bonds
 from tests.gpu_util import announce, ham, seeded_start
 
 pytestmark = pytest.mark.gpu
@@ -22,6 +22,10 @@ SMALL = [
     ("t44_2x4_U1.5", 16, torus_bonds(4, 4), 2, 4, 1.0, 1.5),
     ("t44_4x1_U8", 16, torus_bonds(4, 4), 4, 1, 1.0, 8.0),
     ("ring12_6x5", 12, ring_bonds(12), 6, 5, 1.0, 2.0),
+    # all-to-all hopping: the widest tables (36 hops -> stride 40; 64 hops = the largest stride accepted)
+    ("complete12_6x6", 12, complete_bonds(12), 6, 6, 1.0, 2.5),
+    ("complete16_8x1_maxwidth_up", 16, complete_bonds(16), 8, 1, 1.0, 3.0),
+    ("complete16_1x8_maxwidth_dn", 16, complete_bonds(16), 1, 8, 0.6, 3.0),
 ]
 
 

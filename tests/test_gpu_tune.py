@@ -5,7 +5,7 @@ import pytest
 import torch
 
 import paper_1511_00863_amd as ed
-from synth import ring_bonds, torus_bonds
+from synth import complete_bonds, ring_bonds, torus_bonds
 from tests.gpu_util import announce, ham, seeded_start
 
 pytestmark = pytest.mark.gpu
@@ -13,7 +13,7 @@ pytestmark = pytest.mark.gpu
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("ns,bonds,nu,nd", [(16, torus_bonds(4, 4), 4, 4), (16, torus_bonds(4, 4), 3, 5),
-                                            (8, ring_bonds(8), 4, 4)])
+                                            (8, ring_bonds(8), 4, 4), (12, complete_bonds(12), 6, 6)])
 def test_every_tile_gives_identical_hv(ns, bonds, nu, nd, dtype):
     h = ham(ns, bonds, nu, nd, 1.0, 3.0, dtype)
     _, x = seeded_start(21, h.dim, dtype)

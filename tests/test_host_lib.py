@@ -171,3 +171,39 @@ def test_tridiag_near_degenerate_vector():
 def test_tridiag_rejects_nan():
     with pytest.raises(ed.EdError):
         ed.tridiag_lowest([1.0, np.nan], [0.5])
+
+
+def test_device_calls_validate_before_touching_the_device():
+    """Bad descriptors are rejected on the host with the documented codes (no GPU needed)."""
+    import ctypes
+    lib = ed.lib()
+    dummy = ctypes.c_void_p(4096)   # never dereferenced: every case fails validation first
+
+    def ham(**kw):
+        f = dict(dim_up=70, dim_dn=70, w_up=8, w_dn=8, tab_up=dummy, tab_dn=dummy, st_up=dummy, st_dn=dummy,
+                 t=1.0, U=4.0, dtype=0, tile=0)
+        f.update(kw)
+        return _ffi.EdHam(**f)
+
+    nbytes = ctypes.c_int64(0)
+    assert lib.ed_workspace_size(ctypes.byref(ham()), 10, ctypes.byref(nbytes)) == 0 and nbytes.value > 0
+    cases = [
+        (dict(dim_up=40000), -3),            # per-spin dimension above 15-bit ranks
+        (dict(dim_dn=0), -1),
+        (dict(w_up=12), -1),                 # stride not a multiple of 8
+        (dict(w_dn=72), -3),                 # stride above 64
+        (dict(w_up=8, tab_up=None), -1),     # hopping without a table
+        (dict(st_dn=None), -1),
+        (dict(dtype=7), -1),
+        (dict(tile=0x7FFF0000), -1),
+        (dict(U=float("nan")), -1),
+        (dict(t=float("inf")), -1),
+    ]
+    for kw, code in cases:
+        h = ham(**kw)
+        assert lib.ed_workspace_size(ctypes.byref(h), 10, ctypes.byref(nbytes)) == code, kw
+        assert lib.ed_hv(ctypes.byref(h), dummy, ctypes.c_void_p(8192), dummy, None) == code, kw
+        assert lib.ed_last_error().decode()
+    # a species without hopping may pass no table
+    h = ham(w_dn=0, tab_dn=None)
+    assert lib.ed_workspace_size(ctypes.byref(h), 10, ctypes.byref(nbytes)) == 0

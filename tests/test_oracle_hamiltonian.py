@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from oracle.hamiltonian import Model
-from synth import ring_bonds, start_vector, torus_bonds, two_site_bonds
+from synth import complete_bonds, ring_bonds, start_vector, torus_bonds, two_site_bonds
 
 
 def _e0_dense(m):
@@ -85,3 +85,14 @@ def test_unit_vector_columns():
         e = np.zeros(m.dim)
         e[k] = 1.0
         assert np.array_equal(m.hv(e), h[:, k])
+
+
+@pytest.mark.parametrize("n,nu,nd", [(6, 3, 3), (7, 2, 3), (7, 4, 1), (5, 2, 0)])
+def test_u0_band_sum_complete_graph(n, nu, nd):
+    # all-to-all hopping -t sum_{i<j} (c+_i c_j + h.c.): one-particle levels -t(n-1) once and +t (n-1 times),
+    # so N fermions of one species have E = -t(n-1) + (N-1) t.  Most bonds join non-adjacent indices,
+    # so every fermion sign of the tables enters; a table without them gives other levels.
+    t = 0.9
+    m = Model(n, complete_bonds(n), nu, nd, t, 0.0)
+    band = lambda N: 0.0 if N == 0 else -t * (n - 1) + (N - 1) * t
+    assert abs(_e0_dense(m) - (band(nu) + band(nd))) < 1e-10
