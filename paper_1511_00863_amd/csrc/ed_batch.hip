@@ -345,9 +345,14 @@ __global__ __launch_bounds__(kBatchBlock, 4) void k_batch(BInst *__restrict__ in
                 const bool has_prev = I.j > 0;
                 const float sig = (float)I.sig_cur;
                 const float cprev = (float)(I.b[I.j] * I.sig_prev);
-                down_rows<float, 2, 4>(xs, io, p, (const uint16_t *)I.tab_dn, (const uint64_t *)I.st_up + r0,
-                                       (const uint64_t *)I.st_dn, I.Ddn, I.W8d, nr, base,
-                                       I.rpb > 1, (float)I.t, (float)I.U, sig, cprev, has_prev, s);
+                if (I.W8d == 0)   // the down species cannot hop: no table to read
+                    down_rows<float, 2, 0>(xs, io, p, (const uint16_t *)I.tab_dn, (const uint64_t *)I.st_up + r0,
+                                           (const uint64_t *)I.st_dn, I.Ddn, I.W8d, nr, base,
+                                           I.rpb > 1, (float)I.t, (float)I.U, sig, cprev, has_prev, s);
+                else
+                    down_rows<float, 2, 4>(xs, io, p, (const uint16_t *)I.tab_dn, (const uint64_t *)I.st_up + r0,
+                                           (const uint64_t *)I.st_dn, I.Ddn, I.W8d, nr, base,
+                                           I.rpb > 1, (float)I.t, (float)I.U, sig, cprev, has_prev, s);
                 double tot[5];
                 block_sum<5>(s, tot);
                 if (threadIdx.x == 0)

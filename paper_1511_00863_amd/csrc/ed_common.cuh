@@ -41,6 +41,12 @@ __device__ __forceinline__ unsigned entry(const uint4 &q, int k) {
     return (k & 1) ? (w >> 16) : (w & 0xFFFFu);
 }
 
+// One rounding per term: every up-part kernel adds a row's terms as
+// acc = fma(sign, x, acc) in ascending column order, so all of them (every
+// tile, the batched launch) produce the same bits.
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 // Up part (Eq. 4) on one tile = (column stripe s of width w = 64/R, row chunk rci):
 // out[r, c] = t * sum_k sgn_k * x[J_up[r,k], c].  A wave serves R consecutive
 // rows x w columns; the row index is wave-uniform, so each row's table chunks
@@ -63,7 +69,7 @@ __device__ __forceinline__ void up_tile(const T *__restrict__ x, T *__restrict__
     const int nch = W8 >> 3;
     for (int rb = rci * rc + wave * R; rb < r1; rb += nwave * R) {
         const int r = rb + sub;
-        T acc0 = T(0), acc1 = T(0);
+        T acc = T(0);
         for (int k8 = 0; k8 < nch; ++k8) {
             uint4 q[R];
             bool any = false;
@@ -86,12 +92,9 @@ __device__ __forceinline__ void up_tile(const T *__restrict__ x, T *__restrict__
                 v[k] = xc[(int64_t)(pk ? (e >> 1) : 0u) * Ddn];
             }
 #pragma unroll
-            for (int k = 0; k < 8; k += 2) {
-                acc0 += sg[k] * v[k];
-                acc1 += sg[k + 1] * v[k + 1];
-            }
+            for (int k = 0; k < 8; ++k) acc = fma_t(sg[k], v[k], acc);
         }
-        if (cok && r < r1) __builtin_nontemporal_store(t * (acc0 + acc1), out + (int64_t)r * Ddn + c);
+        if (cok && r < r1) __builtin_nontemporal_store(t * acc, out + (int64_t)r * Ddn + c);
     }
 }
 
@@ -133,18 +136,16 @@ __device__ __forceinline__ void up_row(const T *__restrict__ xs, unsigned cc, in
             v[k8][k] = xr[cc];
         }
     if (pend_ptr) __builtin_nontemporal_store(pend, pend_ptr);
-    T acc0 = T(0), acc1 = T(0);
+    T acc = T(0);
 #pragma unroll
     for (int k8 = 0; k8 < NL; ++k8)
 #pragma unroll
-        for (int k = 0; k < 8; k += 2) {
-            const unsigned e0 = entry(q[k8], k), e1 = entry(q[k8], k + 1);
-            const T s0 = e0 == 0xFFFFu ? T(0) : ((e0 & 1u) ? T(-1) : T(1));
-            const T s1 = e1 == 0xFFFFu ? T(0) : ((e1 & 1u) ? T(-1) : T(1));
-            acc0 += s0 * v[k8][k];
-            acc1 += s1 * v[k8][k + 1];
+        for (int k = 0; k < 8; ++k) {
+            const unsigned e = entry(q[k8], k);
+            const T sg = e == 0xFFFFu ? T(0) : ((e & 1u) ? T(-1) : T(1));
+            acc = fma_t(sg, v[k8][k], acc);
         }
-    pend = t * (acc0 + acc1);
+    pend = t * acc;
     pend_ptr = row_out;
 }
 
@@ -197,16 +198,31 @@ __device__ __forceinline__ void up_tile_wide(const T *__restrict__ x, T *__restr
 }
 
 // Chunk k8 of column c in the 8-interleaved table; chunks at or beyond nch
-// read as padding.  The load always goes to a valid table address and the
-// value is selected afterwards: selecting between the table's address and a
-// constant's would make the address space unknown and turn the 16-byte load
-// into flat dword loads.
-// A species without hopping (nch = 0) may pass no table at all: then nothing
-// is loaded (nch is uniform, so this is a scalar branch, not a select).
+// read as padding.  The load always goes to a valid table address (nch >= 1
+// in every variant with NCH >= 1) and the value is selected afterwards:
+// selecting between the table's address and a constant's would make the
+// address space unknown and turn the 16-byte load into flat dword loads, and
+// a branch around the load would make the wait counts inexact.  NCH = 0 is the
+// variant for a species without hopping, which may pass no table at all.
+template <int NCH>
 __device__ __forceinline__ uint4 table_chunk(const uint4 *__restrict__ til, int k8, int nch, int Ddn, int c) {
-    if (nch == 0) return make_uint4(~0u, ~0u, ~0u, ~0u);
-    const uint4 v = til[(int64_t)(k8 < nch ? k8 : 0) * Ddn + c];
-    return k8 < nch ? v : make_uint4(~0u, ~0u, ~0u, ~0u);
+    if constexpr (NCH == 0) {
+        return make_uint4(~0u, ~0u, ~0u, ~0u);
+    } else {
+        // padding is all ones: OR it in, so the load is always consumed and
+        // the compiler cannot sink it into a branch
+        const unsigned m = k8 < nch ? 0u : ~0u;
+        const uint4 v = til[(int64_t)(k8 < nch ? k8 : 0) * Ddn + c];
+        return make_uint4(v.x | m, v.y | m, v.z | m, v.w | m);
+    }
+}
+
+// v if keep, else +0, without a branch (the loaded value is always consumed)
+__device__ __forceinline__ double keep_or_zero(double v, bool keep) {
+    return __longlong_as_double(__double_as_longlong(v) & (keep ? ~0ll : 0ll));
+}
+__device__ __forceinline__ float keep_or_zero(float v, bool keep) {
+    return __int_as_float(__float_as_int(v) & (keep ? ~0 : 0));
 }
 
 // ---------------------------------------------------------------------------
@@ -259,30 +275,38 @@ __device__ __forceinline__ void down_rows(const T *__restrict__ xrows, T *__rest
     const uint4 *til = reinterpret_cast<const uint4 *>(tab + (int64_t)Ddn * W8);   // 8-interleaved part
     const int nch = W8 >> 3;
     const int n = nr * Ddn;
+    // Every global operand of a column (table chunks, up part, f_{j-1}, the
+    // down state) is fetched one column ahead, so that the wait for the
+    // current column's operands (memory counters complete in issue order)
+    // never includes the next column's.
+    // The loads are unconditional (the last column's prefetch re-reads a valid
+    // element; f_{j-1} is read whenever a Lanczos step has one and zeroed when
+    // it is not used) so that the wait count is exact on every path.
     int i = threadIdx.x;
-    uint4 tq[NCH];
-    T iov = T(0), pv = T(0);
-    int c = 0, rr = 0;
-    if (i < n) {
-        if (multi_row) { rr = i / Ddn; c = i - rr * Ddn; } else { c = i; }
+    if (i >= n) return;
+    uint4 tq[NCH > 0 ? NCH : 1];
+    T iov, pv;
+    uint64_t sdv, suv;
+    int c, rr;
+    if (multi_row) { rr = i / Ddn; c = i - rr * Ddn; } else { rr = 0; c = i; }
 #pragma unroll
-        for (int k8 = 0; k8 < NCH; ++k8) tq[k8] = table_chunk(til, k8, nch, Ddn, c);
-        iov = io[base + i];
-        if (use_p) pv = p[base + i];
-    }
+    for (int k8 = 0; k8 < NCH; ++k8) tq[k8] = table_chunk<NCH>(til, k8, nch, Ddn, c);
+    iov = io[base + i];
+    if constexpr (MODE != 0) pv = keep_or_zero(p[base + i], use_p); else pv = T(0);
+    sdv = st_dn[c];
+    suv = st_up_r0[rr];
     for (; i < n; i += blockDim.x) {
-        // prefetch the next column of this thread
-        const int in = i + blockDim.x;
-        int cn = 0, rrn = 0;
-        uint4 tqn[NCH];
-        T iovn = T(0), pvn = T(0);
-        if (in < n) {
-            if (multi_row) { rrn = in / Ddn; cn = in - rrn * Ddn; } else { cn = in; }
+        const int in = min(i + (int)blockDim.x, n - 1);
+        int cn, rrn;
+        if (multi_row) { rrn = in / Ddn; cn = in - rrn * Ddn; } else { rrn = 0; cn = in; }
+        uint4 tqn[NCH > 0 ? NCH : 1];
 #pragma unroll
-            for (int k8 = 0; k8 < NCH; ++k8) tqn[k8] = table_chunk(til, k8, nch, Ddn, cn);
-            iovn = io[base + in];
-            if (use_p) pvn = p[base + in];
-        }
+        for (int k8 = 0; k8 < NCH; ++k8) tqn[k8] = table_chunk<NCH>(til, k8, nch, Ddn, cn);
+        const T iovn = io[base + in];
+        T pvn;
+        if constexpr (MODE != 0) pvn = keep_or_zero(p[base + in], use_p); else pvn = T(0);
+        const uint64_t sdn = st_dn[cn];
+        const uint64_t sun = st_up_r0[rrn];
         const T *xrow = xrows + (int64_t)rr * Ddn;
         T acc0 = T(0), acc1 = T(0);
 #pragma unroll
@@ -306,7 +330,7 @@ __device__ __forceinline__ void down_rows(const T *__restrict__ xrows, T *__rest
             }
         }
         const T xv = xrow[c];
-        const T nd = static_cast<T>(__popcll(st_up_r0[rr] & st_dn[c]));
+        const T nd = static_cast<T>(__popcll(suv & sdv));
         T q = iov + t * (acc0 + acc1) + U * nd * xv;
         if (MODE != 0) {
             q *= sig;
@@ -328,6 +352,8 @@ __device__ __forceinline__ void down_rows(const T *__restrict__ xrows, T *__rest
         rr = rrn;
         iov = iovn;
         pv = pvn;
+        sdv = sdn;
+        suv = sun;
 #pragma unroll
         for (int k8 = 0; k8 < NCH; ++k8) tq[k8] = tqn[k8];
     }

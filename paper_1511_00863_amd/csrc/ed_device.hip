@@ -458,7 +458,9 @@ static int launch_down(const ed_ham *h, const Tile &tl, const T *x, T *io, const
     const int grid = (int)((h->dim_up + rpb - 1) / rpb);
     const size_t shm = lds ? (size_t)(row_bytes * rpb) : 0;
     const int nch = h->w_dn >> 3;
-    if (!lds) launch_down_k<T, MODE, false, 8>(h, tl, grid, 1, 0, x, io, p, bvec, hdr, part, max_steps, s);
+    if (!lds && nch == 0) launch_down_k<T, MODE, false, 0>(h, tl, grid, 1, 0, x, io, p, bvec, hdr, part, max_steps, s);
+    else if (!lds) launch_down_k<T, MODE, false, 8>(h, tl, grid, 1, 0, x, io, p, bvec, hdr, part, max_steps, s);
+    else if (nch == 0) launch_down_k<T, MODE, true, 0>(h, tl, grid, rpb, shm, x, io, p, bvec, hdr, part, max_steps, s);
     else if (nch <= 2) launch_down_k<T, MODE, true, 2>(h, tl, grid, rpb, shm, x, io, p, bvec, hdr, part, max_steps, s);
     else if (nch <= 4) launch_down_k<T, MODE, true, 4>(h, tl, grid, rpb, shm, x, io, p, bvec, hdr, part, max_steps, s);
     else launch_down_k<T, MODE, true, 8>(h, tl, grid, rpb, shm, x, io, p, bvec, hdr, part, max_steps, s);
@@ -483,8 +485,9 @@ static hipError_t set_lds_attr() {
 
 template <typename T>
 static hipError_t set_lds_attrs_t() {
-    const hipError_t es[] = {set_lds_attr<T, 0, 2>(), set_lds_attr<T, 0, 4>(), set_lds_attr<T, 0, 8>(),
-                             set_lds_attr<T, 1, 2>(), set_lds_attr<T, 1, 4>(), set_lds_attr<T, 1, 8>(),
+    const hipError_t es[] = {set_lds_attr<T, 0, 0>(), set_lds_attr<T, 0, 2>(), set_lds_attr<T, 0, 4>(),
+                             set_lds_attr<T, 0, 8>(), set_lds_attr<T, 1, 0>(), set_lds_attr<T, 1, 2>(),
+                             set_lds_attr<T, 1, 4>(), set_lds_attr<T, 1, 8>(), set_lds_attr<T, 2, 0>(),
                              set_lds_attr<T, 2, 2>(), set_lds_attr<T, 2, 4>(), set_lds_attr<T, 2, 8>()};
     for (hipError_t e : es)
         if (e != hipSuccess) return e;
