@@ -345,14 +345,18 @@ __global__ __launch_bounds__(kBatchBlock, 4) void k_batch(BInst *__restrict__ in
                 const bool has_prev = I.j > 0;
                 const float sig = (float)I.sig_cur;
                 const float cprev = (float)(I.b[I.j] * I.sig_prev);
+                const uint16_t *tdn = (const uint16_t *)I.tab_dn;
+                const uint64_t *su = (const uint64_t *)I.st_up + r0, *sd = (const uint64_t *)I.st_dn;
+                const float tt = (float)I.t, uu = (float)I.U;
                 if (I.W8d == 0)   // the down species cannot hop: no table to read
-                    down_rows<float, 2, 0>(xs, io, p, (const uint16_t *)I.tab_dn, (const uint64_t *)I.st_up + r0,
-                                           (const uint64_t *)I.st_dn, I.Ddn, I.W8d, nr, base,
-                                           I.rpb > 1, (float)I.t, (float)I.U, sig, cprev, has_prev, s);
+                    down_rows<float, 2, 0, true>(xs, io, p, tdn, su, sd, I.Ddn, I.W8d, nr, base, tt, uu, sig, cprev,
+                                                 has_prev, s);
+                else if (I.rpb > 1)
+                    down_rows<float, 2, 4, true>(xs, io, p, tdn, su, sd, I.Ddn, I.W8d, nr, base, tt, uu, sig, cprev,
+                                                 has_prev, s);
                 else
-                    down_rows<float, 2, 4>(xs, io, p, (const uint16_t *)I.tab_dn, (const uint64_t *)I.st_up + r0,
-                                           (const uint64_t *)I.st_dn, I.Ddn, I.W8d, nr, base,
-                                           I.rpb > 1, (float)I.t, (float)I.U, sig, cprev, has_prev, s);
+                    down_rows<float, 2, 4, false>(xs, io, p, tdn, su, sd, I.Ddn, I.W8d, nr, base, tt, uu, sig, cprev,
+                                                  has_prev, s);
                 double tot[5];
                 block_sum<5>(s, tot);
                 if (threadIdx.x == 0)

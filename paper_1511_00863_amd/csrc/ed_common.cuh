@@ -266,11 +266,11 @@ __device__ __forceinline__ void stage_rows(const T *__restrict__ src, T *__restr
 // down-part + U Docc x) - cprev * p, in place on io; per-thread partial sums
 // added to s[].  xrows: the rows (LDS copy or global); base: offset of row r0
 // in the global vectors.
-template <typename T, int MODE, int NCH>
+template <typename T, int MODE, int NCH, bool MULTI>
 __device__ __forceinline__ void down_rows(const T *__restrict__ xrows, T *__restrict__ io, const T *__restrict__ p,
                                           const uint16_t *__restrict__ tab, const uint64_t *__restrict__ st_up_r0,
                                           const uint64_t *__restrict__ st_dn, int Ddn, int W8, int nr,
-                                          int64_t base, bool multi_row, T t, T U, T sig, T cprev, bool use_p,
+                                          int64_t base, T t, T U, T sig, T cprev, bool use_p,
                                           double (&s)[MODE == 2 ? 5 : 1]) {
     const uint4 *til = reinterpret_cast<const uint4 *>(tab + (int64_t)Ddn * W8);   // 8-interleaved part
     const int nch = W8 >> 3;
@@ -282,23 +282,26 @@ __device__ __forceinline__ void down_rows(const T *__restrict__ xrows, T *__rest
     // The loads are unconditional (the last column's prefetch re-reads a valid
     // element; f_{j-1} is read whenever a Lanczos step has one and zeroed when
     // it is not used) so that the wait count is exact on every path.
+    // MULTI: the block holds several (short) rows and a thread's columns move
+    // between them; else one row, whose up state is a wave-uniform constant.
     int i = threadIdx.x;
     if (i >= n) return;
+    const uint64_t su0 = st_up_r0[0];
     uint4 tq[NCH > 0 ? NCH : 1];
     T iov, pv;
-    uint64_t sdv, suv;
+    uint64_t sdv, suv = su0;
     int c, rr;
-    if (multi_row) { rr = i / Ddn; c = i - rr * Ddn; } else { rr = 0; c = i; }
+    if constexpr (MULTI) { rr = i / Ddn; c = i - rr * Ddn; } else { rr = 0; c = i; }
 #pragma unroll
     for (int k8 = 0; k8 < NCH; ++k8) tq[k8] = table_chunk<NCH>(til, k8, nch, Ddn, c);
     iov = io[base + i];
     if constexpr (MODE != 0) pv = keep_or_zero(p[base + i], use_p); else pv = T(0);
     sdv = st_dn[c];
-    suv = st_up_r0[rr];
+    if constexpr (MULTI) suv = st_up_r0[rr];
     for (; i < n; i += blockDim.x) {
         const int in = min(i + (int)blockDim.x, n - 1);
         int cn, rrn;
-        if (multi_row) { rrn = in / Ddn; cn = in - rrn * Ddn; } else { rrn = 0; cn = in; }
+        if constexpr (MULTI) { rrn = in / Ddn; cn = in - rrn * Ddn; } else { rrn = 0; cn = in; }
         uint4 tqn[NCH > 0 ? NCH : 1];
 #pragma unroll
         for (int k8 = 0; k8 < NCH; ++k8) tqn[k8] = table_chunk<NCH>(til, k8, nch, Ddn, cn);
@@ -306,7 +309,8 @@ __device__ __forceinline__ void down_rows(const T *__restrict__ xrows, T *__rest
         T pvn;
         if constexpr (MODE != 0) pvn = keep_or_zero(p[base + in], use_p); else pvn = T(0);
         const uint64_t sdn = st_dn[cn];
-        const uint64_t sun = st_up_r0[rrn];
+        uint64_t sun = su0;
+        if constexpr (MULTI) sun = st_up_r0[rrn];
         const T *xrow = xrows + (int64_t)rr * Ddn;
         T acc0 = T(0), acc1 = T(0);
 #pragma unroll

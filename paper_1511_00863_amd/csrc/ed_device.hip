@@ -160,8 +160,11 @@ __global__ void k_ctr_reset(int *ctr, const Hdr *hdr, int gate, int max_steps) {
     if (threadIdx.x < 8) ctr[threadIdx.x] = 0;
 }
 
-template <typename T, int MODE, bool LDS, int NCH>
-__global__ __launch_bounds__(1024) void k_down(const T *__restrict__ x, T *__restrict__ io, const T *__restrict__ p,
+// float rows are half the size: three 512-thread workgroups fit a CU's LDS,
+// which needs at most 80 VGPRs (6 waves per SIMD)
+template <typename T, int MODE, bool LDS, int NCH, bool MULTI>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NCH <= 4 ? 6 : 1)))
+void k_down(const T *__restrict__ x, T *__restrict__ io, const T *__restrict__ p,
                                                const uint16_t *__restrict__ tab,
                                                const uint64_t *__restrict__ st_up,
                                                const uint64_t *__restrict__ st_dn, int Dup, int Ddn, int W8,
@@ -190,8 +193,8 @@ __global__ __launch_bounds__(1024) void k_down(const T *__restrict__ x, T *__res
     double s[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) s[k] = 0.0;
-    down_rows<T, MODE, NCH>(LDS ? xs : x + base, io, p, tab, st_up + r0, st_dn, Ddn, W8, nr, base, rpb > 1, t, U,
-                            sig, cprev, MODE != 0 && has_prev, s);
+    down_rows<T, MODE, NCH, MULTI>(LDS ? xs : x + base, io, p, tab, st_up + r0, st_dn, Ddn, W8, nr, base, t, U,
+                                   sig, cprev, MODE != 0 && has_prev, s);
     if (MODE != 0) {
         double tot[NV];
         block_sum<NV>(s, tot);
@@ -444,9 +447,14 @@ template <typename T, int MODE, bool LDS, int NCH>
 static void launch_down_k(const ed_ham *h, const Tile &tl, int grid, int rpb, size_t shm, const T *x, T *io,
                           const T *p, const double *bvec, const Hdr *hdr, double *part, int max_steps,
                           hipStream_t s) {
-    hipLaunchKernelGGL((k_down<T, MODE, LDS, NCH>), dim3(grid), dim3(tl.dn_block), shm, s, x, io, p, h->tab_dn,
-                       h->st_up, h->st_dn, (int)h->dim_up, (int)h->dim_dn, h->w_dn, rpb, static_cast<T>(h->t),
-                       static_cast<T>(h->U), bvec, hdr, part, max_steps);
+    if (rpb > 1)
+        hipLaunchKernelGGL((k_down<T, MODE, LDS, NCH, true>), dim3(grid), dim3(tl.dn_block), shm, s, x, io, p,
+                           h->tab_dn, h->st_up, h->st_dn, (int)h->dim_up, (int)h->dim_dn, h->w_dn, rpb,
+                           static_cast<T>(h->t), static_cast<T>(h->U), bvec, hdr, part, max_steps);
+    else
+        hipLaunchKernelGGL((k_down<T, MODE, LDS, NCH, false>), dim3(grid), dim3(tl.dn_block), shm, s, x, io, p,
+                           h->tab_dn, h->st_up, h->st_dn, (int)h->dim_up, (int)h->dim_dn, h->w_dn, rpb,
+                           static_cast<T>(h->t), static_cast<T>(h->U), bvec, hdr, part, max_steps);
 }
 
 template <typename T, int MODE>
@@ -479,7 +487,10 @@ static int down_grid(const ed_ham *h, const Tile &tl) {
 // outside any stream capture.
 template <typename T, int MODE, int NCH>
 static hipError_t set_lds_attr() {
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(k_down<T, MODE, true, NCH>),
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_down<T, MODE, true, NCH, false>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(k_down<T, MODE, true, NCH, true>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget);
 }
 
