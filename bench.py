@@ -201,7 +201,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="use the built-in default tile instead of ed_tune")
     ap.add_argument("--no-learned", action="store_true", help="skip the time-to-E0 comparison with the learned start")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batched run")
-    ap.add_argument("--train-iters", type=int, default=1500)
+    ap.add_argument("--train-iters", type=int, default=3000)
     ap.add_argument("--held-out", default="3.5", help="comma-separated held-out U values for time-to-E0")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

@@ -49,13 +49,13 @@ def training_data(up, dn, t, us, seed=100, dtype="f32", tol=1e-9, extra_steps=20
     return out
 
 
-def train_network(data, iters=1500, batch=4096, seed=7, init_seed=3, lr=1e-3):
+def train_network(data, iters=1500, batch=4096, seed=7, init_seed=3, lr=1e-3, lr_final=None):
     ws, bs = mlp_init(init_seed)
     net = mlp.StartVectorNet.from_init(ws, bs, batch=batch, device=data[0][1].device)
     uni = torch.from_numpy(minibatch_uniforms(seed, iters, batch)).to(data[0][1].device)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    losses = mlp.train(net, data, uni, iters, lr=lr)
+    losses = mlp.train(net, data, uni, iters, lr=lr, lr_final=lr_final)
     torch.cuda.synchronize()
     return net, losses, time.perf_counter() - t0
 

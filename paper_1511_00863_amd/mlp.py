@@ -125,17 +125,20 @@ def neel_index(ham, lx: int = 4, ly: int = 4) -> int:
     return iu * ham.dim_dn + idn
 
 
-def train(net, data, uniforms, iters, lr=1e-3, log_every=0):
+def train(net, data, uniforms, iters, lr=1e-3, lr_final=None, log_every=0):
     """Adam steps on minibatches cycling over the training ground states.
 
     data: list of (ham, psi, cdf) on the device; uniforms: device tensor
-    [iters, batch, 2] of seeded uniforms.  Returns the loss after each step (host)."""
+    [iters, batch, 2] of seeded uniforms.  lr_final: if given, the step size
+    decays geometrically from lr to lr_final over the run.  Returns the loss
+    after each step (host)."""
     losses = torch.empty(iters, dtype=torch.float64, device=net.device)
     for it in range(iters):
         ham, psi, cdf = data[it % len(data)]
         idx, tgt = sample(psi, ham, cdf, uniforms[it])
         net.forward(ham.up.dev_states, ham.dn.dev_states, idx)
         net.backward(tgt)
-        net.adam(lr)
+        step_lr = lr if lr_final is None else lr * (lr_final / lr) ** (it / max(1, iters - 1))
+        net.adam(step_lr)
         losses[it:it + 1].copy_(net.loss)
     return losses.cpu().numpy()
