@@ -26,7 +26,7 @@ namespace ed {
 #define ED_GLOBAL __attribute__((address_space(1)))
 
 constexpr int kBatchBlock = 256;
-constexpr int kBatchLds = 40 * 1024;        // four workgroups per CU
+constexpr int kBatchLds = 40 * 1024;        // rows of up to 10240 floats; three workgroups per CU
 constexpr int64_t kUpdChunk = 65536;         // elements per update tile
 constexpr int kConverged = 10;
 constexpr int kBadStart = 100;
@@ -35,7 +35,7 @@ constexpr unsigned long long kSpinLimit = 1ull << 24;   // about a second of s_s
 struct BInst {
     // set by the host
     int Dup, Ddn, W8u, W8d;
-    int R, rc, n_stripes, n_rc;
+    int R, V, rc, n_stripes, n_rc;   // rows and columns per lane of the up-part tile
     int up_tiles, rpb, dn_tiles, upd_tiles;
     int64_t n, part_off, part2_off;
     // global-memory pointers: typed so, the kernel's loads through pointers
@@ -184,7 +184,7 @@ __device__ double ritz_lowest_wave(const double *a, const double *boff, int m) {
     return 0.5 * (lo + hi);
 }
 
-__global__ __launch_bounds__(kBatchBlock, 4) void k_batch(BInst *__restrict__ inst, int ni, double *__restrict__ part,
+__global__ __launch_bounds__(kBatchBlock, 3) void k_batch(BInst *__restrict__ inst, int ni, double *__restrict__ part,
                                                        double *__restrict__ part2, GridBar *gb, int max_steps,
                                                        double tol) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -302,15 +302,19 @@ __global__ __launch_bounds__(kBatchBlock, 4) void k_batch(BInst *__restrict__ in
                 float *out = (float *)I.vec[(I.rot + 1) % 3];
                 const uint16_t *tab = (const uint16_t *)I.tab_up;
                 const float t = (float)I.t;
-                if (I.R == 1) {
+                if (I.V == 2) {   // the plan guarantees W8 <= 32 and an even row length
+                    switch (nch_class(I.W8u >> 3)) {
+                    case 1: up_tile_vec<float, 2, 1>(x, out, tab, I.Dup, I.Ddn, I.W8u, I.rc, s, rci, t); break;
+                    case 2: up_tile_vec<float, 2, 2>(x, out, tab, I.Dup, I.Ddn, I.W8u, I.rc, s, rci, t); break;
+                    default: up_tile_vec<float, 2, 4>(x, out, tab, I.Dup, I.Ddn, I.W8u, I.rc, s, rci, t); break;
+                    }
+                } else {
                     switch (nch_class(I.W8u >> 3)) {
                     case 1: up_tile_wide<float, 1>(x, out, tab, I.Dup, I.Ddn, I.W8u, I.rc, s, rci, t); break;
                     case 2: up_tile_wide<float, 2>(x, out, tab, I.Dup, I.Ddn, I.W8u, I.rc, s, rci, t); break;
                     case 4: up_tile_wide<float, 4>(x, out, tab, I.Dup, I.Ddn, I.W8u, I.rc, s, rci, t); break;
                     default: up_tile_wide<float, 8>(x, out, tab, I.Dup, I.Ddn, I.W8u, I.rc, s, rci, t); break;
                     }
-                } else {
-                    up_tile<float, 2>(x, out, tab, I.Dup, I.Ddn, I.W8u, I.rc, s, rci, t);
                 }
                 if (threadIdx.x == 0) s_tile = pre;
                 __syncthreads();
@@ -411,19 +415,54 @@ __global__ __launch_bounds__(kBatchBlock, 4) void k_batch(BInst *__restrict__ in
                 double s[1] = {0.0};
                 const int64_t B = blockDim.x;
                 int64_t k = lo + threadIdx.x;
-                for (; k + 3 * B < hi; k += 4 * B) {   // four independent elements in flight
-                    float xv[4], qv[4], pv[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        xv[u] = x[k + u * B];
-                        qv[u] = q[k + u * B];
-                        pv[u] = cp != 0.0 ? p[k + u * B] : 0.f;
+                // 16-byte loads (four elements per lane, two in flight) when the
+                // vectors are 16-byte aligned; chunk starts are multiples of 4
+                const bool al = ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(q) |
+                                  reinterpret_cast<uintptr_t>(p)) & 15) == 0;
+                if (al) {
+                    const int64_t nv = (hi - lo) >> 2;
+                    const float4 *x4 = reinterpret_cast<const float4 *>(x + lo);
+                    const float4 *p4 = reinterpret_cast<const float4 *>(p + lo);
+                    float4 *q4 = reinterpret_cast<float4 *>(q + lo);
+                    const bool use_p = cp != 0.0;
+                    auto upd4 = [&](const float4 &xv, const float4 &qv, const float4 &pv) {
+                        float4 st;
+                        st.x = (float)((double)qv.x - cx * (double)xv.x - cp * (double)pv.x);
+                        st.y = (float)((double)qv.y - cx * (double)xv.y - cp * (double)pv.y);
+                        st.z = (float)((double)qv.z - cx * (double)xv.z - cp * (double)pv.z);
+                        st.w = (float)((double)qv.w - cx * (double)xv.w - cp * (double)pv.w);
+                        s[0] += (double)st.x * (double)st.x + (double)st.y * (double)st.y +
+                                (double)st.z * (double)st.z + (double)st.w * (double)st.w;
+                        return st;
+                    };
+                    int64_t v = threadIdx.x;
+                    for (; v + B < nv; v += 2 * B) {
+                        const float4 xa = x4[v], qa = q4[v], xb = x4[v + B], qb = q4[v + B];
+                        const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+                        const float4 pa = use_p ? p4[v] : z, pb = use_p ? p4[v + B] : z;
+                        q4[v] = upd4(xa, qa, pa);
+                        q4[v + B] = upd4(xb, qb, pb);
                     }
+                    for (; v < nv; v += B) {
+                        const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+                        q4[v] = upd4(x4[v], q4[v], use_p ? p4[v] : z);
+                    }
+                    k = lo + 4 * nv + threadIdx.x;   // the tail (n not a multiple of 4)
+                } else {
+                    for (; k + 3 * B < hi; k += 4 * B) {   // four independent elements in flight
+                        float xv[4], qv[4], pv[4];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const float st = (float)((double)qv[u] - cx * (double)xv[u] - cp * (double)pv[u]);
-                        q[k + u * B] = st;
-                        s[0] += (double)st * (double)st;
+                        for (int u = 0; u < 4; ++u) {
+                            xv[u] = x[k + u * B];
+                            qv[u] = q[k + u * B];
+                            pv[u] = cp != 0.0 ? p[k + u * B] : 0.f;
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const float st = (float)((double)qv[u] - cx * (double)xv[u] - cp * (double)pv[u]);
+                            q[k + u * B] = st;
+                            s[0] += (double)st * (double)st;
+                        }
                     }
                 }
                 for (; k < hi; k += B) {
@@ -529,8 +568,11 @@ static int plan_batch(const ed_batch_item *items, int n, int32_t max_steps, Batc
         I.Ddn = (int)h.dim_dn;
         I.W8u = h.w_up;
         I.W8d = h.w_dn;
-        I.R = tl.up_wlog2 >= 6 ? 1 : 2;
-        const int w = 64 / I.R;
+        // one row per wave on 64- or 128-column stripes (two columns per lane
+        // where the tile asks for wider stripes and the rows allow it)
+        I.R = 1;
+        I.V = (tl.up_wlog2 >= 7 && !(I.Ddn & 1) && I.W8u <= 32) ? 2 : 1;
+        const int w = 64 * I.V;
         I.rc = tl.up_rc;
         I.n_stripes = (I.Ddn + w - 1) / w;
         I.n_rc = (I.Dup + I.rc - 1) / I.rc;

@@ -197,6 +197,185 @@ __device__ __forceinline__ void up_tile_wide(const T *__restrict__ x, T *__restr
     if (pend_ptr) __builtin_nontemporal_store(pend, pend_ptr);
 }
 
+// Up part with 64*V-column stripes: the one-row kernel with V adjacent
+// columns per lane (V = 2: float2 / double2, V = 4: float4), so each gather
+// instruction moves V times the bytes and a row needs 1/V of the
+// instructions (the up part is bound by gather instructions in flight, not by
+// bytes).  Needs row starts aligned to V elements (row length a multiple of
+// V); each column's terms are still added in ascending order with one fused
+// multiply-add each.
+template <typename T, int V> struct VecT;
+template <> struct VecT<float, 2> { using type = float2; };
+template <> struct VecT<double, 2> { using type = double2; };
+template <> struct VecT<float, 4> { using type = float4; };
+
+template <typename VT> __device__ __forceinline__ auto vcomp(const VT &v, int i) {
+    if constexpr (sizeof(VT) / sizeof(v.x) == 2) return i == 0 ? v.x : v.y;
+    else return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
+}
+
+template <typename T, int V, int NL, int NCH>
+__device__ __forceinline__ void up_rowv(const T *__restrict__ xs, unsigned cc, int Ddn, const uint4 (&q)[NCH], T t,
+                                        T (&pend)[V], T *&pend_ptr, T *row_out) {
+    using VT = typename VecT<T, V>::type;
+    VT v[NL > 0 ? NL : 1][8];
+#pragma unroll
+    for (int k8 = 0; k8 < NL; ++k8)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const unsigned e = entry(q[k8], k);
+            const T *xr = xs + (int64_t)(e != 0xFFFFu ? (e >> 1) : 0u) * Ddn;
+            v[k8][k] = *reinterpret_cast<const VT *>(xr + cc);
+        }
+    if (pend_ptr) {
+#pragma unroll
+        for (int i = 0; i < V; ++i) __builtin_nontemporal_store(pend[i], pend_ptr + i);
+    }
+    T a[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) a[i] = T(0);
+#pragma unroll
+    for (int k8 = 0; k8 < NL; ++k8)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const unsigned e = entry(q[k8], k);
+            const T sg = e == 0xFFFFu ? T(0) : ((e & 1u) ? T(-1) : T(1));
+#pragma unroll
+            for (int i = 0; i < V; ++i) a[i] = fma_t(sg, vcomp(v[k8][k], i), a[i]);
+        }
+#pragma unroll
+    for (int i = 0; i < V; ++i) pend[i] = t * a[i];
+    pend_ptr = row_out;
+}
+
+template <typename T, int V, int NCH>
+__device__ __forceinline__ void up_tile_vec(const T *__restrict__ x, T *__restrict__ out,
+                                            const uint16_t *__restrict__ tab, int Dup, int Ddn, int W8, int rc,
+                                            int s, int rci, T t) {
+    const int lane = threadIdx.x & 63, nwave = blockDim.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int c = s * 64 * V + V * lane;
+    const bool cok = c < Ddn;   // Ddn a multiple of V: the lane's other columns are valid too
+    const T *xs = x + s * 64 * V;
+    const unsigned cc = cok ? (unsigned)(V * lane) : 0u;
+    const int r1 = min(Dup, (rci + 1) * rc);
+    const int nch = W8 >> 3;
+    int rb = rci * rc + wave;
+    if (rb >= r1) return;
+    uint4 q[NCH];
+    row_chunks<NCH>(tab, rb, W8, nch, q);
+    T pend[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) pend[i] = T(0);
+    T *pend_ptr = nullptr;
+    for (; rb < r1; rb += nwave) {
+        int nl = 0;
+#pragma unroll
+        for (int k8 = 0; k8 < NCH; ++k8) nl += entry(q[k8], 0) != 0xFFFFu ? 1 : 0;
+        uint4 qn[NCH];
+        row_chunks<NCH>(tab, min(rb + nwave, r1 - 1), W8, nch, qn);
+        T *row_out = cok ? out + (int64_t)rb * Ddn + c : nullptr;
+        switch (nl) {
+        case 0: up_rowv<T, V, 0, NCH>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
+        case 1: up_rowv<T, V, 1, NCH>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
+        case 2: if constexpr (NCH >= 2) up_rowv<T, V, 2, NCH>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
+        case 3: if constexpr (NCH >= 4) up_rowv<T, V, 3, NCH>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
+        default: if constexpr (NCH >= 4) up_rowv<T, V, 4, NCH>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
+        }
+#pragma unroll
+        for (int k8 = 0; k8 < NCH; ++k8) q[k8] = qn[k8];
+    }
+    if (pend_ptr) {
+#pragma unroll
+        for (int i = 0; i < V; ++i) __builtin_nontemporal_store(pend[i], pend_ptr + i);
+    }
+}
+
+// Up part with 32-column stripes, two rows per wave (lanes 0-31 row rb,
+// lanes 32-63 row rb+1): half the stripe footprint of the one-row kernel, so
+// a stripe of x stays in an XCD's L2, with the same latency tolerance.  Both
+// rows' table chunks are scalar loads fetched one pair ahead; each lane picks
+// its row's entry, and every gather of the pair is issued before the first is
+// consumed (the chunk count is the larger of the two rows').  A row beyond the
+// tile or the table reads as padding (its chunks are loaded from a valid row
+// and discarded).  Used for tables of at most 4 chunks (scalar registers).
+template <typename T, int NL, int NCH>
+__device__ __forceinline__ void up_pair(const T *__restrict__ xc, int Ddn, bool hi, const uint4 (&qa)[NCH],
+                                        const uint4 (&qb)[NCH], T t, T &pend, T *&pend_ptr, T *row_out) {
+    T v[NL > 0 ? NL : 1][8];
+#pragma unroll
+    for (int k8 = 0; k8 < NL; ++k8)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const unsigned e = hi ? entry(qb[k8], k) : entry(qa[k8], k);
+            v[k8][k] = xc[(int64_t)(e != 0xFFFFu ? (e >> 1) : 0u) * Ddn];
+        }
+    if (pend_ptr) __builtin_nontemporal_store(pend, pend_ptr);
+    T acc = T(0);
+#pragma unroll
+    for (int k8 = 0; k8 < NL; ++k8)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const unsigned e = hi ? entry(qb[k8], k) : entry(qa[k8], k);
+            const T sg = e == 0xFFFFu ? T(0) : ((e & 1u) ? T(-1) : T(1));
+            acc = fma_t(sg, v[k8][k], acc);
+        }
+    pend = t * acc;
+    pend_ptr = row_out;
+}
+
+template <int NCH>
+__device__ __forceinline__ int live_chunks(const uint4 (&q)[NCH]) {
+    int n = 0;
+#pragma unroll
+    for (int k8 = 0; k8 < NCH; ++k8) n += entry(q[k8], 0) != 0xFFFFu ? 1 : 0;
+    return n;
+}
+
+template <typename T, int NCH>
+__device__ __forceinline__ void up_tile_pair(const T *__restrict__ x, T *__restrict__ out,
+                                             const uint16_t *__restrict__ tab, int Dup, int Ddn, int W8, int rc,
+                                             int s, int rci, T t) {
+    static_assert(NCH <= 4, "two rows of scalar table chunks");
+    const int lane = threadIdx.x & 63, nwave = blockDim.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const bool hi = lane >= 32;
+    const int c = s * 32 + (lane & 31);
+    const bool cok = c < Ddn;
+    const T *xc = x + (cok ? c : 0);
+    const int r1 = min(Dup, (rci + 1) * rc);
+    const int nch = W8 >> 3;
+    int rb = rci * rc + 2 * wave;
+    if (rb >= r1) return;
+    uint4 qa[NCH], qb[NCH];
+    row_chunks<NCH>(tab, rb, W8, nch, qa);
+    row_chunks<NCH>(tab, min(rb + 1, Dup - 1), W8, rb + 1 < r1 ? nch : 0, qb);
+    T pend = T(0);
+    T *pend_ptr = nullptr;
+    for (; rb < r1; rb += 2 * nwave) {
+        const int nl = max(live_chunks<NCH>(qa), live_chunks<NCH>(qb));
+        const int rn = min(rb + 2 * nwave, r1 - 1);
+        uint4 qan[NCH], qbn[NCH];
+        row_chunks<NCH>(tab, rn, W8, nch, qan);
+        row_chunks<NCH>(tab, min(rn + 1, Dup - 1), W8, rn + 1 < r1 ? nch : 0, qbn);
+        const int r = rb + (hi ? 1 : 0);
+        T *row_out = (cok && r < r1) ? out + (int64_t)r * Ddn + c : nullptr;
+        switch (nl) {
+        case 0: up_pair<T, 0, NCH>(xc, Ddn, hi, qa, qb, t, pend, pend_ptr, row_out); break;
+        case 1: up_pair<T, 1, NCH>(xc, Ddn, hi, qa, qb, t, pend, pend_ptr, row_out); break;
+        case 2: if constexpr (NCH >= 2) up_pair<T, 2, NCH>(xc, Ddn, hi, qa, qb, t, pend, pend_ptr, row_out); break;
+        case 3: if constexpr (NCH >= 4) up_pair<T, 3, NCH>(xc, Ddn, hi, qa, qb, t, pend, pend_ptr, row_out); break;
+        default: if constexpr (NCH >= 4) up_pair<T, 4, NCH>(xc, Ddn, hi, qa, qb, t, pend, pend_ptr, row_out); break;
+        }
+#pragma unroll
+        for (int k8 = 0; k8 < NCH; ++k8) {
+            qa[k8] = qan[k8];
+            qb[k8] = qbn[k8];
+        }
+    }
+    if (pend_ptr) __builtin_nontemporal_store(pend, pend_ptr);
+}
+
 // Chunk k8 of column c in the 8-interleaved table; chunks at or beyond nch
 // read as padding.  The load always goes to a valid table address (nch >= 1
 // in every variant with NCH >= 1) and the value is selected afterwards:

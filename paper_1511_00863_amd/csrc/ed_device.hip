@@ -121,8 +121,31 @@ __global__ __launch_bounds__(512) void k_up(const T *__restrict__ x, T *__restri
     if (s >= n_stripes) return;
     if constexpr (R == 1)
         up_tile_wide<T, NCH>(x, out, tab, Dup, Ddn, W8, rc, s, rci, t);
+    else if constexpr (R == 2 && NCH <= 4)
+        up_tile_pair<T, NCH>(x, out, tab, Dup, Ddn, W8, rc, s, rci, t);
     else
         up_tile<T, R>(x, out, tab, Dup, Ddn, W8, rc, s, rci, t);
+}
+
+// k_upv: k_up's tiling with 64*V-column stripes (V columns per lane).
+template <typename T, int V, int NCH>
+__global__ __launch_bounds__(512) void k_upv(const T *__restrict__ x, T *__restrict__ out,
+                                             const uint16_t *__restrict__ tab, int Dup, int Ddn, int W8, int rc,
+                                             int n_stripes, int n_rc, int map, T t, const Hdr *__restrict__ hdr,
+                                             int gate, int max_steps) {
+    if (gate && frozen(hdr, max_steps)) return;
+    int s, rci;
+    if (map == 0) {
+        const int g = blockIdx.x, xcd = g & 7, local = g >> 3;
+        const int sl = local / n_rc;
+        rci = local - sl * n_rc;
+        s = sl * 8 + xcd;
+    } else {
+        s = blockIdx.x / n_rc;
+        rci = blockIdx.x - s * n_rc;
+    }
+    if (s >= n_stripes) return;
+    up_tile_vec<T, V, NCH>(x, out, tab, Dup, Ddn, W8, rc, s, rci, t);
 }
 
 // k_up_q, persistent mapping (map 2): one queue per XCD holding the tiles of
@@ -149,6 +172,8 @@ __global__ __launch_bounds__(512) void k_up_q(const T *__restrict__ x, T *__rest
             const int sl = tq / n_rc;
             if constexpr (R == 1)
                 up_tile_wide<T, NCH>(x, out, tab, Dup, Ddn, W8, rc, q + 8 * sl, tq - sl * n_rc, t);
+            else if constexpr (R == 2 && NCH <= 4)
+                up_tile_pair<T, NCH>(x, out, tab, Dup, Ddn, W8, rc, q + 8 * sl, tq - sl * n_rc, t);
             else
                 up_tile<T, R>(x, out, tab, Dup, Ddn, W8, rc, q + 8 * sl, tq - sl * n_rc, t);
         }
@@ -430,6 +455,31 @@ static int launch_up(const ed_ham *h, const Tile &tl, const T *x, T *out, int *c
         ED_LAUNCHED("k_fill0");
         return ED_OK;
     }
+    if (tl.up_wlog2 >= 7) {   // V columns per lane (resolve_tile_id guarantees W8 <= 32 and aligned rows)
+        const int w = 1 << tl.up_wlog2;
+        const int n_stripes = (int)((h->dim_dn + w - 1) / w);
+        const int n_rc = (int)((h->dim_up + tl.up_rc - 1) / tl.up_rc);
+        const int64_t grid = tl.up_map == 0 ? 8LL * n_rc * ((n_stripes + 7) / 8) : (int64_t)n_rc * n_stripes;
+        if (grid > 0x7fffffffLL) return set_error(ED_EOVERFLOW, "k_upv grid too large");
+        const T t = static_cast<T>(h->t);
+        const int map = tl.up_map == 0 ? 0 : 1;
+        const int nc = nch_class(h->w_up >> 3);
+#define ED_UPV(V, N)                                                                                          \
+    hipLaunchKernelGGL((k_upv<T, V, N>), dim3((unsigned)grid), dim3(tl.up_block), 0, s, x, out, h->tab_up,      \
+                       (int)h->dim_up, (int)h->dim_dn, h->w_up, tl.up_rc, n_stripes, n_rc, map, t, hdr, gate,  \
+                       max_steps)
+        if constexpr (sizeof(T) == 4) {
+            if (tl.up_wlog2 == 8) {
+                if (nc == 1) ED_UPV(4, 1); else if (nc == 2) ED_UPV(4, 2); else ED_UPV(4, 4);
+                ED_LAUNCHED("k_upv");
+                return ED_OK;
+            }
+        }
+        if (nc == 1) ED_UPV(2, 1); else if (nc == 2) ED_UPV(2, 2); else ED_UPV(2, 4);
+#undef ED_UPV
+        ED_LAUNCHED("k_upv");
+        return ED_OK;
+    }
     switch (tl.up_wlog2) {
     case 6:
         switch (nch_class(h->w_up >> 3)) {
@@ -438,7 +488,13 @@ static int launch_up(const ed_ham *h, const Tile &tl, const T *x, T *out, int *c
         case 4: return launch_up_r<T, 1, 4>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
         default: return launch_up_r<T, 1, 8>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
         }
-    case 5: return launch_up_r<T, 2, 1>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
+    case 5:
+        switch (nch_class(h->w_up >> 3)) {
+        case 1: return launch_up_r<T, 2, 1>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
+        case 2: return launch_up_r<T, 2, 2>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
+        case 4: return launch_up_r<T, 2, 4>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
+        default: return launch_up_r<T, 2, 8>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
+        }
     default: return launch_up_r<T, 4, 1>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
     }
 }

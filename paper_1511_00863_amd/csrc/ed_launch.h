@@ -13,7 +13,7 @@
 namespace ed {
 
 struct Tile {
-    int up_wlog2;   // stripe width = 2^up_wlog2 columns (8..64)
+    int up_wlog2;   // stripe width = 2^up_wlog2 columns (16..256; 128/256 = 2/4 columns per lane)
     int up_rc;      // rows per k_up tile
     int up_block;   // k_up threads per workgroup
     int up_map;     // 0 XCD round-robin remap, 1 linear, 2 per-XCD queues
@@ -38,6 +38,8 @@ static const UpTile kUpTiles[] = {
     {6, 32, 256, 2}, {5, 32, 256, 2}, {4, 32, 256, 2},
     {6, 128, 256, 2}, {5, 128, 256, 2}, {4, 128, 256, 2},
     {6, 64, 512, 0}, {5, 64, 512, 0}, {6, 128, 512, 0}, {5, 128, 512, 0},
+    {7, 16, 256, 0}, {7, 32, 256, 0}, {7, 64, 256, 0}, {7, 128, 256, 0}, {7, 64, 512, 0},
+    {7, 8, 256, 0}, {7, 16, 512, 0}, {8, 8, 256, 0}, {8, 16, 256, 0}, {8, 32, 256, 0}, {8, 16, 512, 0},
 };
 static const DnTile kDnTiles[] = {
     {0, 0}, {1024, 0}, {512, 0}, {256, 0}, {1024, 1}, {512, 1}, {256, 1}, {1024, 2}, {512, 2}, {256, 4},
@@ -57,9 +59,9 @@ static inline Tile resolve_tile_id(const ed_ham *h, int id) {
         t.up_rc = kUpTiles[ui].rc;
         t.up_block = kUpTiles[ui].block;
         t.up_map = kUpTiles[ui].map;
-    } else {
-        t.up_wlog2 = es == 8 ? 5 : 6;
-        t.up_rc = 64;
+    } else {   // two columns per lane on 128-column stripes, 16-row tiles (falls back below)
+        t.up_wlog2 = 7;
+        t.up_rc = 16;
         t.up_block = 256;
         t.up_map = 0;
     }
@@ -70,6 +72,11 @@ static inline Tile resolve_tile_id(const ed_ham *h, int id) {
         t.dn_block = h->dim_dn >= 1024 ? 1024 : 256;
         t.dn_rpb = 0;
     }
+    // V = 2 or 4 columns per lane need row starts aligned to V elements (a row
+    // length that is a multiple of V) and at most 4 table chunks; 4 columns
+    // per lane is float only (16-byte loads)
+    if (t.up_wlog2 == 8 && (es != 4 || (h->dim_dn & 3) || h->w_up > 32)) t.up_wlog2 = 7;
+    if (t.up_wlog2 == 7 && ((h->dim_dn & 1) || h->w_up > 32)) t.up_wlog2 = 6;
     // stripes much wider than the row are pointless
     while (t.up_wlog2 > 4 && (1 << (t.up_wlog2 - 1)) >= h->dim_dn) --t.up_wlog2;
     if (t.up_wlog2 < 4) t.up_wlog2 = 4;
