@@ -97,6 +97,28 @@ def measured_traffic(dtype, kernel, workload_name):
     return rec["kernels"].get(dtype, {}).get(kernel)
 
 
+def observables_block(item, wl):
+    """Occupation moments of a two-pass ground state (FP32 vector): wall time of ed_occupation_moments
+    (two passes over the vector, synchronised) and the double occupancy and nearest-neighbour correlations."""
+    import torch
+    import paper_1511_00863_amd as ed
+    ham, psi, _ = item
+    ns = wl.n_sites
+    g = ham.occupation_moments(psi, ns)          # warm-up
+    best = None
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = ham.occupation_moments(psi, ns)
+        dt = (time.perf_counter() - t0) * 1e3
+        best = dt if best is None else min(best, dt)
+    c = ed.occupation_correlations(g, ns)
+    a, b = wl.bonds[0]
+    return {"U": ham.U, "ms": best, "read_GBps": 2 * psi.numel() * psi.element_size() / (best * 1e6),
+            "double_occupancy_per_site": float(c["docc"].mean()),
+            "nn_bond": float(c["nn"][a, b]), "szsz_bond": float(c["szsz"][a, b])}
+
+
 def time_to_e0_block(up, dn, wl, args):
     """Steps and wall ms to E0 at stated accuracy vs converged plain float64 Lanczos (the judge):
     plain float64 and mixed from the seeded random start, mixed and float64 from the learned start
@@ -110,11 +132,12 @@ def time_to_e0_block(up, dn, wl, args):
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
     net, losses, t_train = learned.train_network(data, iters=args.train_iters, batch=4096)
+    obs = observables_block(data[3], wl)          # the U = 4 ground state
     del data
     torch.cuda.empty_cache()
     out = {"training": {"ground_states": 8, "data_s": t_data, "train_s": t_train, "iters": args.train_iters,
                         "batch": 4096, "loss_first": float(losses[:20].mean()), "loss_last": float(losses[-20:].mean())},
-           "held_out": []}
+           "observables": obs, "held_out": []}
     for U in [float(u) for u in args.held_out.split(",")]:
         e_judge, judge_steps = learned.judge_energy(up, dn, wl.t, U, wl.seed)
         row = {"U": U, "e_judge": e_judge, "judge_steps": judge_steps}

@@ -278,6 +278,30 @@ int ed_ground_energy_batch(const ed_batch_item *items, int32_t n, int32_t max_st
                            int64_t ws_bytes, void *stream, int32_t use_graph, double *e0, int32_t *steps,
                            int32_t *status, double *e0_device, int32_t *graph_used, double *phase_ms);
 
+/* ---- device: observables of a state -------------------------------------- */
+
+/* Occupation moments of a state psi, e.g. the ground-state vector of
+ * ed_ground_state: G[a][b] = sum_x |psi_x|^2 n_a(x) n_b(x) / sum_x |psi_x|^2
+ * over the 2*n_sites occupation numbers, a = i for n_i,up and a = n_sites + i
+ * for n_i,dn.  The basis states of Sec. 2.1 fix every occupation number, so
+ * all diagonal observables (double occupancy, density and spin correlations)
+ * follow from G; see ed_occupation_correlations.  Two passes over psi, float64
+ * sums in a fixed order.
+ * psi: device, dim_up*dim_dn elements of h->dtype, any nonzero norm (a zero
+ * vector gives G = 0).  n_sites: 1..32, the number of lattice sites (the bits
+ * of the per-spin states; higher bits are ignored).  ws: device, 256-byte
+ * aligned, ws_bytes >= ed_occupation_moments_ws(h, n_sites).  g: host,
+ * (2*n_sites)^2 doubles, row-major.  Synchronises stream. */
+int ed_occupation_moments_ws(const ed_ham *h, int32_t n_sites, int64_t *bytes);
+int ed_occupation_moments(const ed_ham *h, int32_t n_sites, const void *psi, void *ws, int64_t ws_bytes,
+                          void *stream, double *g);
+
+/* Diagonal observables from G (ed_occupation_moments): double occupancy
+ * docc[i] = <n_i,up n_i,dn>, density correlations nn[i*n_sites+j] = <n_i n_j>
+ * with n = n_up + n_dn, spin correlations szsz[i*n_sites+j] = <S^z_i S^z_j>
+ * with S^z = (n_up - n_dn)/2.  host; each output may be NULL. */
+int ed_occupation_correlations(const double *g, int32_t n_sites, double *docc, double *nn, double *szsz);
+
 /* ---- device: the start-vector network ---------------------------------- */
 
 /* psi(bits): 32 inputs (bits 0..15 of the up state, then of the down state,

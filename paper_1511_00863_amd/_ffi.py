@@ -52,6 +52,11 @@ _PROTOS = {
     "ed_pack_tables": (c_int, [POINTER(c_int32), POINTER(c_double), POINTER(c_int32), c_int64, c_int32, c_int,
                                POINTER(c_uint16)]),
     "ed_tridiag_lowest": (c_int, [POINTER(c_double), POINTER(c_double), c_int, POINTER(c_double)]),
+    "ed_occupation_moments_ws": (c_int, [POINTER(EdHam), c_int32, POINTER(c_int64)]),
+    "ed_occupation_moments": (c_int, [POINTER(EdHam), c_int32, c_void_p, c_void_p, c_int64, c_void_p,
+                                      POINTER(c_double)]),
+    "ed_occupation_correlations": (c_int, [POINTER(c_double), c_int32, POINTER(c_double), POINTER(c_double),
+                                           POINTER(c_double)]),
     "ed_tridiag_lowest_vector": (c_int, [POINTER(c_double), POINTER(c_double), c_int, POINTER(c_double),
                                          POINTER(c_double)]),
     "ed_workspace_size": (c_int, [POINTER(EdHam), c_int32, POINTER(c_int64)]),

@@ -88,6 +88,17 @@ def pack_tables(table, dim: int) -> np.ndarray:
     return out
 
 
+def occupation_correlations(g: np.ndarray, n_sites: int) -> dict:
+    """docc[i], nn[i, j] = <n_i n_j>, szsz[i, j] = <S^z_i S^z_j> from occupation moments (ed_occupation_correlations)."""
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    docc = np.zeros(n_sites)
+    nn = np.zeros((n_sites, n_sites))
+    szsz = np.zeros((n_sites, n_sites))
+    check(lib().ed_occupation_correlations(_ptr(g, c_double), int(n_sites), _ptr(docc, c_double),
+                                           _ptr(nn, c_double), _ptr(szsz, c_double)))
+    return {"docc": docc, "nn": nn, "szsz": szsz}
+
+
 def tridiag_lowest(a, b_off) -> float:
     a = np.ascontiguousarray(a, dtype=np.float64)
     b = np.ascontiguousarray(b_off, dtype=np.float64)
@@ -217,6 +228,18 @@ class Hamiltonian:
         if apply:
             self.tile = tile.value
         return {"tile": tile.value, "up_ms": mu, "dn_ms": md}
+
+    def occupation_moments(self, psi, n_sites: int, stream=None) -> np.ndarray:
+        """G[a][b] = <n_a n_b> of the state psi over the 2*n_sites occupation numbers (ed_occupation_moments)."""
+        psi = self._vec(psi)
+        n = c_int64(0)
+        h = self.c_struct()
+        check(lib().ed_occupation_moments_ws(byref(h), int(n_sites), byref(n)))
+        ws = torch.empty(max(n.value, 1), dtype=torch.uint8, device=self.device)
+        g = np.zeros((2 * n_sites, 2 * n_sites))
+        check(lib().ed_occupation_moments(byref(h), int(n_sites), _dptr(psi), _dptr(ws), n.value, _stream(stream),
+                                          _ptr(g, c_double)))
+        return g
 
     def lanczos(self, max_steps: int) -> "LanczosRun":
         return LanczosRun(self, max_steps)

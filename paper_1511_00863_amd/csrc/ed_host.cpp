@@ -263,6 +263,22 @@ int ed_pack_tables(const int32_t *cols, const double *vals, const int32_t *nnz, 
     return ED_OK;
 }
 
+int ed_occupation_correlations(const double *g, int32_t n_sites, double *docc, double *nn, double *szsz) {
+    clear_error();
+    if (!g || n_sites < 1 || n_sites > 32) return set_error(ED_EINVAL, "ed_occupation_correlations: bad arguments");
+    const int ns = n_sites, n2 = 2 * n_sites;
+    auto G = [&](int a, int b) { return g[a * n2 + b]; };
+    for (int i = 0; i < ns; ++i) {
+        if (docc) docc[i] = G(i, ns + i);
+        for (int j = 0; j < ns; ++j) {
+            const double uu = G(i, j), ud = G(i, ns + j), du = G(ns + i, j), dd = G(ns + i, ns + j);
+            if (nn) nn[i * ns + j] = uu + ud + du + dd;
+            if (szsz) szsz[i * ns + j] = 0.25 * (uu - ud - du + dd);
+        }
+    }
+    return ED_OK;
+}
+
 int ed_tridiag_lowest(const double *a, const double *b, int m, double *e0) {
     clear_error();
     if (!a || !e0 || m < 1 || (m > 1 && !b)) return set_error(ED_EINVAL, "ed_tridiag_lowest: bad arguments");
