@@ -45,8 +45,8 @@ def kernel_bytes(h, es):
     and both bases.  k_update reads q and f_j (and f_{j-1} in the mixed form)
     and writes f_{j+1}.  k_reduce and k_norm read a few hundred KB of partial sums."""
     D = h.dim
-    tab_up = h.dim_up * h.up.width * 2
-    tab_dn = h.dim_dn * h.dn.width * 2
+    tab_up = h.dim_up * h.up.width * h.up.entry_bytes
+    tab_dn = h.dim_dn * h.dn.width * h.dn.entry_bytes
     states = 8 * (h.dim_up + h.dim_dn)
     upd = (4 if es == 4 else 3) * es * D
     return {"k_up": 2 * es * D + tab_up, "k_down": 4 * es * D + tab_dn + states,
@@ -95,6 +95,35 @@ def measured_traffic(dtype, kernel, workload_name):
     if hashlib.sha256(src).hexdigest()[:16] != rec.get("source_sha256_prefix") or rec.get("workload") != workload_name:
         return None
     return rec["kernels"].get(dtype, {}).get(kernel)
+
+
+def scale_block(args):
+    """Lanczos steps/s on the 18-site chain at 9 + 9 (D = 48620^2 = 2,363,904,400): a sector whose
+    complex double-precision vector (38 GB) no coprocessor of the paper's day could hold, run here in
+    float64 (18.9 GB per vector) and in the mixed form, with 32-bit tables (48620 states per species)."""
+    import torch
+    import paper_1511_00863_amd as ed
+    from synth import workload
+    wl = workload("ring18_9x9")
+    dev = "cuda:0"
+    tab = ed.SpinTables(wl.n_sites, wl.bonds, wl.n_up, dev)
+    out = {"workload": wl.name, "dim": tab.dim * tab.dim, "U": wl.U, "table_entry_bytes": tab.entry_bytes,
+           "start": "uniform(-1/2,1/2) from torch's device generator, seed %d" % wl.seed}
+    for dtype in ("f64", "f32"):
+        h = ed.Hamiltonian(tab, tab, wl.t, wl.U, dtype)
+        src = ed.api.apply_tuned_tile(h, tune_if_missing=False)
+        g = torch.Generator(device=dev)
+        g.manual_seed(wl.seed)
+        x = torch.rand(h.dim, dtype=h.torch_dtype, device=dev, generator=g).sub_(0.5)
+        ms, per, _ = time_run(h, x, 2, args.scale_steps, 2)
+        es = 8 if dtype == "f64" else 4
+        out[dtype] = {"steps_per_s": 1000.0 / ms, "ms_per_step": ms, "kernel_ms": per,
+                      "GB_per_vector": es * h.dim / 1e9, "tile": {"id": h.tile, "source": src, **h.tile_params()}}
+        del x, h
+        torch.cuda.empty_cache()
+    del tab
+    torch.cuda.empty_cache()
+    return out
 
 
 def observables_block(item, wl):
@@ -226,6 +255,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batched run")
     ap.add_argument("--train-iters", type=int, default=3000)
     ap.add_argument("--held-out", default="3.5", help="comma-separated held-out U values for time-to-E0")
+    ap.add_argument("--no-scale", action="store_true", help="skip the 18-site 9+9 run (2.4e9 states)")
+    ap.add_argument("--scale-steps", type=int, default=6)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this method runs on one GPU; --gpus %d is not supported (use --gpus 1)" % args.gpus,
@@ -255,7 +286,7 @@ def main():
         ms, per, st = time_run(h, x, args.warmup, args.steps, args.kernel_samples)
         es = 8 if dtype == "f64" else 4
         kb = kernel_bytes(h, es)
-        hv_bytes = 2 * es * h.dim + h.dim_up * h.up.width * 2 + h.dim_dn * h.dn.width * 2
+        hv_bytes = 2 * es * h.dim + h.dim_up * h.up.width * h.up.entry_bytes + h.dim_dn * h.dn.width * h.dn.entry_bytes
         results[dtype] = {"ms_per_step": ms, "steps_per_s": 1000.0 / ms, "kernel_ms": per, "kernel_bytes": kb,
                           "tile": h.tile, "tile_params": h.tile_params(), "tile_src": tile_src,
                           "hv_alg_GBps": hv_bytes / ((per["k_up"] + per["k_down"]) * 1e-3) / 1e9,
@@ -299,6 +330,8 @@ def main():
         line["time_to_e0"] = time_to_e0_block(up, dn, wl, args)
     if not args.no_batch:
         line["batch"] = batch_block(args)
+    if not args.no_scale:
+        line["scale"] = scale_block(args)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
     print(json.dumps(line), flush=True)

@@ -103,6 +103,15 @@ int ed_build_hopping(int n_sites, const int32_t *bonds, int n_bonds, const uint6
 int ed_pack_tables(const int32_t *cols, const double *vals, const int32_t *nnz, int64_t dim,
                    int32_t width, int layout, uint16_t *packed);
 
+/* The same table with uint32 entries e = (col << 1) | (val < 0) and padding
+ * 0xFFFFFFFF, for per-spin dimensions above 32767: the 18-site half-filled
+ * sector that Sec. 4 places beyond the memory of any coprocessor has 48620
+ * states per species.  Identical layouts and stride W8, 32-byte chunks.
+ * dim > 2^30 -> ED_EOVERFLOW.  packed: host, 2 * dim * W8 entries;
+ * ed_ham.eb_up/eb_dn = 4 selects it. */
+int ed_pack_tables32(const int32_t *cols, const double *vals, const int32_t *nnz, int64_t dim,
+                     int32_t width, int layout, uint32_t *packed);
+
 /* Lowest eigenvalue of the m-by-m symmetric tridiagonal T (Sec. 2.2) with
  * diagonal a[0..m-1] = a_1..a_m and off-diagonal b[0..m-2] = b_2..b_m, by
  * Sturm-sequence bisection in float64 to full precision.  host pointers. */
@@ -115,19 +124,23 @@ int ed_tridiag_lowest_vector(const double *a, const double *b, int m, double *e0
 /* ---- device: the Hamiltonian and H.v ----------------------------------- */
 
 /* One instance (lattice, fillings, t, U).  All pointers are device memory.
- * tab_up/tab_dn: ed_pack_tables output for H_up and H_dn, with row strides
- * w_up/w_dn (multiples of 8; 0 when a species cannot hop).  st_up/st_dn: the per-spin bases (for the U term).
- * dtype: ED_F64 or ED_F32 (vectors and H.v).  tile: 0 = default launch
- * configuration, else an id returned by ed_tune.  dim_up, dim_dn <= 32767
- * (the table format; ED_EOVERFLOW otherwise). */
+ * tab_up/tab_dn: ed_pack_tables (eb = 2, or 0) or ed_pack_tables32 (eb = 4)
+ * output for H_up and H_dn, with row strides w_up/w_dn (multiples of 8; 0
+ * when a species cannot hop); the two species may use different formats.
+ * st_up/st_dn: the per-spin bases (for the U term).  dtype: ED_F64 or ED_F32
+ * (vectors and H.v).  tile: 0 = default launch configuration, else an id
+ * returned by ed_tune.  A species with 16-bit tables has dim <= 32767, one
+ * with 32-bit tables dim <= 2^30 (ED_EOVERFLOW otherwise); eb other than 0,
+ * 2, 4 -> ED_EINVAL.  The batched launch takes 16-bit tables only. */
 typedef struct ed_ham {
     int64_t dim_up, dim_dn;
     int32_t w_up, w_dn;
-    const uint16_t *tab_up, *tab_dn;
+    const void *tab_up, *tab_dn;
     const uint64_t *st_up, *st_dn;
     double t, U;
     int32_t dtype;
     int32_t tile;
+    int32_t eb_up, eb_dn;   /* bytes per table entry of each species */
 } ed_ham;
 
 /* Bytes of device workspace (`ws` below) the calls on this instance need

@@ -5,7 +5,7 @@ Loading fails loudly when the built library is missing: there is no fallback.
 
 import ctypes
 import os
-from ctypes import POINTER, c_char_p, c_double, c_float, c_int, c_int32, c_int64, c_uint16, c_uint64, c_void_p
+from ctypes import POINTER, c_char_p, c_double, c_float, c_int, c_int32, c_int64, c_uint16, c_uint32, c_uint64, c_void_p
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libed_mi355x.so")
@@ -26,7 +26,8 @@ class EdError(RuntimeError):
 class EdHam(ctypes.Structure):
     _fields_ = [("dim_up", c_int64), ("dim_dn", c_int64), ("w_up", c_int32), ("w_dn", c_int32),
                 ("tab_up", c_void_p), ("tab_dn", c_void_p), ("st_up", c_void_p), ("st_dn", c_void_p),
-                ("t", c_double), ("U", c_double), ("dtype", c_int32), ("tile", c_int32)]
+                ("t", c_double), ("U", c_double), ("dtype", c_int32), ("tile", c_int32),
+                ("eb_up", c_int32), ("eb_dn", c_int32)]
 
 
 class EdBatchItem(ctypes.Structure):
@@ -51,6 +52,8 @@ _PROTOS = {
                                  POINTER(c_int32), POINTER(c_double), POINTER(c_int32), POINTER(c_int32)]),
     "ed_pack_tables": (c_int, [POINTER(c_int32), POINTER(c_double), POINTER(c_int32), c_int64, c_int32, c_int,
                                POINTER(c_uint16)]),
+    "ed_pack_tables32": (c_int, [POINTER(c_int32), POINTER(c_double), POINTER(c_int32), c_int64, c_int32, c_int,
+                                 POINTER(c_uint32)]),
     "ed_tridiag_lowest": (c_int, [POINTER(c_double), POINTER(c_double), c_int, POINTER(c_double)]),
     "ed_occupation_moments_ws": (c_int, [POINTER(EdHam), c_int32, POINTER(c_int64)]),
     "ed_occupation_moments": (c_int, [POINTER(EdHam), c_int32, c_void_p, c_void_p, c_int64, c_void_p,

@@ -8,7 +8,7 @@ exceptions.  Names follow the C entry points of include/ed.h.
 import ctypes
 import json
 import os
-from ctypes import POINTER, byref, c_double, c_int32, c_int64, c_uint16, c_uint64
+from ctypes import POINTER, byref, c_double, c_int32, c_int64, c_uint16, c_uint32, c_uint64
 
 import numpy as np
 import torch
@@ -76,15 +76,25 @@ def table_stride(width: int) -> int:
     return (int(width) + 7) & ~7
 
 
-def pack_tables(table, dim: int) -> np.ndarray:
-    """Device table (uint16; row-major then 8-interleaved, stride table_stride(width))."""
+NARROW_MAX_DIM = 32767   # largest per-spin dimension of the 16-bit table format
+
+
+def pack_tables(table, dim: int, entry_bytes: int = 2) -> np.ndarray:
+    """Device table (row-major then 8-interleaved, stride table_stride(width)) with uint16 entries
+    (ed_pack_tables, dim <= 32767) or uint32 entries (ed_pack_tables32, larger dimensions)."""
+    if entry_bytes not in (2, 4):
+        raise ValueError("entry_bytes must be 2 or 4")
     width = table["width"]
     stride = table_stride(width)
-    out = np.zeros(max(2 * stride * dim, 1), dtype=np.uint16)
+    out = np.zeros(max(2 * stride * dim, 1), dtype=np.uint16 if entry_bytes == 2 else np.uint32)
     if width == 0:
         return out[:0]
-    check(lib().ed_pack_tables(_ptr(table["cols"], c_int32), _ptr(table["vals"], c_double),
-                               _ptr(table["nnz"], c_int32), dim, width, table["layout"], _ptr(out, c_uint16)))
+    args = (_ptr(table["cols"], c_int32), _ptr(table["vals"], c_double), _ptr(table["nnz"], c_int32), dim, width,
+            table["layout"])
+    if entry_bytes == 2:
+        check(lib().ed_pack_tables(*args, _ptr(out, c_uint16)))
+    else:
+        check(lib().ed_pack_tables32(*args, _ptr(out, c_uint32)))
     return out
 
 
@@ -121,7 +131,8 @@ def tridiag_lowest_vector(a, b_off):
 class SpinTables:
     """Basis and packed hopping table of one species, on the host and on the device."""
 
-    def __init__(self, n_sites: int, bonds, n_part: int, device=None):
+    def __init__(self, n_sites: int, bonds, n_part: int, device=None, entry_bytes=None):
+        """entry_bytes: 2 or 4 bytes per device table entry; by default 2 while dim <= 32767, else 4."""
         self.n_sites, self.n_part = n_sites, n_part
         self.bonds = [tuple(int(v) for v in b) for b in bonds]
         self.states = build_basis(n_sites, n_part)
@@ -129,11 +140,14 @@ class SpinTables:
         self.table = build_hopping(n_sites, self.bonds, self.states, ED_COL_MAJOR)
         self.width = self.table["width"]
         self.stride = table_stride(self.width)
-        self.packed = pack_tables(self.table, self.dim)
+        # 16-bit entries while the ranks fit in 15 bits, 32-bit beyond
+        self.entry_bytes = int(entry_bytes) if entry_bytes else (2 if self.dim <= NARROW_MAX_DIM else 4)
+        self.packed = pack_tables(self.table, self.dim, self.entry_bytes)
         self.device = torch.device(device if device is not None else "cuda")
         self.dev_states = torch.from_numpy(self.states.view(np.int64).copy()).to(self.device)
-        self.dev_tab = (torch.from_numpy(self.packed.view(np.int16).copy()).to(self.device)
-                        if self.width else torch.zeros(1, dtype=torch.int16, device=self.device))
+        signed = np.int16 if self.entry_bytes == 2 else np.int32
+        self.dev_tab = (torch.from_numpy(self.packed.view(signed).copy()).to(self.device)
+                        if self.width else torch.zeros(1, dtype=torch.int32, device=self.device))
 
 
 class Hamiltonian:
@@ -147,9 +161,10 @@ class Hamiltonian:
         self.device = up.device
 
     @classmethod
-    def from_lattice(cls, n_sites, bonds, n_up, n_dn, t=1.0, U=0.0, dtype="f64", device=None, tile=0):
-        up = SpinTables(n_sites, bonds, n_up, device)
-        dn = up if n_dn == n_up else SpinTables(n_sites, bonds, n_dn, device)
+    def from_lattice(cls, n_sites, bonds, n_up, n_dn, t=1.0, U=0.0, dtype="f64", device=None, tile=0,
+                     entry_bytes=None):
+        up = SpinTables(n_sites, bonds, n_up, device, entry_bytes)
+        dn = up if n_dn == n_up else SpinTables(n_sites, bonds, n_dn, device, entry_bytes)
         return cls(up, dn, t, U, dtype, tile)
 
     @property
@@ -172,7 +187,7 @@ class Hamiltonian:
         return EdHam(self.dim_up, self.dim_dn, self.up.stride, self.dn.stride,
                      self.up.dev_tab.data_ptr(), self.dn.dev_tab.data_ptr(),
                      self.up.dev_states.data_ptr(), self.dn.dev_states.data_ptr(),
-                     self.t, self.U, self.dtype, self.tile)
+                     self.t, self.U, self.dtype, self.tile, self.up.entry_bytes, self.dn.entry_bytes)
 
     def workspace_bytes(self, max_steps: int = 1) -> int:
         n = c_int64(0)

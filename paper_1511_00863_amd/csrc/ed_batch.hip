@@ -554,6 +554,8 @@ static int plan_batch(const ed_batch_item *items, int n, int32_t max_steps, Batc
         int rc = check_ham(&h, "ed_ground_energy_batch");
         if (rc) return rc;
         if (h.dtype != ED_F32) return set_error(ED_EINVAL, "ed_ground_energy_batch: item %d is not ED_F32", i);
+        if (wide_up(&h) || wide_dn(&h))
+            return set_error(ED_EINVAL, "ed_ground_energy_batch: item %d has 32-bit tables", i);
         if (h.w_dn > 32) return set_error(ED_EOVERFLOW, "ed_ground_energy_batch: down table stride above 32");
         if (h.w_up == 0) return set_error(ED_EINVAL, "ed_ground_energy_batch: item %d has no up-spin hopping", i);
         if (h.dim_dn * 4 > kBatchLds) return set_error(ED_EOVERFLOW, "ed_ground_energy_batch: rows above 40 KB");

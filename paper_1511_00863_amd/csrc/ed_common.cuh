@@ -35,10 +35,34 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *out) {
 
 
 // ---------------------------------------------------------------------------
-// table entries: 8 uint16 per 16-byte chunk, e = (col << 1) | negative, 0xFFFF = pad
-__device__ __forceinline__ unsigned entry(const uint4 &q, int k) {
-    const unsigned w = k < 2 ? q.x : (k < 4 ? q.y : (k < 6 ? q.z : q.w));
-    return (k & 1) ? (w >> 16) : (w & 0xFFFFu);
+// table entries e = (col << 1) | negative in an unsigned type E: uint16_t for a
+// per-spin dimension up to 32767 (padding 0xFFFF), uint32_t beyond it (padding
+// 0xFFFFFFFF).  Kernels read them in chunks of 8 (16 or 32 bytes); every
+// kernel is generic over E, which the table pointer's type selects.
+template <typename E> struct Chunk8 { uint4 q[sizeof(E) / 2]; };
+
+template <typename E> __device__ __forceinline__ constexpr unsigned pad_entry() {
+    return sizeof(E) == 2 ? 0xFFFFu : 0xFFFFFFFFu;
+}
+template <typename E> __device__ __forceinline__ bool is_pad(unsigned e) { return e == pad_entry<E>(); }
+
+template <typename E> __device__ __forceinline__ Chunk8<E> pad_chunk() {
+    Chunk8<E> c;
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(E) / 2); ++i) c.q[i] = make_uint4(~0u, ~0u, ~0u, ~0u);
+    return c;
+}
+
+template <typename E> __device__ __forceinline__ unsigned entry(const Chunk8<E> &c, int k) {
+    if constexpr (sizeof(E) == 2) {
+        const uint4 &q = c.q[0];
+        const unsigned w = k < 2 ? q.x : (k < 4 ? q.y : (k < 6 ? q.z : q.w));
+        return (k & 1) ? (w >> 16) : (w & 0xFFFFu);
+    } else {
+        const uint4 &q = c.q[k >> 2];
+        const int j = k & 3;
+        return j == 0 ? q.x : (j == 1 ? q.y : (j == 2 ? q.z : q.w));
+    }
 }
 
 // One rounding per term: every up-part kernel adds a row's terms as
@@ -53,9 +77,9 @@ __device__ __forceinline__ float fma_t(float a, float b, float c) { return __bui
 // are scalar loads, chunks that are padding for every row of the wave are
 // skipped, and the 8 gathers of a chunk per row are issued back to back
 // (padding inside a chunk re-reads x[0, c] and is multiplied by zero).
-template <typename T, int R>
+template <typename T, int R, typename E>
 __device__ __forceinline__ void up_tile(const T *__restrict__ x, T *__restrict__ out,
-                                        const uint16_t *__restrict__ tab, int Dup, int Ddn, int W8, int rc, int s,
+                                        const E *__restrict__ tab, int Dup, int Ddn, int W8, int rc, int s,
                                         int rci, T t) {
     constexpr int w = 64 / R;
     const int lane = threadIdx.x & 63, nwave = blockDim.x >> 6;
@@ -71,13 +95,13 @@ __device__ __forceinline__ void up_tile(const T *__restrict__ x, T *__restrict__
         const int r = rb + sub;
         T acc = T(0);
         for (int k8 = 0; k8 < nch; ++k8) {
-            uint4 q[R];
+            Chunk8<E> q[R];
             bool any = false;
 #pragma unroll
             for (int u = 0; u < R; ++u) {
                 const int ru = min(rb + u, Dup - 1);
-                q[u] = *reinterpret_cast<const uint4 *>(tab + (int64_t)ru * W8 + 8 * k8);
-                any = any || (entry(q[u], 0) != 0xFFFFu && rb + u < r1);
+                q[u] = *reinterpret_cast<const Chunk8<E> *>(tab + (int64_t)ru * W8 + 8 * k8);
+                any = any || (!is_pad<E>(entry(q[u], 0)) && rb + u < r1);
             }
             if (!any) break;   // ascending columns, padding at the end: the rest is padding too
             T v[8], sg[8];
@@ -87,7 +111,7 @@ __device__ __forceinline__ void up_tile(const T *__restrict__ x, T *__restrict__
 #pragma unroll
                 for (int u = 1; u < R; ++u)
                     if (sub == u) e = entry(q[u], k);
-                const bool pk = e != 0xFFFFu;
+                const bool pk = !is_pad<E>(e);
                 sg[k] = pk ? ((e & 1u) ? T(-1) : T(1)) : T(0);
                 v[k] = xc[(int64_t)(pk ? (e >> 1) : 0u) * Ddn];
             }
@@ -107,14 +131,14 @@ __host__ __device__ constexpr int nch_class(int nch) { return nch <= 1 ? 1 : (nc
 // NCH*8 entries from the row start, which stays inside the packed table: its
 // second (interleaved) half of dim*W8 entries follows the row-major half and
 // NCH*8 - W8 < W8.
-template <int NCH>
-__device__ __forceinline__ void row_chunks(const uint16_t *__restrict__ tab, int row, int W8, int nch,
-                                           uint4 (&q)[NCH]) {
-    const uint4 *p = reinterpret_cast<const uint4 *>(tab + (int64_t)row * W8);
+template <int NCH, typename E>
+__device__ __forceinline__ void row_chunks(const E *__restrict__ tab, int row, int W8, int nch,
+                                           Chunk8<E> (&q)[NCH]) {
+    const Chunk8<E> *p = reinterpret_cast<const Chunk8<E> *>(tab + (int64_t)row * W8);
 #pragma unroll
     for (int k8 = 0; k8 < NCH; ++k8) {
-        const uint4 v = p[k8];
-        q[k8] = k8 < nch ? v : make_uint4(~0u, ~0u, ~0u, ~0u);
+        const Chunk8<E> v = p[k8];
+        q[k8] = k8 < nch ? v : pad_chunk<E>();
     }
 }
 
@@ -122,8 +146,8 @@ __device__ __forceinline__ void row_chunks(const uint16_t *__restrict__ tab, int
 // issued, then the previous row's result is stored (so the store does not
 // sit ahead of these gathers in the in-order memory counter, and its data
 // register is not reused while it is in flight), then the row is summed.
-template <typename T, int NL, int NCH>
-__device__ __forceinline__ void up_row(const T *__restrict__ xs, unsigned cc, int Ddn, const uint4 (&q)[NCH], T t,
+template <typename T, int NL, int NCH, typename E>
+__device__ __forceinline__ void up_row(const T *__restrict__ xs, unsigned cc, int Ddn, const Chunk8<E> (&q)[NCH], T t,
                                        T &pend, T *&pend_ptr, T *row_out) {
     T v[NL > 0 ? NL : 1][8];
 #pragma unroll
@@ -132,7 +156,7 @@ __device__ __forceinline__ void up_row(const T *__restrict__ xs, unsigned cc, in
         for (int k = 0; k < 8; ++k) {
             const unsigned e = entry(q[k8], k);
             // wave-uniform row base, 32-bit lane offset
-            const T *xr = xs + (int64_t)(e != 0xFFFFu ? (e >> 1) : 0u) * Ddn;
+            const T *xr = xs + (int64_t)(!is_pad<E>(e) ? (e >> 1) : 0u) * Ddn;
             v[k8][k] = xr[cc];
         }
     if (pend_ptr) __builtin_nontemporal_store(pend, pend_ptr);
@@ -142,7 +166,7 @@ __device__ __forceinline__ void up_row(const T *__restrict__ xs, unsigned cc, in
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const unsigned e = entry(q[k8], k);
-            const T sg = e == 0xFFFFu ? T(0) : ((e & 1u) ? T(-1) : T(1));
+            const T sg = is_pad<E>(e) ? T(0) : ((e & 1u) ? T(-1) : T(1));
             acc = fma_t(sg, v[k8][k], acc);
         }
     pend = t * acc;
@@ -155,9 +179,9 @@ __device__ __forceinline__ void up_row(const T *__restrict__ xs, unsigned cc, in
 // padding is a suffix) selects straight-line code that issues every gather
 // of the row before the first is consumed.  Padding inside the last live
 // chunk re-reads x[0, c] and is multiplied by zero.
-template <typename T, int NCH>
+template <typename T, int NCH, typename E>
 __device__ __forceinline__ void up_tile_wide(const T *__restrict__ x, T *__restrict__ out,
-                                             const uint16_t *__restrict__ tab, int Dup, int Ddn, int W8, int rc,
+                                             const E *__restrict__ tab, int Dup, int Ddn, int W8, int rc,
                                              int s, int rci, T t) {
     const int lane = threadIdx.x & 63, nwave = blockDim.x >> 6;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -169,27 +193,27 @@ __device__ __forceinline__ void up_tile_wide(const T *__restrict__ x, T *__restr
     const int nch = W8 >> 3;
     int rb = rci * rc + wave;
     if (rb >= r1) return;
-    uint4 q[NCH];
+    Chunk8<E> q[NCH];
     row_chunks<NCH>(tab, rb, W8, nch, q);
     T pend = T(0);
     T *pend_ptr = nullptr;
     for (; rb < r1; rb += nwave) {
         int nl = 0;
 #pragma unroll
-        for (int k8 = 0; k8 < NCH; ++k8) nl += entry(q[k8], 0) != 0xFFFFu ? 1 : 0;
-        uint4 qn[NCH];
+        for (int k8 = 0; k8 < NCH; ++k8) nl += !is_pad<E>(entry(q[k8], 0)) ? 1 : 0;
+        Chunk8<E> qn[NCH];
         row_chunks<NCH>(tab, min(rb + nwave, r1 - 1), W8, nch, qn);
         T *row_out = cok ? out + (int64_t)rb * Ddn + c : nullptr;
         switch (nl) {
-        case 0: up_row<T, 0, NCH>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
-        case 1: up_row<T, 1, NCH>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
-        case 2: if constexpr (NCH >= 2) up_row<T, 2, NCH>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
-        case 3: if constexpr (NCH >= 4) up_row<T, 3, NCH>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
-        case 4: if constexpr (NCH >= 4) up_row<T, 4, NCH>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
-        case 5: if constexpr (NCH >= 8) up_row<T, 5, NCH>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
-        case 6: if constexpr (NCH >= 8) up_row<T, 6, NCH>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
-        case 7: if constexpr (NCH >= 8) up_row<T, 7, NCH>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
-        default: if constexpr (NCH >= 8) up_row<T, 8, NCH>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
+        case 0: up_row<T, 0, NCH, E>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
+        case 1: up_row<T, 1, NCH, E>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
+        case 2: if constexpr (NCH >= 2) up_row<T, 2, NCH, E>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
+        case 3: if constexpr (NCH >= 4) up_row<T, 3, NCH, E>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
+        case 4: if constexpr (NCH >= 4) up_row<T, 4, NCH, E>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
+        case 5: if constexpr (NCH >= 8) up_row<T, 5, NCH, E>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
+        case 6: if constexpr (NCH >= 8) up_row<T, 6, NCH, E>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
+        case 7: if constexpr (NCH >= 8) up_row<T, 7, NCH, E>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
+        default: if constexpr (NCH >= 8) up_row<T, 8, NCH, E>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
         }
 #pragma unroll
         for (int k8 = 0; k8 < NCH; ++k8) q[k8] = qn[k8];
@@ -214,8 +238,8 @@ template <typename VT> __device__ __forceinline__ auto vcomp(const VT &v, int i)
     else return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
 }
 
-template <typename T, int V, int NL, int NCH>
-__device__ __forceinline__ void up_rowv(const T *__restrict__ xs, unsigned cc, int Ddn, const uint4 (&q)[NCH], T t,
+template <typename T, int V, int NL, int NCH, typename E>
+__device__ __forceinline__ void up_rowv(const T *__restrict__ xs, unsigned cc, int Ddn, const Chunk8<E> (&q)[NCH], T t,
                                         T (&pend)[V], T *&pend_ptr, T *row_out) {
     using VT = typename VecT<T, V>::type;
     VT v[NL > 0 ? NL : 1][8];
@@ -224,7 +248,7 @@ __device__ __forceinline__ void up_rowv(const T *__restrict__ xs, unsigned cc, i
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const unsigned e = entry(q[k8], k);
-            const T *xr = xs + (int64_t)(e != 0xFFFFu ? (e >> 1) : 0u) * Ddn;
+            const T *xr = xs + (int64_t)(!is_pad<E>(e) ? (e >> 1) : 0u) * Ddn;
             v[k8][k] = *reinterpret_cast<const VT *>(xr + cc);
         }
     if (pend_ptr) {
@@ -239,7 +263,7 @@ __device__ __forceinline__ void up_rowv(const T *__restrict__ xs, unsigned cc, i
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const unsigned e = entry(q[k8], k);
-            const T sg = e == 0xFFFFu ? T(0) : ((e & 1u) ? T(-1) : T(1));
+            const T sg = is_pad<E>(e) ? T(0) : ((e & 1u) ? T(-1) : T(1));
 #pragma unroll
             for (int i = 0; i < V; ++i) a[i] = fma_t(sg, vcomp(v[k8][k], i), a[i]);
         }
@@ -248,9 +272,9 @@ __device__ __forceinline__ void up_rowv(const T *__restrict__ xs, unsigned cc, i
     pend_ptr = row_out;
 }
 
-template <typename T, int V, int NCH>
+template <typename T, int V, int NCH, typename E>
 __device__ __forceinline__ void up_tile_vec(const T *__restrict__ x, T *__restrict__ out,
-                                            const uint16_t *__restrict__ tab, int Dup, int Ddn, int W8, int rc,
+                                            const E *__restrict__ tab, int Dup, int Ddn, int W8, int rc,
                                             int s, int rci, T t) {
     const int lane = threadIdx.x & 63, nwave = blockDim.x >> 6;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -262,7 +286,7 @@ __device__ __forceinline__ void up_tile_vec(const T *__restrict__ x, T *__restri
     const int nch = W8 >> 3;
     int rb = rci * rc + wave;
     if (rb >= r1) return;
-    uint4 q[NCH];
+    Chunk8<E> q[NCH];
     row_chunks<NCH>(tab, rb, W8, nch, q);
     T pend[V];
 #pragma unroll
@@ -271,16 +295,16 @@ __device__ __forceinline__ void up_tile_vec(const T *__restrict__ x, T *__restri
     for (; rb < r1; rb += nwave) {
         int nl = 0;
 #pragma unroll
-        for (int k8 = 0; k8 < NCH; ++k8) nl += entry(q[k8], 0) != 0xFFFFu ? 1 : 0;
-        uint4 qn[NCH];
+        for (int k8 = 0; k8 < NCH; ++k8) nl += !is_pad<E>(entry(q[k8], 0)) ? 1 : 0;
+        Chunk8<E> qn[NCH];
         row_chunks<NCH>(tab, min(rb + nwave, r1 - 1), W8, nch, qn);
         T *row_out = cok ? out + (int64_t)rb * Ddn + c : nullptr;
         switch (nl) {
-        case 0: up_rowv<T, V, 0, NCH>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
-        case 1: up_rowv<T, V, 1, NCH>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
-        case 2: if constexpr (NCH >= 2) up_rowv<T, V, 2, NCH>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
-        case 3: if constexpr (NCH >= 4) up_rowv<T, V, 3, NCH>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
-        default: if constexpr (NCH >= 4) up_rowv<T, V, 4, NCH>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
+        case 0: up_rowv<T, V, 0, NCH, E>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
+        case 1: up_rowv<T, V, 1, NCH, E>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
+        case 2: if constexpr (NCH >= 2) up_rowv<T, V, 2, NCH, E>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
+        case 3: if constexpr (NCH >= 4) up_rowv<T, V, 3, NCH, E>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
+        default: if constexpr (NCH >= 4) up_rowv<T, V, 4, NCH, E>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
         }
 #pragma unroll
         for (int k8 = 0; k8 < NCH; ++k8) q[k8] = qn[k8];
@@ -299,16 +323,16 @@ __device__ __forceinline__ void up_tile_vec(const T *__restrict__ x, T *__restri
 // consumed (the chunk count is the larger of the two rows').  A row beyond the
 // tile or the table reads as padding (its chunks are loaded from a valid row
 // and discarded).  Used for tables of at most 4 chunks (scalar registers).
-template <typename T, int NL, int NCH>
-__device__ __forceinline__ void up_pair(const T *__restrict__ xc, int Ddn, bool hi, const uint4 (&qa)[NCH],
-                                        const uint4 (&qb)[NCH], T t, T &pend, T *&pend_ptr, T *row_out) {
+template <typename T, int NL, int NCH, typename E>
+__device__ __forceinline__ void up_pair(const T *__restrict__ xc, int Ddn, bool hi, const Chunk8<E> (&qa)[NCH],
+                                        const Chunk8<E> (&qb)[NCH], T t, T &pend, T *&pend_ptr, T *row_out) {
     T v[NL > 0 ? NL : 1][8];
 #pragma unroll
     for (int k8 = 0; k8 < NL; ++k8)
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const unsigned e = hi ? entry(qb[k8], k) : entry(qa[k8], k);
-            v[k8][k] = xc[(int64_t)(e != 0xFFFFu ? (e >> 1) : 0u) * Ddn];
+            v[k8][k] = xc[(int64_t)(!is_pad<E>(e) ? (e >> 1) : 0u) * Ddn];
         }
     if (pend_ptr) __builtin_nontemporal_store(pend, pend_ptr);
     T acc = T(0);
@@ -317,24 +341,24 @@ __device__ __forceinline__ void up_pair(const T *__restrict__ xc, int Ddn, bool 
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const unsigned e = hi ? entry(qb[k8], k) : entry(qa[k8], k);
-            const T sg = e == 0xFFFFu ? T(0) : ((e & 1u) ? T(-1) : T(1));
+            const T sg = is_pad<E>(e) ? T(0) : ((e & 1u) ? T(-1) : T(1));
             acc = fma_t(sg, v[k8][k], acc);
         }
     pend = t * acc;
     pend_ptr = row_out;
 }
 
-template <int NCH>
-__device__ __forceinline__ int live_chunks(const uint4 (&q)[NCH]) {
+template <int NCH, typename E>
+__device__ __forceinline__ int live_chunks(const Chunk8<E> (&q)[NCH]) {
     int n = 0;
 #pragma unroll
-    for (int k8 = 0; k8 < NCH; ++k8) n += entry(q[k8], 0) != 0xFFFFu ? 1 : 0;
+    for (int k8 = 0; k8 < NCH; ++k8) n += !is_pad<E>(entry(q[k8], 0)) ? 1 : 0;
     return n;
 }
 
-template <typename T, int NCH>
+template <typename T, int NCH, typename E>
 __device__ __forceinline__ void up_tile_pair(const T *__restrict__ x, T *__restrict__ out,
-                                             const uint16_t *__restrict__ tab, int Dup, int Ddn, int W8, int rc,
+                                             const E *__restrict__ tab, int Dup, int Ddn, int W8, int rc,
                                              int s, int rci, T t) {
     static_assert(NCH <= 4, "two rows of scalar table chunks");
     const int lane = threadIdx.x & 63, nwave = blockDim.x >> 6;
@@ -347,25 +371,25 @@ __device__ __forceinline__ void up_tile_pair(const T *__restrict__ x, T *__restr
     const int nch = W8 >> 3;
     int rb = rci * rc + 2 * wave;
     if (rb >= r1) return;
-    uint4 qa[NCH], qb[NCH];
+    Chunk8<E> qa[NCH], qb[NCH];
     row_chunks<NCH>(tab, rb, W8, nch, qa);
     row_chunks<NCH>(tab, min(rb + 1, Dup - 1), W8, rb + 1 < r1 ? nch : 0, qb);
     T pend = T(0);
     T *pend_ptr = nullptr;
     for (; rb < r1; rb += 2 * nwave) {
-        const int nl = max(live_chunks<NCH>(qa), live_chunks<NCH>(qb));
+        const int nl = max(live_chunks(qa), live_chunks(qb));
         const int rn = min(rb + 2 * nwave, r1 - 1);
-        uint4 qan[NCH], qbn[NCH];
+        Chunk8<E> qan[NCH], qbn[NCH];
         row_chunks<NCH>(tab, rn, W8, nch, qan);
         row_chunks<NCH>(tab, min(rn + 1, Dup - 1), W8, rn + 1 < r1 ? nch : 0, qbn);
         const int r = rb + (hi ? 1 : 0);
         T *row_out = (cok && r < r1) ? out + (int64_t)r * Ddn + c : nullptr;
         switch (nl) {
-        case 0: up_pair<T, 0, NCH>(xc, Ddn, hi, qa, qb, t, pend, pend_ptr, row_out); break;
-        case 1: up_pair<T, 1, NCH>(xc, Ddn, hi, qa, qb, t, pend, pend_ptr, row_out); break;
-        case 2: if constexpr (NCH >= 2) up_pair<T, 2, NCH>(xc, Ddn, hi, qa, qb, t, pend, pend_ptr, row_out); break;
-        case 3: if constexpr (NCH >= 4) up_pair<T, 3, NCH>(xc, Ddn, hi, qa, qb, t, pend, pend_ptr, row_out); break;
-        default: if constexpr (NCH >= 4) up_pair<T, 4, NCH>(xc, Ddn, hi, qa, qb, t, pend, pend_ptr, row_out); break;
+        case 0: up_pair<T, 0, NCH, E>(xc, Ddn, hi, qa, qb, t, pend, pend_ptr, row_out); break;
+        case 1: up_pair<T, 1, NCH, E>(xc, Ddn, hi, qa, qb, t, pend, pend_ptr, row_out); break;
+        case 2: if constexpr (NCH >= 2) up_pair<T, 2, NCH, E>(xc, Ddn, hi, qa, qb, t, pend, pend_ptr, row_out); break;
+        case 3: if constexpr (NCH >= 4) up_pair<T, 3, NCH, E>(xc, Ddn, hi, qa, qb, t, pend, pend_ptr, row_out); break;
+        default: if constexpr (NCH >= 4) up_pair<T, 4, NCH, E>(xc, Ddn, hi, qa, qb, t, pend, pend_ptr, row_out); break;
         }
 #pragma unroll
         for (int k8 = 0; k8 < NCH; ++k8) {
@@ -383,16 +407,20 @@ __device__ __forceinline__ void up_tile_pair(const T *__restrict__ x, T *__restr
 // address space unknown and turn the 16-byte load into flat dword loads, and
 // a branch around the load would make the wait counts inexact.  NCH = 0 is the
 // variant for a species without hopping, which may pass no table at all.
-template <int NCH>
-__device__ __forceinline__ uint4 table_chunk(const uint4 *__restrict__ til, int k8, int nch, int Ddn, int c) {
+template <int NCH, typename E>
+__device__ __forceinline__ Chunk8<E> table_chunk(const Chunk8<E> *__restrict__ til, int k8, int nch, int Ddn,
+                                                 int c) {
     if constexpr (NCH == 0) {
-        return make_uint4(~0u, ~0u, ~0u, ~0u);
+        return pad_chunk<E>();
     } else {
         // padding is all ones: OR it in, so the load is always consumed and
         // the compiler cannot sink it into a branch
         const unsigned m = k8 < nch ? 0u : ~0u;
-        const uint4 v = til[(int64_t)(k8 < nch ? k8 : 0) * Ddn + c];
-        return make_uint4(v.x | m, v.y | m, v.z | m, v.w | m);
+        Chunk8<E> v = til[(int64_t)(k8 < nch ? k8 : 0) * Ddn + c];
+#pragma unroll
+        for (int i = 0; i < (int)(sizeof(E) / 2); ++i)
+            v.q[i] = make_uint4(v.q[i].x | m, v.q[i].y | m, v.q[i].z | m, v.q[i].w | m);
+        return v;
     }
 }
 
@@ -445,13 +473,13 @@ __device__ __forceinline__ void stage_rows(const T *__restrict__ src, T *__restr
 // down-part + U Docc x) - cprev * p, in place on io; per-thread partial sums
 // added to s[].  xrows: the rows (LDS copy or global); base: offset of row r0
 // in the global vectors.
-template <typename T, int MODE, int NCH, bool MULTI>
+template <typename T, int MODE, int NCH, bool MULTI, typename E>
 __device__ __forceinline__ void down_rows(const T *__restrict__ xrows, T *__restrict__ io, const T *__restrict__ p,
-                                          const uint16_t *__restrict__ tab, const uint64_t *__restrict__ st_up_r0,
+                                          const E *__restrict__ tab, const uint64_t *__restrict__ st_up_r0,
                                           const uint64_t *__restrict__ st_dn, int Ddn, int W8, int nr,
                                           int64_t base, T t, T U, T sig, T cprev, bool use_p,
                                           double (&s)[MODE == 2 ? 5 : 1]) {
-    const uint4 *til = reinterpret_cast<const uint4 *>(tab + (int64_t)Ddn * W8);   // 8-interleaved part
+    const Chunk8<E> *til = reinterpret_cast<const Chunk8<E> *>(tab + (int64_t)Ddn * W8);   // 8-interleaved part
     const int nch = W8 >> 3;
     const int n = nr * Ddn;
     // Every global operand of a column (table chunks, up part, f_{j-1}, the
@@ -466,13 +494,13 @@ __device__ __forceinline__ void down_rows(const T *__restrict__ xrows, T *__rest
     int i = threadIdx.x;
     if (i >= n) return;
     const uint64_t su0 = st_up_r0[0];
-    uint4 tq[NCH > 0 ? NCH : 1];
+    Chunk8<E> tq[NCH > 0 ? NCH : 1];
     T iov, pv;
     uint64_t sdv, suv = su0;
     int c, rr;
     if constexpr (MULTI) { rr = i / Ddn; c = i - rr * Ddn; } else { rr = 0; c = i; }
 #pragma unroll
-    for (int k8 = 0; k8 < NCH; ++k8) tq[k8] = table_chunk<NCH>(til, k8, nch, Ddn, c);
+    for (int k8 = 0; k8 < NCH; ++k8) tq[k8] = table_chunk<NCH, E>(til, k8, nch, Ddn, c);
     iov = io[base + i];
     if constexpr (MODE != 0) pv = keep_or_zero(p[base + i], use_p); else pv = T(0);
     sdv = st_dn[c];
@@ -481,9 +509,9 @@ __device__ __forceinline__ void down_rows(const T *__restrict__ xrows, T *__rest
         const int in = min(i + (int)blockDim.x, n - 1);
         int cn, rrn;
         if constexpr (MULTI) { rrn = in / Ddn; cn = in - rrn * Ddn; } else { rrn = 0; cn = in; }
-        uint4 tqn[NCH > 0 ? NCH : 1];
+        Chunk8<E> tqn[NCH > 0 ? NCH : 1];
 #pragma unroll
-        for (int k8 = 0; k8 < NCH; ++k8) tqn[k8] = table_chunk<NCH>(til, k8, nch, Ddn, cn);
+        for (int k8 = 0; k8 < NCH; ++k8) tqn[k8] = table_chunk<NCH, E>(til, k8, nch, Ddn, cn);
         const T iovn = io[base + in];
         T pvn;
         if constexpr (MODE != 0) pvn = keep_or_zero(p[base + in], use_p); else pvn = T(0);
@@ -497,12 +525,12 @@ __device__ __forceinline__ void down_rows(const T *__restrict__ xrows, T *__rest
             if (k8 >= nch) break;
             // a chunk whose first entry is padding is padding throughout; skip it
             // when that holds for every lane of the wave
-            if (!__any(entry(tq[k8], 0) != 0xFFFFu)) break;
+            if (!__any(!is_pad<E>(entry(tq[k8], 0)))) break;
             T v[8], sg[8];
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 const unsigned e = entry(tq[k8], k);
-                const bool pk = e != 0xFFFFu;
+                const bool pk = !is_pad<E>(e);
                 sg[k] = pk ? ((e & 1u) ? T(-1) : T(1)) : T(0);
                 v[k] = xrow[pk ? (int)(e >> 1) : 0];   // padding: one broadcast address
             }

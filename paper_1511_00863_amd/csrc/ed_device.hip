@@ -102,9 +102,24 @@ __device__ __forceinline__ bool frozen(const Hdr *hdr, int max_steps) {
     return hdr->status != 0 || hdr->jdev >= max_steps;
 }
 
-template <typename T, int R, int NCH>
+// Which up-part tile a (R, NCH, E) variant runs: one row per wave with all
+// chunks in scalar registers, two rows per wave (16-bit tables of at most 4
+// chunks), or the chunk-at-a-time tile otherwise (32-bit tables of 8 chunks
+// would not fit the scalar registers of the one-row kernel).
+template <typename T, int R, int NCH, typename E>
+__device__ __forceinline__ void up_tile_any(const T *__restrict__ x, T *__restrict__ out, const E *__restrict__ tab,
+                                            int Dup, int Ddn, int W8, int rc, int s, int rci, T t) {
+    if constexpr (R == 1 && (sizeof(E) == 2 || NCH <= 4))
+        up_tile_wide<T, NCH>(x, out, tab, Dup, Ddn, W8, rc, s, rci, t);
+    else if constexpr (R == 2 && NCH <= 4 && sizeof(E) == 2)
+        up_tile_pair<T, NCH>(x, out, tab, Dup, Ddn, W8, rc, s, rci, t);
+    else
+        up_tile<T, R>(x, out, tab, Dup, Ddn, W8, rc, s, rci, t);
+}
+
+template <typename T, int R, int NCH, typename E>
 __global__ __launch_bounds__(512) void k_up(const T *__restrict__ x, T *__restrict__ out,
-                                            const uint16_t *__restrict__ tab, int Dup, int Ddn, int W8, int rc,
+                                            const E *__restrict__ tab, int Dup, int Ddn, int W8, int rc,
                                             int n_stripes, int n_rc, int map, T t, const Hdr *__restrict__ hdr,
                                             int gate, int max_steps) {
     if (gate && frozen(hdr, max_steps)) return;
@@ -119,18 +134,13 @@ __global__ __launch_bounds__(512) void k_up(const T *__restrict__ x, T *__restri
         rci = blockIdx.x - s * n_rc;
     }
     if (s >= n_stripes) return;
-    if constexpr (R == 1)
-        up_tile_wide<T, NCH>(x, out, tab, Dup, Ddn, W8, rc, s, rci, t);
-    else if constexpr (R == 2 && NCH <= 4)
-        up_tile_pair<T, NCH>(x, out, tab, Dup, Ddn, W8, rc, s, rci, t);
-    else
-        up_tile<T, R>(x, out, tab, Dup, Ddn, W8, rc, s, rci, t);
+    up_tile_any<T, R, NCH>(x, out, tab, Dup, Ddn, W8, rc, s, rci, t);
 }
 
 // k_upv: k_up's tiling with 64*V-column stripes (V columns per lane).
-template <typename T, int V, int NCH>
+template <typename T, int V, int NCH, typename E>
 __global__ __launch_bounds__(512) void k_upv(const T *__restrict__ x, T *__restrict__ out,
-                                             const uint16_t *__restrict__ tab, int Dup, int Ddn, int W8, int rc,
+                                             const E *__restrict__ tab, int Dup, int Ddn, int W8, int rc,
                                              int n_stripes, int n_rc, int map, T t, const Hdr *__restrict__ hdr,
                                              int gate, int max_steps) {
     if (gate && frozen(hdr, max_steps)) return;
@@ -152,9 +162,9 @@ __global__ __launch_bounds__(512) void k_upv(const T *__restrict__ x, T *__restr
 // the stripes s = q (mod 8).  A workgroup reads the XCD it runs on from the
 // XCC_ID hardware register, drains that XCD's queue (integer atomics), then
 // helps the other queues, so every tile is processed whatever the dispatch.
-template <typename T, int R, int NCH>
+template <typename T, int R, int NCH, typename E>
 __global__ __launch_bounds__(512) void k_up_q(const T *__restrict__ x, T *__restrict__ out,
-                                              const uint16_t *__restrict__ tab, int Dup, int Ddn, int W8, int rc,
+                                              const E *__restrict__ tab, int Dup, int Ddn, int W8, int rc,
                                               int n_stripes, int n_rc, T t, int *__restrict__ ctr,
                                               const Hdr *__restrict__ hdr, int gate, int max_steps) {
     if (gate && frozen(hdr, max_steps)) return;
@@ -170,12 +180,7 @@ __global__ __launch_bounds__(512) void k_up_q(const T *__restrict__ x, T *__rest
             __syncthreads();
             if (tq >= ntiles) break;
             const int sl = tq / n_rc;
-            if constexpr (R == 1)
-                up_tile_wide<T, NCH>(x, out, tab, Dup, Ddn, W8, rc, q + 8 * sl, tq - sl * n_rc, t);
-            else if constexpr (R == 2 && NCH <= 4)
-                up_tile_pair<T, NCH>(x, out, tab, Dup, Ddn, W8, rc, q + 8 * sl, tq - sl * n_rc, t);
-            else
-                up_tile<T, R>(x, out, tab, Dup, Ddn, W8, rc, q + 8 * sl, tq - sl * n_rc, t);
+            up_tile_any<T, R, NCH>(x, out, tab, Dup, Ddn, W8, rc, q + 8 * sl, tq - sl * n_rc, t);
         }
     }
 }
@@ -186,11 +191,14 @@ __global__ void k_ctr_reset(int *ctr, const Hdr *hdr, int gate, int max_steps) {
 }
 
 // float rows are half the size: three 512-thread workgroups fit a CU's LDS,
-// which needs at most 80 VGPRs (6 waves per SIMD)
-template <typename T, int MODE, bool LDS, int NCH, bool MULTI>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NCH <= 4 ? 6 : 1)))
+// which needs at most 80 VGPRs (6 waves per SIMD).  32-bit tables double the
+// registers of the prefetched table chunks: workgroups of at most 512 threads
+// (256 VGPRs) and no occupancy target.
+template <typename T, int MODE, bool LDS, int NCH, bool MULTI, typename E>
+__global__ __launch_bounds__(sizeof(E) == 4 ? 512 : 1024)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NCH <= 4 && sizeof(E) == 2 ? 6 : 1)))
 void k_down(const T *__restrict__ x, T *__restrict__ io, const T *__restrict__ p,
-                                               const uint16_t *__restrict__ tab,
+                                               const E *__restrict__ tab,
                                                const uint64_t *__restrict__ st_up,
                                                const uint64_t *__restrict__ st_dn, int Dup, int Ddn, int W8,
                                                int rpb, T t, T U, const double *__restrict__ bvec,
@@ -402,7 +410,7 @@ static int grid_for(int64_t n, int block, int cap = 4096) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
 }
 
-template <typename T, int R, int NCH>
+template <typename T, int R, int NCH, typename E>
 static int up_queue_grid(int block) {
     static int cached = 0;
     if (cached) return cached;
@@ -410,45 +418,46 @@ static int up_queue_grid(int block) {
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void *>(k_up_q<T, R, NCH>), block,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void *>(k_up_q<T, R, NCH, E>), block,
                                                      0) != hipSuccess)
         return 0;
     cached = std::max(1, ncu * std::max(1, occ));
     return cached;
 }
 
-template <typename T, int R, int NCH>
+template <typename T, int R, int NCH, typename E>
 static int launch_up_r(const ed_ham *h, const Tile &tl, const T *x, T *out, int *ctr, const Hdr *hdr, int gate,
                        int max_steps, hipStream_t s) {
     constexpr int w = 64 / R;
+    const E *tab = static_cast<const E *>(h->tab_up);
     const int n_stripes = (int)((h->dim_dn + w - 1) / w);
     const int n_rc = (int)((h->dim_up + tl.up_rc - 1) / tl.up_rc);
     const T t = static_cast<T>(h->t);
     if (tl.up_map == 2) {
         if (!ctr) return set_error(ED_EINVAL, "k_up_q needs the workspace");
         const int total = n_stripes * n_rc;
-        int grid = up_queue_grid<T, R, NCH>(tl.up_block);
+        int grid = up_queue_grid<T, R, NCH, E>(tl.up_block);
         if (grid <= 0) return set_error(ED_EDEVICE, "occupancy query for k_up_q failed");
         grid = std::min(grid, total);
         hipLaunchKernelGGL(k_ctr_reset, dim3(1), dim3(64), 0, s, ctr, hdr, gate, max_steps);
         ED_LAUNCHED("k_ctr_reset");
-        hipLaunchKernelGGL((k_up_q<T, R, NCH>), dim3(grid), dim3(tl.up_block), 0, s, x, out, h->tab_up, (int)h->dim_up,
+        hipLaunchKernelGGL((k_up_q<T, R, NCH, E>), dim3(grid), dim3(tl.up_block), 0, s, x, out, tab, (int)h->dim_up,
                            (int)h->dim_dn, h->w_up, tl.up_rc, n_stripes, n_rc, t, ctr, hdr, gate, max_steps);
         ED_LAUNCHED("k_up_q");
         return ED_OK;
     }
     const int64_t grid = tl.up_map == 0 ? 8LL * n_rc * ((n_stripes + 7) / 8) : (int64_t)n_rc * n_stripes;
     if (grid > 0x7fffffffLL) return set_error(ED_EOVERFLOW, "k_up grid too large");
-    hipLaunchKernelGGL((k_up<T, R, NCH>), dim3((unsigned)grid), dim3(tl.up_block), 0, s, x, out, h->tab_up,
+    hipLaunchKernelGGL((k_up<T, R, NCH, E>), dim3((unsigned)grid), dim3(tl.up_block), 0, s, x, out, tab,
                        (int)h->dim_up, (int)h->dim_dn, h->w_up, tl.up_rc, n_stripes, n_rc, tl.up_map, t, hdr, gate,
                        max_steps);
     ED_LAUNCHED("k_up");
     return ED_OK;
 }
 
-template <typename T>
-static int launch_up(const ed_ham *h, const Tile &tl, const T *x, T *out, int *ctr, const Hdr *hdr, int gate,
-                     int max_steps, hipStream_t s) {
+template <typename T, typename E>
+static int launch_up_e(const ed_ham *h, const Tile &tl, const T *x, T *out, int *ctr, const Hdr *hdr, int gate,
+                       int max_steps, hipStream_t s) {
     if (h->w_up == 0) {   // no up hopping: out = 0
         hipLaunchKernelGGL(k_fill0<T>, dim3(grid_for(h->dim_up * h->dim_dn, 256)), dim3(256), 0, s, out,
                            h->dim_up * h->dim_dn);
@@ -465,10 +474,11 @@ static int launch_up(const ed_ham *h, const Tile &tl, const T *x, T *out, int *c
         const int map = tl.up_map == 0 ? 0 : 1;
         const int nc = nch_class(h->w_up >> 3);
 #define ED_UPV(V, N)                                                                                          \
-    hipLaunchKernelGGL((k_upv<T, V, N>), dim3((unsigned)grid), dim3(tl.up_block), 0, s, x, out, h->tab_up,      \
+    hipLaunchKernelGGL((k_upv<T, V, N, E>), dim3((unsigned)grid), dim3(tl.up_block), 0, s, x, out,              \
+                       static_cast<const E *>(h->tab_up),                                                      \
                        (int)h->dim_up, (int)h->dim_dn, h->w_up, tl.up_rc, n_stripes, n_rc, map, t, hdr, gate,  \
                        max_steps)
-        if constexpr (sizeof(T) == 4) {
+        if constexpr (sizeof(T) == 4 && sizeof(E) == 2) {
             if (tl.up_wlog2 == 8) {
                 if (nc == 1) ED_UPV(4, 1); else if (nc == 2) ED_UPV(4, 2); else ED_UPV(4, 4);
                 ED_LAUNCHED("k_upv");
@@ -483,53 +493,81 @@ static int launch_up(const ed_ham *h, const Tile &tl, const T *x, T *out, int *c
     switch (tl.up_wlog2) {
     case 6:
         switch (nch_class(h->w_up >> 3)) {
-        case 1: return launch_up_r<T, 1, 1>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
-        case 2: return launch_up_r<T, 1, 2>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
-        case 4: return launch_up_r<T, 1, 4>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
-        default: return launch_up_r<T, 1, 8>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
+        case 1: return launch_up_r<T, 1, 1, E>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
+        case 2: return launch_up_r<T, 1, 2, E>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
+        case 4: return launch_up_r<T, 1, 4, E>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
+        default: return launch_up_r<T, 1, 8, E>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
         }
     case 5:
+        if constexpr (sizeof(E) == 4)   // chunk-at-a-time tile: one variant serves every width
+            return launch_up_r<T, 2, 8, E>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
         switch (nch_class(h->w_up >> 3)) {
-        case 1: return launch_up_r<T, 2, 1>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
-        case 2: return launch_up_r<T, 2, 2>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
-        case 4: return launch_up_r<T, 2, 4>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
-        default: return launch_up_r<T, 2, 8>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
+        case 1: return launch_up_r<T, 2, 1, E>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
+        case 2: return launch_up_r<T, 2, 2, E>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
+        case 4: return launch_up_r<T, 2, 4, E>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
+        default: return launch_up_r<T, 2, 8, E>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
         }
-    default: return launch_up_r<T, 4, 1>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
+    default: return launch_up_r<T, 4, 1, E>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
     }
 }
 
-template <typename T, int MODE, bool LDS, int NCH>
+template <typename T>
+static int launch_up(const ed_ham *h, const Tile &tl, const T *x, T *out, int *ctr, const Hdr *hdr, int gate,
+                     int max_steps, hipStream_t s) {
+    if (wide_up(h)) return launch_up_e<T, uint32_t>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
+    return launch_up_e<T, uint16_t>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
+}
+
+template <typename T, int MODE, bool LDS, int NCH, typename E>
 static void launch_down_k(const ed_ham *h, const Tile &tl, int grid, int rpb, size_t shm, const T *x, T *io,
                           const T *p, const double *bvec, const Hdr *hdr, double *part, int max_steps,
                           hipStream_t s) {
+    const E *tab = static_cast<const E *>(h->tab_dn);
     if (rpb > 1)
-        hipLaunchKernelGGL((k_down<T, MODE, LDS, NCH, true>), dim3(grid), dim3(tl.dn_block), shm, s, x, io, p,
-                           h->tab_dn, h->st_up, h->st_dn, (int)h->dim_up, (int)h->dim_dn, h->w_dn, rpb,
+        hipLaunchKernelGGL((k_down<T, MODE, LDS, NCH, true, E>), dim3(grid), dim3(tl.dn_block), shm, s, x, io, p,
+                           tab, h->st_up, h->st_dn, (int)h->dim_up, (int)h->dim_dn, h->w_dn, rpb,
                            static_cast<T>(h->t), static_cast<T>(h->U), bvec, hdr, part, max_steps);
     else
-        hipLaunchKernelGGL((k_down<T, MODE, LDS, NCH, false>), dim3(grid), dim3(tl.dn_block), shm, s, x, io, p,
-                           h->tab_dn, h->st_up, h->st_dn, (int)h->dim_up, (int)h->dim_dn, h->w_dn, rpb,
+        hipLaunchKernelGGL((k_down<T, MODE, LDS, NCH, false, E>), dim3(grid), dim3(tl.dn_block), shm, s, x, io, p,
+                           tab, h->st_up, h->st_dn, (int)h->dim_up, (int)h->dim_dn, h->w_dn, rpb,
                            static_cast<T>(h->t), static_cast<T>(h->U), bvec, hdr, part, max_steps);
 }
 
-template <typename T, int MODE>
-static int launch_down(const ed_ham *h, const Tile &tl, const T *x, T *io, const T *p, const double *bvec,
-                       const Hdr *hdr, double *part, int max_steps, hipStream_t s) {
+template <typename T, int MODE, typename E>
+static int launch_down_e(const ed_ham *h, const Tile &tl, const T *x, T *io, const T *p, const double *bvec,
+                         const Hdr *hdr, double *part, int max_steps, hipStream_t s) {
     const int64_t row_bytes = h->dim_dn * (int64_t)sizeof(T);
     const bool lds = row_bytes * tl.dn_rpb <= kLdsBudget;
     const int rpb = lds ? tl.dn_rpb : 1;
     const int grid = (int)((h->dim_up + rpb - 1) / rpb);
     const size_t shm = lds ? (size_t)(row_bytes * rpb) : 0;
     const int nch = h->w_dn >> 3;
-    if (!lds && nch == 0) launch_down_k<T, MODE, false, 0>(h, tl, grid, 1, 0, x, io, p, bvec, hdr, part, max_steps, s);
-    else if (!lds) launch_down_k<T, MODE, false, 8>(h, tl, grid, 1, 0, x, io, p, bvec, hdr, part, max_steps, s);
-    else if (nch == 0) launch_down_k<T, MODE, true, 0>(h, tl, grid, rpb, shm, x, io, p, bvec, hdr, part, max_steps, s);
-    else if (nch <= 2) launch_down_k<T, MODE, true, 2>(h, tl, grid, rpb, shm, x, io, p, bvec, hdr, part, max_steps, s);
-    else if (nch <= 4) launch_down_k<T, MODE, true, 4>(h, tl, grid, rpb, shm, x, io, p, bvec, hdr, part, max_steps, s);
-    else launch_down_k<T, MODE, true, 8>(h, tl, grid, rpb, shm, x, io, p, bvec, hdr, part, max_steps, s);
+    if constexpr (sizeof(E) == 4) {   // no one-size variant without LDS: its chunk registers would spill
+        if (!lds && nch == 0) launch_down_k<T, MODE, false, 0, E>(h, tl, grid, 1, 0, x, io, p, bvec, hdr, part, max_steps, s);
+        else if (!lds && nch <= 2) launch_down_k<T, MODE, false, 2, E>(h, tl, grid, 1, 0, x, io, p, bvec, hdr, part, max_steps, s);
+        else if (!lds && nch <= 4) launch_down_k<T, MODE, false, 4, E>(h, tl, grid, 1, 0, x, io, p, bvec, hdr, part, max_steps, s);
+        else if (!lds) launch_down_k<T, MODE, false, 8, E>(h, tl, grid, 1, 0, x, io, p, bvec, hdr, part, max_steps, s);
+        else if (nch == 0) launch_down_k<T, MODE, true, 0, E>(h, tl, grid, rpb, shm, x, io, p, bvec, hdr, part, max_steps, s);
+        else if (nch <= 2) launch_down_k<T, MODE, true, 2, E>(h, tl, grid, rpb, shm, x, io, p, bvec, hdr, part, max_steps, s);
+        else if (nch <= 4) launch_down_k<T, MODE, true, 4, E>(h, tl, grid, rpb, shm, x, io, p, bvec, hdr, part, max_steps, s);
+        else launch_down_k<T, MODE, true, 8, E>(h, tl, grid, rpb, shm, x, io, p, bvec, hdr, part, max_steps, s);
+    } else {
+        if (!lds && nch == 0) launch_down_k<T, MODE, false, 0, E>(h, tl, grid, 1, 0, x, io, p, bvec, hdr, part, max_steps, s);
+        else if (!lds) launch_down_k<T, MODE, false, 8, E>(h, tl, grid, 1, 0, x, io, p, bvec, hdr, part, max_steps, s);
+        else if (nch == 0) launch_down_k<T, MODE, true, 0, E>(h, tl, grid, rpb, shm, x, io, p, bvec, hdr, part, max_steps, s);
+        else if (nch <= 2) launch_down_k<T, MODE, true, 2, E>(h, tl, grid, rpb, shm, x, io, p, bvec, hdr, part, max_steps, s);
+        else if (nch <= 4) launch_down_k<T, MODE, true, 4, E>(h, tl, grid, rpb, shm, x, io, p, bvec, hdr, part, max_steps, s);
+        else launch_down_k<T, MODE, true, 8, E>(h, tl, grid, rpb, shm, x, io, p, bvec, hdr, part, max_steps, s);
+    }
     ED_LAUNCHED("k_down");
     return ED_OK;
+}
+
+template <typename T, int MODE>
+static int launch_down(const ed_ham *h, const Tile &tl, const T *x, T *io, const T *p, const double *bvec,
+                       const Hdr *hdr, double *part, int max_steps, hipStream_t s) {
+    if (wide_dn(h)) return launch_down_e<T, MODE, uint32_t>(h, tl, x, io, p, bvec, hdr, part, max_steps, s);
+    return launch_down_e<T, MODE, uint16_t>(h, tl, x, io, p, bvec, hdr, part, max_steps, s);
 }
 
 static int down_grid(const ed_ham *h, const Tile &tl) {
@@ -541,13 +579,20 @@ static int down_grid(const ed_ham *h, const Tile &tl) {
 
 // Kernels staging rows in LDS may use up to kLdsBudget bytes of it; set once,
 // outside any stream capture.
-template <typename T, int MODE, int NCH>
-static hipError_t set_lds_attr() {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_down<T, MODE, true, NCH, false>),
+template <typename T, int MODE, int NCH, typename E>
+static hipError_t set_lds_attr_e() {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_down<T, MODE, true, NCH, false, E>),
                                              hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(k_down<T, MODE, true, NCH, true>),
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(k_down<T, MODE, true, NCH, true, E>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget);
+}
+
+template <typename T, int MODE, int NCH>
+static hipError_t set_lds_attr() {
+    const hipError_t e = set_lds_attr_e<T, MODE, NCH, uint16_t>();
+    if (e != hipSuccess) return e;
+    return set_lds_attr_e<T, MODE, NCH, uint32_t>();
 }
 
 template <typename T>
@@ -771,6 +816,7 @@ static int tune_impl(const ed_ham *h, const T *x, T *y, const WsLayout &w, int r
         if (ms_dn) ms_dn[di] = -1.0;
         if (kDnTiles[di].rpb > 0 && (int64_t)kDnTiles[di].rpb * h->dim_dn * (int64_t)sizeof(T) > kLdsBudget) continue;
         if (kDnTiles[di].rpb > h->dim_up) continue;
+        if (tl.dn_block != kDnTiles[di].block) continue;   // clamped duplicate of a smaller workgroup
         rc = launch_down<T, SM>(h, tl, x, y, x, w.y, w.hdr, w.part, 2, s);
         if (rc) break;
         rc = hip_check(hipEventRecord(e0, s), "hipEventRecord");

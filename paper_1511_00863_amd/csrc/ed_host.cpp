@@ -103,6 +103,38 @@ double tridiag_lowest(const double *a, const double *b, int m) {
     return 0.5 * (lo + hi);
 }
 
+// The two device table formats differ only in the entry type.
+template <typename E>
+static int pack_tables_impl(const char *who, const int32_t *cols, const double *vals, const int32_t *nnz, int64_t dim,
+                     int32_t width, int layout, int64_t max_dim, E *packed) {
+    if (!cols || !vals || !nnz || !packed || dim < 1 || width < 0)
+        return set_error(ED_EINVAL, "%s: bad arguments", who);
+    if (dim > max_dim) return set_error(ED_EOVERFLOW, "%s: dim %lld > %lld", who, (long long)dim, (long long)max_dim);
+    if (layout != ED_ROW_MAJOR && layout != ED_COL_MAJOR) return set_error(ED_EINVAL, "%s: bad layout %d", who, layout);
+    const int64_t stride = (width + 7) & ~7;
+    const E pad = static_cast<E>(~E(0));
+    for (int64_t r = 0; r < dim; ++r) {
+        if (nnz[r] < 0 || nnz[r] > width)
+            return set_error(ED_EINVAL, "%s: nnz[%lld] = %d out of range", who, (long long)r, nnz[r]);
+        int64_t last = -1;
+        for (int64_t k = 0; k < stride; ++k) {
+            E e = pad;
+            if (k < nnz[r]) {
+                int64_t at = layout == ED_ROW_MAJOR ? r * width + k : k * dim + r;
+                if (cols[at] < 0 || cols[at] >= dim) return set_error(ED_EINVAL, "%s: column %d out of range", who, cols[at]);
+                if (cols[at] <= last)
+                    return set_error(ED_EINVAL, "%s: row %lld not in ascending column order", who, (long long)r);
+                if (vals[at] != 1.0 && vals[at] != -1.0) return set_error(ED_EINVAL, "%s: value %g is not +-1", who, vals[at]);
+                last = cols[at];
+                e = static_cast<E>(((uint64_t)cols[at] << 1) | (vals[at] < 0 ? 1u : 0u));
+            }
+            packed[r * stride + k] = e;                                   // row-major part
+            packed[dim * stride + ((k >> 3) * dim + r) * 8 + (k & 7)] = e;  // 8-interleaved part
+        }
+    }
+    return ED_OK;
+}
+
 }  // namespace ed
 
 using namespace ed;
@@ -233,34 +265,14 @@ int ed_build_hopping(int n_sites, const int32_t *bonds, int n_bonds, const uint6
 int ed_pack_tables(const int32_t *cols, const double *vals, const int32_t *nnz, int64_t dim,
                    int32_t width, int layout, uint16_t *packed) {
     clear_error();
-    if (!cols || !vals || !nnz || !packed || dim < 1 || width < 0)
-        return set_error(ED_EINVAL, "ed_pack_tables: bad arguments");
-    if (dim > 32767) return set_error(ED_EOVERFLOW, "ed_pack_tables: dim %lld > 32767", (long long)dim);
-    if (layout != ED_ROW_MAJOR && layout != ED_COL_MAJOR)
-        return set_error(ED_EINVAL, "ed_pack_tables: bad layout %d", layout);
-    const int64_t stride = (width + 7) & ~7;
-    for (int64_t r = 0; r < dim; ++r) {
-        if (nnz[r] < 0 || nnz[r] > width)
-            return set_error(ED_EINVAL, "ed_pack_tables: nnz[%lld] = %d out of range", (long long)r, nnz[r]);
-        int32_t last = -1;
-        for (int64_t k = 0; k < stride; ++k) {
-            uint16_t e = 0xFFFF;
-            if (k < nnz[r]) {
-                int64_t at = layout == ED_ROW_MAJOR ? r * width + k : k * dim + r;
-                if (cols[at] < 0 || cols[at] >= dim)
-                    return set_error(ED_EINVAL, "ed_pack_tables: column %d out of range", cols[at]);
-                if (cols[at] <= last)
-                    return set_error(ED_EINVAL, "ed_pack_tables: row %lld not in ascending column order", (long long)r);
-                if (vals[at] != 1.0 && vals[at] != -1.0)
-                    return set_error(ED_EINVAL, "ed_pack_tables: value %g is not +-1", vals[at]);
-                last = cols[at];
-                e = (uint16_t)((cols[at] << 1) | (vals[at] < 0 ? 1 : 0));
-            }
-            packed[r * stride + k] = e;                                   // row-major part
-            packed[dim * stride + ((k >> 3) * dim + r) * 8 + (k & 7)] = e;  // 8-interleaved part
-        }
-    }
-    return ED_OK;
+    return pack_tables_impl<uint16_t>("ed_pack_tables", cols, vals, nnz, dim, width, layout, 32767, packed);
+}
+
+int ed_pack_tables32(const int32_t *cols, const double *vals, const int32_t *nnz, int64_t dim,
+                     int32_t width, int layout, uint32_t *packed) {
+    clear_error();
+    return pack_tables_impl<uint32_t>("ed_pack_tables32", cols, vals, nnz, dim, width, layout, int64_t(1) << 30,
+                                      packed);
 }
 
 int ed_occupation_correlations(const double *g, int32_t n_sites, double *docc, double *nn, double *szsz) {

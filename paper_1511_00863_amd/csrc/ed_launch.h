@@ -47,8 +47,13 @@ static const DnTile kDnTiles[] = {
 constexpr int kNumUp = sizeof(kUpTiles) / sizeof(kUpTiles[0]);
 constexpr int kNumDn = sizeof(kDnTiles) / sizeof(kDnTiles[0]);
 constexpr int kLdsBudget = 152 * 1024;
+constexpr int kMaxWideDim = 1 << 30;   // per-spin dimension limit of the 32-bit table format
 
 static inline int elem_size(const ed_ham *h) { return h->dtype == ED_F64 ? 8 : 4; }
+
+// 32-bit table entries (ed_pack_tables32) for a species; 16-bit otherwise
+static inline bool wide_up(const ed_ham *h) { return h->eb_up == 4; }
+static inline bool wide_dn(const ed_ham *h) { return h->eb_dn == 4; }
 
 static inline Tile resolve_tile_id(const ed_ham *h, int id) {
     const int ui = id & 0xFF, di = (id >> 8) & 0xFF;
@@ -72,10 +77,11 @@ static inline Tile resolve_tile_id(const ed_ham *h, int id) {
         t.dn_block = h->dim_dn >= 1024 ? 1024 : 256;
         t.dn_rpb = 0;
     }
+    if (wide_dn(h)) t.dn_block = std::min(t.dn_block, 512);   // the 32-bit table variants' launch bound
     // V = 2 or 4 columns per lane need row starts aligned to V elements (a row
     // length that is a multiple of V) and at most 4 table chunks; 4 columns
     // per lane is float only (16-byte loads)
-    if (t.up_wlog2 == 8 && (es != 4 || (h->dim_dn & 3) || h->w_up > 32)) t.up_wlog2 = 7;
+    if (t.up_wlog2 == 8 && (es != 4 || (h->dim_dn & 3) || h->w_up > 32 || wide_up(h))) t.up_wlog2 = 7;
     if (t.up_wlog2 == 7 && ((h->dim_dn & 1) || h->w_up > 32)) t.up_wlog2 = 6;
     // stripes much wider than the row are pointless
     while (t.up_wlog2 > 4 && (1 << (t.up_wlog2 - 1)) >= h->dim_dn) --t.up_wlog2;
@@ -99,8 +105,12 @@ static inline bool valid_tile_id(int id) {
 static inline int check_ham(const ed_ham *h, const char *who) {
     if (!h) return set_error(ED_EINVAL, "%s: ham is NULL", who);
     if (h->dim_up < 1 || h->dim_dn < 1) return set_error(ED_EINVAL, "%s: bad dims", who);
-    if (h->dim_up > 32767 || h->dim_dn > 32767)
-        return set_error(ED_EOVERFLOW, "%s: per-spin dims must be <= 32767", who);
+    if ((h->eb_up != 0 && h->eb_up != 2 && h->eb_up != 4) || (h->eb_dn != 0 && h->eb_dn != 2 && h->eb_dn != 4))
+        return set_error(ED_EINVAL, "%s: table entry bytes must be 0, 2 or 4", who);
+    if ((!wide_up(h) && h->dim_up > 32767) || (!wide_dn(h) && h->dim_dn > 32767))
+        return set_error(ED_EOVERFLOW, "%s: per-spin dims above 32767 need 32-bit tables", who);
+    if (h->dim_up > kMaxWideDim || h->dim_dn > kMaxWideDim)
+        return set_error(ED_EOVERFLOW, "%s: per-spin dims must be <= %d", who, kMaxWideDim);
     if (h->w_up < 0 || h->w_dn < 0 || (h->w_up && !h->tab_up) || (h->w_dn && !h->tab_dn) || !h->st_up ||
         !h->st_dn)
         return set_error(ED_EINVAL, "%s: missing tables or states", who);

@@ -1,6 +1,6 @@
 """Named workloads: lattice, fillings, couplings, precision, step budget, seed.
 
-These are the five synthetic configurations the benchmarks and parity tests use.
+The synthetic configurations the benchmarks and parity tests use.
 Nothing here computes anything of the method.
 """
 
@@ -37,6 +37,9 @@ WORKLOADS = {
                         "6x6 periodic tight binding (U=0), 3 up + 3 down, dim 50,979,600"),
     "torus4x4_8x8": _wl("torus4x4_8x8", 16, torus_bonds(4, 4), 8, 1.0, 4.0, 300, 5,
                         "4x4 periodic Hubbard at half filling, 8 up + 8 down, dim 165,636,900"),
+    "ring18_9x9": _wl("ring18_9x9", 18, ring_bonds(18), 9, 1.0, 4.0, 100, 6,
+                      "18-site periodic Hubbard chain at half filling, 9 up + 9 down, dim 2,363,904,400 "
+                      "(18.9 GB per float64 vector; 48620 states per species need 32-bit tables)"),
 }
 
 

@@ -120,6 +120,45 @@ def test_pack_tables_roundtrip():
     assert np.array_equal(ed.pack_tables(tc, st.size), packed)
 
 
+def test_pack_tables32_widens_the_16bit_table():
+    """The 32-bit format holds the same entries (padding all ones) in the same two layouts."""
+    st = ed.build_basis(16, 5)
+    t = ed.build_hopping(16, torus_bonds(4, 4), st, ed.ED_COL_MAJOR)
+    p16 = ed.pack_tables(t, st.size)
+    p32 = ed.pack_tables(t, st.size, entry_bytes=4)
+    assert p32.dtype == np.uint32 and p32.size == p16.size
+    want = np.where(p16 == 0xFFFF, np.uint32(0xFFFFFFFF), p16.astype(np.uint32))
+    assert np.array_equal(p32, want)
+
+
+def test_pack_tables32_beyond_15bit_ranks_matches_oracle():
+    """18-site chain, 9 particles: 48620 states, more than 15-bit ranks hold.  The 16-bit packer
+    refuses; the 32-bit table decodes to the oracle's hopping matrix (columns and signs), row by row."""
+    n_sites, n = 18, 9
+    st = ed.build_basis(n_sites, n)
+    assert st.size == 48620
+    t = ed.build_hopping(n_sites, ring_bonds(n_sites), st, ed.ED_COL_MAJOR)
+    with pytest.raises(ed.EdError) as ei:
+        ed.pack_tables(t, st.size)
+    assert ei.value.code == -3          # ED_EOVERFLOW
+    p = ed.pack_tables(t, st.size, entry_bytes=4)
+    w8 = ed.api.table_stride(t["width"])
+    rm = p[:st.size * w8].reshape(st.size, w8)
+    il = p[st.size * w8:].reshape(w8 // 8, st.size, 8)
+    assert np.array_equal(il.transpose(1, 0, 2).reshape(st.size, w8), rm)
+    h = hopping_matrix(n_sites, ring_bonds(n_sites), basis_states(n_sites, n), 1.0).tocsr()
+    for r in list(range(0, st.size, 997)) + [st.size - 1]:
+        row = h.getrow(r)
+        order = np.argsort(row.indices)
+        cols, vals = row.indices[order], row.data[order]
+        e = rm[r]
+        live = e != 0xFFFFFFFF
+        assert live.sum() == cols.size and np.all(~live[cols.size:])
+        assert np.array_equal((e[live] >> 1).astype(np.int64), cols)
+        # the sign bit: the entry is the matrix element at t = 1
+        assert np.array_equal(np.where(e[live] & 1, -1.0, 1.0), vals)
+
+
 def test_hopping_errors():
     st = ed.build_basis(4, 2)
     with pytest.raises(ed.EdError):
@@ -204,6 +243,12 @@ def test_device_calls_validate_before_touching_the_device():
         assert lib.ed_workspace_size(ctypes.byref(h), 10, ctypes.byref(nbytes)) == code, kw
         assert lib.ed_hv(ctypes.byref(h), dummy, ctypes.c_void_p(8192), dummy, None) == code, kw
         assert lib.ed_last_error().decode()
+    for kw, code in [(dict(eb_up=3), -1), (dict(eb_dn=1), -1),
+                     (dict(eb_up=4, dim_up=(1 << 30) + 1), -3), (dict(eb_dn=2, dim_dn=40000), -3)]:
+        h = ham(**kw)
+        assert lib.ed_workspace_size(ctypes.byref(h), 10, ctypes.byref(nbytes)) == code, kw
+    # 32-bit tables lift the 15-bit rank limit of a species (validation only: nothing is launched)
+    assert lib.ed_workspace_size(ctypes.byref(ham(eb_up=4, dim_up=48620)), 10, ctypes.byref(nbytes)) == 0
     # a species without hopping may pass no table
     h = ham(w_dn=0, tab_dn=None)
     assert lib.ed_workspace_size(ctypes.byref(h), 10, ctypes.byref(nbytes)) == 0
