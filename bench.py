@@ -126,6 +126,41 @@ def scale_block(args):
     return out
 
 
+def single_block(args):
+    """One spin species, the shape of the paper's one-species benchmarks: the 26-site chain with 13
+    particles (D = 10,400,600) and a 30-site periodic lattice with 9 (D = 14,307,150).  All particles
+    in the down species, so H x is the down-part kernel over one row of length D, split into column
+    blocks, with no up part.  Algorithmic bytes of that kernel per launch: the start vector, f_{j-1}
+    and q once each, the 8-interleaved table (D x W8 entries) and the states."""
+    import torch
+    import paper_1511_00863_amd as ed
+    from synth import start_vector, workload
+    dev = "cuda:0"
+    out = {}
+    for name in ("ring26_0x13", "torus5x6_0x9"):
+        wl = workload(name)
+        up = ed.SpinTables(wl.n_sites, wl.bonds, wl.n_up, dev)
+        dn = ed.SpinTables(wl.n_sites, wl.bonds, wl.n_dn, dev)
+        x_host = start_vector(wl.seed, up.dim * dn.dim)
+        rec = {"dim": up.dim * dn.dim, "table_stride": dn.stride, "table_entry_bytes": dn.entry_bytes}
+        for dtype in ("f64", "f32"):
+            h = ed.Hamiltonian(up, dn, wl.t, wl.U, dtype)
+            src = ed.api.apply_tuned_tile(h, tune_if_missing=False)
+            x = torch.from_numpy(x_host).to(dev, h.torch_dtype)
+            ms, per, _ = time_run(h, x, 3, args.single_steps, 3)
+            es = 8 if dtype == "f64" else 4
+            dn_bytes = 3 * es * h.dim + h.dim * dn.stride * dn.entry_bytes + 8 * h.dim
+            rec[dtype] = {"steps_per_s": 1000.0 / ms, "ms_per_step": ms, "kernel_ms": per,
+                          "k_down_alg_GBps": dn_bytes / (per["k_down"] * 1e-3) / 1e9,
+                          "tile": {"id": h.tile, "source": src, **h.tile_params()}}
+            del x, h
+            torch.cuda.empty_cache()
+        out[name] = rec
+        del up, dn, x_host
+        torch.cuda.empty_cache()
+    return out
+
+
 def observables_block(item, wl):
     """Occupation moments of a two-pass ground state (FP32 vector): wall time of ed_occupation_moments
     (two passes over the vector, synchronised) and the double occupancy and nearest-neighbour correlations."""
@@ -256,6 +291,8 @@ def main():
     ap.add_argument("--train-iters", type=int, default=3000)
     ap.add_argument("--held-out", default="3.5", help="comma-separated held-out U values for time-to-E0")
     ap.add_argument("--no-scale", action="store_true", help="skip the 18-site 9+9 run (2.4e9 states)")
+    ap.add_argument("--no-single", action="store_true", help="skip the one-species runs")
+    ap.add_argument("--single-steps", type=int, default=20)
     ap.add_argument("--scale-steps", type=int, default=6)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -332,6 +369,8 @@ def main():
         line["batch"] = batch_block(args)
     if not args.no_scale:
         line["scale"] = scale_block(args)
+    if not args.no_single:
+        line["single_species"] = single_block(args)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
     print(json.dumps(line), flush=True)

@@ -12,6 +12,10 @@ Everything here is plain, slow and float64, written from the paper:
 * ``hamiltonian`` -- H = H_up x I + I x H_dn + diag(U n_up n_dn) (Eq. 1, 3-5)
 * ``fock``        -- brute force in the full Fock space from Jordan-Wigner
                      Kronecker products (tiny lattices)
+* ``elements``    -- (H x) at selected basis states from the operator form of
+                     Eq. 1, term by term, with no matrix (any sector size)
+* ``observables`` -- occupation moments <n_a n_b> of a state (diagonal
+                     observables in the occupation basis, Sec. 2.1)
 * ``lanczos``     -- the Lanczos iteration in the paper's order (Alg. 1), the
                      lowest eigenvalue of T (Sec. 2.2), the two-pass ground state
 * ``mlp``         -- float64 forward/backward/Adam of the start-vector network,

@@ -353,13 +353,13 @@ __global__ __launch_bounds__(kBatchBlock, 3) void k_batch(BInst *__restrict__ in
                 const uint64_t *su = (const uint64_t *)I.st_up + r0, *sd = (const uint64_t *)I.st_dn;
                 const float tt = (float)I.t, uu = (float)I.U;
                 if (I.W8d == 0)   // the down species cannot hop: no table to read
-                    down_rows<float, 2, 0, true>(xs, io, p, tdn, su, sd, I.Ddn, I.W8d, nr, base, tt, uu, sig, cprev,
+                    down_rows<float, 2, 0, true>(xs, io, p, tdn, su, sd, I.Ddn, I.W8d, 0, nr * I.Ddn, base, tt, uu, sig, cprev,
                                                  has_prev, s);
                 else if (I.rpb > 1)
-                    down_rows<float, 2, 4, true>(xs, io, p, tdn, su, sd, I.Ddn, I.W8d, nr, base, tt, uu, sig, cprev,
+                    down_rows<float, 2, 4, true>(xs, io, p, tdn, su, sd, I.Ddn, I.W8d, 0, nr * I.Ddn, base, tt, uu, sig, cprev,
                                                  has_prev, s);
                 else
-                    down_rows<float, 2, 4, false>(xs, io, p, tdn, su, sd, I.Ddn, I.W8d, nr, base, tt, uu, sig, cprev,
+                    down_rows<float, 2, 4, false>(xs, io, p, tdn, su, sd, I.Ddn, I.W8d, 0, nr * I.Ddn, base, tt, uu, sig, cprev,
                                                   has_prev, s);
                 double tot[5];
                 block_sum<5>(s, tot);

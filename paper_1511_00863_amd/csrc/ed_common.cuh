@@ -469,19 +469,22 @@ __device__ __forceinline__ void stage_rows(const T *__restrict__ src, T *__restr
     }
 }
 
-// One block of nr rows starting at row r0 of one instance: q = sig * (io + t *
+// Elements [i0, iend) of a block of rows starting at row r0 of one instance
+// (element i = row i / Ddn, column i % Ddn of the block): q = sig * (io + t *
 // down-part + U Docc x) - cprev * p, in place on io; per-thread partial sums
 // added to s[].  xrows: the rows (LDS copy or global); base: offset of row r0
-// in the global vectors.
-template <typename T, int MODE, int NCH, bool MULTI, typename E>
+// in the global vectors.  A workgroup takes whole rows (i0 = 0, iend = rows *
+// Ddn) or, for one long row, a range of its columns.  IO = false: there is
+// no up part (the up species cannot hop); io is written but not read.
+template <typename T, int MODE, int NCH, bool MULTI, bool IO = true, typename E>
 __device__ __forceinline__ void down_rows(const T *__restrict__ xrows, T *__restrict__ io, const T *__restrict__ p,
                                           const E *__restrict__ tab, const uint64_t *__restrict__ st_up_r0,
-                                          const uint64_t *__restrict__ st_dn, int Ddn, int W8, int nr,
+                                          const uint64_t *__restrict__ st_dn, int Ddn, int W8, int i0, int iend,
                                           int64_t base, T t, T U, T sig, T cprev, bool use_p,
                                           double (&s)[MODE == 2 ? 5 : 1]) {
     const Chunk8<E> *til = reinterpret_cast<const Chunk8<E> *>(tab + (int64_t)Ddn * W8);   // 8-interleaved part
     const int nch = W8 >> 3;
-    const int n = nr * Ddn;
+    const int n = iend;
     // Every global operand of a column (table chunks, up part, f_{j-1}, the
     // down state) is fetched one column ahead, so that the wait for the
     // current column's operands (memory counters complete in issue order)
@@ -491,7 +494,7 @@ __device__ __forceinline__ void down_rows(const T *__restrict__ xrows, T *__rest
     // it is not used) so that the wait count is exact on every path.
     // MULTI: the block holds several (short) rows and a thread's columns move
     // between them; else one row, whose up state is a wave-uniform constant.
-    int i = threadIdx.x;
+    int i = i0 + threadIdx.x;
     if (i >= n) return;
     const uint64_t su0 = st_up_r0[0];
     Chunk8<E> tq[NCH > 0 ? NCH : 1];
@@ -501,7 +504,7 @@ __device__ __forceinline__ void down_rows(const T *__restrict__ xrows, T *__rest
     if constexpr (MULTI) { rr = i / Ddn; c = i - rr * Ddn; } else { rr = 0; c = i; }
 #pragma unroll
     for (int k8 = 0; k8 < NCH; ++k8) tq[k8] = table_chunk<NCH, E>(til, k8, nch, Ddn, c);
-    iov = io[base + i];
+    if constexpr (IO) iov = io[base + i]; else iov = T(0);
     if constexpr (MODE != 0) pv = keep_or_zero(p[base + i], use_p); else pv = T(0);
     sdv = st_dn[c];
     if constexpr (MULTI) suv = st_up_r0[rr];
@@ -512,7 +515,8 @@ __device__ __forceinline__ void down_rows(const T *__restrict__ xrows, T *__rest
         Chunk8<E> tqn[NCH > 0 ? NCH : 1];
 #pragma unroll
         for (int k8 = 0; k8 < NCH; ++k8) tqn[k8] = table_chunk<NCH, E>(til, k8, nch, Ddn, cn);
-        const T iovn = io[base + in];
+        T iovn;
+        if constexpr (IO) iovn = io[base + in]; else iovn = T(0);
         T pvn;
         if constexpr (MODE != 0) pvn = keep_or_zero(p[base + in], use_p); else pvn = T(0);
         const uint64_t sdn = st_dn[cn];

@@ -76,7 +76,10 @@ struct WsLayout {
     double *part2;
 };
 
-static int64_t n_partial_slots(const ed_ham *h) { return std::max<int64_t>(h->dim_up, 1); }
+// k_down partial-sum slots: one per workgroup.  Rows too long for LDS are split
+// into column blocks until the launch has kDownBlocks workgroups, so the grid
+// is at most dim_up + kDownBlocks.
+static int64_t n_partial_slots(const ed_ham *h) { return std::max<int64_t>(h->dim_up, 1) + kDownBlocks; }
 
 static int64_t ws_bytes(const ed_ham *h, int32_t max_steps) {
     return 512 + align256(8 * (int64_t)std::max(max_steps, 1)) + align256(8 * kPartStride * n_partial_slots(h)) +
@@ -194,14 +197,14 @@ __global__ void k_ctr_reset(int *ctr, const Hdr *hdr, int gate, int max_steps) {
 // which needs at most 80 VGPRs (6 waves per SIMD).  32-bit tables double the
 // registers of the prefetched table chunks: workgroups of at most 512 threads
 // (256 VGPRs) and no occupancy target.
-template <typename T, int MODE, bool LDS, int NCH, bool MULTI, typename E>
+template <typename T, int MODE, bool LDS, int NCH, bool MULTI, typename E, bool IO = true>
 __global__ __launch_bounds__(sizeof(E) == 4 ? 512 : 1024)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NCH <= 4 && sizeof(E) == 2 ? 6 : 1)))
 void k_down(const T *__restrict__ x, T *__restrict__ io, const T *__restrict__ p,
                                                const E *__restrict__ tab,
                                                const uint64_t *__restrict__ st_up,
                                                const uint64_t *__restrict__ st_dn, int Dup, int Ddn, int W8,
-                                               int rpb, T t, T U, const double *__restrict__ bvec,
+                                               int rpb, int csplit, T t, T U, const double *__restrict__ bvec,
                                                const Hdr *__restrict__ hdr, double *__restrict__ partials,
                                                int max_steps) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -215,8 +218,19 @@ void k_down(const T *__restrict__ x, T *__restrict__ io, const T *__restrict__ p
         sig = static_cast<T>(hdr->sig_cur);
         cprev = static_cast<T>(bvec[j] * hdr->sig_prev);
     }
-    const int r0 = blockIdx.x * rpb;
+    // rows staged in LDS: rpb whole rows per workgroup; otherwise one row, or
+    // one of its csplit column blocks (64-column aligned)
+    int rblk = blockIdx.x, i0 = 0, iend = 0;
+    if constexpr (!LDS) {
+        rblk = blockIdx.x / csplit;
+        const int cb = blockIdx.x - rblk * csplit;
+        const int cw = ((Ddn + csplit - 1) / csplit + 63) & ~63;
+        i0 = min(Ddn, cb * cw);
+        iend = min(Ddn, i0 + cw);
+    }
+    const int r0 = rblk * rpb;
     const int nr = min(rpb, Dup - r0);
+    if constexpr (LDS) iend = nr * Ddn;
     const int64_t base = (int64_t)r0 * Ddn;
     if (LDS) {
         stage_rows<T>(x + base, xs, nr * Ddn);
@@ -226,8 +240,8 @@ void k_down(const T *__restrict__ x, T *__restrict__ io, const T *__restrict__ p
     double s[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) s[k] = 0.0;
-    down_rows<T, MODE, NCH, MULTI>(LDS ? xs : x + base, io, p, tab, st_up + r0, st_dn, Ddn, W8, nr, base, t, U,
-                                   sig, cprev, MODE != 0 && has_prev, s);
+    down_rows<T, MODE, NCH, MULTI, IO>(LDS ? xs : x + base, io, p, tab, st_up + r0, st_dn, Ddn, W8, i0, iend, base, t,
+                                   U, sig, cprev, MODE != 0 && has_prev, s);
     if (MODE != 0) {
         double tot[NV];
         block_sum<NV>(s, tot);
@@ -410,6 +424,25 @@ static int grid_for(int64_t n, int block, int cap = 4096) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
 }
 
+// Launch shape of k_down: rows per workgroup (LDS staging) or, for rows too
+// long for LDS, one row per workgroup split into csplit column blocks.
+struct DownShape { bool lds; int rpb, csplit, grid; };
+
+static DownShape down_shape(const ed_ham *h, const Tile &tl) {
+    DownShape d;
+    const int64_t row_bytes = h->dim_dn * (int64_t)elem_size(h);
+    d.lds = row_bytes * tl.dn_rpb <= kLdsBudget;
+    d.rpb = d.lds ? tl.dn_rpb : 1;
+    d.csplit = 1;
+    if (!d.lds) {
+        const int64_t want = (kDownBlocks + h->dim_up - 1) / h->dim_up;
+        const int64_t most = (h->dim_dn + tl.dn_block - 1) / tl.dn_block;
+        d.csplit = (int)std::max<int64_t>(1, std::min(want, most));
+    }
+    d.grid = (int)((h->dim_up + d.rpb - 1) / d.rpb) * d.csplit;
+    return d;
+}
+
 template <typename T, int R, int NCH, typename E>
 static int up_queue_grid(int block) {
     static int cached = 0;
@@ -458,7 +491,8 @@ static int launch_up_r(const ed_ham *h, const Tile &tl, const T *x, T *out, int 
 template <typename T, typename E>
 static int launch_up_e(const ed_ham *h, const Tile &tl, const T *x, T *out, int *ctr, const Hdr *hdr, int gate,
                        int max_steps, hipStream_t s) {
-    if (h->w_up == 0) {   // no up hopping: out = 0
+    if (h->w_up == 0) {   // no up hopping: out = 0, unless the down part does not read it
+        if (!down_shape(h, tl).lds) return ED_OK;
         hipLaunchKernelGGL(k_fill0<T>, dim3(grid_for(h->dim_up * h->dim_dn, 256)), dim3(256), 0, s, out,
                            h->dim_up * h->dim_dn);
         ED_LAUNCHED("k_fill0");
@@ -518,46 +552,60 @@ static int launch_up(const ed_ham *h, const Tile &tl, const T *x, T *out, int *c
     return launch_up_e<T, uint16_t>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
 }
 
-template <typename T, int MODE, bool LDS, int NCH, typename E>
-static void launch_down_k(const ed_ham *h, const Tile &tl, int grid, int rpb, size_t shm, const T *x, T *io,
-                          const T *p, const double *bvec, const Hdr *hdr, double *part, int max_steps,
+template <typename T, int MODE, bool LDS, int NCH, typename E, bool IO = true>
+static void launch_down_k(const ed_ham *h, const Tile &tl, int grid, int rpb, int csplit, size_t shm, const T *x,
+                          T *io, const T *p, const double *bvec, const Hdr *hdr, double *part, int max_steps,
                           hipStream_t s) {
     const E *tab = static_cast<const E *>(h->tab_dn);
     if (rpb > 1)
-        hipLaunchKernelGGL((k_down<T, MODE, LDS, NCH, true, E>), dim3(grid), dim3(tl.dn_block), shm, s, x, io, p,
-                           tab, h->st_up, h->st_dn, (int)h->dim_up, (int)h->dim_dn, h->w_dn, rpb,
+        hipLaunchKernelGGL((k_down<T, MODE, LDS, NCH, true, E, IO>), dim3(grid), dim3(tl.dn_block), shm, s, x, io, p,
+                           tab, h->st_up, h->st_dn, (int)h->dim_up, (int)h->dim_dn, h->w_dn, rpb, csplit,
                            static_cast<T>(h->t), static_cast<T>(h->U), bvec, hdr, part, max_steps);
     else
-        hipLaunchKernelGGL((k_down<T, MODE, LDS, NCH, false, E>), dim3(grid), dim3(tl.dn_block), shm, s, x, io, p,
-                           tab, h->st_up, h->st_dn, (int)h->dim_up, (int)h->dim_dn, h->w_dn, rpb,
+        hipLaunchKernelGGL((k_down<T, MODE, LDS, NCH, false, E, IO>), dim3(grid), dim3(tl.dn_block), shm, s, x, io, p,
+                           tab, h->st_up, h->st_dn, (int)h->dim_up, (int)h->dim_dn, h->w_dn, rpb, csplit,
                            static_cast<T>(h->t), static_cast<T>(h->U), bvec, hdr, part, max_steps);
 }
 
 template <typename T, int MODE, typename E>
 static int launch_down_e(const ed_ham *h, const Tile &tl, const T *x, T *io, const T *p, const double *bvec,
                          const Hdr *hdr, double *part, int max_steps, hipStream_t s) {
-    const int64_t row_bytes = h->dim_dn * (int64_t)sizeof(T);
-    const bool lds = row_bytes * tl.dn_rpb <= kLdsBudget;
-    const int rpb = lds ? tl.dn_rpb : 1;
-    const int grid = (int)((h->dim_up + rpb - 1) / rpb);
-    const size_t shm = lds ? (size_t)(row_bytes * rpb) : 0;
+    const DownShape d = down_shape(h, tl);
+    const bool lds = d.lds;
+    const int rpb = d.rpb, grid = d.grid, cs = d.csplit;
+    const size_t shm = lds ? (size_t)(h->dim_dn * (int64_t)sizeof(T) * rpb) : 0;
     const int nch = h->w_dn >> 3;
+    if (!lds && h->w_up == 0) {   // one species: no up part to add (launch_up wrote nothing)
+        if (nch == 0) {
+            launch_down_k<T, MODE, false, 0, E, false>(h, tl, grid, 1, cs, 0, x, io, p, bvec, hdr, part, max_steps, s);
+        } else {
+            if constexpr (sizeof(E) == 4) {
+                if (nch <= 2) launch_down_k<T, MODE, false, 2, E, false>(h, tl, grid, 1, cs, 0, x, io, p, bvec, hdr, part, max_steps, s);
+                else if (nch <= 4) launch_down_k<T, MODE, false, 4, E, false>(h, tl, grid, 1, cs, 0, x, io, p, bvec, hdr, part, max_steps, s);
+                else launch_down_k<T, MODE, false, 8, E, false>(h, tl, grid, 1, cs, 0, x, io, p, bvec, hdr, part, max_steps, s);
+            } else {
+                launch_down_k<T, MODE, false, 8, E, false>(h, tl, grid, 1, cs, 0, x, io, p, bvec, hdr, part, max_steps, s);
+            }
+        }
+        ED_LAUNCHED("k_down");
+        return ED_OK;
+    }
     if constexpr (sizeof(E) == 4) {   // no one-size variant without LDS: its chunk registers would spill
-        if (!lds && nch == 0) launch_down_k<T, MODE, false, 0, E>(h, tl, grid, 1, 0, x, io, p, bvec, hdr, part, max_steps, s);
-        else if (!lds && nch <= 2) launch_down_k<T, MODE, false, 2, E>(h, tl, grid, 1, 0, x, io, p, bvec, hdr, part, max_steps, s);
-        else if (!lds && nch <= 4) launch_down_k<T, MODE, false, 4, E>(h, tl, grid, 1, 0, x, io, p, bvec, hdr, part, max_steps, s);
-        else if (!lds) launch_down_k<T, MODE, false, 8, E>(h, tl, grid, 1, 0, x, io, p, bvec, hdr, part, max_steps, s);
-        else if (nch == 0) launch_down_k<T, MODE, true, 0, E>(h, tl, grid, rpb, shm, x, io, p, bvec, hdr, part, max_steps, s);
-        else if (nch <= 2) launch_down_k<T, MODE, true, 2, E>(h, tl, grid, rpb, shm, x, io, p, bvec, hdr, part, max_steps, s);
-        else if (nch <= 4) launch_down_k<T, MODE, true, 4, E>(h, tl, grid, rpb, shm, x, io, p, bvec, hdr, part, max_steps, s);
-        else launch_down_k<T, MODE, true, 8, E>(h, tl, grid, rpb, shm, x, io, p, bvec, hdr, part, max_steps, s);
+        if (!lds && nch == 0) launch_down_k<T, MODE, false, 0, E>(h, tl, grid, 1, cs, 0, x, io, p, bvec, hdr, part, max_steps, s);
+        else if (!lds && nch <= 2) launch_down_k<T, MODE, false, 2, E>(h, tl, grid, 1, cs, 0, x, io, p, bvec, hdr, part, max_steps, s);
+        else if (!lds && nch <= 4) launch_down_k<T, MODE, false, 4, E>(h, tl, grid, 1, cs, 0, x, io, p, bvec, hdr, part, max_steps, s);
+        else if (!lds) launch_down_k<T, MODE, false, 8, E>(h, tl, grid, 1, cs, 0, x, io, p, bvec, hdr, part, max_steps, s);
+        else if (nch == 0) launch_down_k<T, MODE, true, 0, E>(h, tl, grid, rpb, 1, shm, x, io, p, bvec, hdr, part, max_steps, s);
+        else if (nch <= 2) launch_down_k<T, MODE, true, 2, E>(h, tl, grid, rpb, 1, shm, x, io, p, bvec, hdr, part, max_steps, s);
+        else if (nch <= 4) launch_down_k<T, MODE, true, 4, E>(h, tl, grid, rpb, 1, shm, x, io, p, bvec, hdr, part, max_steps, s);
+        else launch_down_k<T, MODE, true, 8, E>(h, tl, grid, rpb, 1, shm, x, io, p, bvec, hdr, part, max_steps, s);
     } else {
-        if (!lds && nch == 0) launch_down_k<T, MODE, false, 0, E>(h, tl, grid, 1, 0, x, io, p, bvec, hdr, part, max_steps, s);
-        else if (!lds) launch_down_k<T, MODE, false, 8, E>(h, tl, grid, 1, 0, x, io, p, bvec, hdr, part, max_steps, s);
-        else if (nch == 0) launch_down_k<T, MODE, true, 0, E>(h, tl, grid, rpb, shm, x, io, p, bvec, hdr, part, max_steps, s);
-        else if (nch <= 2) launch_down_k<T, MODE, true, 2, E>(h, tl, grid, rpb, shm, x, io, p, bvec, hdr, part, max_steps, s);
-        else if (nch <= 4) launch_down_k<T, MODE, true, 4, E>(h, tl, grid, rpb, shm, x, io, p, bvec, hdr, part, max_steps, s);
-        else launch_down_k<T, MODE, true, 8, E>(h, tl, grid, rpb, shm, x, io, p, bvec, hdr, part, max_steps, s);
+        if (!lds && nch == 0) launch_down_k<T, MODE, false, 0, E>(h, tl, grid, 1, cs, 0, x, io, p, bvec, hdr, part, max_steps, s);
+        else if (!lds) launch_down_k<T, MODE, false, 8, E>(h, tl, grid, 1, cs, 0, x, io, p, bvec, hdr, part, max_steps, s);
+        else if (nch == 0) launch_down_k<T, MODE, true, 0, E>(h, tl, grid, rpb, 1, shm, x, io, p, bvec, hdr, part, max_steps, s);
+        else if (nch <= 2) launch_down_k<T, MODE, true, 2, E>(h, tl, grid, rpb, 1, shm, x, io, p, bvec, hdr, part, max_steps, s);
+        else if (nch <= 4) launch_down_k<T, MODE, true, 4, E>(h, tl, grid, rpb, 1, shm, x, io, p, bvec, hdr, part, max_steps, s);
+        else launch_down_k<T, MODE, true, 8, E>(h, tl, grid, rpb, 1, shm, x, io, p, bvec, hdr, part, max_steps, s);
     }
     ED_LAUNCHED("k_down");
     return ED_OK;
@@ -570,12 +618,7 @@ static int launch_down(const ed_ham *h, const Tile &tl, const T *x, T *io, const
     return launch_down_e<T, MODE, uint16_t>(h, tl, x, io, p, bvec, hdr, part, max_steps, s);
 }
 
-static int down_grid(const ed_ham *h, const Tile &tl) {
-    const int es = elem_size(h);
-    const bool lds = h->dim_dn * (int64_t)es * tl.dn_rpb <= kLdsBudget;
-    const int rpb = lds ? tl.dn_rpb : 1;
-    return (int)((h->dim_up + rpb - 1) / rpb);
-}
+static int down_grid(const ed_ham *h, const Tile &tl) { return down_shape(h, tl).grid; }
 
 // Kernels staging rows in LDS may use up to kLdsBudget bytes of it; set once,
 // outside any stream capture.

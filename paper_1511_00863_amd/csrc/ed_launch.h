@@ -48,6 +48,7 @@ constexpr int kNumUp = sizeof(kUpTiles) / sizeof(kUpTiles[0]);
 constexpr int kNumDn = sizeof(kDnTiles) / sizeof(kDnTiles[0]);
 constexpr int kLdsBudget = 152 * 1024;
 constexpr int kMaxWideDim = 1 << 30;   // per-spin dimension limit of the 32-bit table format
+constexpr int kDownBlocks = 2048;      // workgroups a k_down launch of long rows is split into, at least
 
 static inline int elem_size(const ed_ham *h) { return h->dtype == ED_F64 ? 8 : 4; }
 

@@ -37,6 +37,11 @@ WORKLOADS = {
                         "6x6 periodic tight binding (U=0), 3 up + 3 down, dim 50,979,600"),
     "torus4x4_8x8": _wl("torus4x4_8x8", 16, torus_bonds(4, 4), 8, 1.0, 4.0, 300, 5,
                         "4x4 periodic Hubbard at half filling, 8 up + 8 down, dim 165,636,900"),
+    # one species: every particle has the same spin (N_up = 0); the hopping alone, no on-site term
+    "ring26_0x13": Workload("ring26_0x13", 26, tuple(ring_bonds(26)), 0, 13, 1.0, 0.0, 100, 7,
+                            "26-site periodic chain, 13 particles of one species, dim 10,400,600"),
+    "torus5x6_0x9": Workload("torus5x6_0x9", 30, tuple(torus_bonds(5, 6)), 0, 9, 1.0, 0.0, 100, 8,
+                             "30-site 5x6 periodic square lattice, 9 particles of one species, dim 14,307,150"),
     "ring18_9x9": _wl("ring18_9x9", 18, ring_bonds(18), 9, 1.0, 4.0, 100, 6,
                       "18-site periodic Hubbard chain at half filling, 9 up + 9 down, dim 2,363,904,400 "
                       "(18.9 GB per float64 vector; 48620 states per species need 32-bit tables)"),
