@@ -35,33 +35,42 @@ def rank_in(states: np.ndarray, mask: int) -> int:
     return k
 
 
-def species_terms(occ: list, bonds, states: np.ndarray):
-    """(sign, index) of every state reached from occ by one hop c+_b c_a, over bonds (a, b) both ways."""
+def species_terms(occ: list, bonds, states: np.ndarray, amps=None):
+    """(matrix element / t, index q) of every nonzero <p| H_sigma |q> for the row state p = occ.
+
+    For the term a c+_i c_j, <p| c+_i c_j |q> is nonzero for q = c+_j c_i p, with the sign of that
+    application (real); the Hermitian partner conj(a) c+_j c_i gives q = c+_i c_j p.  Without
+    amplitudes every a is -1."""
     out = []
-    for (i, j) in bonds:
-        for (a, b) in ((i, j), (j, i)):
-            r = hop(occ, a, b)
+    for k, (i, j) in enumerate(bonds):
+        a = -1.0 if amps is None else complex(amps[k])
+        ac = a if amps is None else a.conjugate()
+        for (p_, q_, amp) in ((j, i, a), (i, j, ac)):
+            r = hop(occ, p_, q_)
             if r is not None:
                 sign, new = r
-                out.append((sign, rank_in(states, mask_of(new))))
+                out.append((amp * sign, rank_in(states, mask_of(new))))
     return out
 
 
 def hv_elements(n_sites: int, bonds, st_up: np.ndarray, st_dn: np.ndarray, t: float, U: float,
-                x: np.ndarray, picks) -> np.ndarray:
-    """(H x)[p] for each flat index p in ``picks`` (float64)."""
+                x: np.ndarray, picks, amps=None) -> np.ndarray:
+    """(H x)[p] for each flat index p in ``picks`` (float64, or complex128 with amplitudes or a
+    complex x).  amps: optional complex amplitude per bond, as in ``hamiltonian.Model``."""
     d_dn = len(st_dn)
     bonds = [tuple(int(v) for v in b) for b in bonds]
-    out = np.zeros(len(picks))
+    cplx = amps is not None or np.iscomplexobj(x)
+    out = np.zeros(len(picks), dtype=np.complex128 if cplx else np.float64)
+    val = complex if cplx else float
     for n, p in enumerate(picks):
         iu, idn = divmod(int(p), d_dn)
         su, sd = int(st_up[iu]), int(st_dn[idn])
-        acc = 0.0
-        for sign, k in species_terms(occupations(su, n_sites), bonds, st_up):
-            acc += -t * sign * float(x[k * d_dn + idn])
-        for sign, k in species_terms(occupations(sd, n_sites), bonds, st_dn):
-            acc += -t * sign * float(x[iu * d_dn + k])
-        acc += U * bin(su & sd).count("1") * float(x[p])
+        acc = val(0)
+        for h, k in species_terms(occupations(su, n_sites), bonds, st_up, amps):
+            acc += t * h * val(x[k * d_dn + idn])
+        for h, k in species_terms(occupations(sd, n_sites), bonds, st_dn, amps):
+            acc += t * h * val(x[iu * d_dn + k])
+        acc += U * bin(su & sd).count("1") * val(x[p])
         out[n] = acc
     return out
 

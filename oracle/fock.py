@@ -27,16 +27,21 @@ def annihilator(m: int, n_modes: int) -> sp.csr_matrix:
     return op
 
 
-def fock_hamiltonian(n_sites: int, bonds, t: float, U: float) -> sp.csr_matrix:
+def fock_hamiltonian(n_sites: int, bonds, t: float, U: float, amps=None) -> sp.csr_matrix:
+    """amps: optional complex amplitude per bond, term t * (a c+_i c_j + conj(a) c+_j c_i); default -1."""
     n_modes = 2 * n_sites
     c = [annihilator(m, n_modes) for m in range(n_modes)]
     cd = [op.T.tocsr() for op in c]
     dim = 2 ** n_modes
-    h = sp.csr_matrix((dim, dim))
+    h = sp.csr_matrix((dim, dim), dtype=np.complex128 if amps is not None else np.float64)
     for sigma in range(2):
-        for (i, j) in bonds:
+        for k, (i, j) in enumerate(bonds):
             a, b = sigma * n_sites + i, sigma * n_sites + j
-            h = h - t * (cd[a] @ c[b] + cd[b] @ c[a])
+            if amps is None:
+                h = h - t * (cd[a] @ c[b] + cd[b] @ c[a])
+            else:
+                amp = complex(amps[k])
+                h = h + t * (amp * (cd[a] @ c[b]) + amp.conjugate() * (cd[b] @ c[a]))
     for i in range(n_sites):
         nu = cd[i] @ c[i]
         nd = cd[n_sites + i] @ c[n_sites + i]
@@ -44,9 +49,9 @@ def fock_hamiltonian(n_sites: int, bonds, t: float, U: float) -> sp.csr_matrix:
     return h.tocsr()
 
 
-def sector_block(n_sites: int, bonds, n_up: int, n_dn: int, t: float, U: float) -> np.ndarray:
+def sector_block(n_sites: int, bonds, n_up: int, n_dn: int, t: float, U: float, amps=None) -> np.ndarray:
     """Dense sector Hamiltonian in the ordering index = i_up * D_dn + i_dn."""
-    h = fock_hamiltonian(n_sites, bonds, t, U)
+    h = fock_hamiltonian(n_sites, bonds, t, U, amps)
     su, sd = basis_states(n_sites, n_up), basis_states(n_sites, n_dn)
     fock_idx = [int(a) | (int(b) << n_sites) for a in su for b in sd]
     return h[fock_idx][:, fock_idx].toarray()

@@ -15,7 +15,7 @@ import numpy as np
 import scipy.sparse as sp
 
 from .basis import basis_states
-from .hopping import hopping_matrix
+from .hopping import hopping_matrix, hopping_matrix_complex
 
 
 def popcount_u64(a: np.ndarray) -> np.ndarray:
@@ -34,14 +34,22 @@ def double_occupancy(states_up: np.ndarray, states_dn: np.ndarray) -> np.ndarray
 class Model:
     """Everything the oracle needs for one (lattice, N_up, N_dn, t, U) instance."""
 
-    def __init__(self, n_sites, bonds, n_up, n_dn, t=1.0, U=0.0):
+    def __init__(self, n_sites, bonds, n_up, n_dn, t=1.0, U=0.0, amps=None):
+        """amps: optional complex amplitude a_ij per bond (term t * (a_ij c+_i c_j + h.c.) for both
+        species); without it every bond carries -t (Eq. 1)."""
         self.n_sites, self.bonds = n_sites, list(bonds)
         self.n_up, self.n_dn, self.t, self.U = n_up, n_dn, float(t), float(U)
+        self.amps = None if amps is None else [complex(a) for a in amps]
         self.st_up = basis_states(n_sites, n_up)
         self.st_dn = basis_states(n_sites, n_dn)
-        self.h_up = hopping_matrix(n_sites, self.bonds, self.st_up, self.t)
-        self.h_dn = (self.h_up if (n_dn == n_up) else
-                     hopping_matrix(n_sites, self.bonds, self.st_dn, self.t))
+
+        def hop_matrix(states):
+            if self.amps is None:
+                return hopping_matrix(n_sites, self.bonds, states, self.t)
+            return self.t * hopping_matrix_complex(n_sites, self.bonds, self.amps, states)
+
+        self.h_up = hop_matrix(self.st_up)
+        self.h_dn = self.h_up if (n_dn == n_up) else hop_matrix(self.st_dn)
         self._docc = None
 
     @property
@@ -64,14 +72,18 @@ class Model:
 
     def hv(self, x: np.ndarray) -> np.ndarray:
         """y = H x by Eq. 4 (up part on whole subvectors) and Eq. 5 (down part per subvector)."""
-        X = np.asarray(x, dtype=np.float64).reshape(self.dim_up, self.dim_dn)
+        X = self._view(x).reshape(self.dim_up, self.dim_dn)
         up = self.h_up @ X
         dn = (self.h_dn @ X.T).T
         return (up + dn + self.U * self.docc * X).ravel()
 
+    def _view(self, x):
+        x = np.asarray(x)
+        return x.astype(np.complex128) if (np.iscomplexobj(x) or self.amps is not None) else x.astype(np.float64)
+
     def hv_rows(self, x: np.ndarray, rows) -> np.ndarray:
         """(H x)[r, :] for selected up-rows r only, shape (len(rows), D_dn)."""
-        X = np.asarray(x, dtype=np.float64).reshape(self.dim_up, self.dim_dn)
+        X = self._view(x).reshape(self.dim_up, self.dim_dn)
         rows = np.asarray(rows)
         up = self.h_up[rows] @ X
         dn = (self.h_dn @ X[rows].T).T

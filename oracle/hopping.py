@@ -103,3 +103,27 @@ def to_ell(a):
 def ell_flatten(mat: np.ndarray, layout: str) -> np.ndarray:
     """Flatten an ELL array: 'col' = column-major (GPU), 'row' = row-major (CPU)."""
     return mat.flatten(order="F" if layout == "col" else "C")
+
+
+def hopping_matrix_complex(n_sites: int, bonds, amps, states: np.ndarray) -> sp.csr_matrix:
+    """One species' hopping with a complex amplitude per bond: sum over bonds (i, j) of
+    a_ij c+_i c_j + conj(a_ij) c+_j c_i (Hermitian by construction).  With every a_ij = -t this is
+    ``hopping_matrix``.  Element [row, col] = <row| H_sigma |col>, complex128."""
+    idx = index_of(states)
+    rows, cols, vals = [], [], []
+    for col, s in enumerate(states):
+        occ = occupations(int(s), n_sites)
+        for (i, j), a in zip(bonds, amps):
+            a = complex(a)
+            for (p, q, amp) in ((i, j, a), (j, i, a.conjugate())):
+                r = hop(occ, p, q)            # c+_p c_q |col>
+                if r is None:
+                    continue
+                sign, new = r
+                rows.append(idx[mask_of(new)])
+                cols.append(col)
+                vals.append(amp * sign)
+    d = len(states)
+    m = sp.coo_matrix((np.array(vals, dtype=np.complex128), (rows, cols)), shape=(d, d)).tocsr()
+    m.sum_duplicates()
+    return m

@@ -3,7 +3,9 @@
 ``lanczos`` follows the paper's order exactly, in float64, with no
 re-orthogonalisation: q = H f_j - b_j f_{j-1}; a_j = q.f_j; q = q - a_j f_j;
 b_{j+1} = |q|; stop if b_{j+1} vanishes; f_{j+1} = q / b_{j+1}; b_1 = 0 and
-f_0 = 0.  The vectors are real (real hopping t), so q^dagger f = q^T f.
+f_0 = 0.  Inner products are f^dagger q: with complex hopping amplitudes the
+vectors are complex, and a_j is the real part of f_j^dagger q (H is Hermitian,
+so the imaginary part is rounding); with real hopping this is q^T f.
 
 Readings:
 * "b_{j+1} = 0" is tested as b_{j+1} <= 64 * eps * max_k(|a_k|, b_k) with
@@ -24,9 +26,18 @@ import scipy.linalg as sla
 EPS64 = 2.0 ** -52
 
 
+def _as_vector(f1) -> np.ndarray:
+    return np.asarray(f1, dtype=np.complex128 if np.iscomplexobj(f1) else np.float64)
+
+
+def _inner(u, v) -> float:
+    """Re(u^dagger v)."""
+    return float(np.real(np.vdot(u, v)))
+
+
 def normalise(f1) -> np.ndarray:
-    f = np.asarray(f1, dtype=np.float64)
-    n = np.sqrt(np.dot(f, f))
+    f = _as_vector(f1)
+    n = np.sqrt(_inner(f, f))
     if not np.isfinite(n) or n == 0.0:
         raise ValueError("start vector has zero or non-finite norm")
     return f / n
@@ -47,9 +58,9 @@ def lanczos(hv, f1, m: int, vectors=False):
     scale = 0.0
     for j in range(m):
         q = hv(f) - b[j] * f_prev
-        aj = float(np.dot(q, f))
+        aj = _inner(f, q)
         q = q - aj * f
-        bj1 = float(np.sqrt(np.dot(q, q)))
+        bj1 = float(np.sqrt(_inner(q, q)))
         a.append(aj)
         b.append(bj1)
         scale = max(scale, abs(aj), bj1)
@@ -107,7 +118,7 @@ def ground_state_two_pass(hv, f1, m: int):
         q = q - a[j] * f
         f_prev, f = f, q / b[j + 1]
         v = v + y[j + 1] * f
-    v = v / np.sqrt(np.dot(v, v))
+    v = v / np.sqrt(_inner(v, v))
     return e0, v
 
 

@@ -7,9 +7,11 @@ Both the oracle (``oracle/``) and the device path read their inputs from here
 and from nowhere else, so neither side can feed the other.
 """
 
-from .lattice import ring_bonds, torus_bonds, two_site_bonds, complete_bonds, site_index
+from .lattice import (ring_bonds, torus_bonds, two_site_bonds, complete_bonds, site_index,
+                      checkerboard_bonds, checkerboard_terms)
 from .draws import (
     start_vector,
+    start_vector_complex,
     batch_instances,
     mlp_init,
     minibatch_uniforms,
@@ -19,6 +21,7 @@ from .workloads import WORKLOADS, Workload, workload
 
 __all__ = [
     "ring_bonds", "torus_bonds", "two_site_bonds", "complete_bonds", "site_index",
-    "start_vector", "batch_instances", "mlp_init", "minibatch_uniforms", "MLP_SIZES",
+    "checkerboard_bonds", "checkerboard_terms",
+    "start_vector", "start_vector_complex", "batch_instances", "mlp_init", "minibatch_uniforms", "MLP_SIZES",
     "WORKLOADS", "Workload", "workload",
 ]

@@ -49,3 +49,9 @@ def minibatch_uniforms(seed: int, n_iters: int, batch: int) -> np.ndarray:
     """
     rng = np.random.default_rng(seed)
     return rng.random((n_iters, batch, 2))
+
+
+def start_vector_complex(seed: int, dim: int) -> np.ndarray:
+    """Complex start vector: ``start_vector(seed, 2 * dim)`` read as interleaved (re, im) pairs,
+    the memory layout of a complex128 array."""
+    return start_vector(seed, 2 * int(dim)).view(np.complex128)

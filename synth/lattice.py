@@ -54,3 +54,54 @@ def complete_bonds(n_sites: int) -> List[Bond]:
     paper: it gives the widest hopping tables at a small dimension (a state
     with N particles has N * (n_sites - N) hops), for edge-case tests."""
     return [(i, j) for i in range(n_sites) for j in range(i + 1, n_sites)]
+
+
+def checkerboard_bonds(l1: int, l2: int) -> List[Bond]:
+    """Checkerboard lattice: l1 x l2 periodic unit cells of two sites, A = 2k and B = 2k + 1 for cell
+    k = c1 + l1*c2 (B sits at the cell centre).  Each site has 12 bonds: 4 nearest neighbours on the other
+    sublattice, 4 next-nearest along the cell axes a1, a2 and 4 third-nearest along a1 +- a2.  Needs
+    l1, l2 >= 3, so that no two of these land on the same pair of sites."""
+    return [b for b, _ in checkerboard_terms(l1, l2, 1.0, 0.0, 1.0, 1.0)]
+
+
+def checkerboard_terms(l1: int, l2: int, t1: float, phi: float, t2: float, t3: float):
+    """Bonds of ``checkerboard_bonds`` with a complex amplitude each: the term a * c+_i c_j + h.c. for bond
+    (i, j), i < j.  These are synthetic stand-ins for a flat-band checkerboard model:
+      nearest neighbours   -t1 exp(+-i phi): +phi for A -> B hops along the (+,+) and (-,-) diagonals,
+                           -phi along (+,-) and (-,+);
+      next-nearest         -t2 along a1 and +t2 along a2 from A sites, the opposite signs from B sites;
+      third-nearest        -t3.
+    Returns a list of ((i, j), complex amplitude) in a fixed order."""
+    import cmath
+    if l1 < 3 or l2 < 3:
+        raise ValueError("checkerboard cells need l1, l2 >= 3")
+
+    def cell(c1, c2):
+        return (c1 % l1) + l1 * (c2 % l2)
+
+    terms = {}
+
+    def add(i, j, amp):   # term amp * c+_i c_j (+ h.c.), stored on the ordered pair
+        if i == j:
+            raise ValueError("self bond")
+        key, a = ((i, j), amp) if i < j else ((j, i), amp.conjugate())
+        if key in terms:
+            raise ValueError("two terms on the pair %r: the cell grid is too small" % (key,))
+        terms[key] = a
+
+    nn = -t1 * cmath.exp(1j * phi)
+    for c2 in range(l2):
+        for c1 in range(l1):
+            a = 2 * cell(c1, c2)
+            # the four B neighbours of A: B(c) at (+1/2,+1/2), B(c-a1) at (-,+), B(c-a2) at (+,-), B(c-a1-a2) at (-,-)
+            add(a, 2 * cell(c1, c2) + 1, nn)
+            add(a, 2 * cell(c1 - 1, c2) + 1, nn.conjugate())
+            add(a, 2 * cell(c1, c2 - 1) + 1, nn.conjugate())
+            add(a, 2 * cell(c1 - 1, c2 - 1) + 1, nn)
+            for s, sign in ((0, 1.0), (1, -1.0)):      # sublattice A, B
+                i = 2 * cell(c1, c2) + s
+                add(i, 2 * cell(c1 + 1, c2) + s, complex(-t2 * sign))
+                add(i, 2 * cell(c1, c2 + 1) + s, complex(t2 * sign))
+                add(i, 2 * cell(c1 + 1, c2 + 1) + s, complex(-t3))
+                add(i, 2 * cell(c1 + 1, c2 - 1) + s, complex(-t3))
+    return sorted(terms.items())
