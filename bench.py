@@ -161,6 +161,34 @@ def single_block(args):
     return out
 
 
+def complex_block(args):
+    """The paper's largest two-species checkerboard case: 18 sites, 5 + 5 (D = 73,410,624), complex
+    nearest-neighbour amplitudes (synthetic values on the same lattice: 12 bonds per site), float64
+    and the mixed form.  The paper's K40 took 712 ms (double) and 425 ms (single) per Lanczos
+    iteration on this size (its checkerboard tables, 10 particles): context, other hardware."""
+    import torch
+    import paper_1511_00863_amd as ed
+    from synth import start_vector_complex, workload
+    wl = workload("checker18_5x5")
+    dev = "cuda:0"
+    tab = ed.SpinTables(wl.n_sites, wl.bonds, wl.n_up, dev, amps=list(wl.amps))
+    x_host = start_vector_complex(wl.seed, tab.dim * tab.dim)
+    out = {"workload": wl.name, "dim": tab.dim * tab.dim, "U": wl.U, "table_stride": tab.stride,
+           "n_amplitudes": tab.n_amps, "paper_k40_ms_per_step": {"f64": 712.0, "f32": 425.0}}
+    for dtype in ("f64", "f32"):
+        h = ed.Hamiltonian(tab, tab, wl.t, wl.U, dtype)
+        x = torch.from_numpy(x_host).to(dev, h.torch_dtype)
+        ms, per, _ = time_run(h, x, 3, args.complex_steps, 3)
+        es = 16 if dtype == "f64" else 8
+        dn_bytes = 4 * es * h.dim + tab.dim * tab.stride * 4 + 8 * 2 * tab.dim
+        out[dtype] = {"steps_per_s": 1000.0 / ms, "ms_per_step": ms, "kernel_ms": per,
+                      "k_down_alg_GBps": dn_bytes / (per["k_down"] * 1e-3) / 1e9,
+                      "up_alg_GBps": (2 * es * h.dim) / (per["k_up"] * 1e-3) / 1e9}
+        del x, h
+        torch.cuda.empty_cache()
+    return out
+
+
 def observables_block(item, wl):
     """Occupation moments of a two-pass ground state (FP32 vector): wall time of ed_occupation_moments
     (two passes over the vector, synchronised) and the double occupancy and nearest-neighbour correlations."""
@@ -292,6 +320,8 @@ def main():
     ap.add_argument("--held-out", default="3.5", help="comma-separated held-out U values for time-to-E0")
     ap.add_argument("--no-scale", action="store_true", help="skip the 18-site 9+9 run (2.4e9 states)")
     ap.add_argument("--no-single", action="store_true", help="skip the one-species runs")
+    ap.add_argument("--no-complex", action="store_true", help="skip the complex-amplitude checkerboard run")
+    ap.add_argument("--complex-steps", type=int, default=20)
     ap.add_argument("--single-steps", type=int, default=20)
     ap.add_argument("--scale-steps", type=int, default=6)
     args = ap.parse_args()
@@ -371,6 +401,8 @@ def main():
         line["scale"] = scale_block(args)
     if not args.no_single:
         line["single_species"] = single_block(args)
+    if not args.no_complex:
+        line["complex"] = complex_block(args)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
     print(json.dumps(line), flush=True)

@@ -112,6 +112,29 @@ int ed_pack_tables(const int32_t *cols, const double *vals, const int32_t *nnz, 
 int ed_pack_tables32(const int32_t *cols, const double *vals, const int32_t *nnz, int64_t dim,
                      int32_t width, int layout, uint32_t *packed);
 
+/* Complex hopping amplitudes (the paper's checkerboard lattice has complex
+ * nearest-neighbour hoppings, Sec. 2.1 and its lattice figure): H_sigma =
+ * sum over bonds (i, j) of a_ij c+_i c_j + conj(a_ij) c+_j c_i, t = 1 (t
+ * scales at H.v time).  amps: host, n_bonds (re, im) pairs, a_ij for the
+ * bond as given (i first).  Output as ed_build_hopping, with vals holding
+ * (re, im) pairs: the element <row| H_sigma |col>, that is a_ij times the
+ * fermion sign when the row state has the particle at i, conj(a_ij) times it
+ * when at j.  With every a_ij = -1 this is ed_build_hopping.  vals: host,
+ * 2 * cap_width * dim doubles.  Non-finite amplitudes -> ED_EINVAL. */
+int ed_build_hopping_complex(int n_sites, const int32_t *bonds, int n_bonds, const double *amps,
+                             const uint64_t *states, int64_t dim, int layout, int32_t cap_width, int32_t *cols,
+                             double *vals, int32_t *nnz, int32_t *width);
+
+/* Device table for complex values: uint32 entries e = (col << 6) | index of
+ * the value in amps (distinct values numbered in first-seen order, row by
+ * row), padding 0xFFFFFFFF; the two layouts and stride W8 of ed_pack_tables.
+ * amps: host, 128 doubles (64 (re, im) pairs) written with the n_amps
+ * distinct values; copy all 128 (the unused ones zero) to the device for
+ * ed_ham.amp_up / amp_dn.  More than 64 distinct values or dim > 2^26 - 1
+ * -> ED_EOVERFLOW.  packed: host, 2 * dim * W8 entries. */
+int ed_pack_tables_complex(const int32_t *cols, const double *vals, const int32_t *nnz, int64_t dim,
+                           int32_t width, int layout, uint32_t *packed, double *amps, int32_t *n_amps);
+
 /* Lowest eigenvalue of the m-by-m symmetric tridiagonal T (Sec. 2.2) with
  * diagonal a[0..m-1] = a_1..a_m and off-diagonal b[0..m-2] = b_2..b_m, by
  * Sturm-sequence bisection in float64 to full precision.  host pointers. */
@@ -131,7 +154,16 @@ int ed_tridiag_lowest_vector(const double *a, const double *b, int m, double *e0
  * (vectors and H.v).  tile: 0 = default launch configuration, else an id
  * returned by ed_tune.  A species with 16-bit tables has dim <= 32767, one
  * with 32-bit tables dim <= 2^30 (ED_EOVERFLOW otherwise); eb other than 0,
- * 2, 4 -> ED_EINVAL.  The batched launch takes 16-bit tables only. */
+ * 2, 4 -> ED_EINVAL.  The batched launch takes 16-bit tables only.
+ * cplx = 1: complex amplitudes.  Both tables come from
+ * ed_pack_tables_complex (eb = 4), amp_up/amp_dn are device arrays of 64
+ * complex values (128 doubles, interleaved re, im) from it, and every vector
+ * of the device calls holds dim_up*dim_dn complex numbers as interleaved
+ * (re, im) pairs of dtype (so 2*dim_up*dim_dn reals).  a_j and b_j stay real
+ * (H is Hermitian; a_j = Re f_j^dagger q).  Complex instances are accepted by
+ * ed_hv, the Lanczos calls and ed_ground_state (gauge_index = -1 only);
+ * ed_tune, the batch, the start-vector network and the observables return
+ * ED_EINVAL for them.  cplx = 0: amp_up/amp_dn are ignored. */
 typedef struct ed_ham {
     int64_t dim_up, dim_dn;
     int32_t w_up, w_dn;
@@ -141,6 +173,9 @@ typedef struct ed_ham {
     int32_t dtype;
     int32_t tile;
     int32_t eb_up, eb_dn;   /* bytes per table entry of each species */
+    int32_t cplx;           /* 0: real hopping, 1: complex amplitudes and vectors */
+    int32_t reserved;       /* 0 */
+    const double *amp_up, *amp_dn;
 } ed_ham;
 
 /* Bytes of device workspace (`ws` below) the calls on this instance need

@@ -76,6 +76,46 @@ def table_stride(width: int) -> int:
     return (int(width) + 7) & ~7
 
 
+def build_hopping_complex(n_sites: int, bonds, amps, states, layout: int = ED_COL_MAJOR):
+    """Exported ELL table of H_sigma with a complex amplitude per bond (term a c+_i c_j + h.c., t = 1):
+    dict(cols, vals (complex128), nnz, width, layout) (ed_build_hopping_complex)."""
+    st = np.ascontiguousarray(states, dtype=np.uint64)
+    b = _bond_array(bonds)
+    a = np.ascontiguousarray(np.asarray(amps, dtype=np.complex128).reshape(-1))
+    if a.size != b.shape[0]:
+        raise ValueError("one amplitude per bond")
+    ad = a.view(np.float64)
+    w = c_int32(0)
+    f = lib().ed_build_hopping_complex
+    check(f(n_sites, _ptr(b, c_int32), b.shape[0], _ptr(ad, c_double), _ptr(st, c_uint64), st.size, layout, 0,
+            None, None, None, byref(w)))
+    width = w.value
+    cap = max(width, 1)
+    cols = np.zeros(cap * st.size, dtype=np.int32)
+    vals = np.zeros(cap * st.size, dtype=np.complex128)
+    nnz = np.zeros(st.size, dtype=np.int32)
+    check(f(n_sites, _ptr(b, c_int32), b.shape[0], _ptr(ad, c_double), _ptr(st, c_uint64), st.size, layout, cap,
+            _ptr(cols, c_int32), _ptr(vals.view(np.float64), c_double), _ptr(nnz, c_int32), byref(w)))
+    return {"cols": cols[:width * st.size], "vals": vals[:width * st.size], "nnz": nnz, "width": width,
+            "layout": layout}
+
+
+def pack_tables_complex(table, dim: int):
+    """(packed uint32 table, 64 complex amplitudes as 128 doubles, number used) (ed_pack_tables_complex)."""
+    width = table["width"]
+    stride = table_stride(width)
+    out = np.zeros(max(2 * stride * dim, 1), dtype=np.uint32)
+    amps = np.zeros(128, dtype=np.float64)
+    n = c_int32(0)
+    if width == 0:
+        return out[:0], amps, 0
+    vals = np.ascontiguousarray(table["vals"], dtype=np.complex128).view(np.float64)
+    check(lib().ed_pack_tables_complex(_ptr(table["cols"], c_int32), _ptr(vals, c_double),
+                                       _ptr(table["nnz"], c_int32), dim, width, table["layout"],
+                                       _ptr(out, c_uint32), _ptr(amps, c_double), byref(n)))
+    return out, amps, n.value
+
+
 NARROW_MAX_DIM = 32767   # largest per-spin dimension of the 16-bit table format
 
 
@@ -131,19 +171,31 @@ def tridiag_lowest_vector(a, b_off):
 class SpinTables:
     """Basis and packed hopping table of one species, on the host and on the device."""
 
-    def __init__(self, n_sites: int, bonds, n_part: int, device=None, entry_bytes=None):
-        """entry_bytes: 2 or 4 bytes per device table entry; by default 2 while dim <= 32767, else 4."""
+    def __init__(self, n_sites: int, bonds, n_part: int, device=None, entry_bytes=None, amps=None):
+        """entry_bytes: 2 or 4 bytes per device table entry; by default 2 while dim <= 32767, else 4.
+        amps: a complex amplitude per bond (term a c+_i c_j + h.c.); then the table is the complex format
+        (32-bit entries indexing a table of at most 64 amplitudes) and the vectors are complex."""
         self.n_sites, self.n_part = n_sites, n_part
         self.bonds = [tuple(int(v) for v in b) for b in bonds]
         self.states = build_basis(n_sites, n_part)
         self.dim = int(self.states.size)
-        self.table = build_hopping(n_sites, self.bonds, self.states, ED_COL_MAJOR)
-        self.width = self.table["width"]
-        self.stride = table_stride(self.width)
-        # 16-bit entries while the ranks fit in 15 bits, 32-bit beyond
-        self.entry_bytes = int(entry_bytes) if entry_bytes else (2 if self.dim <= NARROW_MAX_DIM else 4)
-        self.packed = pack_tables(self.table, self.dim, self.entry_bytes)
+        self.cplx = amps is not None
         self.device = torch.device(device if device is not None else "cuda")
+        self.dev_amp = None
+        if self.cplx:
+            self.table = build_hopping_complex(n_sites, self.bonds, amps, self.states, ED_COL_MAJOR)
+            self.width = self.table["width"]
+            self.stride = table_stride(self.width)
+            self.entry_bytes = 4
+            self.packed, self.amps, self.n_amps = pack_tables_complex(self.table, self.dim)
+            self.dev_amp = torch.from_numpy(self.amps.copy()).to(self.device)
+        else:
+            self.table = build_hopping(n_sites, self.bonds, self.states, ED_COL_MAJOR)
+            self.width = self.table["width"]
+            self.stride = table_stride(self.width)
+            # 16-bit entries while the ranks fit in 15 bits, 32-bit beyond
+            self.entry_bytes = int(entry_bytes) if entry_bytes else (2 if self.dim <= NARROW_MAX_DIM else 4)
+            self.packed = pack_tables(self.table, self.dim, self.entry_bytes)
         self.dev_states = torch.from_numpy(self.states.view(np.int64).copy()).to(self.device)
         signed = np.int16 if self.entry_bytes == 2 else np.int32
         self.dev_tab = (torch.from_numpy(self.packed.view(signed).copy()).to(self.device)
@@ -156,15 +208,18 @@ class Hamiltonian:
     def __init__(self, up: SpinTables, dn: SpinTables, t: float = 1.0, U: float = 0.0, dtype: str = "f64",
                  tile: int = 0):
         self.up, self.dn, self.t, self.U = up, dn, float(t), float(U)
-        self.dtype = ED_F64 if dtype in ("f64", torch.float64) else ED_F32
+        if up.cplx != dn.cplx:
+            raise ValueError("both species need complex tables, or neither")
+        self.cplx = up.cplx
+        self.dtype = ED_F64 if dtype in ("f64", torch.float64, torch.complex128) else ED_F32
         self.tile = int(tile)
         self.device = up.device
 
     @classmethod
     def from_lattice(cls, n_sites, bonds, n_up, n_dn, t=1.0, U=0.0, dtype="f64", device=None, tile=0,
-                     entry_bytes=None):
-        up = SpinTables(n_sites, bonds, n_up, device, entry_bytes)
-        dn = up if n_dn == n_up else SpinTables(n_sites, bonds, n_dn, device, entry_bytes)
+                     entry_bytes=None, amps=None):
+        up = SpinTables(n_sites, bonds, n_up, device, entry_bytes, amps)
+        dn = up if n_dn == n_up else SpinTables(n_sites, bonds, n_dn, device, entry_bytes, amps)
         return cls(up, dn, t, U, dtype, tile)
 
     @property
@@ -181,13 +236,18 @@ class Hamiltonian:
 
     @property
     def torch_dtype(self):
+        if self.cplx:
+            return torch.complex128 if self.dtype == ED_F64 else torch.complex64
         return torch.float64 if self.dtype == ED_F64 else torch.float32
 
     def c_struct(self) -> EdHam:
         return EdHam(self.dim_up, self.dim_dn, self.up.stride, self.dn.stride,
                      self.up.dev_tab.data_ptr(), self.dn.dev_tab.data_ptr(),
                      self.up.dev_states.data_ptr(), self.dn.dev_states.data_ptr(),
-                     self.t, self.U, self.dtype, self.tile, self.up.entry_bytes, self.dn.entry_bytes)
+                     self.t, self.U, self.dtype, self.tile, self.up.entry_bytes, self.dn.entry_bytes,
+                     int(self.cplx), 0,
+                     self.up.dev_amp.data_ptr() if self.up.dev_amp is not None else None,
+                     self.dn.dev_amp.data_ptr() if self.dn.dev_amp is not None else None)
 
     def workspace_bytes(self, max_steps: int = 1) -> int:
         n = c_int64(0)
@@ -275,7 +335,7 @@ TUNE_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cach
 
 def tune_key(ham: "Hamiltonian") -> str:
     """Cache key of a tuned tile: architecture, per-spin dims, table strides, dtype."""
-    dt = "f64" if ham.dtype == ED_F64 else "f32"
+    dt = ("c128" if ham.dtype == ED_F64 else "c64") if ham.cplx else ("f64" if ham.dtype == ED_F64 else "f32")
     return "gfx950/%dx%d/w%dx%d/%s" % (ham.dim_up, ham.dim_dn, ham.up.stride, ham.dn.stride, dt)
 
 
@@ -290,6 +350,8 @@ def apply_tuned_tile(ham: "Hamiltonian", x=None, path: str = TUNE_CACHE, tune_if
     """Set ham.tile from the tuning cache, or run ed_tune when the key is absent.
 
     Returns "cache" or "tuned" (or "default" when missing and tune_if_missing is False)."""
+    if ham.cplx:   # complex amplitudes run a fixed launch shape (ed_tune takes real instances)
+        return "default"
     entry = load_tune_cache(path).get(tune_key(ham))
     if entry is not None:
         ham.tile = int(entry["tile"])

@@ -551,7 +551,7 @@ static int plan_batch(const ed_batch_item *items, int n, int32_t max_steps, Batc
     plan.part_doubles = plan.part2_doubles = 0;
     for (int i = 0; i < n; ++i) {
         const ed_ham &h = items[i].h;
-        int rc = check_ham(&h, "ed_ground_energy_batch");
+        int rc = check_real(&h, "ed_ground_energy_batch");
         if (rc) return rc;
         if (h.dtype != ED_F32) return set_error(ED_EINVAL, "ed_ground_energy_batch: item %d is not ED_F32", i);
         if (wide_up(&h) || wide_dn(&h))

@@ -252,6 +252,186 @@ void k_down(const T *__restrict__ x, T *__restrict__ io, const T *__restrict__ p
 }
 
 // ---------------------------------------------------------------------------
+// Complex amplitudes.  Vectors are interleaved (re, im) pairs; every kernel of
+// the step other than these two treats them as real arrays of 2D values, which
+// is exact: a_j = Re(f_j^dagger q) is the real dot product of the pairs and the
+// update coefficients are real.  A table entry is (col << 6) | index into the
+// species' 64 complex amplitudes (sign included), padding 0xFFFFFFFF.
+template <typename T> struct Cplx;
+template <> struct Cplx<double> { using type = double2; };
+template <> struct Cplx<float> { using type = float2; };
+
+// Up part, t * (H_up (x) I) x: one row per wave on 64-column stripes (XCD
+// round-robin as in k_up); the row's entries are wave-uniform scalar loads,
+// so its amplitudes are too; the 8 gathers of a chunk are issued together.
+template <typename T>
+__global__ __launch_bounds__(256) void k_upc(const typename Cplx<T>::type *__restrict__ x,
+                                             typename Cplx<T>::type *__restrict__ out,
+                                             const uint32_t *__restrict__ tab, const double *__restrict__ amp,
+                                             int Dup, int Ddn, int W8, int rc, int n_stripes, int n_rc, T t,
+                                             const Hdr *__restrict__ hdr, int gate, int max_steps) {
+    using T2 = typename Cplx<T>::type;
+    if (gate && frozen(hdr, max_steps)) return;
+    const int g = blockIdx.x, xcd = g & 7, local = g >> 3;
+    const int sl = local / n_rc;
+    const int rci = local - sl * n_rc;
+    const int s = sl * 8 + xcd;
+    if (s >= n_stripes) return;
+    const int lane = threadIdx.x & 63, nwave = blockDim.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int c = s * 64 + lane;
+    const bool cok = c < Ddn;
+    const T2 *xc = x + (cok ? c : 0);
+    const int r1 = min(Dup, (rci + 1) * rc);
+    const int nch = W8 >> 3;
+    for (int r = rci * rc + wave; r < r1; r += nwave) {
+        const uint32_t *row = tab + (int64_t)r * W8;
+        T re = T(0), im = T(0);
+        for (int k8 = 0; k8 < nch; ++k8) {
+            uint32_t e[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) e[k] = row[8 * k8 + k];
+            if (e[0] == 0xFFFFFFFFu) break;   // ascending columns, padding at the end
+            T2 v[8];
+            T ar[8], ai[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const bool pk = e[k] != 0xFFFFFFFFu;
+                const unsigned ia = pk ? (e[k] & 63u) : 0u;
+                v[k] = xc[(int64_t)(pk ? (e[k] >> 6) : 0u) * Ddn];
+                ar[k] = pk ? static_cast<T>(amp[2 * ia]) : T(0);
+                ai[k] = pk ? static_cast<T>(amp[2 * ia + 1]) : T(0);
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                re = fma_t(ar[k], v[k].x, re);
+                re = fma_t(-ai[k], v[k].y, re);
+                im = fma_t(ar[k], v[k].y, im);
+                im = fma_t(ai[k], v[k].x, im);
+            }
+        }
+        if (cok) {
+            T2 o;
+            o.x = t * re;
+            o.y = t * im;
+            out[(int64_t)r * Ddn + c] = o;
+        }
+    }
+}
+
+// Down part and the rest of the step row by row, as k_down: q = sig * (io +
+// t * (I (x) H_dn) x + U Docc x) - cprev * p, in place on io, with partial
+// dot products of the (re, im) pairs.  One row per workgroup, staged in LDS
+// when it fits (after the amplitude table, whose slot kAmpSlots is zero and
+// serves padding); longer rows are split into column blocks and gathered
+// from global memory.
+template <typename T, int MODE, bool LDS>
+__global__ __launch_bounds__(512) void k_downc(const typename Cplx<T>::type *__restrict__ x,
+                                               typename Cplx<T>::type *__restrict__ io,
+                                               const typename Cplx<T>::type *__restrict__ p,
+                                               const uint32_t *__restrict__ tab, const double *__restrict__ amp,
+                                               const uint64_t *__restrict__ st_up,
+                                               const uint64_t *__restrict__ st_dn, int Ddn, int W8, int csplit,
+                                               T t, T U, const double *__restrict__ bvec,
+                                               const Hdr *__restrict__ hdr, double *__restrict__ partials,
+                                               int max_steps) {
+    using T2 = typename Cplx<T>::type;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T2 *amp_s = reinterpret_cast<T2 *>(smem);
+    T2 *xs = amp_s + kAmpSlots + 2;   // kAmpSlots + 1 used; one more keeps 16-byte alignment for float2
+    bool use_p = false;
+    T sig = T(1), cprev = T(0);
+    if (MODE != 0) {
+        if (frozen(hdr, max_steps)) return;
+        const int j = hdr->jdev;
+        use_p = j > 0;
+        sig = static_cast<T>(hdr->sig_cur);
+        cprev = static_cast<T>(bvec[j] * hdr->sig_prev);
+    }
+    int r = blockIdx.x, i0 = 0, iend = Ddn;
+    if constexpr (!LDS) {
+        r = blockIdx.x / csplit;
+        const int cb = blockIdx.x - r * csplit;
+        const int cw = ((Ddn + csplit - 1) / csplit + 63) & ~63;
+        i0 = min(Ddn, cb * cw);
+        iend = min(Ddn, i0 + cw);
+    }
+    const int64_t base = (int64_t)r * Ddn;
+    for (int k = threadIdx.x; k <= kAmpSlots; k += blockDim.x) {   // amp is NULL for a species without hopping
+        T2 a;
+        a.x = (amp && k < kAmpSlots) ? static_cast<T>(amp[2 * k]) : T(0);
+        a.y = (amp && k < kAmpSlots) ? static_cast<T>(amp[2 * k + 1]) : T(0);
+        amp_s[k] = a;
+    }
+    if constexpr (LDS)
+        for (int k = threadIdx.x; k < Ddn; k += blockDim.x) xs[k] = x[base + k];
+    __syncthreads();
+    const T2 *row = LDS ? xs : x + base;
+    const Chunk8<uint32_t> *til = reinterpret_cast<const Chunk8<uint32_t> *>(tab + (int64_t)Ddn * W8);
+    const int nch = W8 >> 3;
+    const uint64_t su = st_up[r];
+    constexpr int NV = MODE == 2 ? 5 : 1;
+    double s[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) s[k] = 0.0;
+    for (int c = i0 + threadIdx.x; c < iend; c += blockDim.x) {
+        T re = T(0), im = T(0);
+        for (int k8 = 0; k8 < nch; ++k8) {
+            const Chunk8<uint32_t> q = til[(int64_t)k8 * Ddn + c];
+            if (!__any(!is_pad<uint32_t>(entry(q, 0)))) break;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const unsigned e = entry(q, k);
+                const bool pk = !is_pad<uint32_t>(e);
+                const T2 v = row[pk ? (int)(e >> 6) : 0];
+                const T2 a = amp_s[pk ? (int)(e & 63u) : kAmpSlots];
+                re = fma_t(a.x, v.x, re);
+                re = fma_t(-a.y, v.y, re);
+                im = fma_t(a.x, v.y, im);
+                im = fma_t(a.y, v.x, im);
+            }
+        }
+        const T2 xv = row[c];
+        const T2 iov = io[base + c];
+        const T nd = static_cast<T>(__popcll(su & st_dn[c]));
+        T qr = iov.x + t * re + U * nd * xv.x;
+        T qi = iov.y + t * im + U * nd * xv.y;
+        T2 pv;
+        pv.x = T(0);
+        pv.y = T(0);
+        if (MODE != 0) {
+            qr *= sig;
+            qi *= sig;
+            if (use_p) {
+                pv = p[base + c];
+                qr -= cprev * pv.x;
+                qi -= cprev * pv.y;
+            }
+        }
+        T2 qv;
+        qv.x = qr;
+        qv.y = qi;
+        io[base + c] = qv;
+        if (MODE != 0) {
+            s[0] += (double)qr * xv.x + (double)qi * xv.y;
+            if constexpr (MODE == 2) {
+                s[1] += (double)qr * pv.x + (double)qi * pv.y;
+                s[2] += (double)xv.x * xv.x + (double)xv.y * xv.y;
+                s[3] += (double)xv.x * pv.x + (double)xv.y * pv.y;
+                s[4] += (double)pv.x * pv.x + (double)pv.y * pv.y;
+            }
+        }
+    }
+    if (MODE != 0) {
+        double tot[NV];
+        block_sum<NV>(s, tot);
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int k = 0; k < NV; ++k) partials[(int64_t)blockIdx.x * kPartStride + k] = tot[k];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // k_reduce: fixed-order sum of the partial dots, then a_j and the update
 // coefficients.  MODE 1 (Alg. 1, float64): a_j = q.f_j, remove a_j f_j.
 // MODE 2 (mixed, local re-orthogonalisation): remove q's projection onto
@@ -428,11 +608,19 @@ static int grid_for(int64_t n, int block, int cap = 4096) {
 // long for LDS, one row per workgroup split into csplit column blocks.
 struct DownShape { bool lds; int rpb, csplit, grid; };
 
+// LDS bytes of k_downc's amplitude table (kAmpSlots + 1 values, padded)
+static int64_t complex_amp_lds(const ed_ham *h) { return (int64_t)(kAmpSlots + 2) * 2 * elem_size(h); }
+
 static DownShape down_shape(const ed_ham *h, const Tile &tl) {
     DownShape d;
-    const int64_t row_bytes = h->dim_dn * (int64_t)elem_size(h);
-    d.lds = row_bytes * tl.dn_rpb <= kLdsBudget;
-    d.rpb = d.lds ? tl.dn_rpb : 1;
+    const int64_t row_bytes = h->dim_dn * (int64_t)elem_size(h) * (h->cplx ? 2 : 1);
+    if (h->cplx) {   // one row per workgroup
+        d.lds = row_bytes + complex_amp_lds(h) <= kLdsBudget;
+        d.rpb = 1;
+    } else {
+        d.lds = row_bytes * tl.dn_rpb <= kLdsBudget;
+        d.rpb = d.lds ? tl.dn_rpb : 1;
+    }
     d.csplit = 1;
     if (!d.lds) {
         const int64_t want = (kDownBlocks + h->dim_up - 1) / h->dim_up;
@@ -546,8 +734,31 @@ static int launch_up_e(const ed_ham *h, const Tile &tl, const T *x, T *out, int 
 }
 
 template <typename T>
+static int launch_up_c(const ed_ham *h, const Tile &tl, const T *x, T *out, const Hdr *hdr, int gate,
+                       int max_steps, hipStream_t s) {
+    using T2 = typename Cplx<T>::type;
+    const int64_t n = 2 * h->dim_up * h->dim_dn;
+    if (h->w_up == 0) {   // no up hopping: out = 0 (k_downc adds it)
+        hipLaunchKernelGGL(k_fill0<T>, dim3(grid_for(n, 256)), dim3(256), 0, s, out, n);
+        ED_LAUNCHED("k_fill0");
+        return ED_OK;
+    }
+    const int n_stripes = (int)((h->dim_dn + 63) / 64);
+    const int n_rc = (int)((h->dim_up + tl.up_rc - 1) / tl.up_rc);
+    const int64_t grid = 8LL * n_rc * ((n_stripes + 7) / 8);
+    if (grid > 0x7fffffffLL) return set_error(ED_EOVERFLOW, "k_upc grid too large");
+    hipLaunchKernelGGL((k_upc<T>), dim3((unsigned)grid), dim3(256), 0, s, reinterpret_cast<const T2 *>(x),
+                       reinterpret_cast<T2 *>(out), static_cast<const uint32_t *>(h->tab_up), h->amp_up,
+                       (int)h->dim_up, (int)h->dim_dn, h->w_up, tl.up_rc, n_stripes, n_rc, static_cast<T>(h->t), hdr,
+                       gate, max_steps);
+    ED_LAUNCHED("k_upc");
+    return ED_OK;
+}
+
+template <typename T>
 static int launch_up(const ed_ham *h, const Tile &tl, const T *x, T *out, int *ctr, const Hdr *hdr, int gate,
                      int max_steps, hipStream_t s) {
+    if (h->cplx) return launch_up_c<T>(h, tl, x, out, hdr, gate, max_steps, s);
     if (wide_up(h)) return launch_up_e<T, uint32_t>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
     return launch_up_e<T, uint16_t>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
 }
@@ -612,8 +823,31 @@ static int launch_down_e(const ed_ham *h, const Tile &tl, const T *x, T *io, con
 }
 
 template <typename T, int MODE>
+static int launch_down_c(const ed_ham *h, const Tile &tl, const T *x, T *io, const T *p, const double *bvec,
+                         const Hdr *hdr, double *part, int max_steps, hipStream_t s) {
+    using T2 = typename Cplx<T>::type;
+    const DownShape d = down_shape(h, tl);
+    const int block = std::min(tl.dn_block, 512);
+    const size_t shm = (size_t)complex_amp_lds(h) + (d.lds ? (size_t)(h->dim_dn * 2 * sizeof(T)) : 0);
+    const T2 *x2 = reinterpret_cast<const T2 *>(x), *p2 = reinterpret_cast<const T2 *>(p);
+    T2 *io2 = reinterpret_cast<T2 *>(io);
+    const uint32_t *tab = static_cast<const uint32_t *>(h->tab_dn);
+    if (d.lds)
+        hipLaunchKernelGGL((k_downc<T, MODE, true>), dim3(d.grid), dim3(block), shm, s, x2, io2, p2, tab, h->amp_dn,
+                           h->st_up, h->st_dn, (int)h->dim_dn, h->w_dn, d.csplit, static_cast<T>(h->t),
+                           static_cast<T>(h->U), bvec, hdr, part, max_steps);
+    else
+        hipLaunchKernelGGL((k_downc<T, MODE, false>), dim3(d.grid), dim3(block), shm, s, x2, io2, p2, tab,
+                           h->amp_dn, h->st_up, h->st_dn, (int)h->dim_dn, h->w_dn, d.csplit, static_cast<T>(h->t),
+                           static_cast<T>(h->U), bvec, hdr, part, max_steps);
+    ED_LAUNCHED("k_downc");
+    return ED_OK;
+}
+
+template <typename T, int MODE>
 static int launch_down(const ed_ham *h, const Tile &tl, const T *x, T *io, const T *p, const double *bvec,
                        const Hdr *hdr, double *part, int max_steps, hipStream_t s) {
+    if (h->cplx) return launch_down_c<T, MODE>(h, tl, x, io, p, bvec, hdr, part, max_steps, s);
     if (wide_dn(h)) return launch_down_e<T, MODE, uint32_t>(h, tl, x, io, p, bvec, hdr, part, max_steps, s);
     return launch_down_e<T, MODE, uint16_t>(h, tl, x, io, p, bvec, hdr, part, max_steps, s);
 }
@@ -649,11 +883,25 @@ static hipError_t set_lds_attrs_t() {
     return hipSuccess;
 }
 
+template <typename T>
+static hipError_t set_lds_attrs_c() {
+    const void *ks[] = {reinterpret_cast<const void *>(k_downc<T, 0, true>),
+                        reinterpret_cast<const void *>(k_downc<T, 1, true>),
+                        reinterpret_cast<const void *>(k_downc<T, 2, true>)};
+    for (const void *k : ks) {
+        const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 static int ensure_attrs() {
     static int rc = -1000;
     if (rc != -1000) return rc;
     hipError_t e = set_lds_attrs_t<double>();
     if (e == hipSuccess) e = set_lds_attrs_t<float>();
+    if (e == hipSuccess) e = set_lds_attrs_c<double>();
+    if (e == hipSuccess) e = set_lds_attrs_c<float>();
     rc = hip_check(e, "hipFuncSetAttribute(k_down)");
     return rc;
 }
@@ -666,6 +914,9 @@ static int hv_impl(const ed_ham *h, const Tile &tl, const T *x, T *y, int *ctr, 
 }
 
 static int upd_grid(int64_t n) { return grid_for(n, 256 * 4, kUpdBlocks); }
+
+// values of dtype per vector: D, or 2 D (re, im pairs) with complex amplitudes
+static int64_t vec_len(const ed_ham *h) { return h->dim_up * h->dim_dn * (h->cplx ? 2 : 1); }
 
 // One Alg. 1 step on raw pointers (v != nullptr: also v += y_j f_j).  With
 // ev != nullptr an event is recorded before each kernel and after the last.
@@ -682,7 +933,7 @@ static int step_impl(const ed_ham *h, const Tile &tl, const T *f_prev, const T *
     hipLaunchKernelGGL(k_reduce<MODE>, dim3(1), dim3(1024), 0, s, w.part, down_grid(h, tl), w.hdr, a, max_steps);
     ED_LAUNCHED("k_reduce");
     if (ev) ED_HIP(hipEventRecord(ev[3], s));
-    const int64_t n = h->dim_up * h->dim_dn;
+    const int64_t n = vec_len(h);
     const int g = upd_grid(n);
     hipLaunchKernelGGL(k_update<T>, dim3(g), dim3(256), 0, s, f_next, f_cur, f_prev, v, w.y, w.hdr, w.part2, n,
                        max_steps);
@@ -741,7 +992,7 @@ static void rotate(ed_lanczos *st) {
 }
 
 static int init_impl(const ed_ham *h, ed_lanczos *st, const void *f1, const WsLayout &w, hipStream_t s) {
-    const int64_t n = h->dim_up * h->dim_dn;
+    const int64_t n = vec_len(h);
     if (h->dtype == ED_F64)
         return norm_launch<double>((const double *)f1, (double *)st->f_cur, n, w, st->b, 0, s);
     return norm_launch<float>((const float *)f1, (float *)st->f_cur, n, w, st->b, 0, s);
@@ -927,7 +1178,7 @@ int ed_tile_params(int32_t tile, const ed_ham *h, int32_t *params) {
 int ed_tune(const ed_ham *h, const void *x, void *y, void *ws, void *stream, int32_t reps, int32_t *tile,
             double *ms_up, double *ms_dn) {
     clear_error();
-    int rc = check_ham(h, "ed_tune");
+    int rc = check_real(h, "ed_tune");
     if (rc) return rc;
     rc = ensure_attrs();
     if (rc) return rc;
@@ -1103,6 +1354,8 @@ int ed_ground_state(const ed_ham *h, ed_lanczos *st, const void *f1, int32_t m, 
         return set_error(ED_EINVAL, "ed_ground_state: bad arguments (need 1 <= m <= max_steps)");
     if (v == st->f_prev || v == st->f_cur || v == st->f_next || v == f1)
         return set_error(ED_EINVAL, "ed_ground_state: v must not alias f1 or the Lanczos vectors");
+    if (h->cplx && gauge_index >= 0)
+        return set_error(ED_EINVAL, "ed_ground_state: a complex state's phase is not fixed by an index (pass -1)");
     // pass 1: m steps (fewer on breakdown)
     ed_lanczos s1 = *st;
     s1.max_steps = m;
@@ -1118,7 +1371,7 @@ int ed_ground_state(const ed_ham *h, ed_lanczos *st, const void *f1, int32_t m, 
     hipStream_t s = static_cast<hipStream_t>(stream);
     const WsLayout w = ws_layout(h, ws, m);
     ED_HIP(hipMemcpyAsync(w.y, y.data(), 8 * (size_t)k, hipMemcpyHostToDevice, s));
-    const int64_t n = h->dim_up * h->dim_dn;
+    const int64_t n = vec_len(h);
     ed_lanczos s2 = *st;
     rc = init_impl(h, &s2, f1, w, s);
     if (rc) return rc;

@@ -11,6 +11,7 @@
 #include <set>
 #include <string>
 #include <utility>
+#include <tuple>
 #include <vector>
 
 #include "../../include/ed.h"
@@ -103,6 +104,9 @@ double tridiag_lowest(const double *a, const double *b, int m) {
     return 0.5 * (lo + hi);
 }
 
+constexpr int kComplexMaxAmps = 64;                 // distinct values of a complex table (6-bit index)
+constexpr int kComplexMaxDim = (1 << 26) - 1;       // columns in 26 bits; the largest entry stays below padding
+
 // The two device table formats differ only in the entry type.
 template <typename E>
 static int pack_tables_impl(const char *who, const int32_t *cols, const double *vals, const int32_t *nnz, int64_t dim,
@@ -188,10 +192,11 @@ int ed_state_rank(int n_sites, int n_part, const uint64_t *states, int64_t n, in
     return ED_OK;
 }
 
-int ed_build_hopping(int n_sites, const int32_t *bonds, int n_bonds, const uint64_t *states,
-                     int64_t dim, int layout, int32_t cap_width, int32_t *cols, double *vals,
-                     int32_t *nnz, int32_t *width) {
-    clear_error();
+// One species' hopping rows (real values -sign, or with amps the complex amplitude of the term that
+// connects the row state to the column state times the sign); vals has 1 or 2 doubles per entry.
+static int build_hopping_impl(int n_sites, const int32_t *bonds, int n_bonds, const double *amps,
+                              const uint64_t *states, int64_t dim, int layout, int32_t cap_width, int32_t *cols,
+                              double *vals, int32_t *nnz, int32_t *width) {
     if (!width) return set_error(ED_EINVAL, "ed_build_hopping: width is NULL");
     if (n_sites < 1 || n_sites > 64) return set_error(ED_EINVAL, "ed_build_hopping: n_sites=%d", n_sites);
     if (n_bonds < 0 || (n_bonds > 0 && !bonds)) return set_error(ED_EINVAL, "ed_build_hopping: bad bonds");
@@ -236,9 +241,11 @@ int ed_build_hopping(int n_sites, const int32_t *bonds, int n_bonds, const uint6
     if (cols == nullptr && vals == nullptr && nnz == nullptr && cap_width == 0) return ED_OK;
     if (!cols || !vals || !nnz) return set_error(ED_EINVAL, "ed_build_hopping: NULL output buffer");
     if (cap_width < w) return set_error(ED_ECAPACITY, "ed_build_hopping: cap_width %d < width %d", cap_width, w);
-    std::vector<std::pair<int32_t, double>> row;
+    // (column, value re, value im) of each nonzero of a row
+    std::vector<std::tuple<int32_t, double, double>> row;
     row.reserve(n_bonds);
     const int64_t W = cap_width;
+    const int nv = amps ? 2 : 1;
     for (int64_t r = 0; r < dim; ++r) {
         uint64_t s = states[r];
         row.clear();
@@ -247,19 +254,46 @@ int ed_build_hopping(int n_sites, const int32_t *bonds, int n_bonds, const uint6
             if (!m || m == bmask[k]) continue;      // both empty or both occupied: no hop
             uint64_t t = s ^ bmask[k];
             int sign = (__builtin_popcountll(s & between[k]) & 1) ? -1 : 1;
-            row.push_back({(int32_t)colex_rank(t), -1.0 * sign});
+            double re = -1.0, im = 0.0;
+            if (amps) {
+                // term a c+_i c_j + conj(a) c+_j c_i of bond (i, j): the row state holds the particle at i
+                // for a (it came from j), at j for conj(a)
+                const int i = bonds[2 * k];
+                re = amps[2 * k];
+                im = ((s >> i) & 1ULL) ? amps[2 * k + 1] : -amps[2 * k + 1];
+            }
+            row.emplace_back((int32_t)colex_rank(t), re * sign, im * sign);
         }
-        std::sort(row.begin(), row.end());
+        std::sort(row.begin(), row.end(), [](const auto &a, const auto &b) { return std::get<0>(a) < std::get<0>(b); });
         nnz[r] = (int32_t)row.size();
         for (int64_t k = 0; k < W; ++k) {
-            int32_t c = k < (int64_t)row.size() ? row[k].first : 0;
-            double v = k < (int64_t)row.size() ? row[k].second : 0.0;
+            const bool live = k < (int64_t)row.size();
             int64_t at = layout == ED_ROW_MAJOR ? r * W + k : k * dim + r;
-            cols[at] = c;
-            vals[at] = v;
+            cols[at] = live ? std::get<0>(row[k]) : 0;
+            vals[nv * at] = live ? std::get<1>(row[k]) : 0.0;
+            if (amps) vals[nv * at + 1] = live ? std::get<2>(row[k]) : 0.0;
         }
     }
     return ED_OK;
+}
+
+int ed_build_hopping(int n_sites, const int32_t *bonds, int n_bonds, const uint64_t *states,
+                     int64_t dim, int layout, int32_t cap_width, int32_t *cols, double *vals,
+                     int32_t *nnz, int32_t *width) {
+    clear_error();
+    return build_hopping_impl(n_sites, bonds, n_bonds, nullptr, states, dim, layout, cap_width, cols, vals, nnz,
+                              width);
+}
+
+int ed_build_hopping_complex(int n_sites, const int32_t *bonds, int n_bonds, const double *amps,
+                             const uint64_t *states, int64_t dim, int layout, int32_t cap_width, int32_t *cols,
+                             double *vals, int32_t *nnz, int32_t *width) {
+    clear_error();
+    if (n_bonds > 0 && !amps) return set_error(ED_EINVAL, "ed_build_hopping_complex: amps is NULL");
+    for (int k = 0; k < 2 * n_bonds; ++k)
+        if (!std::isfinite(amps[k])) return set_error(ED_EINVAL, "ed_build_hopping_complex: non-finite amplitude");
+    return build_hopping_impl(n_sites, bonds, n_bonds, amps, states, dim, layout, cap_width, cols, vals, nnz,
+                              width);
 }
 
 int ed_pack_tables(const int32_t *cols, const double *vals, const int32_t *nnz, int64_t dim,
@@ -273,6 +307,49 @@ int ed_pack_tables32(const int32_t *cols, const double *vals, const int32_t *nnz
     clear_error();
     return pack_tables_impl<uint32_t>("ed_pack_tables32", cols, vals, nnz, dim, width, layout, int64_t(1) << 30,
                                       packed);
+}
+
+int ed_pack_tables_complex(const int32_t *cols, const double *vals, const int32_t *nnz, int64_t dim,
+                           int32_t width, int layout, uint32_t *packed, double *amps, int32_t *n_amps) {
+    clear_error();
+    const char *who = "ed_pack_tables_complex";
+    if (!cols || !vals || !nnz || !packed || !amps || !n_amps || dim < 1 || width < 0)
+        return set_error(ED_EINVAL, "%s: bad arguments", who);
+    if (dim > kComplexMaxDim) return set_error(ED_EOVERFLOW, "%s: dim %lld > %d", who, (long long)dim, kComplexMaxDim);
+    if (layout != ED_ROW_MAJOR && layout != ED_COL_MAJOR) return set_error(ED_EINVAL, "%s: bad layout %d", who, layout);
+    const int64_t stride = (width + 7) & ~7;
+    int n = 0;
+    for (int64_t r = 0; r < dim; ++r) {
+        if (nnz[r] < 0 || nnz[r] > width)
+            return set_error(ED_EINVAL, "%s: nnz[%lld] = %d out of range", who, (long long)r, nnz[r]);
+        int64_t last = -1;
+        for (int64_t k = 0; k < stride; ++k) {
+            uint32_t e = 0xFFFFFFFFu;
+            if (k < nnz[r]) {
+                const int64_t at = layout == ED_ROW_MAJOR ? r * width + k : k * dim + r;
+                const int32_t c = cols[at];
+                if (c < 0 || c >= dim) return set_error(ED_EINVAL, "%s: column %d out of range", who, c);
+                if (c <= last) return set_error(ED_EINVAL, "%s: row %lld not in ascending column order", who, (long long)r);
+                last = c;
+                const double re = vals[2 * at], im = vals[2 * at + 1];
+                if (!std::isfinite(re) || !std::isfinite(im)) return set_error(ED_EINVAL, "%s: non-finite value", who);
+                int idx = 0;
+                while (idx < n && !(amps[2 * idx] == re && amps[2 * idx + 1] == im)) ++idx;
+                if (idx == n) {
+                    if (n == kComplexMaxAmps)
+                        return set_error(ED_EOVERFLOW, "%s: more than %d distinct values", who, kComplexMaxAmps);
+                    amps[2 * n] = re;
+                    amps[2 * n + 1] = im;
+                    ++n;
+                }
+                e = ((uint32_t)c << 6) | (uint32_t)idx;
+            }
+            packed[r * stride + k] = e;                                   // row-major part
+            packed[dim * stride + ((k >> 3) * dim + r) * 8 + (k & 7)] = e;  // 8-interleaved part
+        }
+    }
+    *n_amps = n;
+    return ED_OK;
 }
 
 int ed_occupation_correlations(const double *g, int32_t n_sites, double *docc, double *nn, double *szsz) {

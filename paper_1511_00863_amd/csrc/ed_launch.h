@@ -48,6 +48,8 @@ constexpr int kNumUp = sizeof(kUpTiles) / sizeof(kUpTiles[0]);
 constexpr int kNumDn = sizeof(kDnTiles) / sizeof(kDnTiles[0]);
 constexpr int kLdsBudget = 152 * 1024;
 constexpr int kMaxWideDim = 1 << 30;   // per-spin dimension limit of the 32-bit table format
+constexpr int kComplexMaxDim = (1 << 26) - 1;   // columns of a complex table entry: 26 bits
+constexpr int kAmpSlots = 64;                    // complex amplitude values per species (6-bit index)
 constexpr int kDownBlocks = 2048;      // workgroups a k_down launch of long rows is split into, at least
 
 static inline int elem_size(const ed_ham *h) { return h->dtype == ED_F64 ? 8 : 4; }
@@ -118,8 +120,23 @@ static inline int check_ham(const ed_ham *h, const char *who) {
     if ((h->w_up & 7) || (h->w_dn & 7)) return set_error(ED_EINVAL, "%s: table strides must be multiples of 8", who);
     if (h->w_up > 64 || h->w_dn > 64) return set_error(ED_EOVERFLOW, "%s: table strides above 64 unsupported", who);
     if (h->dtype != ED_F64 && h->dtype != ED_F32) return set_error(ED_EINVAL, "%s: bad dtype %d", who, h->dtype);
+    if (h->cplx != 0 && h->cplx != 1) return set_error(ED_EINVAL, "%s: cplx must be 0 or 1", who);
+    if (h->cplx) {
+        if ((h->w_up && (!wide_up(h) || !h->amp_up)) || (h->w_dn && (!wide_dn(h) || !h->amp_dn)))
+            return set_error(ED_EINVAL, "%s: complex amplitudes need 32-bit complex tables and amplitude arrays", who);
+        if (h->dim_up > kComplexMaxDim || h->dim_dn > kComplexMaxDim)
+            return set_error(ED_EOVERFLOW, "%s: per-spin dims above %d with complex tables", who, kComplexMaxDim);
+    }
     if (!valid_tile_id(h->tile)) return set_error(ED_EINVAL, "%s: bad tile id %d", who, h->tile);
     if (!std::isfinite(h->t) || !std::isfinite(h->U)) return set_error(ED_EINVAL, "%s: non-finite t or U", who);
+    return ED_OK;
+}
+
+// calls that take real instances only
+static inline int check_real(const ed_ham *h, const char *who) {
+    int rc = check_ham(h, who);
+    if (rc) return rc;
+    if (h->cplx) return set_error(ED_EINVAL, "%s: complex amplitudes are not supported by this call", who);
     return ED_OK;
 }
 

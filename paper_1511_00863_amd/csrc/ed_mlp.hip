@@ -565,7 +565,7 @@ int ed_mlp_adam(float *params, const float *grad, float *m, float *v, int32_t st
 
 int ed_mlp_start_vector(const float *params, const ed_ham *h, void *f1, void *stream) {
     clear_error();
-    int rc = check_ham(h, "ed_mlp_start_vector");
+    int rc = check_real(h, "ed_mlp_start_vector");
     if (rc) return rc;
     if (!params || !f1) return set_error(ED_EINVAL, "ed_mlp_start_vector: bad arguments");
     const int64_t n = h->dim_up * h->dim_dn;
@@ -584,7 +584,7 @@ int ed_mlp_start_vector(const float *params, const ed_ham *h, void *f1, void *st
 
 int ed_mlp_row_cdf(const void *psi, const ed_ham *h, double *cdf, void *stream) {
     clear_error();
-    int rc = check_ham(h, "ed_mlp_row_cdf");
+    int rc = check_real(h, "ed_mlp_row_cdf");
     if (rc) return rc;
     if (!psi || !cdf) return set_error(ED_EINVAL, "ed_mlp_row_cdf: bad arguments");
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -604,7 +604,7 @@ int ed_mlp_row_cdf(const void *psi, const ed_ham *h, double *cdf, void *stream) 
 int ed_mlp_sample(const void *psi, const ed_ham *h, const double *row_cdf, const double *uniforms, int32_t n,
                   int32_t *idx, float *target, void *stream) {
     clear_error();
-    int rc = check_ham(h, "ed_mlp_sample");
+    int rc = check_real(h, "ed_mlp_sample");
     if (rc) return rc;
     if (!psi || !row_cdf || !uniforms || n < 1 || !idx || !target)
         return set_error(ED_EINVAL, "ed_mlp_sample: bad arguments");

@@ -129,7 +129,7 @@ static int64_t obs_ws_bytes(const ed_ham *h, int ns) {
 }
 
 static int obs_check(const ed_ham *h, int ns, const char *who) {
-    int rc = check_ham(h, who);
+    int rc = check_real(h, who);
     if (rc) return rc;
     if (ns < 1 || ns > kObsMaxSites) return set_error(ED_EINVAL, "%s: n_sites %d outside 1..%d", who, ns, kObsMaxSites);
     return ED_OK;

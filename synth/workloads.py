@@ -7,7 +7,11 @@ Nothing here computes anything of the method.
 from dataclasses import dataclass, field
 from typing import List, Tuple
 
-from .lattice import ring_bonds, torus_bonds
+from .lattice import checkerboard_terms, ring_bonds, torus_bonds
+
+# synthetic checkerboard amplitudes: t1 = 1, phase pi/4, next-nearest 0.3, third-nearest 0.2
+CHECKER_PARAMS = (1.0, 0.7853981633974483, 0.3, 0.2)
+_CHECKER18 = checkerboard_terms(3, 3, *CHECKER_PARAMS)
 
 
 @dataclass(frozen=True)
@@ -22,6 +26,7 @@ class Workload:
     steps: int
     seed: int
     note: str = ""
+    amps: Tuple[complex, ...] = ()     # a complex amplitude per bond (empty: -t on every bond)
 
 
 def _wl(name, n_sites, bonds, n, t, U, steps, seed, note=""):
@@ -42,6 +47,11 @@ WORKLOADS = {
                             "26-site periodic chain, 13 particles of one species, dim 10,400,600"),
     "torus5x6_0x9": Workload("torus5x6_0x9", 30, tuple(torus_bonds(5, 6)), 0, 9, 1.0, 0.0, 100, 8,
                              "30-site 5x6 periodic square lattice, 9 particles of one species, dim 14,307,150"),
+    # complex amplitudes: the paper's largest two-species checkerboard case
+    "checker18_5x5": Workload("checker18_5x5", 18, tuple(b for b, _ in _CHECKER18), 5, 5, 1.0, 4.0, 100, 9,
+                              "18-site checkerboard (3x3 two-site cells, 12 bonds per site, synthetic complex "
+                              "amplitudes), 5 up + 5 down, dim 73,410,624 complex",
+                              tuple(a for _, a in _CHECKER18)),
     "ring18_9x9": _wl("ring18_9x9", 18, ring_bonds(18), 9, 1.0, 4.0, 100, 6,
                       "18-site periodic Hubbard chain at half filling, 9 up + 9 down, dim 2,363,904,400 "
                       "(18.9 GB per float64 vector; 48620 states per species need 32-bit tables)"),

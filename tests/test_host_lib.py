@@ -159,6 +159,44 @@ def test_pack_tables32_beyond_15bit_ranks_matches_oracle():
         assert np.array_equal(np.where(e[live] & 1, -1.0, 1.0), vals)
 
 
+def test_complex_tables_decode_to_the_oracle_matrix():
+    """18-site checkerboard (complex nearest-neighbour amplitudes): the exported rows and the packed
+    complex table (column, amplitude index) reproduce the oracle's complex hopping matrix."""
+    from oracle.hopping import hopping_matrix_complex
+    from synth import checkerboard_terms
+    terms = checkerboard_terms(3, 3, 1.0, np.pi / 4, 0.3, 0.2)
+    bonds, amps = [b for b, _ in terms], [a for _, a in terms]
+    st = ed.build_basis(18, 3)
+    t = ed.api.build_hopping_complex(18, bonds, amps, st, ed.ED_ROW_MAJOR)
+    ref = hopping_matrix_complex(18, bonds, amps, basis_states(18, 3)).toarray()
+    w = t["width"]
+    assert w == int(np.max(np.count_nonzero(ref, axis=1)))
+    cols, vals = t["cols"].reshape(st.size, w), t["vals"].reshape(st.size, w)
+    got = np.zeros_like(ref)
+    for r in range(st.size):
+        for k in range(t["nnz"][r]):
+            got[r, cols[r, k]] = vals[r, k]
+    assert np.max(np.abs(got - ref)) < 1e-15
+    packed, table, n = ed.api.pack_tables_complex(t, st.size)
+    amp = table[0::2] + 1j * table[1::2]
+    assert 1 <= n <= 64 and np.all(amp[n:] == 0)
+    w8 = ed.api.table_stride(w)
+    rm = packed[:st.size * w8].reshape(st.size, w8)
+    il = packed[st.size * w8:].reshape(w8 // 8, st.size, 8)
+    assert np.array_equal(il.transpose(1, 0, 2).reshape(st.size, w8), rm)
+    dec = np.zeros_like(ref)
+    for r in range(st.size):
+        for e in rm[r]:
+            if e != 0xFFFFFFFF:
+                dec[r, int(e) >> 6] = amp[int(e) & 63]
+    assert np.array_equal(dec, got)
+    # every amplitude -1 is the real table
+    tr = ed.build_hopping(18, bonds, st, ed.ED_ROW_MAJOR)
+    tc = ed.api.build_hopping_complex(18, bonds, [-1.0] * len(bonds), st, ed.ED_ROW_MAJOR)
+    assert np.array_equal(tc["cols"], tr["cols"]) and np.array_equal(tc["vals"].real, tr["vals"])
+    assert np.all(tc["vals"].imag == 0)
+
+
 def test_hopping_errors():
     st = ed.build_basis(4, 2)
     with pytest.raises(ed.EdError):
