@@ -303,6 +303,18 @@ def cpu_baseline(wl, n_steps):
                       % (n_steps, wl.name, m.dim, dt)}
 
 
+_T0 = None
+
+
+def progress(what: str):
+    """One progress line on stderr (stdout carries only the JSON line)."""
+    global _T0
+    if _T0 is None:
+        _T0 = time.time()
+    sys.stderr.write("[bench %6.1f s] %s\n" % (time.time() - _T0, what))
+    sys.stderr.flush()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -354,6 +366,7 @@ def main():
         es = 8 if dtype == "f64" else 4
         kb = kernel_bytes(h, es)
         hv_bytes = 2 * es * h.dim + h.dim_up * h.up.width * h.up.entry_bytes + h.dim_dn * h.dn.width * h.dn.entry_bytes
+        progress("%s step timed: %.3f ms" % (dtype, ms))
         results[dtype] = {"ms_per_step": ms, "steps_per_s": 1000.0 / ms, "kernel_ms": per, "kernel_bytes": kb,
                           "tile": h.tile, "tile_params": h.tile_params(), "tile_src": tile_src,
                           "hv_alg_GBps": hv_bytes / ((per["k_up"] + per["k_down"]) * 1e-3) / 1e9,
@@ -394,16 +407,22 @@ def main():
                          "kernel_ms": r32["kernel_ms"], "step_floor_frac": r32["step_floor_GBps"] / HBM_PEAK_GBPS,
                          "tile": {"id": r32["tile"], "source": r32["tile_src"], **r32["tile_params"]}}
     if not args.no_learned:
+        progress("time to E0 (training the start-vector network)")
         line["time_to_e0"] = time_to_e0_block(up, dn, wl, args)
     if not args.no_batch:
+        progress("batch")
         line["batch"] = batch_block(args)
     if not args.no_scale:
+        progress("18-site 9+9 scale run")
         line["scale"] = scale_block(args)
     if not args.no_single:
+        progress("one-species runs")
         line["single_species"] = single_block(args)
     if not args.no_complex:
+        progress("complex-amplitude checkerboard run")
         line["complex"] = complex_block(args)
     if not args.no_cpu_baseline:
+        progress("CPU baseline (the oracle)")
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
     print(json.dumps(line), flush=True)
 
