@@ -287,15 +287,20 @@ __global__ __launch_bounds__(256) void k_upc(const typename Cplx<T>::type *__res
     for (int r = rci * rc + wave; r < r1; r += nwave) {
         const uint32_t *row = tab + (int64_t)r * W8;
         T re = T(0), im = T(0);
-        for (int k8 = 0; k8 < nch; ++k8) {
-            uint32_t e[8];
+        // two chunks (16 gathers) in flight per pass; a second chunk beyond the row's nch reads the next 8
+        // entries of the table (still inside it: the interleaved half follows) and counts as padding
+        for (int k8 = 0; k8 < nch; k8 += 2) {
+            uint32_t e[16];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) e[k] = row[8 * k8 + k];
+            for (int k = 0; k < 16; ++k) {
+                const uint32_t v = row[8 * k8 + k];
+                e[k] = (k < 8 || k8 + 1 < nch) ? v : 0xFFFFFFFFu;
+            }
             if (e[0] == 0xFFFFFFFFu) break;   // ascending columns, padding at the end
-            T2 v[8];
-            T ar[8], ai[8];
+            T2 v[16];
+            T ar[16], ai[16];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
+            for (int k = 0; k < 16; ++k) {
                 const bool pk = e[k] != 0xFFFFFFFFu;
                 const unsigned ia = pk ? (e[k] & 63u) : 0u;
                 v[k] = xc[(int64_t)(pk ? (e[k] >> 6) : 0u) * Ddn];
@@ -303,7 +308,7 @@ __global__ __launch_bounds__(256) void k_upc(const typename Cplx<T>::type *__res
                 ai[k] = pk ? static_cast<T>(amp[2 * ia + 1]) : T(0);
             }
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
+            for (int k = 0; k < 16; ++k) {
                 re = fma_t(ar[k], v[k].x, re);
                 re = fma_t(-ai[k], v[k].y, re);
                 im = fma_t(ar[k], v[k].y, im);
@@ -326,7 +331,7 @@ __global__ __launch_bounds__(256) void k_upc(const typename Cplx<T>::type *__res
 // serves padding); longer rows are split into column blocks and gathered
 // from global memory.
 template <typename T, int MODE, bool LDS>
-__global__ __launch_bounds__(512) void k_downc(const typename Cplx<T>::type *__restrict__ x,
+__global__ __launch_bounds__(1024) void k_downc(const typename Cplx<T>::type *__restrict__ x,
                                                typename Cplx<T>::type *__restrict__ io,
                                                const typename Cplx<T>::type *__restrict__ p,
                                                const uint32_t *__restrict__ tab, const double *__restrict__ amp,
@@ -375,38 +380,46 @@ __global__ __launch_bounds__(512) void k_downc(const typename Cplx<T>::type *__r
 #pragma unroll
     for (int k = 0; k < NV; ++k) s[k] = 0.0;
     for (int c = i0 + threadIdx.x; c < iend; c += blockDim.x) {
-        T re = T(0), im = T(0);
-        for (int k8 = 0; k8 < nch; ++k8) {
-            const Chunk8<uint32_t> q = til[(int64_t)k8 * Ddn + c];
-            if (!__any(!is_pad<uint32_t>(entry(q, 0)))) break;
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const unsigned e = entry(q, k);
-                const bool pk = !is_pad<uint32_t>(e);
-                const T2 v = row[pk ? (int)(e >> 6) : 0];
-                const T2 a = amp_s[pk ? (int)(e & 63u) : kAmpSlots];
-                re = fma_t(a.x, v.x, re);
-                re = fma_t(-a.y, v.y, re);
-                im = fma_t(a.x, v.y, im);
-                im = fma_t(a.y, v.x, im);
-            }
-        }
-        const T2 xv = row[c];
+        // the epilogue's global operands first, so they are in flight during the gathers
         const T2 iov = io[base + c];
-        const T nd = static_cast<T>(__popcll(su & st_dn[c]));
-        T qr = iov.x + t * re + U * nd * xv.x;
-        T qi = iov.y + t * im + U * nd * xv.y;
+        const uint64_t sdv = st_dn[c];
         T2 pv;
         pv.x = T(0);
         pv.y = T(0);
         if (MODE != 0) {
+            const T2 pl = p[base + c];   // always a valid element; zeroed when there is no f_{j-1}
+            pv.x = keep_or_zero(pl.x, use_p);
+            pv.y = keep_or_zero(pl.y, use_p);
+        }
+        T re = T(0), im = T(0);
+        if (nch > 0) {   // a species without hopping may pass no table
+            Chunk8<uint32_t> q = table_chunk<8, uint32_t>(til, 0, nch, Ddn, c);
+            for (int k8 = 0; k8 < nch; ++k8) {
+                const Chunk8<uint32_t> qn = table_chunk<8, uint32_t>(til, k8 + 1, nch, Ddn, c);   // next chunk
+                if (!__any(!is_pad<uint32_t>(entry(q, 0)))) break;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const unsigned e = entry(q, k);
+                    const bool pk = !is_pad<uint32_t>(e);
+                    const T2 v = row[pk ? (int)(e >> 6) : 0];
+                    const T2 a = amp_s[pk ? (int)(e & 63u) : kAmpSlots];
+                    re = fma_t(a.x, v.x, re);
+                    re = fma_t(-a.y, v.y, re);
+                    im = fma_t(a.x, v.y, im);
+                    im = fma_t(a.y, v.x, im);
+                }
+                q = qn;
+            }
+        }
+        const T2 xv = row[c];
+        const T nd = static_cast<T>(__popcll(su & sdv));
+        T qr = iov.x + t * re + U * nd * xv.x;
+        T qi = iov.y + t * im + U * nd * xv.y;
+        if (MODE != 0) {
             qr *= sig;
             qi *= sig;
-            if (use_p) {
-                pv = p[base + c];
-                qr -= cprev * pv.x;
-                qi -= cprev * pv.y;
-            }
+            qr -= cprev * pv.x;   // pv is zero without f_{j-1}
+            qi -= cprev * pv.y;
         }
         T2 qv;
         qv.x = qr;
@@ -827,7 +840,7 @@ static int launch_down_c(const ed_ham *h, const Tile &tl, const T *x, T *io, con
                          const Hdr *hdr, double *part, int max_steps, hipStream_t s) {
     using T2 = typename Cplx<T>::type;
     const DownShape d = down_shape(h, tl);
-    const int block = std::min(tl.dn_block, 512);
+    const int block = std::min(tl.dn_block, 1024);
     const size_t shm = (size_t)complex_amp_lds(h) + (d.lds ? (size_t)(h->dim_dn * 2 * sizeof(T)) : 0);
     const T2 *x2 = reinterpret_cast<const T2 *>(x), *p2 = reinterpret_cast<const T2 *>(p);
     T2 *io2 = reinterpret_cast<T2 *>(io);
