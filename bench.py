@@ -279,10 +279,21 @@ def batch_block(args):
         seq_e0.append(rr["e0"])
         del x
     seq_e0 = np.array(seq_e0)
+    # the same instances one after another in the batch's own precision (mixed form), same tolerance
+    mix_ms = 0.0
+    for h, (U, n, s) in zip(hams, draws):
+        x = torch.from_numpy(start_vector(s, h.dim)).to("cuda:0", torch.float32)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h.ground_energy(x, 500, tol=1e-6, check_every=9)
+        torch.cuda.synchronize()
+        mix_ms += (time.perf_counter() - t0) * 1e3
+        del x
     import numpy as np_
     return {"instances": 64, "total_dim": int(sum(h.dim for h in hams)), "wall_ms": r["wall_ms"],
             "graph_used": r["graph_used"], "converged": int((r["status"] == 0).sum()),
             "max_steps_used": int(r["steps"].max()), "sequential_plain_f64_ms": seq_ms,
+            "sequential_mixed_ms": mix_ms,
             "max_rel_dev_vs_f64": float(np_.max(np_.abs(r["e0"] - seq_e0) / np_.abs(seq_e0)))}
 
 

@@ -26,6 +26,7 @@ namespace ed {
 #define ED_GLOBAL __attribute__((address_space(1)))
 
 constexpr int kBatchBlock = 256;
+constexpr int kBatchUpRows = 64;            // rows per up tile at least: amortises the queue's atomic and barriers
 constexpr int kBatchLds = 40 * 1024;        // rows of up to 10240 floats; three workgroups per CU
 constexpr int64_t kUpdChunk = 65536;         // elements per update tile
 constexpr int kConverged = 10;
@@ -312,8 +313,7 @@ __global__ __launch_bounds__(kBatchBlock, 3) void k_batch(BInst *__restrict__ in
                     switch (nch_class(I.W8u >> 3)) {
                     case 1: up_tile_wide<float, 1>(x, out, tab, I.Dup, I.Ddn, I.W8u, I.rc, s, rci, t); break;
                     case 2: up_tile_wide<float, 2>(x, out, tab, I.Dup, I.Ddn, I.W8u, I.rc, s, rci, t); break;
-                    case 4: up_tile_wide<float, 4>(x, out, tab, I.Dup, I.Ddn, I.W8u, I.rc, s, rci, t); break;
-                    default: up_tile_wide<float, 8>(x, out, tab, I.Dup, I.Ddn, I.W8u, I.rc, s, rci, t); break;
+                    default: up_tile_wide<float, 4>(x, out, tab, I.Dup, I.Ddn, I.W8u, I.rc, s, rci, t); break;
                     }
                 }
                 if (threadIdx.x == 0) s_tile = pre;
@@ -556,7 +556,8 @@ static int plan_batch(const ed_batch_item *items, int n, int32_t max_steps, Batc
         if (h.dtype != ED_F32) return set_error(ED_EINVAL, "ed_ground_energy_batch: item %d is not ED_F32", i);
         if (wide_up(&h) || wide_dn(&h))
             return set_error(ED_EINVAL, "ed_ground_energy_batch: item %d has 32-bit tables", i);
-        if (h.w_dn > 32) return set_error(ED_EOVERFLOW, "ed_ground_energy_batch: down table stride above 32");
+        // the persistent kernel's registers serve every phase: its tiles hold at most 4 table chunks
+        if (h.w_dn > 32 || h.w_up > 32) return set_error(ED_EOVERFLOW, "ed_ground_energy_batch: table stride above 32");
         if (h.w_up == 0) return set_error(ED_EINVAL, "ed_ground_energy_batch: item %d has no up-spin hopping", i);
         if (h.dim_dn * 4 > kBatchLds) return set_error(ED_EOVERFLOW, "ed_ground_energy_batch: rows above 40 KB");
         if (fill_ptrs) {
@@ -575,7 +576,7 @@ static int plan_batch(const ed_batch_item *items, int n, int32_t max_steps, Batc
         I.R = 1;
         I.V = (tl.up_wlog2 >= 7 && !(I.Ddn & 1) && I.W8u <= 32) ? 2 : 1;
         const int w = 64 * I.V;
-        I.rc = tl.up_rc;
+        I.rc = std::max(tl.up_rc, kBatchUpRows);
         I.n_stripes = (I.Ddn + w - 1) / w;
         I.n_rc = (I.Dup + I.rc - 1) / I.rc;
         I.up_tiles = h.w_up ? 8 * I.n_rc * ((I.n_stripes + 7) / 8) : 0;

@@ -42,13 +42,18 @@ def test_single_species_band_sum(nu, nd, dtype):
 
 
 def test_batch_rejects_unsupported_shapes():
-    """The batched launch handles down tables up to stride 32 and both species hopping;
+    """The batched launch handles tables up to stride 32 and both species hopping;
     anything else is refused on the host with a clear code, before any launch."""
     wide = ham(12, complete_bonds(12), 6, 6, 1.0, 1.0, "f32")
     _, x = seeded_start(33, wide.dim, "f32")
     announce("batch rejects stride 40")
     with pytest.raises(EdError) as e:
         ed.ground_energy_batch([wide], [x], 50, tol=1e-6)
+    assert e.value.code == -3
+    wide_up = ham(16, complete_bonds(16), 8, 1, 1.0, 1.0, "f32")   # up stride 64, down stride 16
+    _, z = seeded_start(35, wide_up.dim, "f32")
+    with pytest.raises(EdError) as e:
+        ed.ground_energy_batch([wide_up], [z], 50, tol=1e-6)
     assert e.value.code == -3
     no_up = ham(8, ring_bonds(8), 0, 3, 1.0, 1.0, "f32")
     _, y = seeded_start(34, no_up.dim, "f32")
