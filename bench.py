@@ -189,6 +189,47 @@ def complex_block(args):
     return out
 
 
+# The paper's per-iteration times on its K40 (ms; its tables for the 18-site lattices, N_up = N_dn = N/2)
+PAPER_K40_MS = {
+    "ring18": {2: (2.18, 2.26), 3: (2.70, 3.16), 4: (10.4, 17.7), 5: (88.4, 178.0)},        # (SP, DP)
+    "checker18": {2: (2.20, 2.28), 3: (3.84, 5.17), 4: (40.8, 74.8), 5: (425.0, 712.0)},
+}
+
+
+def paper_shapes_block(args):
+    """The paper's own two-species workloads: the 18-site chain (real hopping) and the 18-site checkerboard
+    (complex amplitudes, synthetic values on the same lattice) at N_up = N_dn = 2..5, float64 and the
+    mixed form, with the paper's K40 times beside them (context: other hardware; its FLOP model counts
+    complex arithmetic for both lattices)."""
+    import torch
+    import paper_1511_00863_amd as ed
+    from synth import ring_bonds, start_vector, start_vector_complex, workload
+    dev = "cuda:0"
+    cb = workload("checker18_5x5")
+    out = {}
+    for lat in ("ring18", "checker18"):
+        for n in (2, 3, 4, 5):
+            if lat == "ring18":
+                tab = ed.SpinTables(18, ring_bonds(18), n, dev)
+                x_host = start_vector(11, tab.dim * tab.dim)
+            else:
+                tab = ed.SpinTables(18, cb.bonds, n, dev, amps=list(cb.amps))
+                x_host = start_vector_complex(11, tab.dim * tab.dim)
+            rec = {"dim": tab.dim * tab.dim, "paper_k40_ms": {"f32": PAPER_K40_MS[lat][n][0],
+                                                               "f64": PAPER_K40_MS[lat][n][1]}}
+            for dtype in ("f64", "f32"):
+                h = ed.Hamiltonian(tab, tab, 1.0, 4.0, dtype)
+                ed.api.apply_tuned_tile(h, tune_if_missing=False)
+                x = torch.from_numpy(x_host).to(dev, h.torch_dtype)
+                ms, _, _ = time_run(h, x, 2, args.paper_steps, 1)
+                rec[dtype] = {"ms_per_step": ms, "vs_paper_k40": rec["paper_k40_ms"][dtype] / ms}
+                del x, h
+                torch.cuda.empty_cache()
+            out["%s_%dx%d" % (lat, n, n)] = rec
+            del tab, x_host
+    return out
+
+
 def observables_block(item, wl):
     """Occupation moments of a two-pass ground state (FP32 vector): wall time of ed_occupation_moments
     (two passes over the vector, synchronised) and the double occupancy and nearest-neighbour correlations."""
@@ -344,6 +385,8 @@ def main():
     ap.add_argument("--no-scale", action="store_true", help="skip the 18-site 9+9 run (2.4e9 states)")
     ap.add_argument("--no-single", action="store_true", help="skip the one-species runs")
     ap.add_argument("--no-complex", action="store_true", help="skip the complex-amplitude checkerboard run")
+    ap.add_argument("--no-paper-shapes", action="store_true", help="skip the paper's own 18-site workloads")
+    ap.add_argument("--paper-steps", type=int, default=10)
     ap.add_argument("--complex-steps", type=int, default=20)
     ap.add_argument("--single-steps", type=int, default=20)
     ap.add_argument("--scale-steps", type=int, default=6)
@@ -432,6 +475,9 @@ def main():
     if not args.no_complex:
         progress("complex-amplitude checkerboard run")
         line["complex"] = complex_block(args)
+    if not args.no_paper_shapes:
+        progress("the paper's 18-site workloads")
+        line["paper_shapes"] = paper_shapes_block(args)
     if not args.no_cpu_baseline:
         progress("CPU baseline (the oracle)")
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
