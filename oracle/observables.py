@@ -55,3 +55,53 @@ def correlations(g: np.ndarray, n_sites: int) -> dict:
         "nn": uu + ud + du + dd,                            # <n_i n_j>
         "szsz": (uu - ud - du + dd) / 4.0,                  # <S^z_i S^z_j>
     }
+
+
+def spin_flip_moments(psi: np.ndarray, st_up: np.ndarray, st_dn: np.ndarray, n_sites: int) -> np.ndarray:
+    """C[i, j] = sum_x psi_x * <x'| S+_i S-_j |x> psi_x' over the basis (real psi; raw, not normalised),
+    with S+_i = c+_i,up c_i,dn and S-_j = c+_j,dn c_j,up.
+
+    The operator string c+_i,up c_i,dn c+_j,dn c_j,up is applied right to left to the occupation list of
+    all 2 N_s modes (mode = sigma * N_s + site, every up mode before every down mode, the same order as
+    the basis), one operator at a time, counting occupied modes below each operator for its sign."""
+    from .hopping import annihilate, create
+    ns = n_sites
+    d_dn = len(st_dn)
+    index_up = {int(s): k for k, s in enumerate(st_up)}
+    index_dn = {int(s): k for k, s in enumerate(st_dn)}
+    psi = np.asarray(psi, dtype=np.float64)
+    c = np.zeros((ns, ns))
+    for iu, su in enumerate(st_up):
+        for idn, sd in enumerate(st_dn):
+            amp = psi[iu * d_dn + idn]
+            if amp == 0.0:
+                continue
+            occ = [(int(su) >> k) & 1 for k in range(ns)] + [(int(sd) >> k) & 1 for k in range(ns)]
+            for i in range(ns):
+                for j in range(ns):
+                    state, sign = occ, 1
+                    for op, mode in ((annihilate, j), (create, ns + j), (annihilate, ns + i), (create, i)):
+                        r = op(state, mode)
+                        if r is None:
+                            state = None
+                            break
+                        s_, state = r
+                        sign *= s_
+                    if state is None:
+                        continue
+                    m_up = sum(1 << k for k in range(ns) if state[k])
+                    m_dn = sum(1 << k for k in range(ns) if state[ns + k])
+                    c[i, j] += sign * amp * psi[index_up[m_up] * d_dn + index_dn[m_dn]]
+    return c
+
+
+def spin_correlations(g: np.ndarray, c: np.ndarray, n_sites: int) -> np.ndarray:
+    """<S_i . S_j> from the occupation moments G and the spin-flip moments C (both normalised):
+    <S^z_i S^z_j> + (C[i, j] + C[j, i]) / 2 off the diagonal, and <S_i^2> = 3/4 <(n_up - n_dn)^2> on it."""
+    ns = n_sites
+    zz = correlations(g, ns)["szsz"]
+    out = zz + 0.5 * (c + c.T)
+    for i in range(ns):
+        nu, nd, nud = g[i, i], g[ns + i, ns + i], g[i, ns + i]
+        out[i, i] = 0.75 * (nu + nd - 2.0 * nud)
+    return out

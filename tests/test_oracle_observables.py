@@ -84,3 +84,59 @@ def test_u0_double_occupancy_factorises_ring6():
     assert w[1] - w[0] > 1e-6          # non-degenerate: N = 3 is a closed shell on the 6-ring
     c = correlations(occupation_moments(v[:, 0], m.st_up, m.st_dn, 6), 6)
     assert np.max(np.abs(c["docc"] - 0.25)) < 1e-10
+
+
+def _fock_spin_flip(psi, su, sd, ns):
+    """<psi| S+_i S-_j |psi> with S+- built from the Fock-space Jordan-Wigner annihilators."""
+    n_modes = 2 * ns
+    fock_idx = np.array([int(a) | (int(b) << ns) for a in su for b in sd])
+    full = np.zeros(2 ** n_modes)
+    full[fock_idx] = psi
+    c_ = [annihilator(m, n_modes) for m in range(n_modes)]
+    out = np.zeros((ns, ns))
+    for i in range(ns):
+        sp = (c_[i].T @ c_[ns + i]).tocsr()            # c+_i,up c_i,dn
+        for j in range(ns):
+            sm = (c_[ns + j].T @ c_[j]).tocsr()        # c+_j,dn c_j,up
+            out[i, j] = full @ (sp @ (sm @ full))
+    return out
+
+
+@pytest.mark.parametrize("ns,nu,nd", [(4, 2, 2), (5, 2, 3), (4, 1, 3)])
+def test_spin_flip_moments_match_fock_operators(ns, nu, nd):
+    from oracle.observables import spin_flip_moments
+    su, sd = basis_states(ns, nu), basis_states(ns, nd)
+    psi = start_vector(43 + ns, len(su) * len(sd))
+    assert np.max(np.abs(spin_flip_moments(psi, su, sd, ns) - _fock_spin_flip(psi, su, sd, ns))) < 1e-12
+
+
+@pytest.mark.parametrize("ns,bonds", [(8, ring_bonds(8)), (6, ring_bonds(6)), (4, torus_bonds(2, 2))])
+def test_singlet_ground_state_su2(ns, bonds):
+    """On a bipartite lattice at half filling the ground state is a spin singlet (Lieb): <S+_i S-_j> =
+    2 <S^z_i S^z_j> off the diagonal, and sum_ij <S_i . S_j> = S(S+1) = 0."""
+    from oracle.observables import spin_correlations, spin_flip_moments
+    m = Model(ns, bonds, ns // 2, ns // 2, 1.0, 4.0)
+    _, v = _ground(m)
+    g = occupation_moments(v, m.st_up, m.st_dn, ns)
+    c = spin_flip_moments(v, m.st_up, m.st_dn, ns)
+    zz = correlations(g, ns)["szsz"]
+    off = ~np.eye(ns, dtype=bool)
+    assert np.max(np.abs(c[off] - 2.0 * zz[off])) < 1e-10
+    ss = spin_correlations(g, c, ns)
+    assert abs(ss.sum()) < 1e-10
+    # the diagonal of C is <n_up (1 - n_dn)>
+    assert np.max(np.abs(np.diag(c) - (np.diag(g)[:ns] - np.diag(g[:ns, ns:])))) < 1e-12
+
+
+def test_two_site_singlet_spin_correlation():
+    """Two-site Hubbard ground state (a singlet): <S_0 . S_1> = -(3/4) * (1 - 2 d) with d = <n_up n_dn> per site
+    (each site is singly occupied with probability 1 - 2d and the two spins then form the singlet)."""
+    from oracle.observables import spin_correlations, spin_flip_moments
+    U = 3.0
+    m = Model(2, two_site_bonds(), 1, 1, 1.0, U)
+    _, v = _ground(m)
+    g = occupation_moments(v, m.st_up, m.st_dn, 2)
+    ss = spin_correlations(g, spin_flip_moments(v, m.st_up, m.st_dn, 2), 2)
+    d = g[0, 2]
+    assert abs(ss[0, 1] - (-0.75 * (1.0 - 2.0 * d))) < 1e-12
+    assert 0.0 < d < 0.25
