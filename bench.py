@@ -11,13 +11,16 @@ HBM before the timed region; as in the paper's protocol no transfer is timed.
 Beside the step rate the line carries: the roofline of the dominant kernel
 (HIP events inside this run), time-to-E0 at stated accuracy for plain float64,
 mixed and learned starts at a held-out U (the network trained on the
-method's own ground states at U = 1..8), the 64-instance batched launch
-against the same instances run one by one in plain float64, and the oracle
-timed on the host cores.
+method's own ground states at U = 1..8) with the ground state's observables,
+the 64-instance batched launch against the same instances run one by one
+(plain float64 and mixed), the 18-site chain at 9 + 9 (2.36e9 states), the
+one-species runs, the complex-amplitude checkerboard, the paper's own 18-site
+workloads beside its K40 times, and the oracle timed on the host cores.
 
-Prints ONE JSON line.  Options: --steps K --warmup W (timed / untimed steps),
---gpus N (only 1 is supported: the method runs on one GPU), --no-cpu-baseline,
---no-learned, --no-batch.
+Prints ONE JSON line on stdout (progress lines go to stderr).  Options:
+--steps K --warmup W (timed / untimed steps), --gpus N (only 1 is supported:
+the method runs on one GPU), --no-cpu-baseline, --no-learned, --no-batch,
+--no-scale, --no-single, --no-complex, --no-paper-shapes.
 """
 
 import argparse
@@ -247,9 +250,17 @@ def observables_block(item, wl):
         best = dt if best is None else min(best, dt)
     c = ed.occupation_correlations(g, ns)
     a, b = wl.bonds[0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    flip = ham.spin_flip_moments(psi, ns)         # one pass over psi per site
+    flip_ms = (time.perf_counter() - t0) * 1e3
+    ss = ed.spin_correlations(g, flip, ns)
+    off = ~np.eye(ns, dtype=bool)
     return {"U": ham.U, "ms": best, "read_GBps": 2 * psi.numel() * psi.element_size() / (best * 1e6),
             "double_occupancy_per_site": float(c["docc"].mean()),
-            "nn_bond": float(c["nn"][a, b]), "szsz_bond": float(c["szsz"][a, b])}
+            "nn_bond": float(c["nn"][a, b]), "szsz_bond": float(c["szsz"][a, b]),
+            "spin_flip_ms": flip_ms, "ss_bond": float(ss[a, b]), "ss_total": float(ss.sum()),
+            "singlet_check_max_dev": float(np.max(np.abs(flip[off] - 2.0 * c["szsz"][off])))}
 
 
 def time_to_e0_block(up, dn, wl, args):

@@ -351,6 +351,27 @@ int ed_occupation_moments(const ed_ham *h, int32_t n_sites, const void *psi, voi
  * with S^z = (n_up - n_dn)/2.  host; each output may be NULL. */
 int ed_occupation_correlations(const double *g, int32_t n_sites, double *docc, double *nn, double *szsz);
 
+/* Spin-flip moments of a state: c[i * n_sites + j] = <S+_i S-_j> / <psi|psi>
+ * with S+_i = c+_i,up c_i,dn and S-_j = c+_j,dn c_j,up: an up particle moves
+ * j -> i and a down particle i -> j, both staying in the sector; the
+ * diagonal is <n_i,up (1 - n_i,dn)>.  With the occupation moments they give
+ * the full spin correlation <S_i . S_j> (ed_spin_correlations); the
+ * observable of the ground state, which the paper's Lanczos vector gives
+ * (Sec. 2.2).  psi: device, dim_up*dim_dn real values of h->dtype; ws:
+ * device, ed_spin_flip_moments_ws bytes, 256-byte aligned; c: host, n_sites^2
+ * doubles.  One pass over psi per site i, with the target of each hop found
+ * by its colex rank; sums in float64 in a fixed order.  Synchronises
+ * `stream`.  n_sites outside 1..32 or complex amplitudes -> ED_EINVAL. */
+int ed_spin_flip_moments_ws(const ed_ham *h, int32_t n_sites, int64_t *bytes);
+int ed_spin_flip_moments(const ed_ham *h, int32_t n_sites, const void *psi, void *ws, int64_t ws_bytes,
+                         void *stream, double *c);
+
+/* <S_i . S_j> (host, n_sites^2 doubles) from the normalised occupation
+ * moments g (ed_occupation_moments) and spin-flip moments c: <S^z_i S^z_j> +
+ * (c[i][j] + c[j][i]) / 2 off the diagonal, and <S_i^2> = (3/4) <(n_i,up -
+ * n_i,dn)^2> on it.  All host pointers. */
+int ed_spin_correlations(const double *g, const double *c, int32_t n_sites, double *ss);
+
 /* ---- device: the start-vector network ---------------------------------- */
 
 /* psi(bits): 32 inputs (bits 0..15 of the up state, then of the down state,

@@ -66,6 +66,10 @@ _PROTOS = {
                                       POINTER(c_double)]),
     "ed_occupation_correlations": (c_int, [POINTER(c_double), c_int32, POINTER(c_double), POINTER(c_double),
                                            POINTER(c_double)]),
+    "ed_spin_flip_moments_ws": (c_int, [POINTER(EdHam), c_int32, POINTER(c_int64)]),
+    "ed_spin_flip_moments": (c_int, [POINTER(EdHam), c_int32, c_void_p, c_void_p, c_int64, c_void_p,
+                                     POINTER(c_double)]),
+    "ed_spin_correlations": (c_int, [POINTER(c_double), POINTER(c_double), c_int32, POINTER(c_double)]),
     "ed_tridiag_lowest_vector": (c_int, [POINTER(c_double), POINTER(c_double), c_int, POINTER(c_double),
                                          POINTER(c_double)]),
     "ed_workspace_size": (c_int, [POINTER(EdHam), c_int32, POINTER(c_int64)]),

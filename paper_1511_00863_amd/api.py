@@ -149,6 +149,15 @@ def occupation_correlations(g: np.ndarray, n_sites: int) -> dict:
     return {"docc": docc, "nn": nn, "szsz": szsz}
 
 
+def spin_correlations(g: np.ndarray, c: np.ndarray, n_sites: int) -> np.ndarray:
+    """<S_i . S_j> from occupation moments g and spin-flip moments c (ed_spin_correlations)."""
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    ss = np.zeros((n_sites, n_sites))
+    check(lib().ed_spin_correlations(_ptr(g, c_double), _ptr(c, c_double), int(n_sites), _ptr(ss, c_double)))
+    return ss
+
+
 def tridiag_lowest(a, b_off) -> float:
     a = np.ascontiguousarray(a, dtype=np.float64)
     b = np.ascontiguousarray(b_off, dtype=np.float64)
@@ -315,6 +324,18 @@ class Hamiltonian:
         check(lib().ed_occupation_moments(byref(h), int(n_sites), _dptr(psi), _dptr(ws), n.value, _stream(stream),
                                           _ptr(g, c_double)))
         return g
+
+    def spin_flip_moments(self, psi, n_sites: int, stream=None) -> np.ndarray:
+        """C[i][j] = <S+_i S-_j> of the state psi (ed_spin_flip_moments)."""
+        psi = self._vec(psi)
+        n = c_int64(0)
+        h = self.c_struct()
+        check(lib().ed_spin_flip_moments_ws(byref(h), int(n_sites), byref(n)))
+        ws = torch.empty(max(n.value, 1), dtype=torch.uint8, device=self.device)
+        c = np.zeros((n_sites, n_sites))
+        check(lib().ed_spin_flip_moments(byref(h), int(n_sites), _dptr(psi), _dptr(ws), n.value, _stream(stream),
+                                         _ptr(c, c_double)))
+        return c
 
     def lanczos(self, max_steps: int) -> "LanczosRun":
         return LanczosRun(self, max_steps)

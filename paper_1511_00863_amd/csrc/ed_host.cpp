@@ -368,6 +368,23 @@ int ed_occupation_correlations(const double *g, int32_t n_sites, double *docc, d
     return ED_OK;
 }
 
+int ed_spin_correlations(const double *g, const double *c, int32_t n_sites, double *ss) {
+    clear_error();
+    if (!g || !c || !ss || n_sites < 1 || n_sites > 32) return set_error(ED_EINVAL, "ed_spin_correlations: bad arguments");
+    const int ns = n_sites, n2 = 2 * n_sites;
+    auto G = [&](int a, int b) { return g[a * n2 + b]; };
+    for (int i = 0; i < ns; ++i)
+        for (int j = 0; j < ns; ++j) {
+            if (i == j) {
+                ss[i * ns + i] = 0.75 * (G(i, i) + G(ns + i, ns + i) - 2.0 * G(i, ns + i));
+            } else {
+                const double zz = 0.25 * (G(i, j) - G(i, ns + j) - G(ns + i, j) + G(ns + i, ns + j));
+                ss[i * ns + j] = zz + 0.5 * (c[i * ns + j] + c[j * ns + i]);
+            }
+        }
+    return ED_OK;
+}
+
 int ed_tridiag_lowest(const double *a, const double *b, int m, double *e0) {
     clear_error();
     if (!a || !e0 || m < 1 || (m > 1 && !b)) return set_error(ED_EINVAL, "ed_tridiag_lowest: bad arguments");

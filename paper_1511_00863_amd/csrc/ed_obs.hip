@@ -122,6 +122,131 @@ __global__ __launch_bounds__(1024) void k_obs_final(const double *__restrict__ r
     }
 }
 
+// ---------------------------------------------------------------------------
+// Spin-flip moments C[i][j] = <S+_i S-_j> / <psi|psi> with S+_i = c+_i,up c_i,dn
+// and S-_j = c+_j,dn c_j,up.  For i != j the operator moves an up particle
+// j -> i and a down particle i -> j: reordered, it is -(c+_i,up c_j,up)
+// (c+_j,dn c_i,dn), each factor a same-species hop with the sign of the
+// occupied sites strictly between i and j (the rule of the hopping tables).
+// On the diagonal it is n_i,up (1 - n_i,dn).  One launch per i; a workgroup
+// takes one up state r, whose up hop is uniform (its target row and sign are
+// computed once into LDS); each lane takes down states and applies the down
+// hop, finding the target's rank from a binomial table.  Sums are fixed-order
+// block reductions: the result does not depend on the launch.
+constexpr int kFlipSlots = kObsMaxSites + 1;   // the ns values of row i of C, then |psi|^2
+
+__device__ __forceinline__ int64_t colex_rank_lds(uint64_t s, const int64_t (*binom)[kObsMaxSites + 1]) {
+    int64_t r = 0;
+    int k = 0;
+    while (s) {
+        const int p = __ffsll((unsigned long long)s) - 1;
+        r += binom[p][k + 1];
+        ++k;
+        s &= s - 1;
+    }
+    return r;
+}
+
+__device__ __forceinline__ uint64_t between_mask(int i, int j) {
+    const int lo = min(i, j), hi = max(i, j);
+    return ((1ull << hi) - 1ull) & ~((2ull << lo) - 1ull);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_sflip(const T *__restrict__ psi, const uint64_t *__restrict__ st_up,
+                                               const uint64_t *__restrict__ st_dn, int Ddn, int ns, int i,
+                                               double *__restrict__ part) {
+    __shared__ int64_t binom[kObsMaxSites][kObsMaxSites + 1];   // C(n, k), n < 32
+    __shared__ int64_t row2[kObsMaxSites];                      // target up row of the hop j -> i, or -1
+    __shared__ double sgn_up[kObsMaxSites];
+    for (int e = threadIdx.x; e < kObsMaxSites * (kObsMaxSites + 1); e += blockDim.x) {
+        const int n = e / (kObsMaxSites + 1), k = e - n * (kObsMaxSites + 1);
+        int64_t c = k > n ? 0 : 1;
+        for (int m = 1; m <= k && k <= n; ++m) c = c * (n - k + m) / m;   // exact at every step
+        binom[n][k] = c;
+    }
+    __syncthreads();
+    const int r = blockIdx.x;
+    const uint64_t su = st_up[r];
+    const uint64_t bi = 1ull << i;
+    if (threadIdx.x < kObsMaxSites) {
+        const int j = threadIdx.x;
+        const bool ok = j < ns && !(su & bi) && ((su >> j) & 1ull);
+        row2[j] = ok ? colex_rank_lds(su ^ bi ^ (1ull << j), binom) : -1;
+        sgn_up[j] = (__popcll(su & between_mask(i, j)) & 1) ? -1.0 : 1.0;
+    }
+    __syncthreads();
+    double acc[kFlipSlots];
+#pragma unroll
+    for (int j = 0; j < kFlipSlots; ++j) acc[j] = 0.0;
+    const T *row = psi + (int64_t)r * Ddn;
+    const bool up_hole = !(su & bi);
+    for (int c = threadIdx.x; c < Ddn; c += blockDim.x) {
+        const double x = (double)row[c];
+        const uint64_t sd = st_dn[c];
+        acc[kObsMaxSites] += x * x;
+        if (up_hole) {
+            if (sd & bi) {
+#pragma unroll
+                for (int j = 0; j < kObsMaxSites; ++j) {
+                    if (row2[j] >= 0 && !((sd >> j) & 1ull)) {
+                        const int64_t c2 = colex_rank_lds(sd ^ bi ^ (1ull << j), binom);
+                        const double sd_sign = (__popcll(sd & between_mask(i, j)) & 1) ? -1.0 : 1.0;
+                        acc[j] -= sgn_up[j] * sd_sign * x * (double)psi[row2[j] * Ddn + c2];
+                    }
+                }
+            }
+        } else if (!(sd & bi)) {   // diagonal: n_i,up (1 - n_i,dn)
+#pragma unroll
+            for (int j = 0; j < kObsMaxSites; ++j)
+                if (j == i) acc[j] += x * x;
+        }
+    }
+    double tot[kFlipSlots];
+    block_sum<kFlipSlots>(acc, tot);
+    if (threadIdx.x == 0)
+        for (int j = 0; j < kFlipSlots; ++j) part[(int64_t)r * kFlipSlots + j] = tot[j];
+}
+
+// row i of C: fixed-order sums over the up rows, normalised
+__global__ __launch_bounds__(64) void k_sflip_final(const double *__restrict__ part, int Dup, int ns, int i,
+                                                    double *__restrict__ c) {
+    __shared__ double s_norm;
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int r = 0; r < Dup; ++r) s += part[(int64_t)r * kFlipSlots + kObsMaxSites];
+        s_norm = s;
+    }
+    __syncthreads();
+    const int j = threadIdx.x;
+    if (j >= ns) return;
+    double s = 0.0;
+    for (int r = 0; r < Dup; ++r) s += part[(int64_t)r * kFlipSlots + j];
+    c[i * ns + j] = s_norm > 0.0 ? s / s_norm : 0.0;
+}
+
+static int64_t flip_ws_bytes(const ed_ham *h) {
+    auto al = [](int64_t b) { return (b + 255) & ~int64_t(255); };
+    return al(8 * kFlipSlots * h->dim_up) + al(8 * kObsMaxSites * kObsMaxSites);
+}
+
+template <typename T>
+static int flip_impl(const ed_ham *h, int ns, const T *psi, char *ws, hipStream_t s, double *c_host) {
+    auto al = [](int64_t b) { return (b + 255) & ~int64_t(255); };
+    double *part = reinterpret_cast<double *>(ws);
+    double *c = reinterpret_cast<double *>(ws + al(8 * kFlipSlots * h->dim_up));
+    for (int i = 0; i < ns; ++i) {
+        hipLaunchKernelGGL(k_sflip<T>, dim3((unsigned)h->dim_up), dim3(256), 0, s, psi, h->st_up, h->st_dn,
+                           (int)h->dim_dn, ns, i, part);
+        ED_LAUNCHED("k_sflip");
+        hipLaunchKernelGGL(k_sflip_final, dim3(1), dim3(64), 0, s, part, (int)h->dim_up, ns, i, c);
+        ED_LAUNCHED("k_sflip_final");
+    }
+    ED_HIP(hipMemcpyAsync(c_host, c, sizeof(double) * ns * ns, hipMemcpyDeviceToHost, s));
+    ED_HIP(hipStreamSynchronize(s));
+    return ED_OK;
+}
+
 static int64_t obs_ws_bytes(const ed_ham *h, int ns) {
     auto al = [](int64_t b) { return (b + 255) & ~int64_t(255); };
     const int64_t nchunk = (h->dim_up + kObsRowChunk - 1) / kObsRowChunk;
@@ -186,6 +311,29 @@ int ed_occupation_moments(const ed_ham *h, int32_t n_sites, const void *psi, voi
     if (h->dtype == ED_F64)
         return obs_impl<double>(h, n_sites, static_cast<const double *>(psi), static_cast<char *>(ws), s, g);
     return obs_impl<float>(h, n_sites, static_cast<const float *>(psi), static_cast<char *>(ws), s, g);
+}
+
+int ed_spin_flip_moments_ws(const ed_ham *h, int32_t n_sites, int64_t *bytes) {
+    clear_error();
+    int rc = obs_check(h, n_sites, "ed_spin_flip_moments_ws");
+    if (rc) return rc;
+    if (!bytes) return set_error(ED_EINVAL, "ed_spin_flip_moments_ws: bytes is NULL");
+    *bytes = flip_ws_bytes(h);
+    return ED_OK;
+}
+
+int ed_spin_flip_moments(const ed_ham *h, int32_t n_sites, const void *psi, void *ws, int64_t ws_bytes,
+                         void *stream, double *c) {
+    clear_error();
+    int rc = obs_check(h, n_sites, "ed_spin_flip_moments");
+    if (rc) return rc;
+    if (!psi || !ws || !c) return set_error(ED_EINVAL, "ed_spin_flip_moments: NULL buffer");
+    if (reinterpret_cast<uintptr_t>(ws) & 255) return set_error(ED_EINVAL, "ed_spin_flip_moments: ws not aligned");
+    if (ws_bytes < flip_ws_bytes(h)) return set_error(ED_ECAPACITY, "ed_spin_flip_moments: workspace too small");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (h->dtype == ED_F64)
+        return flip_impl<double>(h, n_sites, static_cast<const double *>(psi), static_cast<char *>(ws), s, c);
+    return flip_impl<float>(h, n_sites, static_cast<const float *>(psi), static_cast<char *>(ws), s, c);
 }
 
 }  // extern "C"

@@ -90,3 +90,46 @@ def test_full_size_sum_rules_t44_8x8():
     assert np.max(np.abs(c["szsz"].sum(axis=1))) < 1e-8                    # S^z_tot = 0
     assert np.max(np.abs(n_up - 0.5)) < 1e-4 and np.ptp(c["docc"]) < 1e-4  # uniform at half filling
     assert 0.0 < c["docc"][0] < 0.25                                      # U > 0 suppresses double occupancy
+
+
+FLIP_CASES = [
+    ("ring8_3x2", 8, ring_bonds(8), 3, 2),
+    ("ring8_4x4", 8, ring_bonds(8), 4, 4),
+    ("t32_3x2", 6, torus_bonds(3, 2), 3, 2),
+    ("ring6_0x3", 6, ring_bonds(6), 0, 3),
+]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("case", FLIP_CASES, ids=[c[0] for c in FLIP_CASES])
+def test_spin_flip_moments_match_oracle(case, dtype):
+    from oracle.observables import spin_flip_moments
+    name, ns, bonds, nu, nd = case
+    h = ham(ns, bonds, nu, nd, 1.0, 2.0, dtype)
+    x_host, x = seeded_start(53, h.dim, dtype)
+    announce("spin-flip moments %s %s" % (name, dtype))
+    c = h.spin_flip_moments(x, ns)
+    ref = spin_flip_moments(x_host, h.up.states, h.dn.states, ns) / np.sum(x_host ** 2)
+    assert np.max(np.abs(c - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_full_size_singlet_t44_8x8():
+    """4x4 torus at half filling (D = 165,636,900): the float64 ground state is a singlet, so the spin-flip
+    moments (one kernel) equal twice the S^z correlations (another) off the diagonal, and sum <S_i . S_j> = 0."""
+    tab = ed.SpinTables(16, torus_bonds(4, 4), 8, "cuda:0")
+    h = ed.Hamiltonian(tab, tab, 1.0, 4.0, "f64")
+    ed.api.apply_tuned_tile(h, tune_if_missing=False)
+    _, x = seeded_start(5, h.dim, "f64")
+    announce("ground state 4x4 8+8 f64")
+    r = h.ground_energy(x, 400, tol=1e-12, check_every=15)
+    e0, steps, psi = h.ground_state(x, r["steps"] + 30, gauge_index=mlp.neel_index(h))
+    del x
+    announce("spin correlations 4x4 8+8")
+    g = h.occupation_moments(psi, 16)
+    c = h.spin_flip_moments(psi, 16)
+    zz = ed.occupation_correlations(g, 16)["szsz"]
+    off = ~np.eye(16, dtype=bool)
+    assert np.max(np.abs(c[off] - 2.0 * zz[off])) < 1e-6
+    ss = ed.spin_correlations(g, c, 16)
+    assert abs(ss.sum()) < 1e-5
+    assert np.all(ss[0, [1, 4]] < 0.0)      # antiferromagnetic nearest neighbours

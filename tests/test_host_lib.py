@@ -290,3 +290,13 @@ def test_device_calls_validate_before_touching_the_device():
     # a species without hopping may pass no table
     h = ham(w_dn=0, tab_dn=None)
     assert lib.ed_workspace_size(ctypes.byref(h), 10, ctypes.byref(nbytes)) == 0
+
+
+def test_spin_correlations_match_oracle_formula():
+    from oracle.observables import spin_correlations
+    r = np.random.default_rng(9)
+    ns = 5
+    g = r.uniform(0, 1, (2 * ns, 2 * ns))
+    g = (g + g.T) / 2
+    c = r.uniform(-0.5, 0.5, (ns, ns))
+    assert np.max(np.abs(ed.spin_correlations(g, c, ns) - spin_correlations(g, c, ns))) < 1e-15
