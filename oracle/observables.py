@@ -23,6 +23,8 @@ matrix per basis state, with no use of the product structure of the basis
 
 import numpy as np
 
+from .basis import occupations
+
 
 def occupation_bits(states: np.ndarray, n_sites: int) -> np.ndarray:
     """Row x = the n_sites occupation numbers of basis state x (bit i = site i)."""
@@ -105,3 +107,29 @@ def spin_correlations(g: np.ndarray, c: np.ndarray, n_sites: int) -> np.ndarray:
         nu, nd, nud = g[i, i], g[ns + i, ns + i], g[i, ns + i]
         out[i, i] = 0.75 * (nu + nd - 2.0 * nud)
     return out
+
+
+def bond_moments(psi: np.ndarray, st_up: np.ndarray, st_dn: np.ndarray, n_sites: int, bonds) -> np.ndarray:
+    """K[b, sigma] = sum_x psi_x <x'| c+_i,sigma c_j,sigma + c+_j,sigma c_i,sigma |x> psi_x' for bond b = (i, j)
+    (real psi, raw sums).  The hops are applied with ``hopping.hop`` to the species' occupation list; a hop of
+    either species moves a pair of operators, so the other species adds no sign."""
+    from .hopping import hop, mask_of
+    d_dn = len(st_dn)
+    index_up = {int(s): k for k, s in enumerate(st_up)}
+    index_dn = {int(s): k for k, s in enumerate(st_dn)}
+    psi = np.asarray(psi, dtype=np.float64)
+    k_out = np.zeros((len(bonds), 2))
+    for iu, su in enumerate(st_up):
+        occ_u = occupations(int(su), n_sites)
+        for idn, sd in enumerate(st_dn):
+            amp = psi[iu * d_dn + idn]
+            occ_d = occupations(int(sd), n_sites)
+            for b, (i, j) in enumerate(bonds):
+                for (p, q) in ((i, j), (j, i)):
+                    r = hop(occ_u, p, q)
+                    if r is not None:
+                        k_out[b, 0] += r[0] * amp * psi[index_up[mask_of(r[1])] * d_dn + idn]
+                    r = hop(occ_d, p, q)
+                    if r is not None:
+                        k_out[b, 1] += r[0] * amp * psi[iu * d_dn + index_dn[mask_of(r[1])]]
+    return k_out

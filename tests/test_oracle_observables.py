@@ -140,3 +140,34 @@ def test_two_site_singlet_spin_correlation():
     d = g[0, 2]
     assert abs(ss[0, 1] - (-0.75 * (1.0 - 2.0 * d))) < 1e-12
     assert 0.0 < d < 0.25
+
+
+@pytest.mark.parametrize("ns,bonds,nu,nd,U", [(8, ring_bonds(8), 3, 2, 2.0), (6, torus_bonds(3, 2), 3, 3, 4.0),
+                                              (6, ring_bonds(6), 0, 3, 1.0)])
+def test_energy_is_kinetic_plus_double_occupancy(ns, bonds, nu, nd, U):
+    """For any state: <H> = -t sum_{b, sigma} K[b, sigma] + U sum_i <n_i,up n_i,dn>."""
+    from oracle.observables import bond_moments
+    t = 0.8
+    m = Model(ns, bonds, nu, nd, t, U)
+    psi = start_vector(44 + ns, m.dim)
+    k = bond_moments(psi, m.st_up, m.st_dn, ns, bonds)
+    g = occupation_moments(psi, m.st_up, m.st_dn, ns)
+    assert abs(psi @ m.hv(psi) - (-t * k.sum() + U * np.trace(g[:ns, ns:]))) < 1e-10 * max(1.0, abs(psi @ m.hv(psi)))
+
+
+def test_bond_moments_match_fock_operators():
+    from oracle.observables import bond_moments
+    ns, nu, nd = 5, 2, 3
+    bonds = ring_bonds(5) + [(0, 2)]
+    su, sd = basis_states(ns, nu), basis_states(ns, nd)
+    psi = start_vector(45, len(su) * len(sd))
+    fock_idx = np.array([int(a) | (int(b) << ns) for a in su for b in sd])
+    full = np.zeros(2 ** (2 * ns))
+    full[fock_idx] = psi
+    c_ = [annihilator(m_, 2 * ns) for m_ in range(2 * ns)]
+    k = bond_moments(psi, su, sd, ns, bonds)
+    for b, (i, j) in enumerate(bonds):
+        for s_ in range(2):
+            a, bb = s_ * ns + i, s_ * ns + j
+            op = (c_[a].T @ c_[bb] + c_[bb].T @ c_[a]).tocsr()
+            assert abs(full @ (op @ full) - k[b, s_]) < 1e-12
