@@ -372,6 +372,19 @@ int ed_spin_flip_moments(const ed_ham *h, int32_t n_sites, const void *psi, void
  * n_i,dn)^2> on it.  All host pointers. */
 int ed_spin_correlations(const double *g, const double *c, int32_t n_sites, double *ss);
 
+/* Bond moments of a state: k[2 * b + sigma] = <c+_i,sigma c_j,sigma + c+_j,sigma
+ * c_i,sigma> / <psi|psi> for bond b = (i, j) of `bonds` (host, n_bonds
+ * pairs, 0 <= i, j < n_sites, i != j) and species sigma (0 up, 1 down).  The
+ * hopping energy is -t times their sum (Eq. 1), so <H> = -t sum k + U sum_i
+ * <n_i,up n_i,dn>.  psi: device, real values of h->dtype; ws: device,
+ * ed_bond_moments_ws bytes, 256-byte aligned; k: host, 2 * n_bonds doubles.
+ * One pass over psi per 16 bonds; sums in float64 in a fixed order.
+ * Synchronises `stream`.  Bad bonds, n_sites outside 1..32 or complex
+ * amplitudes -> ED_EINVAL. */
+int ed_bond_moments_ws(const ed_ham *h, int32_t n_sites, int32_t n_bonds, int64_t *bytes);
+int ed_bond_moments(const ed_ham *h, int32_t n_sites, const int32_t *bonds, int32_t n_bonds, const void *psi,
+                    void *ws, int64_t ws_bytes, void *stream, double *k);
+
 /* ---- device: the start-vector network ---------------------------------- */
 
 /* psi(bits): 32 inputs (bits 0..15 of the up state, then of the down state,

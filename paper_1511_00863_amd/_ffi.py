@@ -70,6 +70,9 @@ _PROTOS = {
     "ed_spin_flip_moments": (c_int, [POINTER(EdHam), c_int32, c_void_p, c_void_p, c_int64, c_void_p,
                                      POINTER(c_double)]),
     "ed_spin_correlations": (c_int, [POINTER(c_double), POINTER(c_double), c_int32, POINTER(c_double)]),
+    "ed_bond_moments_ws": (c_int, [POINTER(EdHam), c_int32, c_int32, POINTER(c_int64)]),
+    "ed_bond_moments": (c_int, [POINTER(EdHam), c_int32, POINTER(c_int32), c_int32, c_void_p, c_void_p, c_int64,
+                                c_void_p, POINTER(c_double)]),
     "ed_tridiag_lowest_vector": (c_int, [POINTER(c_double), POINTER(c_double), c_int, POINTER(c_double),
                                          POINTER(c_double)]),
     "ed_workspace_size": (c_int, [POINTER(EdHam), c_int32, POINTER(c_int64)]),

@@ -337,6 +337,19 @@ class Hamiltonian:
                                          _ptr(c, c_double)))
         return c
 
+    def bond_moments(self, psi, n_sites: int, bonds, stream=None) -> np.ndarray:
+        """K[b, sigma] = <c+_i c_j + c+_j c_i> of species sigma for each bond (ed_bond_moments)."""
+        psi = self._vec(psi)
+        b = _bond_array(bonds)
+        n = c_int64(0)
+        h = self.c_struct()
+        check(lib().ed_bond_moments_ws(byref(h), int(n_sites), b.shape[0], byref(n)))
+        ws = torch.empty(max(n.value, 1), dtype=torch.uint8, device=self.device)
+        k = np.zeros((b.shape[0], 2))
+        check(lib().ed_bond_moments(byref(h), int(n_sites), _ptr(b, c_int32), b.shape[0], _dptr(psi), _dptr(ws),
+                                    n.value, _stream(stream), _ptr(k, c_double)))
+        return k
+
     def lanczos(self, max_steps: int) -> "LanczosRun":
         return LanczosRun(self, max_steps)
 

@@ -247,6 +247,119 @@ static int flip_impl(const ed_ham *h, int ns, const T *psi, char *ws, hipStream_
     return ED_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Bond moments K[b][sigma] = <c+_i c_j + c+_j c_i>_sigma / <psi|psi> for bonds
+// b = (i, j).  An up hop over b is uniform along a row (target row and sign
+// computed once into LDS), so its part is a dot product of two rows; a down
+// hop is per lane, the target found by its colex rank.  kBondGroup bonds per
+// launch; sums in a fixed order.
+constexpr int kBondGroup = 16;
+constexpr int kBondSlots = 2 * kBondGroup + 1;   // up and down per bond, then |psi|^2
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_bond(const T *__restrict__ psi, const uint64_t *__restrict__ st_up,
+                                              const uint64_t *__restrict__ st_dn, int Ddn,
+                                              const int32_t *__restrict__ bonds, int nb,
+                                              double *__restrict__ part) {
+    __shared__ int64_t binom[kObsMaxSites][kObsMaxSites + 1];
+    __shared__ int64_t row2[kBondGroup];
+    __shared__ double sgn_up[kBondGroup];
+    __shared__ uint64_t bmask[kBondGroup], bbetween[kBondGroup];
+    for (int e = threadIdx.x; e < kObsMaxSites * (kObsMaxSites + 1); e += blockDim.x) {
+        const int n = e / (kObsMaxSites + 1), k = e - n * (kObsMaxSites + 1);
+        int64_t c = k > n ? 0 : 1;
+        for (int m = 1; m <= k && k <= n; ++m) c = c * (n - k + m) / m;
+        binom[n][k] = c;
+    }
+    const int r = blockIdx.x;
+    const uint64_t su = st_up[r];
+    if (threadIdx.x < kBondGroup) {
+        const int b = threadIdx.x;
+        uint64_t m = 0, btw = 0;
+        if (b < nb) {
+            const int i = bonds[2 * b], j = bonds[2 * b + 1];
+            m = (1ull << i) | (1ull << j);
+            btw = between_mask(i, j);
+        }
+        bmask[b] = m;
+        bbetween[b] = btw;
+    }
+    __syncthreads();
+    if (threadIdx.x < kBondGroup) {
+        const int b = threadIdx.x;
+        const uint64_t m = bmask[b], o = su & m;
+        const bool hop = m && o && o != m;
+        row2[b] = hop ? colex_rank_lds(su ^ m, binom) : -1;
+        sgn_up[b] = (__popcll(su & bbetween[b]) & 1) ? -1.0 : 1.0;
+    }
+    __syncthreads();
+    double acc[kBondSlots];
+#pragma unroll
+    for (int k = 0; k < kBondSlots; ++k) acc[k] = 0.0;
+    const T *row = psi + (int64_t)r * Ddn;
+    for (int c = threadIdx.x; c < Ddn; c += blockDim.x) {
+        const double x = (double)row[c];
+        const uint64_t sd = st_dn[c];
+        acc[2 * kBondGroup] += x * x;
+#pragma unroll
+        for (int b = 0; b < kBondGroup; ++b) {
+            if (row2[b] >= 0) acc[2 * b] += sgn_up[b] * x * (double)psi[row2[b] * Ddn + c];
+            const uint64_t m = bmask[b], o = sd & m;
+            if (m && o && o != m) {
+                const int64_t c2 = colex_rank_lds(sd ^ m, binom);
+                const double sg = (__popcll(sd & bbetween[b]) & 1) ? -1.0 : 1.0;
+                acc[2 * b + 1] += sg * x * (double)row[c2];
+            }
+        }
+    }
+    double tot[kBondSlots];
+    block_sum<kBondSlots>(acc, tot);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < kBondSlots; ++k) part[(int64_t)r * kBondSlots + k] = tot[k];
+}
+
+__global__ __launch_bounds__(64) void k_bond_final(const double *__restrict__ part, int Dup, int nb, int b0,
+                                                   double *__restrict__ kout) {
+    __shared__ double s_norm;
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int r = 0; r < Dup; ++r) s += part[(int64_t)r * kBondSlots + 2 * kBondGroup];
+        s_norm = s;
+    }
+    __syncthreads();
+    const int k = threadIdx.x;
+    if (k >= 2 * nb) return;
+    double s = 0.0;
+    for (int r = 0; r < Dup; ++r) s += part[(int64_t)r * kBondSlots + k];
+    kout[2 * b0 + k] = s_norm > 0.0 ? s / s_norm : 0.0;
+}
+
+static int64_t bond_ws_bytes(const ed_ham *h, int n_bonds) {
+    auto al = [](int64_t b) { return (b + 255) & ~int64_t(255); };
+    return al(8 * kBondSlots * h->dim_up) + al(8 * 2 * (int64_t)n_bonds) + al(8 * (int64_t)n_bonds);
+}
+
+template <typename T>
+static int bond_impl(const ed_ham *h, const int32_t *bonds_host, int n_bonds, const T *psi, char *ws, hipStream_t s,
+                     double *k_host) {
+    auto al = [](int64_t b) { return (b + 255) & ~int64_t(255); };
+    double *part = reinterpret_cast<double *>(ws);
+    double *kout = reinterpret_cast<double *>(ws + al(8 * kBondSlots * h->dim_up));
+    int32_t *bonds = reinterpret_cast<int32_t *>(ws + al(8 * kBondSlots * h->dim_up) + al(8 * 2 * (int64_t)n_bonds));
+    ED_HIP(hipMemcpyAsync(bonds, bonds_host, sizeof(int32_t) * 2 * n_bonds, hipMemcpyHostToDevice, s));
+    for (int b0 = 0; b0 < n_bonds; b0 += kBondGroup) {
+        const int nb = std::min(kBondGroup, n_bonds - b0);
+        hipLaunchKernelGGL(k_bond<T>, dim3((unsigned)h->dim_up), dim3(256), 0, s, psi, h->st_up, h->st_dn,
+                           (int)h->dim_dn, bonds + 2 * b0, nb, part);
+        ED_LAUNCHED("k_bond");
+        hipLaunchKernelGGL(k_bond_final, dim3(1), dim3(64), 0, s, part, (int)h->dim_up, nb, b0, kout);
+        ED_LAUNCHED("k_bond_final");
+    }
+    ED_HIP(hipMemcpyAsync(k_host, kout, sizeof(double) * 2 * n_bonds, hipMemcpyDeviceToHost, s));
+    ED_HIP(hipStreamSynchronize(s));
+    return ED_OK;
+}
+
 static int64_t obs_ws_bytes(const ed_ham *h, int ns) {
     auto al = [](int64_t b) { return (b + 255) & ~int64_t(255); };
     const int64_t nchunk = (h->dim_up + kObsRowChunk - 1) / kObsRowChunk;
@@ -334,6 +447,34 @@ int ed_spin_flip_moments(const ed_ham *h, int32_t n_sites, const void *psi, void
     if (h->dtype == ED_F64)
         return flip_impl<double>(h, n_sites, static_cast<const double *>(psi), static_cast<char *>(ws), s, c);
     return flip_impl<float>(h, n_sites, static_cast<const float *>(psi), static_cast<char *>(ws), s, c);
+}
+
+int ed_bond_moments_ws(const ed_ham *h, int32_t n_sites, int32_t n_bonds, int64_t *bytes) {
+    clear_error();
+    int rc = obs_check(h, n_sites, "ed_bond_moments_ws");
+    if (rc) return rc;
+    if (!bytes || n_bonds < 1) return set_error(ED_EINVAL, "ed_bond_moments_ws: bad arguments");
+    *bytes = bond_ws_bytes(h, n_bonds);
+    return ED_OK;
+}
+
+int ed_bond_moments(const ed_ham *h, int32_t n_sites, const int32_t *bonds, int32_t n_bonds, const void *psi,
+                    void *ws, int64_t ws_bytes, void *stream, double *k) {
+    clear_error();
+    int rc = obs_check(h, n_sites, "ed_bond_moments");
+    if (rc) return rc;
+    if (!bonds || n_bonds < 1 || !psi || !ws || !k) return set_error(ED_EINVAL, "ed_bond_moments: bad arguments");
+    for (int b = 0; b < n_bonds; ++b) {
+        const int i = bonds[2 * b], j = bonds[2 * b + 1];
+        if (i < 0 || j < 0 || i >= n_sites || j >= n_sites || i == j)
+            return set_error(ED_EINVAL, "ed_bond_moments: bond %d = (%d, %d) invalid", b, i, j);
+    }
+    if (reinterpret_cast<uintptr_t>(ws) & 255) return set_error(ED_EINVAL, "ed_bond_moments: ws not aligned");
+    if (ws_bytes < bond_ws_bytes(h, n_bonds)) return set_error(ED_ECAPACITY, "ed_bond_moments: workspace too small");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (h->dtype == ED_F64)
+        return bond_impl<double>(h, bonds, n_bonds, static_cast<const double *>(psi), static_cast<char *>(ws), s, k);
+    return bond_impl<float>(h, bonds, n_bonds, static_cast<const float *>(psi), static_cast<char *>(ws), s, k);
 }
 
 }  // extern "C"

@@ -133,3 +133,44 @@ def test_full_size_singlet_t44_8x8():
     ss = ed.spin_correlations(g, c, 16)
     assert abs(ss.sum()) < 1e-5
     assert np.all(ss[0, [1, 4]] < 0.0)      # antiferromagnetic nearest neighbours
+
+
+BOND_CASES = [
+    ("ring8_3x2", 8, ring_bonds(8), 3, 2),
+    ("t32_3x3", 6, torus_bonds(3, 2), 3, 3),
+    ("ring6_0x3", 6, ring_bonds(6), 0, 3),
+    ("complete8_3x3", 8, complete_bonds(8), 3, 3),     # 28 bonds: two groups of 16
+]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("case", BOND_CASES, ids=[c[0] for c in BOND_CASES])
+def test_bond_moments_match_oracle(case, dtype):
+    from oracle.observables import bond_moments
+    name, ns, bonds, nu, nd = case
+    h = ham(ns, bonds, nu, nd, 1.0, 2.0, dtype)
+    x_host, x = seeded_start(54, h.dim, dtype)
+    announce("bond moments %s %s" % (name, dtype))
+    k = h.bond_moments(x, ns, bonds)
+    ref = bond_moments(x_host, h.up.states, h.dn.states, ns, bonds) / np.sum(x_host ** 2)
+    assert np.max(np.abs(k - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_full_size_energy_identity_t44_8x8():
+    """4x4 8+8, float64 ground state: E0 = -t sum_b K_b + U sum_i <n_i,up n_i,dn> (bond kernel and occupation
+    moments against the Lanczos energy), and the translation-invariant bonds carry equal energy."""
+    bonds = torus_bonds(4, 4)
+    tab = ed.SpinTables(16, bonds, 8, "cuda:0")
+    h = ed.Hamiltonian(tab, tab, 1.0, 4.0, "f64")
+    ed.api.apply_tuned_tile(h, tune_if_missing=False)
+    _, x = seeded_start(5, h.dim, "f64")
+    announce("ground state 4x4 8+8 f64 (bonds)")
+    r = h.ground_energy(x, 400, tol=1e-12, check_every=15)
+    e0, steps, psi = h.ground_state(x, r["steps"] + 30, gauge_index=mlp.neel_index(h))
+    del x
+    announce("bond moments 4x4 8+8")
+    k = h.bond_moments(psi, 16, bonds)
+    g = h.occupation_moments(psi, 16)
+    energy = -1.0 * k.sum() + 4.0 * np.trace(g[:16, 16:])
+    assert abs(energy - e0) <= 1e-8 * abs(e0), (energy, e0)
+    assert np.ptp(k) < 1e-6 and np.max(np.abs(k[:, 0] - k[:, 1])) < 1e-8
