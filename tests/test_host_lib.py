@@ -13,7 +13,7 @@ import paper_1511_00863_amd as ed
 from paper_1511_00863_amd import _ffi
 from oracle.basis import basis_states
 from oracle.hopping import hopping_matrix, to_ell
-from synth import ring_bonds, torus_bonds, two_site_bonds
+from synth import complete_bonds, ring_bonds, torus_bonds, two_site_bonds
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -300,3 +300,52 @@ def test_spin_correlations_match_oracle_formula():
     g = (g + g.T) / 2
     c = r.uniform(-0.5, 0.5, (ns, ns))
     assert np.max(np.abs(ed.spin_correlations(g, c, ns) - spin_correlations(g, c, ns))) < 1e-15
+
+
+def test_complex_tables_reject_bad_inputs():
+    st = ed.build_basis(6, 2)
+    bonds = ring_bonds(6)
+    with pytest.raises(ed.EdError) as e:
+        ed.api.build_hopping_complex(6, bonds, [1.0] * 5 + [complex(float("nan"), 0.0)], st)
+    assert e.value.code == -1
+    # more than 64 distinct values cannot be indexed with 6 bits
+    many = ed.build_basis(12, 2)
+    cb = complete_bonds(12)
+    amps = [complex(1.0 + 0.01 * k, 0.0) for k in range(len(cb))]   # 66 distinct amplitudes
+    t = ed.api.build_hopping_complex(12, cb, amps, many)
+    with pytest.raises(ed.EdError) as e:
+        ed.api.pack_tables_complex(t, many.size)
+    assert e.value.code == -3
+
+
+def test_observable_and_complex_descriptors_validated_on_the_host():
+    """Argument errors of the observables and of complex descriptors are returned before any device work."""
+    import ctypes
+    lib = ed.lib()
+    dummy = ctypes.c_void_p(4096)   # never dereferenced
+
+    def ham(**kw):
+        f = dict(dim_up=70, dim_dn=70, w_up=8, w_dn=8, tab_up=dummy, tab_dn=dummy, st_up=dummy, st_dn=dummy,
+                 t=1.0, U=4.0, dtype=0, tile=0, eb_up=0, eb_dn=0, cplx=0, reserved=0, amp_up=None, amp_dn=None)
+        f.update(kw)
+        return _ffi.EdHam(**f)
+
+    n = ctypes.c_int64(0)
+    assert lib.ed_workspace_size(ctypes.byref(ham(cplx=2)), 4, ctypes.byref(n)) == -1
+    # complex amplitudes need 32-bit complex tables and amplitude arrays
+    assert lib.ed_workspace_size(ctypes.byref(ham(cplx=1)), 4, ctypes.byref(n)) == -1
+    ok = ham(cplx=1, eb_up=4, eb_dn=4, amp_up=dummy, amp_dn=dummy)
+    assert lib.ed_workspace_size(ctypes.byref(ok), 4, ctypes.byref(n)) == 0
+    # real-only calls refuse complex instances
+    assert lib.ed_occupation_moments_ws(ctypes.byref(ok), 8, ctypes.byref(n)) == -1
+    assert lib.ed_spin_flip_moments_ws(ctypes.byref(ok), 8, ctypes.byref(n)) == -1
+    # observables: site count and bonds
+    real = ham()
+    assert lib.ed_spin_flip_moments_ws(ctypes.byref(real), 33, ctypes.byref(n)) == -1
+    assert lib.ed_bond_moments_ws(ctypes.byref(real), 8, 0, ctypes.byref(n)) == -1
+    bad = (ctypes.c_int32 * 2)(3, 3)
+    c = (ctypes.c_double * 2)()
+    assert lib.ed_bond_moments(ctypes.byref(real), 8, bad, 1, dummy, dummy, 1 << 20, None, c) == -1
+    out_of_range = (ctypes.c_int32 * 2)(0, 8)
+    assert lib.ed_bond_moments(ctypes.byref(real), 8, out_of_range, 1, dummy, dummy, 1 << 20, None, c) == -1
+    assert lib.ed_last_error().decode()
