@@ -40,6 +40,13 @@ WORKLOADS = {
                         "4x4 periodic Hubbard, 5 up + 5 down, dim 19,079,424"),
     "torus6x6_3x3": _wl("torus6x6_3x3", 36, torus_bonds(6, 6), 3, 1.0, 0.0, 300, 3,
                         "6x6 periodic tight binding (U=0), 3 up + 3 down, dim 50,979,600"),
+    # the other fillings of the 64-instance batch (tuned like the others)
+    "torus4x4_3x3": _wl("torus4x4_3x3", 16, torus_bonds(4, 4), 3, 1.0, 4.0, 200, 12,
+                        "4x4 periodic Hubbard, 3 up + 3 down, dim 313,600"),
+    "torus4x4_4x4": _wl("torus4x4_4x4", 16, torus_bonds(4, 4), 4, 1.0, 4.0, 200, 13,
+                        "4x4 periodic Hubbard, 4 up + 4 down, dim 3,312,400"),
+    "torus4x4_6x6": _wl("torus4x4_6x6", 16, torus_bonds(4, 4), 6, 1.0, 4.0, 200, 14,
+                        "4x4 periodic Hubbard, 6 up + 6 down, dim 64,128,064"),
     "torus4x4_8x8": _wl("torus4x4_8x8", 16, torus_bonds(4, 4), 8, 1.0, 4.0, 300, 5,
                         "4x4 periodic Hubbard at half filling, 8 up + 8 down, dim 165,636,900"),
     # one species: every particle has the same spin (N_up = 0); the hopping alone, no on-site term
