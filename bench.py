@@ -13,7 +13,8 @@ Beside the step rate the line carries: the roofline of the dominant kernel
 mixed and learned starts at a held-out U (the network trained on the
 method's own ground states at U = 1..8) with the ground state's observables,
 the 64-instance batched launch against the same instances run one by one
-(plain float64 and mixed), the 18-site chain at 9 + 9 (2.36e9 states), the
+(plain float64 and mixed) and 256 small instances batched against one by one,
+the 18-site chain at 9 + 9 (2.36e9 states), the
 one-species runs, the complex-amplitude checkerboard, the paper's own 18-site
 workloads beside its K40 times, and the oracle timed on the host cores.
 
@@ -341,12 +342,39 @@ def batch_block(args):
         torch.cuda.synchronize()
         mix_ms += (time.perf_counter() - t0) * 1e3
         del x
-    import numpy as np_
-    return {"instances": 64, "total_dim": int(sum(h.dim for h in hams)), "wall_ms": r["wall_ms"],
+    small = small_batch(tabs_for=lambda n: ed.SpinTables(16, bonds, n, "cuda:0"))
+    return {"small_instances": small, "instances": 64, "total_dim": int(sum(h.dim for h in hams)), "wall_ms": r["wall_ms"],
             "graph_used": r["graph_used"], "converged": int((r["status"] == 0).sum()),
             "max_steps_used": int(r["steps"].max()), "sequential_plain_f64_ms": seq_ms,
             "sequential_mixed_ms": mix_ms,
-            "max_rel_dev_vs_f64": float(np_.max(np_.abs(r["e0"] - seq_e0) / np_.abs(seq_e0)))}
+            "max_rel_dev_vs_f64": float(np.max(np.abs(r["e0"] - seq_e0) / np.abs(seq_e0)))}
+
+
+def small_batch(tabs_for, n=256, seed=2000):
+    """Many small instances, the batched launch's intended use: 256 Hubbard instances on the 4x4 torus with
+    N_up = N_dn in {2, 3} (dims 14,400 and 313,600), U ~ U[0, 8], in one persistent launch against the same
+    instances run one after another in the mixed form (same tolerance; tuned tiles where the cache has
+    them, the default tile otherwise)."""
+    import torch
+    import paper_1511_00863_amd as ed
+    from synth import batch_instances, start_vector
+    draws = batch_instances(n, seed, fillings=(2, 3))
+    tabs = {k: tabs_for(k) for k in (2, 3)}
+    hams = [ed.Hamiltonian(tabs[k], tabs[k], 1.0, U, "f32") for (U, k, s) in draws]
+    for h in hams:
+        ed.api.apply_tuned_tile(h, tune_if_missing=False)
+    f1s = [torch.from_numpy(start_vector(s, h.dim)).to("cuda:0", torch.float32) for h, (U, k, s) in zip(hams, draws)]
+    ed.ground_energy_batch(hams, f1s, 500, tol=1e-6)
+    r = ed.ground_energy_batch(hams, f1s, 500, tol=1e-6)
+    seq_ms = 0.0
+    for h, x in zip(hams, f1s):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h.ground_energy(x, 500, tol=1e-6, check_every=9)
+        torch.cuda.synchronize()
+        seq_ms += (time.perf_counter() - t0) * 1e3
+    return {"instances": n, "fillings": [2, 3], "wall_ms": r["wall_ms"], "converged": int((r["status"] == 0).sum()),
+            "sequential_mixed_ms": seq_ms, "speedup": seq_ms / r["wall_ms"]}
 
 
 def cpu_baseline(wl, n_steps):
