@@ -135,6 +135,36 @@ int ed_build_hopping_complex(int n_sites, const int32_t *bonds, int n_bonds, con
 int ed_pack_tables_complex(const int32_t *cols, const double *vals, const int32_t *nnz, int64_t dim,
                            int32_t width, int layout, uint32_t *packed, double *amps, int32_t *n_amps);
 
+/* Basis orders.  The basis of Sec. 2.1 is ascending (colex rank order), and
+ * that is the order of every vector unless a species is reordered here.  Any
+ * order of a species' basis gives the same H up to a permutation P of the
+ * vector elements, and the Lanczos run started from P f_1 yields the same
+ * a_j, b_j and E0 (up to rounding).  Tables and state arrays fix the order the
+ * device calls see; only the calls that find a state by its colex rank (spin-
+ * flip and bond moments) need the ascending order (see ed_ham.order).
+ *
+ * ed_hop_order: perm such that position q of the reordered basis holds state
+ * perm[q] of the given one, sorted by hop count (nonzeros per row, nnz from
+ * ed_build_hopping) from most to fewest, equal counts in their given order.
+ * The down-part kernel gives a wavefront 64 consecutive columns and pays for
+ * the table chunks of its widest column; in this order the columns of a
+ * wavefront have nearly equal hop counts, so whole padding chunks drop out.
+ * nnz: host, dim entries (>= 0); perm: host, dim entries. */
+int ed_hop_order(const int32_t *nnz, int64_t dim, int64_t *perm);
+
+/* Reorder one species' basis and its exported ELL table (Fig. 2 format, as
+ * from ed_build_hopping or ed_build_hopping_complex): position q of the
+ * output is state perm[q] of the input, and each row's columns are renumbered
+ * into the new order and sorted ascending again (padding as in the input
+ * format).  n_vals: 1 (real values) or 2 ((re, im) pairs).  All pointers
+ * host; outputs have the input's sizes and must not overlap the inputs.  The
+ * result packs with ed_pack_tables / ed_pack_tables32 / ed_pack_tables_complex.
+ * perm not a permutation of [0, dim), nnz or a column out of range ->
+ * ED_EINVAL (outputs then undefined). */
+int ed_permute_basis(const uint64_t *states, const int32_t *cols, const double *vals, const int32_t *nnz,
+                     int64_t dim, int32_t width, int layout, int32_t n_vals, const int64_t *perm,
+                     uint64_t *states_out, int32_t *cols_out, double *vals_out, int32_t *nnz_out);
+
 /* Lowest eigenvalue of the m-by-m symmetric tridiagonal T (Sec. 2.2) with
  * diagonal a[0..m-1] = a_1..a_m and off-diagonal b[0..m-2] = b_2..b_m, by
  * Sturm-sequence bisection in float64 to full precision.  host pointers. */
@@ -163,7 +193,12 @@ int ed_tridiag_lowest_vector(const double *a, const double *b, int m, double *e0
  * (H is Hermitian; a_j = Re f_j^dagger q).  Complex instances are accepted by
  * ed_hv, the Lanczos calls and ed_ground_state (gauge_index = -1 only);
  * ed_tune, the batch, the start-vector network and the observables return
- * ED_EINVAL for them.  cplx = 0: amp_up/amp_dn are ignored. */
+ * ED_EINVAL for them.  cplx = 0: amp_up/amp_dn are ignored.
+ * order: 0 when both bases are ascending (ed_build_basis); set bit 0 / bit 1
+ * when the up / down tables and states come from ed_permute_basis.  Every
+ * call accepts reordered bases (tables and state arrays fix the order) except
+ * ed_spin_flip_moments and ed_bond_moments, which find states by colex rank
+ * and return ED_EINVAL unless order = 0; other values -> ED_EINVAL. */
 typedef struct ed_ham {
     int64_t dim_up, dim_dn;
     int32_t w_up, w_dn;
@@ -174,7 +209,7 @@ typedef struct ed_ham {
     int32_t tile;
     int32_t eb_up, eb_dn;   /* bytes per table entry of each species */
     int32_t cplx;           /* 0: real hopping, 1: complex amplitudes and vectors */
-    int32_t reserved;       /* 0 */
+    int32_t order;          /* bit 0 / bit 1: the up / down basis is not ascending (ed_permute_basis) */
     const double *amp_up, *amp_dn;
 } ed_ham;
 
@@ -187,6 +222,18 @@ int ed_workspace_size(const ed_ham *h, int32_t max_steps, int64_t *bytes);
  * elements of h->dtype, distinct buffers.  ws: device workspace of
  * ed_workspace_size(h, 0) bytes (work-queue counters of the up-part kernel). */
 int ed_hv(const ed_ham *h, const void *x, void *y, void *ws, void *stream);
+
+/* A vector in another basis order: y[p, q] = x[perm_up[p], perm_dn[q]] over
+ * the dim_up x dim_dn element grid (Eq. 3), each element dtype (a (re, im)
+ * pair when cplx = 1).  With perm the ed_hop_order output of a species, this
+ * takes an ascending-order vector into the reordered one; its inverse
+ * (inv[perm[q]] = q) takes it back.  perm_up / perm_dn: device int64 arrays of
+ * dim_up / dim_dn entries, or NULL for the identity.  An entry outside its
+ * range makes the affected elements NaN.  x, y: device, must not overlap
+ * (ED_EINVAL).  Only dims, dtype and cplx of h are used; asynchronous on
+ * `stream`. */
+int ed_permute_vector(const ed_ham *h, const int64_t *perm_up, const int64_t *perm_dn, const void *x, void *y,
+                      void *stream);
 
 /* Launch-configuration autotuner (the paper tuned its CPU blocking and GPU
  * block size by experiment, Sec. 4-5; this searches the kernels' tiles).

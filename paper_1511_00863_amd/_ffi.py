@@ -27,7 +27,7 @@ class EdHam(ctypes.Structure):
     _fields_ = [("dim_up", c_int64), ("dim_dn", c_int64), ("w_up", c_int32), ("w_dn", c_int32),
                 ("tab_up", c_void_p), ("tab_dn", c_void_p), ("st_up", c_void_p), ("st_dn", c_void_p),
                 ("t", c_double), ("U", c_double), ("dtype", c_int32), ("tile", c_int32),
-                ("eb_up", c_int32), ("eb_dn", c_int32), ("cplx", c_int32), ("reserved", c_int32),
+                ("eb_up", c_int32), ("eb_dn", c_int32), ("cplx", c_int32), ("order", c_int32),
                 ("amp_up", c_void_p), ("amp_dn", c_void_p)]
 
 
@@ -61,6 +61,11 @@ _PROTOS = {
     "ed_pack_tables_complex": (c_int, [POINTER(c_int32), POINTER(c_double), POINTER(c_int32), c_int64, c_int32,
                                        c_int, POINTER(c_uint32), POINTER(c_double), POINTER(c_int32)]),
     "ed_tridiag_lowest": (c_int, [POINTER(c_double), POINTER(c_double), c_int, POINTER(c_double)]),
+    "ed_hop_order": (c_int, [POINTER(c_int32), c_int64, POINTER(c_int64)]),
+    "ed_permute_basis": (c_int, [POINTER(c_uint64), POINTER(c_int32), POINTER(c_double), POINTER(c_int32), c_int64,
+                                 c_int32, c_int, c_int32, POINTER(c_int64), POINTER(c_uint64), POINTER(c_int32),
+                                 POINTER(c_double), POINTER(c_int32)]),
+    "ed_permute_vector": (c_int, [POINTER(EdHam), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "ed_occupation_moments_ws": (c_int, [POINTER(EdHam), c_int32, POINTER(c_int64)]),
     "ed_occupation_moments": (c_int, [POINTER(EdHam), c_int32, c_void_p, c_void_p, c_int64, c_void_p,
                                       POINTER(c_double)]),

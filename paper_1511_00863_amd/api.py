@@ -46,6 +46,39 @@ def state_rank(n_sites: int, n_part: int, states) -> np.ndarray:
     return out
 
 
+def hop_order(nnz) -> np.ndarray:
+    """ed_hop_order: positions of a basis sorted by hop count, most first, ties in their given order."""
+    n = np.ascontiguousarray(nnz, dtype=np.int32)
+    perm = np.zeros(n.size, dtype=np.int64)
+    check(lib().ed_hop_order(_ptr(n, c_int32), n.size, _ptr(perm, c_int64)))
+    return perm
+
+
+def permute_basis(states, table, perm):
+    """ed_permute_basis: (states, table) of a species in the order perm (real or complex exported tables)."""
+    st = np.ascontiguousarray(states, dtype=np.uint64)
+    pm = np.ascontiguousarray(perm, dtype=np.int64)
+    dim, width = st.size, int(table["width"])
+    nv = 2 if np.iscomplexobj(table["vals"]) else 1
+    vals = np.ascontiguousarray(table["vals"]).view(np.float64) if nv == 2 else np.ascontiguousarray(table["vals"], dtype=np.float64)
+    cols = np.ascontiguousarray(table["cols"], dtype=np.int32)
+    nnz = np.ascontiguousarray(table["nnz"], dtype=np.int32)
+    st_o = np.zeros(dim, dtype=np.uint64)
+    cols_o = np.zeros(max(cols.size, 1), dtype=np.int32)
+    vals_o = np.zeros(max(vals.size, 1), dtype=np.float64)
+    nnz_o = np.zeros(dim, dtype=np.int32)
+    check(lib().ed_permute_basis(_ptr(st, c_uint64), _ptr(cols, c_int32) if cols.size else None,
+                                 _ptr(vals, c_double) if vals.size else None, _ptr(nnz, c_int32), dim, width,
+                                 int(table["layout"]), nv, _ptr(pm, c_int64), _ptr(st_o, c_uint64),
+                                 _ptr(cols_o, c_int32) if cols.size else None,
+                                 _ptr(vals_o, c_double) if vals.size else None, _ptr(nnz_o, c_int32)))
+    out = {"cols": cols_o[:cols.size], "vals": vals_o[:vals.size], "nnz": nnz_o, "width": width,
+           "layout": table["layout"]}
+    if nv == 2:
+        out["vals"] = out["vals"].view(np.complex128)
+    return st_o, out
+
+
 def _bond_array(bonds) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(bonds, dtype=np.int32).reshape(-1, 2))
 
@@ -180,19 +213,30 @@ def tridiag_lowest_vector(a, b_off):
 class SpinTables:
     """Basis and packed hopping table of one species, on the host and on the device."""
 
-    def __init__(self, n_sites: int, bonds, n_part: int, device=None, entry_bytes=None, amps=None):
+    def __init__(self, n_sites: int, bonds, n_part: int, device=None, entry_bytes=None, amps=None,
+                 order: str = "ascending"):
         """entry_bytes: 2 or 4 bytes per device table entry; by default 2 while dim <= 32767, else 4.
         amps: a complex amplitude per bond (term a c+_i c_j + h.c.); then the table is the complex format
-        (32-bit entries indexing a table of at most 64 amplitudes) and the vectors are complex."""
+        (32-bit entries indexing a table of at most 64 amplitudes) and the vectors are complex.
+        order: "ascending" (the basis of Sec. 2.1) or "hops" (sorted by hop count, ed_hop_order); then
+        position q holds ascending state perm[q], and vectors of this species follow that order."""
+        if order not in ("ascending", "hops"):
+            raise ValueError("order must be 'ascending' or 'hops'")
         self.n_sites, self.n_part = n_sites, n_part
         self.bonds = [tuple(int(v) for v in b) for b in bonds]
         self.states = build_basis(n_sites, n_part)
         self.dim = int(self.states.size)
         self.cplx = amps is not None
+        self.order = order
+        self.perm = None
         self.device = torch.device(device if device is not None else "cuda")
         self.dev_amp = None
+        self._dev_perm = self._dev_inv = None
         if self.cplx:
             self.table = build_hopping_complex(n_sites, self.bonds, amps, self.states, ED_COL_MAJOR)
+            if order == "hops":
+                self.perm = hop_order(self.table["nnz"])
+                self.states, self.table = permute_basis(self.states, self.table, self.perm)
             self.width = self.table["width"]
             self.stride = table_stride(self.width)
             self.entry_bytes = 4
@@ -200,6 +244,9 @@ class SpinTables:
             self.dev_amp = torch.from_numpy(self.amps.copy()).to(self.device)
         else:
             self.table = build_hopping(n_sites, self.bonds, self.states, ED_COL_MAJOR)
+            if order == "hops":
+                self.perm = hop_order(self.table["nnz"])
+                self.states, self.table = permute_basis(self.states, self.table, self.perm)
             self.width = self.table["width"]
             self.stride = table_stride(self.width)
             # 16-bit entries while the ranks fit in 15 bits, 32-bit beyond
@@ -209,6 +256,18 @@ class SpinTables:
         signed = np.int16 if self.entry_bytes == 2 else np.int32
         self.dev_tab = (torch.from_numpy(self.packed.view(signed).copy()).to(self.device)
                         if self.width else torch.zeros(1, dtype=torch.int32, device=self.device))
+
+    def dev_perm(self, inverse: bool = False):
+        """Device int64 permutation of this species (None in ascending order): perm (position -> ascending
+        index), or with inverse=True its inverse (ascending index -> position)."""
+        if self.perm is None:
+            return None
+        if self._dev_perm is None:
+            inv = np.empty_like(self.perm)
+            inv[self.perm] = np.arange(self.dim, dtype=np.int64)
+            self._dev_perm = torch.from_numpy(self.perm.copy()).to(self.device)
+            self._dev_inv = torch.from_numpy(inv).to(self.device)
+        return self._dev_inv if inverse else self._dev_perm
 
 
 class Hamiltonian:
@@ -226,9 +285,11 @@ class Hamiltonian:
 
     @classmethod
     def from_lattice(cls, n_sites, bonds, n_up, n_dn, t=1.0, U=0.0, dtype="f64", device=None, tile=0,
-                     entry_bytes=None, amps=None):
-        up = SpinTables(n_sites, bonds, n_up, device, entry_bytes, amps)
-        dn = up if n_dn == n_up else SpinTables(n_sites, bonds, n_dn, device, entry_bytes, amps)
+                     entry_bytes=None, amps=None, order=("ascending", "ascending")):
+        """order: the (up, down) basis orders of SpinTables, or one string for both."""
+        ou, od = (order, order) if isinstance(order, str) else tuple(order)
+        up = SpinTables(n_sites, bonds, n_up, device, entry_bytes, amps, ou)
+        dn = up if (n_dn == n_up and od == ou) else SpinTables(n_sites, bonds, n_dn, device, entry_bytes, amps, od)
         return cls(up, dn, t, U, dtype, tile)
 
     @property
@@ -254,9 +315,31 @@ class Hamiltonian:
                      self.up.dev_tab.data_ptr(), self.dn.dev_tab.data_ptr(),
                      self.up.dev_states.data_ptr(), self.dn.dev_states.data_ptr(),
                      self.t, self.U, self.dtype, self.tile, self.up.entry_bytes, self.dn.entry_bytes,
-                     int(self.cplx), 0,
+                     int(self.cplx), self.order_bits,
                      self.up.dev_amp.data_ptr() if self.up.dev_amp is not None else None,
                      self.dn.dev_amp.data_ptr() if self.dn.dev_amp is not None else None)
+
+    @property
+    def order_bits(self) -> int:
+        """ed_ham.order: bit 0 / bit 1 set when the up / down basis is not ascending."""
+        return (1 if self.up.order != "ascending" else 0) | (2 if self.dn.order != "ascending" else 0)
+
+    def _permute(self, x, inverse: bool):
+        x = self._vec(x)
+        y = self.empty_vec()
+        pu, pd = self.up.dev_perm(inverse), self.dn.dev_perm(inverse)
+        h = self.c_struct()
+        check(lib().ed_permute_vector(byref(h), _dptr(pu) if pu is not None else None,
+                                      _dptr(pd) if pd is not None else None, _dptr(x), _dptr(y), None))
+        return y
+
+    def to_basis_order(self, x):
+        """A vector over the ascending bases of both species, in this instance's basis order (ed_permute_vector)."""
+        return self._permute(x, False)
+
+    def to_ascending(self, x):
+        """A vector in this instance's basis order, back over the ascending bases (ed_permute_vector)."""
+        return self._permute(x, True)
 
     def workspace_bytes(self, max_steps: int = 1) -> int:
         n = c_int64(0)

@@ -352,6 +352,65 @@ int ed_pack_tables_complex(const int32_t *cols, const double *vals, const int32_
     return ED_OK;
 }
 
+int ed_hop_order(const int32_t *nnz, int64_t dim, int64_t *perm) {
+    clear_error();
+    if (!nnz || !perm || dim < 1) return set_error(ED_EINVAL, "ed_hop_order: bad arguments");
+    int32_t most = 0;
+    for (int64_t r = 0; r < dim; ++r) {
+        if (nnz[r] < 0) return set_error(ED_EINVAL, "ed_hop_order: nnz[%lld] = %d", (long long)r, nnz[r]);
+        most = std::max(most, nnz[r]);
+    }
+    // counting sort on (most - nnz): more hops first, ascending index among equals
+    std::vector<int64_t> at(most + 2, 0);
+    for (int64_t r = 0; r < dim; ++r) ++at[most - nnz[r] + 1];
+    for (int32_t b = 1; b <= most + 1; ++b) at[b] += at[b - 1];
+    for (int64_t r = 0; r < dim; ++r) perm[at[most - nnz[r]]++] = r;
+    return ED_OK;
+}
+
+int ed_permute_basis(const uint64_t *states, const int32_t *cols, const double *vals, const int32_t *nnz,
+                     int64_t dim, int32_t width, int layout, int32_t n_vals, const int64_t *perm,
+                     uint64_t *states_out, int32_t *cols_out, double *vals_out, int32_t *nnz_out) {
+    clear_error();
+    const char *who = "ed_permute_basis";
+    if (!states || !nnz || !perm || !states_out || !nnz_out || dim < 1 || width < 0 || (n_vals != 1 && n_vals != 2))
+        return set_error(ED_EINVAL, "%s: bad arguments", who);
+    if (width > 0 && (!cols || !vals || !cols_out || !vals_out)) return set_error(ED_EINVAL, "%s: NULL table", who);
+    if (layout != ED_ROW_MAJOR && layout != ED_COL_MAJOR) return set_error(ED_EINVAL, "%s: bad layout %d", who, layout);
+    if (dim > 0x7fffffffLL) return set_error(ED_EOVERFLOW, "%s: dim too large", who);
+    // inverse permutation; a repeated or out-of-range entry is an error
+    std::vector<int64_t> inv(dim, -1);
+    for (int64_t q = 0; q < dim; ++q) {
+        const int64_t o = perm[q];
+        if (o < 0 || o >= dim || inv[o] >= 0) return set_error(ED_EINVAL, "%s: perm is not a permutation (entry %lld)", who, (long long)q);
+        inv[o] = q;
+    }
+    std::vector<std::pair<int32_t, int64_t>> row;   // (new column, source slot)
+    row.reserve(width);
+    for (int64_t q = 0; q < dim; ++q) {
+        const int64_t o = perm[q];
+        states_out[q] = states[o];
+        const int32_t n = nnz[o];
+        if (n < 0 || n > width) return set_error(ED_EINVAL, "%s: nnz[%lld] = %d out of range", who, (long long)o, n);
+        nnz_out[q] = n;
+        row.clear();
+        for (int32_t k = 0; k < n; ++k) {
+            const int64_t src = layout == ED_ROW_MAJOR ? o * width + k : (int64_t)k * dim + o;
+            const int32_t c = cols[src];
+            if (c < 0 || c >= dim) return set_error(ED_EINVAL, "%s: column %d out of range", who, c);
+            row.emplace_back((int32_t)inv[c], src);
+        }
+        std::sort(row.begin(), row.end());
+        for (int32_t k = 0; k < width; ++k) {
+            const int64_t dst = layout == ED_ROW_MAJOR ? q * width + k : (int64_t)k * dim + q;
+            const bool live = k < n;
+            cols_out[dst] = live ? row[k].first : 0;
+            for (int v = 0; v < n_vals; ++v) vals_out[n_vals * dst + v] = live ? vals[n_vals * row[k].second + v] : 0.0;
+        }
+    }
+    return ED_OK;
+}
+
 int ed_occupation_correlations(const double *g, int32_t n_sites, double *docc, double *nn, double *szsz) {
     clear_error();
     if (!g || n_sites < 1 || n_sites > 32) return set_error(ED_EINVAL, "ed_occupation_correlations: bad arguments");

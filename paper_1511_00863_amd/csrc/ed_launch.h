@@ -121,6 +121,7 @@ static inline int check_ham(const ed_ham *h, const char *who) {
     if (h->w_up > 64 || h->w_dn > 64) return set_error(ED_EOVERFLOW, "%s: table strides above 64 unsupported", who);
     if (h->dtype != ED_F64 && h->dtype != ED_F32) return set_error(ED_EINVAL, "%s: bad dtype %d", who, h->dtype);
     if (h->cplx != 0 && h->cplx != 1) return set_error(ED_EINVAL, "%s: cplx must be 0 or 1", who);
+    if (h->order < 0 || h->order > 3) return set_error(ED_EINVAL, "%s: order must be 0..3", who);
     if (h->cplx) {
         if ((h->w_up && (!wide_up(h) || !h->amp_up)) || (h->w_dn && (!wide_dn(h) || !h->amp_dn)))
             return set_error(ED_EINVAL, "%s: complex amplitudes need 32-bit complex tables and amplitude arrays", who);

@@ -373,6 +373,14 @@ static int obs_check(const ed_ham *h, int ns, const char *who) {
     return ED_OK;
 }
 
+// the calls that find a target state by its colex rank: both bases ascending
+static int ranked_check(const ed_ham *h, int ns, const char *who) {
+    int rc = obs_check(h, ns, who);
+    if (rc) return rc;
+    if (h->order) return set_error(ED_EINVAL, "%s: needs both species in ascending basis order (order = 0)", who);
+    return ED_OK;
+}
+
 template <typename T>
 static int obs_impl(const ed_ham *h, int ns, const T *psi, char *ws, hipStream_t s, double *g_host) {
     auto al = [](int64_t b) { return (b + 255) & ~int64_t(255); };
@@ -428,7 +436,7 @@ int ed_occupation_moments(const ed_ham *h, int32_t n_sites, const void *psi, voi
 
 int ed_spin_flip_moments_ws(const ed_ham *h, int32_t n_sites, int64_t *bytes) {
     clear_error();
-    int rc = obs_check(h, n_sites, "ed_spin_flip_moments_ws");
+    int rc = ranked_check(h, n_sites, "ed_spin_flip_moments_ws");
     if (rc) return rc;
     if (!bytes) return set_error(ED_EINVAL, "ed_spin_flip_moments_ws: bytes is NULL");
     *bytes = flip_ws_bytes(h);
@@ -438,7 +446,7 @@ int ed_spin_flip_moments_ws(const ed_ham *h, int32_t n_sites, int64_t *bytes) {
 int ed_spin_flip_moments(const ed_ham *h, int32_t n_sites, const void *psi, void *ws, int64_t ws_bytes,
                          void *stream, double *c) {
     clear_error();
-    int rc = obs_check(h, n_sites, "ed_spin_flip_moments");
+    int rc = ranked_check(h, n_sites, "ed_spin_flip_moments");
     if (rc) return rc;
     if (!psi || !ws || !c) return set_error(ED_EINVAL, "ed_spin_flip_moments: NULL buffer");
     if (reinterpret_cast<uintptr_t>(ws) & 255) return set_error(ED_EINVAL, "ed_spin_flip_moments: ws not aligned");
@@ -451,7 +459,7 @@ int ed_spin_flip_moments(const ed_ham *h, int32_t n_sites, const void *psi, void
 
 int ed_bond_moments_ws(const ed_ham *h, int32_t n_sites, int32_t n_bonds, int64_t *bytes) {
     clear_error();
-    int rc = obs_check(h, n_sites, "ed_bond_moments_ws");
+    int rc = ranked_check(h, n_sites, "ed_bond_moments_ws");
     if (rc) return rc;
     if (!bytes || n_bonds < 1) return set_error(ED_EINVAL, "ed_bond_moments_ws: bad arguments");
     *bytes = bond_ws_bytes(h, n_bonds);
@@ -461,7 +469,7 @@ int ed_bond_moments_ws(const ed_ham *h, int32_t n_sites, int32_t n_bonds, int64_
 int ed_bond_moments(const ed_ham *h, int32_t n_sites, const int32_t *bonds, int32_t n_bonds, const void *psi,
                     void *ws, int64_t ws_bytes, void *stream, double *k) {
     clear_error();
-    int rc = obs_check(h, n_sites, "ed_bond_moments");
+    int rc = ranked_check(h, n_sites, "ed_bond_moments");
     if (rc) return rc;
     if (!bonds || n_bonds < 1 || !psi || !ws || !k) return set_error(ED_EINVAL, "ed_bond_moments: bad arguments");
     for (int b = 0; b < n_bonds; ++b) {

@@ -1,0 +1,180 @@
+"""Reordered bases on the device: H x, the Lanczos run and the vector permutation with a species in
+hop-count order, against the oracle in the ascending basis.
+
+In the order perm a species' hopping matrix is P H P^T, so for x_ordered = P x_ascending the result
+(H x)_ordered = P (H x)_ascending: element (p, q) of the reordered result is the oracle's element
+(perm_up[p], perm_dn[q]).  The Lanczos run from P f_1 has the same a_j, b_j and E0 up to rounding.
+"""
+
+import ctypes
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as sla
+import torch
+
+import paper_1511_00863_amd as ed
+from oracle.basis import basis_states
+from oracle.elements import hv_elements
+from oracle.hamiltonian import Model
+from oracle.lanczos import lanczos
+from synth import batch_instances, checkerboard_terms, ring_bonds, start_vector, start_vector_complex, torus_bonds
+from tests.gpu_util import announce, seeded_start
+
+pytestmark = pytest.mark.gpu
+
+# (name, n_sites, bonds, n_up, n_dn)
+CASES = [
+    ("torus4x4_3x2", 16, torus_bonds(4, 4), 3, 2),     # 560 x 120
+    ("ring12_5x4", 12, ring_bonds(12), 5, 4),          # 792 x 495
+    ("torus4x4_4x4", 16, torus_bonds(4, 4), 4, 4),     # 1820 x 1820: many tiles and workgroups
+]
+ORDERS = [("ascending", "hops"), ("hops", "ascending"), ("hops", "hops")]
+
+
+def _ham(ns, bonds, nu, nd, dtype, order, U=2.5, amps=None):
+    return ed.Hamiltonian.from_lattice(ns, bonds, nu, nd, 1.0, U, dtype, "cuda:0", amps=amps, order=order)
+
+
+def _perms(h):
+    pu = h.up.perm if h.up.perm is not None else np.arange(h.dim_up)
+    pd = h.dn.perm if h.dn.perm is not None else np.arange(h.dim_dn)
+    return pu, pd
+
+
+def _tol(dtype):
+    return 1e-12 if dtype == "f64" else 2e-5
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("order", ORDERS, ids=["-".join(o) for o in ORDERS])
+@pytest.mark.parametrize("case", CASES[:2], ids=[c[0] for c in CASES[:2]])
+def test_permute_vector_is_the_host_gather_and_round_trips(case, order, dtype):
+    name, ns, bonds, nu, nd = case
+    h = _ham(ns, bonds, nu, nd, dtype, order)
+    x_host, x = seeded_start(91, h.dim, dtype)
+    announce("permute vector %s %s %s" % (name, order, dtype))
+    xo = h.to_basis_order(x)
+    pu, pd = _perms(h)
+    want = x_host.reshape(h.dim_up, h.dim_dn)[np.ix_(pu, pd)].ravel()
+    assert np.array_equal(xo.double().cpu().numpy(), want)
+    assert torch.equal(h.to_ascending(xo), x)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("order", ORDERS, ids=["-".join(o) for o in ORDERS])
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_hv_in_hop_order_matches_oracle(case, order, dtype):
+    name, ns, bonds, nu, nd = case
+    m = Model(ns, bonds, nu, nd, 1.0, 2.5)
+    h = _ham(ns, bonds, nu, nd, dtype, order)
+    x_host, x = seeded_start(92, h.dim, dtype)
+    announce("hv hop order %s %s %s dim=%d" % (name, order, dtype, h.dim))
+    y = h.hv(h.to_basis_order(x))
+    got = h.to_ascending(y).double().cpu().numpy()
+    want = m.hv(x_host)
+    assert float(np.max(np.abs(got - want))) <= _tol(dtype) * max(1.0, float(np.max(np.abs(want))))
+
+
+def test_every_down_tile_gives_the_same_bits_in_hop_order():
+    ns, bonds, nu, nd = CASES[2][1:]
+    h = _ham(ns, bonds, nu, nd, "f64", ("ascending", "hops"))
+    _, x = seeded_start(93, h.dim, "f64")
+    announce("hv hop order tiles torus4x4_4x4 f64")
+    ref = h.hv(x).clone()
+    nu_t, nd_t = ctypes.c_int32(0), ctypes.c_int32(0)
+    ed.lib().ed_tile_count(ctypes.byref(nu_t), ctypes.byref(nd_t))
+    for di in range(1, nd_t.value):
+        h.tile = di << 8
+        assert torch.equal(h.hv(x), ref), (di, h.tile_params())
+
+
+@pytest.mark.parametrize("case", CASES[:2], ids=[c[0] for c in CASES[:2]])
+def test_lanczos_in_hop_order_matches_oracle(case):
+    """Alg. 1 from P f_1: the oracle's a_j, b_j on f_1, and E0 of the sector."""
+    name, ns, bonds, nu, nd = case
+    m = Model(ns, bonds, nu, nd, 1.0, 2.5)
+    h = _ham(ns, bonds, nu, nd, "f64", ("hops", "hops"))
+    x_host, x = seeded_start(94, h.dim, "f64")
+    announce("lanczos hop order %s f64" % name)
+    r = h.ground_energy(h.to_basis_order(x), 40, tol=0.0)
+    ref = lanczos(m.hv, x_host, 20)
+    amax = np.max(np.abs(ref["a"]))
+    assert np.max(np.abs(r["a"][:20] - ref["a"])) <= 1e-12 * amax
+    assert np.max(np.abs(r["b"][:21] - ref["b"])) <= 1e-12 * amax
+    rr = h.ground_energy(h.to_basis_order(x), 400, tol=1e-13, check_every=10)
+    e0 = float(sla.eigsh(m.full_sparse(), k=1, which="SA")[0][0])
+    assert abs(rr["e0"] - e0) <= 1e-10 * abs(e0)
+
+
+def test_complex_hv_in_hop_order_matches_oracle():
+    terms = checkerboard_terms(3, 3, 1.0, np.pi / 4, 0.3, 0.2)
+    bonds, amps = [b for b, _ in terms], [a for _, a in terms]
+    m = Model(18, bonds, 2, 2, 1.0, 2.5, amps)
+    for dtype in ("f64", "f32"):
+        h = _ham(18, bonds, 2, 2, dtype, ("hops", "hops"), amps=amps)
+        x_host = start_vector_complex(95, h.dim)
+        if dtype == "f32":
+            x_host = x_host.astype(np.complex64).astype(np.complex128)
+        x = torch.from_numpy(x_host).to("cuda:0", torch.complex128 if dtype == "f64" else torch.complex64)
+        announce("complex hv hop order checker18 2x2 %s" % dtype)
+        got = h.to_ascending(h.hv(h.to_basis_order(x))).cpu().numpy().astype(np.complex128)
+        want = m.hv(x_host)
+        assert float(np.max(np.abs(got - want))) <= _tol(dtype) * max(1.0, float(np.max(np.abs(want))))
+
+
+def test_observables_in_hop_order():
+    """Occupation moments read the state words and take any order; the rank-based calls refuse it."""
+    ns, bonds, nu, nd = CASES[0][1:]
+    ha = _ham(ns, bonds, nu, nd, "f64", ("ascending", "ascending"))
+    ho = _ham(ns, bonds, nu, nd, "f64", ("hops", "hops"))
+    _, x = seeded_start(96, ha.dim, "f64")
+    announce("observables hop order torus4x4_3x2 f64")
+    ga = ha.occupation_moments(x, ns)
+    go = ho.occupation_moments(ho.to_basis_order(x), ns)
+    assert np.max(np.abs(ga - go)) <= 1e-13
+    with pytest.raises(ed.EdError):
+        ho.spin_flip_moments(ho.to_basis_order(x), ns)
+    with pytest.raises(ed.EdError):
+        ho.bond_moments(ho.to_basis_order(x), ns, bonds)
+
+
+def test_batch_with_instances_in_hop_order():
+    """The batched launch reads tables and state words only: reordered instances give the same E0."""
+    bonds = torus_bonds(4, 4)
+    draws = batch_instances(6, 3000, fillings=(3, 4))
+    res = {}
+    for order in ("ascending", "hops"):
+        tabs = {n: ed.SpinTables(16, bonds, n, "cuda:0", order=order) for n in (3, 4)}
+        hams = [ed.Hamiltonian(tabs[n], tabs[n], 1.0, U, "f32") for (U, n, s) in draws]
+        f1s = []
+        for h, (U, n, s) in zip(hams, draws):
+            x = torch.from_numpy(start_vector(s, h.dim)).to("cuda:0", torch.float32)
+            f1s.append(h.to_basis_order(x) if order == "hops" else x)
+        announce("batch hop order %s" % order)
+        r = ed.ground_energy_batch(hams, f1s, 400, tol=1e-7)
+        assert np.all(r["status"] == 0)
+        res[order] = r["e0"]
+    assert np.max(np.abs(res["hops"] - res["ascending"]) / np.abs(res["ascending"])) <= 1e-6
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_full_size_half_filled_4x4_in_hop_order_sampled_elements(dtype):
+    """4x4 torus, 8 + 8 (D = 165,636,900), down species in hop order, the tuned launch: elements of H x
+    recomputed one by one by the oracle at the ascending positions they came from."""
+    bonds = torus_bonds(4, 4)
+    h = ed.Hamiltonian.from_lattice(16, bonds, 8, 8, 1.0, 4.0, dtype, "cuda:0", order=("ascending", "hops"))
+    ed.api.apply_tuned_tile(h, tune_if_missing=False)
+    x_host, x = seeded_start(5, h.dim, dtype)
+    announce("hv full torus4x4 8x8 hop order %s" % dtype)
+    y = h.hv(h.to_basis_order(x)).double().cpu().numpy()
+    del x
+    rng = np.random.default_rng(97)
+    D = h.dim_dn
+    picks = sorted(set([0, 1, h.dim // 2, h.dim - 2, h.dim - 1] + rng.integers(0, h.dim, 300).tolist()))
+    pu, pd = _perms(h)
+    asc = [int(pu[p // D]) * D + int(pd[p % D]) for p in picks]
+    st = basis_states(16, 8)
+    want = hv_elements(16, bonds, st, st, 1.0, 4.0, x_host, asc)
+    got = y[picks]
+    assert float(np.max(np.abs(got - want))) <= _tol(dtype) * max(1.0, float(np.max(np.abs(want))))

@@ -326,7 +326,7 @@ def test_observable_and_complex_descriptors_validated_on_the_host():
 
     def ham(**kw):
         f = dict(dim_up=70, dim_dn=70, w_up=8, w_dn=8, tab_up=dummy, tab_dn=dummy, st_up=dummy, st_dn=dummy,
-                 t=1.0, U=4.0, dtype=0, tile=0, eb_up=0, eb_dn=0, cplx=0, reserved=0, amp_up=None, amp_dn=None)
+                 t=1.0, U=4.0, dtype=0, tile=0, eb_up=0, eb_dn=0, cplx=0, order=0, amp_up=None, amp_dn=None)
         f.update(kw)
         return _ffi.EdHam(**f)
 

@@ -1,0 +1,189 @@
+"""Reordered bases on the host: the hop-count order (ed_hop_order) and the permuted basis and ELL table
+(ed_permute_basis), checked against the oracle's basis and hopping matrix.  Reordering a species by a
+permutation P turns its hopping matrix into P H P^T, so the permuted table must hold exactly the oracle's
+matrix with rows and columns taken in the order perm."""
+
+import ctypes
+
+import numpy as np
+import pytest
+
+import paper_1511_00863_amd as ed
+from paper_1511_00863_amd import _ffi
+from oracle.basis import basis_states
+from oracle.hopping import hopping_matrix, hopping_matrix_complex
+from synth import checkerboard_terms, ring_bonds, torus_bonds
+
+CASES = [
+    ("torus4x4_3", 16, torus_bonds(4, 4), 3),
+    ("ring12_5", 12, ring_bonds(12), 5),
+    ("torus3x4_6", 12, torus_bonds(3, 4), 6),
+    ("ring9_1", 9, ring_bonds(9), 1),
+]
+
+
+def _dense(table, dim):
+    """The exported ELL table (either layout) as a dense matrix."""
+    w = table["width"]
+    vals = np.asarray(table["vals"])
+    out = np.zeros((dim, dim), dtype=vals.dtype)
+    for r in range(dim):
+        for k in range(table["nnz"][r]):
+            at = r * w + k if table["layout"] == ed.ED_ROW_MAJOR else k * dim + r
+            out[r, table["cols"][at]] += vals[at]
+    return out
+
+
+def _oracle_hops(h):
+    return np.asarray((h != 0).sum(axis=1)).ravel()
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_hop_order_is_the_stable_sort_by_oracle_hop_count(case):
+    _, ns, bonds, n = case
+    st = basis_states(ns, n)
+    hops = _oracle_hops(hopping_matrix(ns, bonds, st))
+    tab = ed.build_hopping(ns, bonds, st)
+    perm = ed.hop_order(tab["nnz"])
+    want = sorted(range(st.size), key=lambda r: (-hops[r], r))
+    assert perm.tolist() == want
+
+
+@pytest.mark.parametrize("layout", [ed.ED_ROW_MAJOR, ed.ED_COL_MAJOR])
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_permuted_table_is_the_oracle_matrix_reordered(case, layout):
+    _, ns, bonds, n = case
+    st = basis_states(ns, n)
+    h = hopping_matrix(ns, bonds, st).toarray()
+    tab = ed.build_hopping(ns, bonds, st, layout)
+    perm = ed.hop_order(tab["nnz"])
+    st2, tab2 = ed.permute_basis(st, tab, perm)
+    assert np.array_equal(st2, st[perm])
+    assert np.array_equal(_dense(tab2, st.size), h[np.ix_(perm, perm)])
+    # rows stay in ascending column order with the padding at the end: the packers accept them
+    ed.pack_tables(tab2, st.size, 2)
+    ed.pack_tables(tab2, st.size, 4)
+    # padding of the exported format
+    for r in range(st.size):
+        for k in range(tab2["nnz"][r], tab2["width"]):
+            at = r * tab2["width"] + k if layout == ed.ED_ROW_MAJOR else k * st.size + r
+            assert tab2["cols"][at] == 0 and tab2["vals"][at] == 0.0
+
+
+def test_hop_order_puts_equal_hop_counts_together_on_the_paper_lattice():
+    """4x4 torus, 8 per species: after the sort a 64-column wavefront holds at most two hop counts except
+    where the count changes, and the chunks of 8 table entries it needs drop from 3.19 to 2.48 on average."""
+    st = basis_states(16, 8)
+    tab = ed.build_hopping(16, torus_bonds(4, 4), st)
+    nnz = tab["nnz"]
+    perm = ed.hop_order(nnz)
+
+    def chunks_per_wave(counts):
+        pad = (-counts.size) % 64
+        w = np.concatenate([counts, np.zeros(pad, dtype=counts.dtype)]).reshape(-1, 64)
+        return float(((w.max(axis=1) + 7) // 8).mean())
+
+    before, after = chunks_per_wave(nnz), chunks_per_wave(nnz[perm])
+    assert after < before
+    assert abs(before - 3.193) < 1e-3 and abs(after - 2.480) < 1e-3
+    assert np.all(np.diff(nnz[perm]) <= 0)
+
+
+def test_permuted_complex_table_is_the_oracle_matrix_reordered():
+    terms = checkerboard_terms(3, 3, 1.0, np.pi / 4, 0.3, 0.2)
+    bonds = [b for b, _ in terms]
+    amps = [a for _, a in terms]
+    st = basis_states(18, 3)
+    h = hopping_matrix_complex(18, bonds, amps, st).toarray()
+    tab = ed.api.build_hopping_complex(18, bonds, amps, st, ed.ED_COL_MAJOR)
+    perm = ed.hop_order(tab["nnz"])
+    st2, tab2 = ed.permute_basis(st, tab, perm)
+    assert np.array_equal(st2, st[perm])
+    assert np.array_equal(_dense(tab2, st.size), h[np.ix_(perm, perm)])
+    ed.api.pack_tables_complex(tab2, st.size)
+
+
+def test_species_that_cannot_hop_and_single_state_bases():
+    for ns, n in ((6, 0), (6, 6)):
+        st = basis_states(ns, n)
+        tab = ed.build_hopping(ns, ring_bonds(ns), st)
+        assert tab["width"] == 0
+        perm = ed.hop_order(tab["nnz"])
+        assert perm.tolist() == [0]
+        st2, tab2 = ed.permute_basis(st, tab, perm)
+        assert np.array_equal(st2, st) and tab2["width"] == 0
+    # a species with no hop anywhere is left in its order
+    assert ed.hop_order(np.zeros(5, dtype=np.int32)).tolist() == [0, 1, 2, 3, 4]
+
+
+def test_order_errors():
+    st = basis_states(8, 3)
+    tab = ed.build_hopping(8, ring_bonds(8), st)
+    bad = np.arange(st.size)
+    bad[3] = bad[4]                                  # repeated entry
+    with pytest.raises(ed.EdError) as e:
+        ed.permute_basis(st, tab, bad)
+    assert e.value.code == _ffi.ED_EINVAL
+    bad = np.arange(st.size)
+    bad[0] = st.size                                 # out of range
+    with pytest.raises(ed.EdError):
+        ed.permute_basis(st, tab, bad)
+    with pytest.raises(ed.EdError):
+        ed.hop_order(np.array([1, -1, 2], dtype=np.int32))
+    lib = ed.lib()
+    perm = np.arange(st.size, dtype=np.int64)
+    out = np.zeros(st.size, dtype=np.uint64)
+    nz = np.zeros(st.size, dtype=np.int32)
+    cols = np.zeros(tab["cols"].size, dtype=np.int32)
+    vals = np.zeros(tab["vals"].size)
+    p = lambda a, t: a.ctypes.data_as(ctypes.POINTER(t))
+    for nv in (0, 3):
+        assert lib.ed_permute_basis(p(st, ctypes.c_uint64), p(tab["cols"], ctypes.c_int32), p(tab["vals"], ctypes.c_double),
+                                    p(tab["nnz"], ctypes.c_int32), st.size, tab["width"], ed.ED_COL_MAJOR, nv,
+                                    p(perm, ctypes.c_int64), p(out, ctypes.c_uint64), p(cols, ctypes.c_int32),
+                                    p(vals, ctypes.c_double), p(nz, ctypes.c_int32)) == _ffi.ED_EINVAL
+
+
+def test_order_field_and_rank_based_calls_validated_on_the_host():
+    """ed_ham.order: 0..3; the spin-flip and bond moments (colex-rank lookups) need 0; vector permutation
+    argument errors return before any device work."""
+    lib = ed.lib()
+    dummy = ctypes.c_void_p(4096)   # never dereferenced
+
+    def ham(**kw):
+        f = dict(dim_up=70, dim_dn=70, w_up=8, w_dn=8, tab_up=dummy, tab_dn=dummy, st_up=dummy, st_dn=dummy,
+                 t=1.0, U=4.0, dtype=0, tile=0, eb_up=0, eb_dn=0, cplx=0, order=0, amp_up=None, amp_dn=None)
+        f.update(kw)
+        return _ffi.EdHam(**f)
+
+    n = ctypes.c_int64(0)
+    for order in (1, 2, 3):
+        h = ham(order=order)
+        assert lib.ed_workspace_size(ctypes.byref(h), 4, ctypes.byref(n)) == 0
+        assert lib.ed_occupation_moments_ws(ctypes.byref(h), 8, ctypes.byref(n)) == 0
+        assert lib.ed_spin_flip_moments_ws(ctypes.byref(h), 8, ctypes.byref(n)) == _ffi.ED_EINVAL
+        assert b"ascending" in lib.ed_last_error()
+        assert lib.ed_bond_moments_ws(ctypes.byref(h), 8, 4, ctypes.byref(n)) == _ffi.ED_EINVAL
+    assert lib.ed_spin_flip_moments_ws(ctypes.byref(ham()), 8, ctypes.byref(n)) == 0
+    for order in (-1, 4):
+        assert lib.ed_workspace_size(ctypes.byref(ham(order=order)), 4, ctypes.byref(n)) == _ffi.ED_EINVAL
+    h = ham()
+    buf = ctypes.c_void_p(1 << 20)
+    assert lib.ed_permute_vector(ctypes.byref(h), None, None, None, buf, None) == _ffi.ED_EINVAL
+    assert lib.ed_permute_vector(ctypes.byref(h), None, None, buf, buf, None) == _ffi.ED_EINVAL
+    near = ctypes.c_void_p((1 << 20) + 8 * 70 * 70 - 8)        # overlaps the last element
+    assert lib.ed_permute_vector(ctypes.byref(h), None, None, buf, near, None) == _ffi.ED_EINVAL
+    assert b"overlap" in lib.ed_last_error()
+
+
+def test_spin_tables_order_option():
+    t = ed.SpinTables(16, torus_bonds(4, 4), 3, "cpu", order="hops")
+    st = basis_states(16, 3)
+    assert np.array_equal(t.states, st[t.perm])
+    assert np.all(np.diff(t.table["nnz"]) <= 0)
+    h = ed.Hamiltonian.from_lattice(16, torus_bonds(4, 4), 3, 3, 1.0, 4.0, "f64", "cpu", order=("ascending", "hops"))
+    assert h.order_bits == 2 and h.up is not h.dn and h.up.perm is None
+    h = ed.Hamiltonian.from_lattice(16, torus_bonds(4, 4), 3, 3, 1.0, 4.0, "f64", "cpu", order="hops")
+    assert h.order_bits == 3 and h.up is h.dn
+    with pytest.raises(ValueError):
+        ed.SpinTables(8, ring_bonds(8), 3, "cpu", order="random")
