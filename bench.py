@@ -5,8 +5,12 @@ down-part/diagonal/recurrence kernel with its partial dot products, the scalar
 reduction and the vector update.  The default workload is the 4x4 periodic
 Hubbard model at half filling (8 up + 8 down, dim 165,636,900, t=1, U=4) from a
 seeded uniform(-1,1) start vector, float64 (the plain method); the mixed form
-(float32 vectors, float64 scalars) is timed beside it.  Inputs are resident in
-HBM before the timed region; as in the paper's protocol no transfer is timed.
+(float32 vectors, float64 scalars) is timed beside it.  The down species' basis
+is taken in hop-count order (ed_hop_order; --basis-order ascending for the
+paper's order): the same H up to a permutation of the vector elements, with
+the start vector permuted alike, so the run has the same a_j, b_j and E0.
+Inputs are resident in HBM before the timed region; as in the paper's protocol
+no transfer is timed.
 
 Beside the step rate the line carries: the roofline of the dominant kernel
 (HIP events inside this run), time-to-E0 at stated accuracy for plain float64,
@@ -21,7 +25,7 @@ workloads beside its K40 times, and the oracle timed on the host cores.
 Prints ONE JSON line on stdout (progress lines go to stderr).  Options:
 --steps K --warmup W (timed / untimed steps), --gpus N (only 1 is supported:
 the method runs on one GPU), --no-cpu-baseline, --no-learned, --no-batch,
---no-scale, --no-single, --no-complex, --no-paper-shapes.
+--no-scale, --no-single, --no-complex, --no-paper-shapes, --basis-order.
 """
 
 import argparse
@@ -29,6 +33,7 @@ import json
 import os
 import sys
 import time
+from math import comb
 
 import numpy as np
 
@@ -83,12 +88,39 @@ def time_run(h, x, warmup, steps, n_kernel_samples):
     return ms, dict(zip(KERNELS, per.tolist())), st
 
 
+# Rows longer than this many states are gathered from global memory by the down part, not from LDS;
+# there the ascending order's locality counts for more than the padding chunks the hop order drops
+# (measured: the one-species 30-site torus ran 25% slower in FP64 in hop order).
+LDS_ROW_STATES = 19456
+
+
+def dn_order_for(args, dim_dn, cplx=False):
+    """The down species' basis order for a run: --basis-order where FP64 rows sit in LDS, else ascending."""
+    return args.basis_order if dim_dn * (2 if cplx else 1) <= LDS_ROW_STATES else "ascending"
+
+
+def species_tables(ed, n_sites, bonds, n_up, n_dn, dev, dn_order, **kw):
+    """(up, down) SpinTables: the up species in ascending order, the down species in dn_order."""
+    up = ed.SpinTables(n_sites, bonds, n_up, dev, **kw)
+    if n_dn == n_up and dn_order == "ascending":
+        return up, up
+    return up, ed.SpinTables(n_sites, bonds, n_dn, dev, order=dn_order, **kw)
+
+
+def start_in_order(h, x_host, dev):
+    """The seeded start vector (ascending order of both species) on the device, in h's basis order."""
+    import torch
+    x = torch.from_numpy(x_host).to(dev, h.torch_dtype)
+    return h.to_basis_order(x) if h.order_bits else x
+
+
 # the step kernels' sources: the traffic record is valid only for these exact bytes
 TRAFFIC_SOURCES = ("ed_device.hip", "ed_common.cuh")
 
 
-def measured_traffic(dtype, kernel, workload_name):
-    """HBM bytes per launch from the committed counter record, if it matches this kernel source."""
+def measured_traffic(dtype, kernel, workload_name, basis_order):
+    """HBM bytes per launch from the committed counter record, if it matches this kernel source, workload and
+    down-species basis order."""
     import hashlib
     here = os.path.join(ROOT, "paper_1511_00863_amd")
     try:
@@ -96,7 +128,8 @@ def measured_traffic(dtype, kernel, workload_name):
         src = b"".join(open(os.path.join(here, "csrc", f), "rb").read() for f in TRAFFIC_SOURCES)
     except OSError:
         return None
-    if hashlib.sha256(src).hexdigest()[:16] != rec.get("source_sha256_prefix") or rec.get("workload") != workload_name:
+    if (hashlib.sha256(src).hexdigest()[:16] != rec.get("source_sha256_prefix") or rec.get("workload") != workload_name
+            or rec.get("basis_order_down", "ascending") != basis_order):
         return None
     return rec["kernels"].get(dtype, {}).get(kernel)
 
@@ -110,11 +143,12 @@ def scale_block(args):
     from synth import workload
     wl = workload("ring18_9x9")
     dev = "cuda:0"
-    tab = ed.SpinTables(wl.n_sites, wl.bonds, wl.n_up, dev)
-    out = {"workload": wl.name, "dim": tab.dim * tab.dim, "U": wl.U, "table_entry_bytes": tab.entry_bytes,
-           "start": "uniform(-1/2,1/2) from torch's device generator, seed %d" % wl.seed}
+    tab, tdn = species_tables(ed, wl.n_sites, wl.bonds, wl.n_up, wl.n_dn, dev, "ascending")   # 48620-state rows
+    out = {"workload": wl.name, "dim": tab.dim * tdn.dim, "U": wl.U, "table_entry_bytes": tab.entry_bytes,
+           "basis_order": {"up": "ascending", "down": tdn.order},
+           "start": "uniform(-1/2,1/2) from torch's device generator, seed %d, drawn in the run's order" % wl.seed}
     for dtype in ("f64", "f32"):
-        h = ed.Hamiltonian(tab, tab, wl.t, wl.U, dtype)
+        h = ed.Hamiltonian(tab, tdn, wl.t, wl.U, dtype)
         src = ed.api.apply_tuned_tile(h, tune_if_missing=False)
         g = torch.Generator(device=dev)
         g.manual_seed(wl.seed)
@@ -125,7 +159,7 @@ def scale_block(args):
                       "GB_per_vector": es * h.dim / 1e9, "tile": {"id": h.tile, "source": src, **h.tile_params()}}
         del x, h
         torch.cuda.empty_cache()
-    del tab
+    del tab, tdn
     torch.cuda.empty_cache()
     return out
 
@@ -143,14 +177,14 @@ def single_block(args):
     out = {}
     for name in ("ring26_0x13", "torus5x6_0x9"):
         wl = workload(name)
-        up = ed.SpinTables(wl.n_sites, wl.bonds, wl.n_up, dev)
-        dn = ed.SpinTables(wl.n_sites, wl.bonds, wl.n_dn, dev)
+        up, dn = species_tables(ed, wl.n_sites, wl.bonds, wl.n_up, wl.n_dn, dev, "ascending")   # one row of D
         x_host = start_vector(wl.seed, up.dim * dn.dim)
-        rec = {"dim": up.dim * dn.dim, "table_stride": dn.stride, "table_entry_bytes": dn.entry_bytes}
+        rec = {"dim": up.dim * dn.dim, "table_stride": dn.stride, "table_entry_bytes": dn.entry_bytes,
+               "basis_order": dn.order}
         for dtype in ("f64", "f32"):
             h = ed.Hamiltonian(up, dn, wl.t, wl.U, dtype)
             src = ed.api.apply_tuned_tile(h, tune_if_missing=False)
-            x = torch.from_numpy(x_host).to(dev, h.torch_dtype)
+            x = start_in_order(h, x_host, dev)
             ms, per, _ = time_run(h, x, 3, args.single_steps, 3)
             es = 8 if dtype == "f64" else 4
             dn_bytes = 3 * es * h.dim + h.dim * dn.stride * dn.entry_bytes + 8 * h.dim
@@ -175,16 +209,18 @@ def complex_block(args):
     from synth import start_vector_complex, workload
     wl = workload("checker18_5x5")
     dev = "cuda:0"
-    tab = ed.SpinTables(wl.n_sites, wl.bonds, wl.n_up, dev, amps=list(wl.amps))
-    x_host = start_vector_complex(wl.seed, tab.dim * tab.dim)
-    out = {"workload": wl.name, "dim": tab.dim * tab.dim, "U": wl.U, "table_stride": tab.stride,
-           "n_amplitudes": tab.n_amps, "paper_k40_ms_per_step": {"f64": 712.0, "f32": 425.0}}
+    tab, tdn = species_tables(ed, wl.n_sites, wl.bonds, wl.n_up, wl.n_dn, dev, dn_order_for(args, comb(wl.n_sites, wl.n_dn), True),
+                              amps=list(wl.amps))
+    x_host = start_vector_complex(wl.seed, tab.dim * tdn.dim)
+    out = {"workload": wl.name, "dim": tab.dim * tdn.dim, "U": wl.U, "table_stride": tab.stride,
+           "n_amplitudes": tab.n_amps, "basis_order": {"up": "ascending", "down": tdn.order},
+           "paper_k40_ms_per_step": {"f64": 712.0, "f32": 425.0}}
     for dtype in ("f64", "f32"):
-        h = ed.Hamiltonian(tab, tab, wl.t, wl.U, dtype)
-        x = torch.from_numpy(x_host).to(dev, h.torch_dtype)
+        h = ed.Hamiltonian(tab, tdn, wl.t, wl.U, dtype)
+        x = start_in_order(h, x_host, dev)
         ms, per, _ = time_run(h, x, 3, args.complex_steps, 3)
         es = 16 if dtype == "f64" else 8
-        dn_bytes = 4 * es * h.dim + tab.dim * tab.stride * 4 + 8 * 2 * tab.dim
+        dn_bytes = 4 * es * h.dim + tdn.dim * tdn.stride * 4 + 8 * 2 * tdn.dim
         out[dtype] = {"steps_per_s": 1000.0 / ms, "ms_per_step": ms, "kernel_ms": per,
                       "k_down_alg_GBps": dn_bytes / (per["k_down"] * 1e-3) / 1e9,
                       "up_alg_GBps": (2 * es * h.dim) / (per["k_up"] * 1e-3) / 1e9}
@@ -214,23 +250,24 @@ def paper_shapes_block(args):
     for lat in ("ring18", "checker18"):
         for n in (2, 3, 4, 5):
             if lat == "ring18":
-                tab = ed.SpinTables(18, ring_bonds(18), n, dev)
-                x_host = start_vector(11, tab.dim * tab.dim)
+                tab, tdn = species_tables(ed, 18, ring_bonds(18), n, n, dev, dn_order_for(args, comb(18, n)))
+                x_host = start_vector(11, tab.dim * tdn.dim)
             else:
-                tab = ed.SpinTables(18, cb.bonds, n, dev, amps=list(cb.amps))
-                x_host = start_vector_complex(11, tab.dim * tab.dim)
-            rec = {"dim": tab.dim * tab.dim, "paper_k40_ms": {"f32": PAPER_K40_MS[lat][n][0],
+                tab, tdn = species_tables(ed, 18, cb.bonds, n, n, dev, dn_order_for(args, comb(18, n), True),
+                                          amps=list(cb.amps))
+                x_host = start_vector_complex(11, tab.dim * tdn.dim)
+            rec = {"dim": tab.dim * tdn.dim, "paper_k40_ms": {"f32": PAPER_K40_MS[lat][n][0],
                                                                "f64": PAPER_K40_MS[lat][n][1]}}
             for dtype in ("f64", "f32"):
-                h = ed.Hamiltonian(tab, tab, 1.0, 4.0, dtype)
+                h = ed.Hamiltonian(tab, tdn, 1.0, 4.0, dtype)
                 ed.api.apply_tuned_tile(h, tune_if_missing=False)
-                x = torch.from_numpy(x_host).to(dev, h.torch_dtype)
+                x = start_in_order(h, x_host, dev)
                 ms, _, _ = time_run(h, x, 2, args.paper_steps, 1)
                 rec[dtype] = {"ms_per_step": ms, "vs_paper_k40": rec["paper_k40_ms"][dtype] / ms}
                 del x, h
                 torch.cuda.empty_cache()
             out["%s_%dx%d" % (lat, n, n)] = rec
-            del tab, x_host
+            del tab, tdn, x_host
     return out
 
 
@@ -310,20 +347,20 @@ def batch_block(args):
     from synth import batch_instances, start_vector, torus_bonds
     bonds = torus_bonds(4, 4)
     draws = batch_instances(64, 1000)
-    tabs = {n: ed.SpinTables(16, bonds, n, "cuda:0") for n in (3, 4, 5, 6)}
-    hams = [ed.Hamiltonian(tabs[n], tabs[n], 1.0, U, "f32") for (U, n, s) in draws]
+    tabs = {n: species_tables(ed, 16, bonds, n, n, "cuda:0", dn_order_for(args, comb(16, n))) for n in (3, 4, 5, 6)}
+    hams = [ed.Hamiltonian(*tabs[n], 1.0, U, "f32") for (U, n, s) in draws]
     for h in hams:
         ed.api.apply_tuned_tile(h, tune_if_missing=False)
-    f1s = [torch.from_numpy(start_vector(s, h.dim)).to("cuda:0", torch.float32) for h, (U, n, s) in zip(hams, draws)]
+    f1s = [start_in_order(h, start_vector(s, h.dim), "cuda:0") for h, (U, n, s) in zip(hams, draws)]
     r = ed.ground_energy_batch(hams, f1s, 500, tol=1e-6)
     r = ed.ground_energy_batch(hams, f1s, 500, tol=1e-6)          # second call timed (warm)
     del f1s
     torch.cuda.empty_cache()
     seq_ms, seq_e0 = 0.0, []
     for (U, n, s) in draws:
-        h = ed.Hamiltonian(tabs[n], tabs[n], 1.0, U, "f64")
+        h = ed.Hamiltonian(*tabs[n], 1.0, U, "f64")
         ed.api.apply_tuned_tile(h, tune_if_missing=False)
-        x = torch.from_numpy(start_vector(s, h.dim)).to("cuda:0", torch.float64)
+        x = start_in_order(h, start_vector(s, h.dim), "cuda:0")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         rr = h.ground_energy(x, 500, tol=1e-6, check_every=9)
@@ -335,15 +372,15 @@ def batch_block(args):
     # the same instances one after another in the batch's own precision (mixed form), same tolerance
     mix_ms = 0.0
     for h, (U, n, s) in zip(hams, draws):
-        x = torch.from_numpy(start_vector(s, h.dim)).to("cuda:0", torch.float32)
+        x = start_in_order(h, start_vector(s, h.dim), "cuda:0")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         h.ground_energy(x, 500, tol=1e-6, check_every=9)
         torch.cuda.synchronize()
         mix_ms += (time.perf_counter() - t0) * 1e3
         del x
-    small = small_batch(tabs_for=lambda n: ed.SpinTables(16, bonds, n, "cuda:0"))
-    return {"small_instances": small, "instances": 64, "total_dim": int(sum(h.dim for h in hams)), "wall_ms": r["wall_ms"],
+    small = small_batch(tabs_for=lambda n: species_tables(ed, 16, bonds, n, n, "cuda:0", dn_order_for(args, comb(16, n))))
+    return {"basis_order": {"up": "ascending", "down": args.basis_order}, "small_instances": small, "instances": 64, "total_dim": int(sum(h.dim for h in hams)), "wall_ms": r["wall_ms"],
             "graph_used": r["graph_used"], "converged": int((r["status"] == 0).sum()),
             "max_steps_used": int(r["steps"].max()), "sequential_plain_f64_ms": seq_ms,
             "sequential_mixed_ms": mix_ms,
@@ -360,10 +397,10 @@ def small_batch(tabs_for, n=256, seed=2000):
     from synth import batch_instances, start_vector
     draws = batch_instances(n, seed, fillings=(2, 3))
     tabs = {k: tabs_for(k) for k in (2, 3)}
-    hams = [ed.Hamiltonian(tabs[k], tabs[k], 1.0, U, "f32") for (U, k, s) in draws]
+    hams = [ed.Hamiltonian(*tabs[k], 1.0, U, "f32") for (U, k, s) in draws]
     for h in hams:
         ed.api.apply_tuned_tile(h, tune_if_missing=False)
-    f1s = [torch.from_numpy(start_vector(s, h.dim)).to("cuda:0", torch.float32) for h, (U, k, s) in zip(hams, draws)]
+    f1s = [start_in_order(h, start_vector(s, h.dim), "cuda:0") for h, (U, k, s) in zip(hams, draws)]
     ed.ground_energy_batch(hams, f1s, 500, tol=1e-6)
     r = ed.ground_energy_batch(hams, f1s, 500, tol=1e-6)
     seq_ms = 0.0
@@ -429,6 +466,8 @@ def main():
     ap.add_argument("--complex-steps", type=int, default=20)
     ap.add_argument("--single-steps", type=int, default=20)
     ap.add_argument("--scale-steps", type=int, default=6)
+    ap.add_argument("--basis-order", choices=("hops", "ascending"), default="hops",
+                    help="basis order of the down species where its rows fit LDS (the up species stays ascending)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this method runs on one GPU; --gpus %d is not supported (use --gpus 1)" % args.gpus,
@@ -446,12 +485,15 @@ def main():
     del x64
     up = ed.SpinTables(wl.n_sites, wl.bonds, wl.n_up, dev)
     dn = up if wl.n_dn == wl.n_up else ed.SpinTables(wl.n_sites, wl.bonds, wl.n_dn, dev)
+    # the timed step: down species in hop-count order (the same H up to a permutation of the elements)
+    order = dn_order_for(args, dn.dim)
+    dn_run = dn if order == "ascending" else ed.SpinTables(wl.n_sites, wl.bonds, wl.n_dn, dev, order=order)
     x_host = start_vector(wl.seed, up.dim * dn.dim)
 
     results = {}
     for dtype in (("f64",) if args.no_mixed else ("f64", "f32")):
-        h = ed.Hamiltonian(up, dn, wl.t, wl.U, dtype)
-        x = torch.from_numpy(x_host).to(dev, h.torch_dtype)
+        h = ed.Hamiltonian(up, dn_run, wl.t, wl.U, dtype)
+        x = h.to_basis_order(torch.from_numpy(x_host).to(dev, h.torch_dtype))   # the same start, reordered
         tile_src = "default"
         if not args.no_tune:           # the project's autotuner (cached per shape); outside the timed region
             tile_src = ed.api.apply_tuned_tile(h, x)
@@ -485,9 +527,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "lattice": "4x4 periodic square" if wl.n_sites == 16 else wl.name,
                    "n_up": wl.n_up, "n_dn": wl.n_dn, "dim": up.dim * dn.dim, "t": wl.t, "U": wl.U,
-                   "start": "uniform(-1,1), seed %d" % wl.seed},
+                   "start": "uniform(-1,1), seed %d" % wl.seed,
+                   "basis_order": {"up": "ascending", "down": dn_run.order}},
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic("f64", dom, wl.name)},
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic("f64", dom, wl.name, dn_run.order)},
         "hv_alg_GBps": r64["hv_alg_GBps"],
         "step_floor_frac": r64["step_floor_GBps"] / HBM_PEAK_GBPS,
         "kernel_ms": r64["kernel_ms"],

@@ -1,10 +1,14 @@
 """The bench's command-line contract and byte model (CPU only: nothing here touches a GPU)."""
 
+import json
+import os
 import subprocess
 import sys
 import types
 
 import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def test_more_than_one_gpu_is_refused_with_a_message():
@@ -33,8 +37,11 @@ def test_algorithmic_bytes_per_launch():
     assert wide["k_up"] == 2 * 8 * 48620 ** 2 + 48620 * 24 * 4
 
 
-def test_traffic_record_only_for_its_workload():
-    assert bench.measured_traffic("f64", "k_down", "some_other_workload") is None
+def test_traffic_record_only_for_its_workload_and_basis_order():
+    assert bench.measured_traffic("f64", "k_down", "some_other_workload", "hops") is None
+    rec = json.load(open(os.path.join(ROOT, "paper_1511_00863_amd", "measured_traffic.json")))
+    other = "ascending" if rec.get("basis_order_down", "ascending") == "hops" else "hops"
+    assert bench.measured_traffic("f64", "k_down", rec["workload"], other) is None
 
 
 def test_progress_lines_go_to_stderr(capsys):
