@@ -530,9 +530,18 @@ __device__ __forceinline__ void down_rows(const T *__restrict__ xrows, T *__rest
             // a chunk whose first entry is padding is padding throughout; skip it
             // when that holds for every lane of the wave
             if (!__any(!is_pad<E>(entry(tq[k8], 0)))) break;
+            // likewise the chunk's second half (entries 4..7), in FP32: gather it only where some lane needs
+            // it (in FP64 the extra branch cost more than the skipped gathers saved)
+            bool upper = true;
+            if constexpr (sizeof(T) == 4) upper = __any(!is_pad<E>(entry(tq[k8], 4)));
             T v[8], sg[8];
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
+                if (k >= 4 && !upper) {
+                    v[k] = T(0);
+                    sg[k] = T(0);
+                    continue;
+                }
                 const unsigned e = entry(tq[k8], k);
                 const bool pk = !is_pad<E>(e);
                 sg[k] = pk ? ((e & 1u) ? T(-1) : T(1)) : T(0);
