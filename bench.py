@@ -302,7 +302,7 @@ def observables_block(item, wl):
 
 
 def time_to_e0_block(up, dn, wl, args):
-    """Steps and wall ms to E0 at stated accuracy vs converged plain float64 Lanczos (the judge):
+    """Steps and wall ms to E0 at stated accuracy vs converged plain float64 Lanczos (the reference):
     plain float64 and mixed from the seeded random start, mixed and float64 from the learned start
     (network inference inside the timed region).  The network trains on ground states at U = 1..8."""
     import torch
@@ -321,15 +321,15 @@ def time_to_e0_block(up, dn, wl, args):
                         "batch": 4096, "loss_first": float(losses[:20].mean()), "loss_last": float(losses[-20:].mean())},
            "observables": obs, "held_out": []}
     for U in [float(u) for u in args.held_out.split(",")]:
-        e_judge, judge_steps = learned.judge_energy(up, dn, wl.t, U, wl.seed)
-        row = {"U": U, "e_judge": e_judge, "judge_steps": judge_steps}
+        e_ref, ref_steps = learned.reference_energy(up, dn, wl.t, U, wl.seed)
+        row = {"U": U, "e_ref": e_ref, "ref_steps": ref_steps}
         for dt, tol in (("f64", 1e-10), ("f32", 1e-6)):
             h = ed.Hamiltonian(up, dn, wl.t, U, dt)
             ed.api.apply_tuned_tile(h, tune_if_missing=False)
             x = torch.from_numpy(start_vector(wl.seed, h.dim)).to("cuda:0", h.torch_dtype)
-            rnd = learned.time_to_e0(h, lambda: x.clone(), e_judge, tol)
+            rnd = learned.time_to_e0(h, lambda: x.clone(), e_ref, tol)
             del x
-            lrn = learned.time_to_e0(h, lambda: learned.learned_start(net, h, wl.seed)[0], e_judge, tol)
+            lrn = learned.time_to_e0(h, lambda: learned.learned_start(net, h, wl.seed)[0], e_ref, tol)
             name = "plain_f64" if dt == "f64" else "mixed"
             row[name + "_random"] = {"steps": rnd["steps"], "ms": rnd["ms"], "rel_tol": tol}
             row[name + "_learned"] = {"steps": lrn["steps"], "ms": lrn["ms"], "rel_tol": tol}

@@ -26,5 +26,5 @@ leaves open are listed in the module docstrings.  Parity status: every function
 is pinned by ``tests/test_oracle_*.py`` against closed forms, brute force,
 printed values or library routines of a different algorithm, except the trained
 network's output, which is parity unpinned (training is not reproducible across
-implementations; it is judged through the energy it reaches).
+implementations; it is assessed through the energy it reaches).
 """

@@ -5,7 +5,7 @@ two-pass Lanczos run (ed_ground_state) at a set of training U values.  The
 network is trained on minibatches drawn from them and then evaluated over all
 states at a held-out U to give the start vector f_1 of Alg. 1.  If that
 vector has zero or non-finite norm the seeded random start is used instead.
-The judge of every run is converged plain float64 Lanczos.
+The reference energy of every run is that of converged plain float64 Lanczos.
 
 Host code here only orchestrates calls into the library; all arithmetic runs
 in its kernels (Lanczos, network, sampling) or in its host C++ (bisection).
@@ -25,7 +25,7 @@ def _random_start(ham, seed):
     return torch.from_numpy(start_vector(seed, ham.dim)).to(ham.device, ham.torch_dtype)
 
 
-def judge_energy(up, dn, t, U, seed, tol=1e-12, max_steps=800, tile=None):
+def reference_energy(up, dn, t, U, seed, tol=1e-12, max_steps=800, tile=None):
     """Converged plain float64 Lanczos from the seeded random start."""
     h = api.Hamiltonian(up, dn, t, U, "f64")
     api.apply_tuned_tile(h, tune_if_missing=False)
@@ -60,24 +60,24 @@ def train_network(data, iters=1500, batch=4096, seed=7, init_seed=3, lr=1e-3, lr
     return net, losses, time.perf_counter() - t0
 
 
-def steps_to_accuracy(a, b, e_judge, rel_tol):
-    """First j with |E0(j) - E_judge| <= rel_tol |E_judge| (host bisection of T_j), or None."""
+def steps_to_accuracy(a, b, e_ref, rel_tol):
+    """First j with |E0(j) - E_ref| <= rel_tol |E_ref| (host bisection of T_j), or None."""
     for j in range(1, len(a) + 1):
         e = api.tridiag_lowest(a[:j], b[1:j])
-        if abs(e - e_judge) <= rel_tol * abs(e_judge):
+        if abs(e - e_ref) <= rel_tol * abs(e_ref):
             return j
     return None
 
 
-def time_to_e0(ham, f1_fn, e_judge, rel_tol, max_steps=600, reps=1):
-    """Steps and wall time to reach E0 within rel_tol of the judge from the start f1_fn().
+def time_to_e0(ham, f1_fn, e_ref, rel_tol, max_steps=600, reps=1):
+    """Steps and wall time to reach E0 within rel_tol of the reference from the start f1_fn().
 
     The run length is found once from the coefficients; the timed region then
     covers producing f1 (network inference for a learned start; a copy of a
     resident vector for a random start) plus exactly that many steps."""
     f1 = f1_fn()
     probe = ham.ground_energy(f1, max_steps, tol=0.0, check_every=30)
-    k = steps_to_accuracy(probe["a"], probe["b"], e_judge, rel_tol)
+    k = steps_to_accuracy(probe["a"], probe["b"], e_ref, rel_tol)
     if k is None:
         return {"steps": None, "ms": None}
     del f1

@@ -1,4 +1,4 @@
-"""What the trained start-vector network gains: fewer Lanczos steps to the judged E0 at held-out U."""
+"""What the trained start-vector network gains: fewer Lanczos steps to the reference E0 at held-out U."""
 
 import numpy as np
 import pytest
@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 def test_learned_start_beats_random_at_held_out_u():
     """4x4 torus, 4+4: train on ground states at U = 1..8, evaluate at U = 1.5, 3.5, 5.5, 7.5.
-    Judge: converged plain float64 Lanczos.  Both starts run the mixed form to 1e-6."""
+    Reference: converged plain float64 Lanczos.  Both starts run the mixed form to 1e-6."""
     tab = ed.SpinTables(16, torus_bonds(4, 4), 4, "cuda:0")
     announce("learned start: training data")
     data = learned.training_data(tab, tab, 1.0, [1, 2, 3, 4, 5, 6, 7, 8])
@@ -24,13 +24,13 @@ def test_learned_start_beats_random_at_held_out_u():
     gains = []
     for U in (1.5, 3.5, 5.5, 7.5):
         announce("learned start: held-out U=%g" % U)
-        e_judge, _ = learned.judge_energy(tab, tab, 1.0, U, 5)
+        e_ref, _ = learned.reference_energy(tab, tab, 1.0, U, 5)
         h = ed.Hamiltonian(tab, tab, 1.0, U, "f32")
         x = torch.from_numpy(start_vector(5, h.dim)).to("cuda:0", torch.float32)
-        rnd = learned.time_to_e0(h, lambda: x.clone(), e_judge, 1e-6)
-        lrn = learned.time_to_e0(h, lambda: learned.learned_start(net, h, 5)[0], e_judge, 1e-6)
+        rnd = learned.time_to_e0(h, lambda: x.clone(), e_ref, 1e-6)
+        lrn = learned.time_to_e0(h, lambda: learned.learned_start(net, h, 5)[0], e_ref, 1e-6)
         assert rnd["steps"] is not None and lrn["steps"] is not None
-        assert abs(lrn["e0"] - e_judge) <= 1e-6 * abs(e_judge)
+        assert abs(lrn["e0"] - e_ref) <= 1e-6 * abs(e_ref)
         gains.append(rnd["steps"] - lrn["steps"])
     assert min(gains) > 0, gains
 
