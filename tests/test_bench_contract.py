@@ -48,3 +48,15 @@ def test_progress_lines_go_to_stderr(capsys):
     bench.progress("a block")
     out, err = capsys.readouterr()
     assert out == "" and "a block" in err
+
+
+def test_down_basis_order_follows_the_lds_row_rule():
+    """Hop-count order where FP64 rows (complex: pairs) fit the down part's LDS staging, ascending beyond."""
+    args = types.SimpleNamespace(basis_order="hops")
+    assert bench.dn_order_for(args, 12870) == "hops"                      # 4x4 torus, 8 per species
+    assert bench.dn_order_for(args, bench.LDS_ROW_STATES) == "hops"
+    assert bench.dn_order_for(args, bench.LDS_ROW_STATES + 1) == "ascending"
+    assert bench.dn_order_for(args, 48620) == "ascending"                 # 18-site chain, 9 per species
+    assert bench.dn_order_for(args, 8568, cplx=True) == "hops"            # 18-site checkerboard, 5 per species
+    assert bench.dn_order_for(args, 12000, cplx=True) == "ascending"
+    assert bench.dn_order_for(types.SimpleNamespace(basis_order="ascending"), 12870) == "ascending"
