@@ -324,22 +324,21 @@ class Hamiltonian:
         """ed_ham.order: bit 0 / bit 1 set when the up / down basis is not ascending."""
         return (1 if self.up.order != "ascending" else 0) | (2 if self.dn.order != "ascending" else 0)
 
-    def _permute(self, x, inverse: bool):
+    def _permute(self, x, inverse: bool, stream=None):
         x = self._vec(x)
         y = self.empty_vec()
         pu, pd = self.up.dev_perm(inverse), self.dn.dev_perm(inverse)
         h = self.c_struct()
-        check(lib().ed_permute_vector(byref(h), _dptr(pu) if pu is not None else None,
-                                      _dptr(pd) if pd is not None else None, _dptr(x), _dptr(y), None))
+        check(lib().ed_permute_vector(byref(h), _dptr(pu), _dptr(pd), _dptr(x), _dptr(y), _stream(stream)))
         return y
 
-    def to_basis_order(self, x):
+    def to_basis_order(self, x, stream=None):
         """A vector over the ascending bases of both species, in this instance's basis order (ed_permute_vector)."""
-        return self._permute(x, False)
+        return self._permute(x, False, stream)
 
-    def to_ascending(self, x):
+    def to_ascending(self, x, stream=None):
         """A vector in this instance's basis order, back over the ascending bases (ed_permute_vector)."""
-        return self._permute(x, True)
+        return self._permute(x, True, stream)
 
     def workspace_bytes(self, max_steps: int = 1) -> int:
         n = c_int64(0)
