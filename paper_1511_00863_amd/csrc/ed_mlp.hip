@@ -435,13 +435,23 @@ __global__ __launch_bounds__(1024) void k_cdf_scan(double *__restrict__ w, int n
     }
 }
 
+// One wavefront per sample.  With uniforms[2k] < 1/2 the row comes from the
+// row distribution (binary search of row_cdf) and the column from the row's
+// own |psi|^2: the wave reads the row coalesced, once for its total and once
+// in 64-element chunks with an inclusive prefix sum, and takes the first
+// column whose running sum exceeds the target.  Otherwise the state is
+// drawn uniformly from the position uniforms[2k+1].
+constexpr int kSampleWaves = 4;   // samples per 256-thread workgroup
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_mlp_sample(const T *__restrict__ psi, int dim_up, int dim_dn,
-                                                    const double *__restrict__ row_cdf,
-                                                    const double *__restrict__ uni, int n, int32_t *__restrict__ idx,
-                                                    float *__restrict__ target) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
+__global__ __launch_bounds__(64 * kSampleWaves) void k_mlp_sample(const T *__restrict__ psi, int dim_up, int dim_dn,
+                                                                  const double *__restrict__ row_cdf,
+                                                                  const double *__restrict__ uni, int n,
+                                                                  int32_t *__restrict__ idx,
+                                                                  float *__restrict__ target) {
+    const int lane = threadIdx.x & 63;
+    const int k = blockIdx.x * kSampleWaves + (threadIdx.x >> 6);
+    if (k >= n) return;   // the whole wave
     const double sel = uni[2 * k], u = uni[2 * k + 1];
     int r, c;
     if (sel < 0.5) {
@@ -453,25 +463,45 @@ __global__ __launch_bounds__(256) void k_mlp_sample(const T *__restrict__ psi, i
         r = lo;
         const double prev = r > 0 ? row_cdf[r - 1] : 0.0;
         const double width = row_cdf[r] - prev;
-        double rem = width > 0.0 ? (u - prev) / width : 0.0;   // position inside the row, in [0, 1)
+        const double rem = width > 0.0 ? (u - prev) / width : 0.0;   // position inside the row, in [0, 1)
         const T *row = psi + (int64_t)r * dim_dn;
         double tot = 0.0;
-        for (int cc = 0; cc < dim_dn; ++cc) tot += (double)row[cc] * (double)row[cc];
+        for (int cc = lane; cc < dim_dn; cc += 64) {
+            const double v = row[cc];
+            tot += v * v;
+        }
+        for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o, 64);
         const double want = rem * tot;
-        double acc = 0.0;
+        double acc = 0.0;   // sum of the chunks before this one
         c = dim_dn - 1;
-        for (int cc = 0; cc < dim_dn; ++cc) {
-            acc += (double)row[cc] * (double)row[cc];
-            if (acc > want) { c = cc; break; }
+        for (int base = 0; base < dim_dn; base += 64) {
+            const int cc = base + lane;
+            double pre = 0.0;
+            if (cc < dim_dn) {
+                const double v = row[cc];
+                pre = v * v;
+            }
+            for (int o = 1; o < 64; o <<= 1) {
+                const double y = __shfl_up(pre, o, 64);
+                if (lane >= o) pre += y;
+            }
+            const unsigned long long hit = __ballot(cc < dim_dn && acc + pre > want);
+            if (hit) {
+                c = base + __ffsll((long long)hit) - 1;
+                break;
+            }
+            acc += __shfl(pre, 63, 64);
         }
     } else {
         const int64_t s = min((int64_t)(u * (double)dim_up * (double)dim_dn), (int64_t)dim_up * dim_dn - 1);
         r = (int)(s / dim_dn);
         c = (int)(s - (int64_t)r * dim_dn);
     }
-    idx[2 * k] = r;
-    idx[2 * k + 1] = c;
-    target[k] = (float)(sqrt((double)dim_up * (double)dim_dn) * (double)psi[(int64_t)r * dim_dn + c]);
+    if (lane == 0) {
+        idx[2 * k] = r;
+        idx[2 * k + 1] = c;
+        target[k] = (float)(sqrt((double)dim_up * (double)dim_dn) * (double)psi[(int64_t)r * dim_dn + c]);
+    }
 }
 
 // workspace layout for a minibatch of n samples (ld = n rounded up to 32)
@@ -609,12 +639,12 @@ int ed_mlp_sample(const void *psi, const ed_ham *h, const double *row_cdf, const
     if (!psi || !row_cdf || !uniforms || n < 1 || !idx || !target)
         return set_error(ED_EINVAL, "ed_mlp_sample: bad arguments");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int grid = (n + 255) / 256;
+    const int grid = (n + kSampleWaves - 1) / kSampleWaves;
     if (h->dtype == ED_F64)
-        hipLaunchKernelGGL(k_mlp_sample<double>, dim3(grid), dim3(256), 0, s, (const double *)psi, (int)h->dim_up,
+        hipLaunchKernelGGL(k_mlp_sample<double>, dim3(grid), dim3(64 * kSampleWaves), 0, s, (const double *)psi, (int)h->dim_up,
                            (int)h->dim_dn, row_cdf, uniforms, n, idx, target);
     else
-        hipLaunchKernelGGL(k_mlp_sample<float>, dim3(grid), dim3(256), 0, s, (const float *)psi, (int)h->dim_up,
+        hipLaunchKernelGGL(k_mlp_sample<float>, dim3(grid), dim3(64 * kSampleWaves), 0, s, (const float *)psi, (int)h->dim_up,
                            (int)h->dim_dn, row_cdf, uniforms, n, idx, target);
     ED_LAUNCHED("k_mlp_sample");
     return ED_OK;
