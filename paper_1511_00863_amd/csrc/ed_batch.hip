@@ -607,10 +607,26 @@ static int plan_batch(const ed_batch_item *items, int n, int32_t max_steps, Batc
     return ED_OK;
 }
 
+// per instance in the result staging area: a[0..max_steps), b[0..max_steps], E0 of the last step
+__host__ __device__ inline int64_t stage_stride(int32_t max_steps) { return 2 * (int64_t)max_steps + 2; }
+
 static int64_t batch_ws_bytes(const BatchPlan &plan, int n, int32_t max_steps) {
     auto al = [](int64_t b) { return (b + 255) & ~int64_t(255); };
     return al(sizeof(GridBar)) + al((int64_t)n * sizeof(BInst)) + al(8 * plan.part_doubles) +
-           al(8 * plan.part2_doubles) + al(8 * (int64_t)n * (max_steps + 1));
+           al(8 * plan.part2_doubles) + al(8 * (int64_t)n * (max_steps + 1)) +
+           al(8 * (int64_t)n * stage_stride(max_steps));
+}
+
+// Gathers every instance's a_j, b_j and last E0 into one array, so that the
+// host fetches them with one copy.  One workgroup per instance; j <= max_steps.
+__global__ __launch_bounds__(256) void k_batch_collect(const BInst *__restrict__ inst, int max_steps,
+                                                       double *__restrict__ stage) {
+    const BInst &I = inst[blockIdx.x];
+    const int k = I.j;
+    double *o = stage + (int64_t)blockIdx.x * stage_stride(max_steps);
+    for (int t = threadIdx.x; t < k; t += blockDim.x) o[t] = I.a[t];
+    for (int t = threadIdx.x; t <= k; t += blockDim.x) o[max_steps + t] = I.b[t];
+    if (threadIdx.x == 0) o[2 * max_steps + 1] = k > 0 ? I.e[k] : 0.0;
 }
 
 }  // namespace ed
@@ -653,6 +669,8 @@ int ed_ground_energy_batch(const ed_batch_item *items, int32_t n, int32_t max_st
     p += al(8 * plan.part2_doubles);
     double *ev = reinterpret_cast<double *>(p);
     for (int i = 0; i < n; ++i) plan.inst[i].e = (ED_GLOBAL double *)(ev + (int64_t)i * (max_steps + 1));
+    p += al(8 * (int64_t)n * (max_steps + 1));
+    double *stage = reinterpret_cast<double *>(p);
 
     int grid = 0;
     rc = batch_grid(&grid);
@@ -703,8 +721,13 @@ int ed_ground_energy_batch(const ed_batch_item *items, int32_t n, int32_t max_st
     if (graph_used) *graph_used = graphed ? 1 : 0;
     std::vector<BInst> out(n);
     GridBar gbh{};
+    const int64_t sst = stage_stride(max_steps);
+    std::vector<double> staged((size_t)n * sst);
+    hipLaunchKernelGGL(k_batch_collect, dim3(n), dim3(256), 0, user, dinst, (int)max_steps, stage);
+    ED_HIP(hipGetLastError());
     ED_HIP(hipMemcpyAsync(out.data(), dinst, n * sizeof(BInst), hipMemcpyDeviceToHost, user));
     ED_HIP(hipMemcpyAsync(&gbh, gb, sizeof gbh, hipMemcpyDeviceToHost, user));
+    ED_HIP(hipMemcpyAsync(staged.data(), stage, 8 * staged.size(), hipMemcpyDeviceToHost, user));
     ED_HIP(hipStreamSynchronize(user));
     if (gbh.err) return set_error(ED_EDEVICE, "ed_ground_energy_batch: grid barrier timed out");
     if (phase_ms) {
@@ -721,16 +744,9 @@ int ed_ground_energy_batch(const ed_batch_item *items, int32_t n, int32_t max_st
         steps[i] = k;
         status[i] = I.status == kConverged ? ED_OK : (I.status == ED_BREAKDOWN ? ED_BREAKDOWN : ED_NOT_CONVERGED);
         if (status[i] == ED_NOT_CONVERGED) result = ED_NOT_CONVERGED;
-        std::vector<double> a(k), b(k + 1), e(k + 1);
-        if (k > 0) {
-            ED_HIP(hipMemcpy(a.data(), items[i].a, 8 * (size_t)k, hipMemcpyDeviceToHost));
-            ED_HIP(hipMemcpy(b.data(), items[i].b, 8 * (size_t)(k + 1), hipMemcpyDeviceToHost));
-            ED_HIP(hipMemcpy(e.data(), (const double *)plan.inst[i].e, 8 * (size_t)(k + 1), hipMemcpyDeviceToHost));
-            e0[i] = tridiag_lowest(a.data(), b.data() + 1, k);
-        } else {
-            e0[i] = NAN;
-        }
-        if (e0_device) e0_device[i] = k > 0 ? e[k] : NAN;
+        const double *a = staged.data() + (size_t)i * sst, *b = a + max_steps;
+        e0[i] = k > 0 ? tridiag_lowest(a, b + 1, k) : NAN;
+        if (e0_device) e0_device[i] = k > 0 ? a[2 * max_steps + 1] : NAN;
     }
     return result;
 }
