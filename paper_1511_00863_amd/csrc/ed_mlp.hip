@@ -45,6 +45,15 @@ __device__ __forceinline__ uint16_t bf16_bits(float f) {
     return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
 }
 __device__ __forceinline__ float bf16_val(uint16_t b) { return __builtin_bit_cast(float, (uint32_t)b << 16); }
+// two floats rounded to bfloat16 (nearest even, as bf16_bits for finite values) in one register, lo first:
+// the hardware conversion of gfx950
+typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2;
+__device__ __forceinline__ uint32_t bf16_pack(float lo, float hi) {
+    bf16x2 v;
+    v[0] = (__bf16)lo;
+    v[1] = (__bf16)hi;
+    return __builtin_bit_cast(uint32_t, v);
+}
 __device__ __forceinline__ __bf16 as_bf(uint16_t b) { return __builtin_bit_cast(__bf16, b); }
 
 // LDS image of the weights (bfloat16) and biases (float32)
@@ -173,7 +182,9 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(const float *__restrict__ P, co
             f32x4 acc = {0.f, 0.f, 0.f, 0.f};
             c[ob] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_first(L.w1, ob, lane), b1, acc, 0, 0, 0);
         }
-        uint16_t h[8][4];
+        // activations as bf16 pairs: hp[ob][0] = features (4g, 4g+1), hp[ob][1] = (4g+2, 4g+3) of tile ob,
+        // which is also the register layout of the next layer's B operand
+        uint32_t hp[8][2];
         bf16x8 b[4];
         const float *bias[3] = {L.b1, L.b2, L.b3};
         uint16_t *store[3] = {h1t, h2t, h3t};
@@ -181,22 +192,36 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(const float *__restrict__ P, co
         for (int layer = 0; layer < 3; ++layer) {
             if (layer > 0) layer_hidden(layer == 1 ? L.w2 : L.w3, b, c, lane);
 #pragma unroll
-            for (int ob = 0; ob < 8; ++ob)
+            for (int ob = 0; ob < 8; ++ob) {
+                const float4 bv = *reinterpret_cast<const float4 *>(bias[layer] + 16 * ob + 4 * g);
+                const float z0 = fmaxf(c[ob][0] + bv.x, 0.f), z1 = fmaxf(c[ob][1] + bv.y, 0.f);
+                const float z2 = fmaxf(c[ob][2] + bv.z, 0.f), z3 = fmaxf(c[ob][3] + bv.w, 0.f);
+                hp[ob][0] = bf16_pack(z0, z1);
+                hp[ob][1] = bf16_pack(z2, z3);
+                if (TRAIN)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int f = 16 * ob + 4 * g + i;
-                    const float z = c[ob][i] + bias[layer][f];
-                    h[ob][i] = bf16_bits(z > 0.f ? z : 0.f);
-                    if (TRAIN) store[layer][(int64_t)f * ld + s] = ok ? h[ob][i] : (uint16_t)0;
-                }
-            tiles_to_b(h, b);
+                    for (int i = 0; i < 4; ++i) {
+                        const int f = 16 * ob + 4 * g + i;
+                        const uint16_t hb = (uint16_t)(hp[ob][i >> 1] >> (16 * (i & 1)));
+                        store[layer][(int64_t)f * ld + s] = ok ? hb : (uint16_t)0;
+                    }
+            }
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) {
+                const uint4 q = make_uint4(hp[2 * kb][0], hp[2 * kb][1], hp[2 * kb + 1][0], hp[2 * kb + 1][1]);
+                b[kb] = __builtin_bit_cast(bf16x8, q);
+            }
         }
         // layer 4 (128 -> 1): float32 dot of the bf16 activations with bf16 weights
         float part = 0.f;
 #pragma unroll
         for (int ob = 0; ob < 8; ++ob)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) part += bf16_val(h[ob][i]) * L.w4[16 * ob + 4 * g + i];
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t w = hp[ob][i >> 1];
+                const float hv = __builtin_bit_cast(float, (i & 1) ? (w & 0xFFFF0000u) : (w << 16));
+                part += hv * L.w4[16 * ob + 4 * g + i];
+            }
         part += __shfl_xor(part, 16, 64);
         part += __shfl_xor(part, 32, 64);
         if (g == 0 && ok) out[s] = static_cast<OUT>(part + L.b4);
