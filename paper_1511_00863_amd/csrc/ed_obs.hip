@@ -208,21 +208,32 @@ __global__ __launch_bounds__(256) void k_sflip(const T *__restrict__ psi, const 
         for (int j = 0; j < kFlipSlots; ++j) part[(int64_t)r * kFlipSlots + j] = tot[j];
 }
 
-// row i of C: fixed-order sums over the up rows, normalised
-__global__ __launch_bounds__(64) void k_sflip_final(const double *__restrict__ part, int Dup, int ns, int i,
-                                                    double *__restrict__ c) {
-    __shared__ double s_norm;
-    if (threadIdx.x == 0) {
+// row i of C: sums over the up rows in a fixed order (thread t adds the rows
+// of its contiguous chunk, then the threads' sums are added in thread order),
+// normalised by the same sum of |psi|^2
+constexpr int kFinalThreads = 512;
+
+__global__ __launch_bounds__(kFinalThreads) void k_sflip_final(const double *__restrict__ part, int Dup, int ns,
+                                                               int i, double *__restrict__ c) {
+    __shared__ double red[kFinalThreads];
+    __shared__ double s_tot[kObsMaxSites + 1];
+    const int t = threadIdx.x;
+    const int chunk = (Dup + kFinalThreads - 1) / kFinalThreads;
+    const int lo = min(Dup, t * chunk), hi = min(Dup, lo + chunk);
+    for (int j = 0; j <= ns; ++j) {
+        const int slot = j < ns ? j : kObsMaxSites;   // the last pass: |psi|^2
         double s = 0.0;
-        for (int r = 0; r < Dup; ++r) s += part[(int64_t)r * kFlipSlots + kObsMaxSites];
-        s_norm = s;
+        for (int r = lo; r < hi; ++r) s += part[(int64_t)r * kFlipSlots + slot];
+        red[t] = s;
+        __syncthreads();
+        if (t == 0) {
+            double tot = 0.0;
+            for (int k = 0; k < kFinalThreads; ++k) tot += red[k];
+            s_tot[j] = tot;
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    const int j = threadIdx.x;
-    if (j >= ns) return;
-    double s = 0.0;
-    for (int r = 0; r < Dup; ++r) s += part[(int64_t)r * kFlipSlots + j];
-    c[i * ns + j] = s_norm > 0.0 ? s / s_norm : 0.0;
+    if (t < ns) c[i * ns + t] = s_tot[ns] > 0.0 ? s_tot[t] / s_tot[ns] : 0.0;
 }
 
 static int64_t flip_ws_bytes(const ed_ham *h) {
@@ -239,7 +250,7 @@ static int flip_impl(const ed_ham *h, int ns, const T *psi, char *ws, hipStream_
         hipLaunchKernelGGL(k_sflip<T>, dim3((unsigned)h->dim_up), dim3(256), 0, s, psi, h->st_up, h->st_dn,
                            (int)h->dim_dn, ns, i, part);
         ED_LAUNCHED("k_sflip");
-        hipLaunchKernelGGL(k_sflip_final, dim3(1), dim3(64), 0, s, part, (int)h->dim_up, ns, i, c);
+        hipLaunchKernelGGL(k_sflip_final, dim3(1), dim3(kFinalThreads), 0, s, part, (int)h->dim_up, ns, i, c);
         ED_LAUNCHED("k_sflip_final");
     }
     ED_HIP(hipMemcpyAsync(c_host, c, sizeof(double) * ns * ns, hipMemcpyDeviceToHost, s));
@@ -318,20 +329,29 @@ __global__ __launch_bounds__(256) void k_bond(const T *__restrict__ psi, const u
         for (int k = 0; k < kBondSlots; ++k) part[(int64_t)r * kBondSlots + k] = tot[k];
 }
 
-__global__ __launch_bounds__(64) void k_bond_final(const double *__restrict__ part, int Dup, int nb, int b0,
-                                                   double *__restrict__ kout) {
-    __shared__ double s_norm;
-    if (threadIdx.x == 0) {
+// the group's 2 nb values, summed over the up rows in the fixed order of
+// k_sflip_final and normalised by |psi|^2
+__global__ __launch_bounds__(kFinalThreads) void k_bond_final(const double *__restrict__ part, int Dup, int nb,
+                                                              int b0, double *__restrict__ kout) {
+    __shared__ double red[kFinalThreads];
+    __shared__ double s_tot[kBondSlots];
+    const int t = threadIdx.x;
+    const int chunk = (Dup + kFinalThreads - 1) / kFinalThreads;
+    const int lo = min(Dup, t * chunk), hi = min(Dup, lo + chunk);
+    for (int k = 0; k <= 2 * nb; ++k) {
+        const int slot = k < 2 * nb ? k : 2 * kBondGroup;   // the last pass: |psi|^2
         double s = 0.0;
-        for (int r = 0; r < Dup; ++r) s += part[(int64_t)r * kBondSlots + 2 * kBondGroup];
-        s_norm = s;
+        for (int r = lo; r < hi; ++r) s += part[(int64_t)r * kBondSlots + slot];
+        red[t] = s;
+        __syncthreads();
+        if (t == 0) {
+            double tot = 0.0;
+            for (int q = 0; q < kFinalThreads; ++q) tot += red[q];
+            s_tot[k] = tot;
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    const int k = threadIdx.x;
-    if (k >= 2 * nb) return;
-    double s = 0.0;
-    for (int r = 0; r < Dup; ++r) s += part[(int64_t)r * kBondSlots + k];
-    kout[2 * b0 + k] = s_norm > 0.0 ? s / s_norm : 0.0;
+    if (t < 2 * nb) kout[2 * b0 + t] = s_tot[2 * nb] > 0.0 ? s_tot[t] / s_tot[2 * nb] : 0.0;
 }
 
 static int64_t bond_ws_bytes(const ed_ham *h, int n_bonds) {
@@ -352,7 +372,7 @@ static int bond_impl(const ed_ham *h, const int32_t *bonds_host, int n_bonds, co
         hipLaunchKernelGGL(k_bond<T>, dim3((unsigned)h->dim_up), dim3(256), 0, s, psi, h->st_up, h->st_dn,
                            (int)h->dim_dn, bonds + 2 * b0, nb, part);
         ED_LAUNCHED("k_bond");
-        hipLaunchKernelGGL(k_bond_final, dim3(1), dim3(64), 0, s, part, (int)h->dim_up, nb, b0, kout);
+        hipLaunchKernelGGL(k_bond_final, dim3(1), dim3(kFinalThreads), 0, s, part, (int)h->dim_up, nb, b0, kout);
         ED_LAUNCHED("k_bond_final");
     }
     ED_HIP(hipMemcpyAsync(k_host, kout, sizeof(double) * 2 * n_bonds, hipMemcpyDeviceToHost, s));
