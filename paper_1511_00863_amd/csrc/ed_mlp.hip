@@ -229,6 +229,104 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(const float *__restrict__ P, co
 }
 
 // ---------------------------------------------------------------------------
+// Inference over every state (the start vector): the forward pass of
+// k_mlp_fwd with NT 16-sample tiles per wavefront, so each weight fragment
+// read from LDS feeds NT matrix products instead of one.  The NT tiles are
+// independent MFMA chains; the scheduling barrier after each output block
+// keeps the compiler from holding every block's fragments at once.
+template <int NT>
+__device__ __forceinline__ void layer_hidden_nt(const uint16_t *w, const bf16x8 (&b)[NT][4], f32x4 (&c)[NT][8],
+                                                int lane) {
+#pragma unroll
+    for (int ob = 0; ob < 8; ++ob) {
+        f32x4 acc[NT];
+#pragma unroll
+        for (int q = 0; q < NT; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) {
+            const bf16x8 a = a_hidden(w, ob, kb, lane);
+#pragma unroll
+            for (int q = 0; q < NT; ++q) acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[q][kb], acc[q], 0, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < NT; ++q) c[q][ob] = acc[q];
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+template <typename OUT, int NT>
+__global__ __launch_bounds__(256) void k_mlp_infer(const float *__restrict__ P, const uint64_t *__restrict__ st_up,
+                                                   const uint64_t *__restrict__ st_dn, int64_t n, int dim_dn,
+                                                   OUT *__restrict__ out) {
+    __shared__ MlpLds L;
+    load_weights(P, L, false);
+    const int lane = threadIdx.x & 63, g = lane >> 4, col = lane & 15;
+    const int64_t ngroup = (n + 16 * NT - 1) / (16 * NT);
+    const int64_t wstride = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t grp = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); grp < ngroup; grp += wstride) {
+        f32x4 c[NT][8];
+        bf16x8 b[NT][4];
+        // layer 1 (32 -> 128) on the occupation bits
+#pragma unroll
+        for (int q = 0; q < NT; ++q) {
+            const int64_t s = (grp * NT + q) * 16 + col;
+            uint64_t su = 0, sd = 0;
+            if (s < n) {
+                const int64_t iu = s / dim_dn;
+                su = st_up[iu];
+                sd = st_dn[s - iu * dim_dn];
+            }
+            uint16_t xb[8];
+            features_b(su, sd, g, b[q][0], xb);
+        }
+#pragma unroll
+        for (int ob = 0; ob < 8; ++ob) {
+            const bf16x8 a = a_first(L.w1, ob, lane);
+#pragma unroll
+            for (int q = 0; q < NT; ++q)
+                c[q][ob] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[q][0], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+        }
+        uint32_t hp[NT][8][2];
+        const float *bias[3] = {L.b1, L.b2, L.b3};
+#pragma unroll
+        for (int layer = 0; layer < 3; ++layer) {
+            if (layer > 0) layer_hidden_nt<NT>(layer == 1 ? L.w2 : L.w3, b, c, lane);
+#pragma unroll
+            for (int q = 0; q < NT; ++q) {
+#pragma unroll
+                for (int ob = 0; ob < 8; ++ob) {
+                    const float4 bv = *reinterpret_cast<const float4 *>(bias[layer] + 16 * ob + 4 * g);
+                    hp[q][ob][0] = bf16_pack(fmaxf(c[q][ob][0] + bv.x, 0.f), fmaxf(c[q][ob][1] + bv.y, 0.f));
+                    hp[q][ob][1] = bf16_pack(fmaxf(c[q][ob][2] + bv.z, 0.f), fmaxf(c[q][ob][3] + bv.w, 0.f));
+                }
+#pragma unroll
+                for (int kb = 0; kb < 4; ++kb)
+                    b[q][kb] = __builtin_bit_cast(bf16x8, make_uint4(hp[q][2 * kb][0], hp[q][2 * kb][1],
+                                                                     hp[q][2 * kb + 1][0], hp[q][2 * kb + 1][1]));
+            }
+        }
+        // layer 4 (128 -> 1): float32 dot of the bf16 activations with bf16 weights
+#pragma unroll
+        for (int q = 0; q < NT; ++q) {
+            float part = 0.f;
+#pragma unroll
+            for (int ob = 0; ob < 8; ++ob)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const uint32_t w = hp[q][ob][i >> 1];
+                    const float hv = __builtin_bit_cast(float, (i & 1) ? (w & 0xFFFF0000u) : (w << 16));
+                    part += hv * L.w4[16 * ob + 4 * g + i];
+                }
+            part += __shfl_xor(part, 16, 64);
+            part += __shfl_xor(part, 32, 64);
+            const int64_t s = (grp * NT + q) * 16 + col;
+            if (g == 0 && s < n) out[s] = static_cast<OUT>(part + L.b4);
+        }
+    }
+}
+constexpr int kInferTiles = 4;
+
+// ---------------------------------------------------------------------------
 // Backward chain on 16-sample tiles: g4 = 2 (out - target) / n, then
 // dZ3 = (g4 w4) o [h3 > 0], dZ2 = (W3^T dZ3) o [h2 > 0], dZ1 = (W2^T dZ2) o [h1 > 0]
 // (bf16 operands, float32 accumulation), stored bf16 [feature][ld]; per-workgroup
@@ -626,14 +724,12 @@ int ed_mlp_start_vector(const float *params, const ed_ham *h, void *f1, void *st
     const int64_t n = h->dim_up * h->dim_dn;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (h->dtype == ED_F64)
-        hipLaunchKernelGGL((k_mlp_fwd<double, false>), dim3(fwd_grid(n)), dim3(256), 0, s, params, h->st_up,
-                           h->st_dn, (const int32_t *)nullptr, n, (int)h->dim_dn, (double *)f1, (uint16_t *)nullptr,
-                           (uint16_t *)nullptr, (uint16_t *)nullptr, (uint16_t *)nullptr, (int64_t)0);
+        hipLaunchKernelGGL((k_mlp_infer<double, kInferTiles>), dim3(fwd_grid(n)), dim3(256), 0, s, params, h->st_up,
+                           h->st_dn, n, (int)h->dim_dn, (double *)f1);
     else
-        hipLaunchKernelGGL((k_mlp_fwd<float, false>), dim3(fwd_grid(n)), dim3(256), 0, s, params, h->st_up,
-                           h->st_dn, (const int32_t *)nullptr, n, (int)h->dim_dn, (float *)f1, (uint16_t *)nullptr,
-                           (uint16_t *)nullptr, (uint16_t *)nullptr, (uint16_t *)nullptr, (int64_t)0);
-    ED_LAUNCHED("k_mlp_fwd");
+        hipLaunchKernelGGL((k_mlp_infer<float, kInferTiles>), dim3(fwd_grid(n)), dim3(256), 0, s, params, h->st_up,
+                           h->st_dn, n, (int)h->dim_dn, (float *)f1);
+    ED_LAUNCHED("k_mlp_infer");
     return ED_OK;
 }
 
