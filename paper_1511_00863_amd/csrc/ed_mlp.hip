@@ -48,6 +48,12 @@ __device__ __forceinline__ float bf16_val(uint16_t b) { return __builtin_bit_cas
 // two floats rounded to bfloat16 (nearest even, as bf16_bits for finite values) in one register, lo first:
 // the hardware conversion of gfx950
 typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2;
+// max(x, 0) in one integer max on the bits: a negative float (sign bit set) is a negative integer, a
+// non-negative one keeps its bits.  fmaxf of a raw accumulator value would canonicalise it first (two
+// instructions).
+__device__ __forceinline__ float relu(float x) {
+    return __builtin_bit_cast(float, max(__builtin_bit_cast(int, x), 0));
+}
 __device__ __forceinline__ uint32_t bf16_pack(float lo, float hi) {
     bf16x2 v;
     v[0] = (__bf16)lo;
@@ -234,14 +240,17 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(const float *__restrict__ P, co
 // read from LDS feeds NT matrix products instead of one.  The NT tiles are
 // independent MFMA chains; the scheduling barrier after each output block
 // keeps the compiler from holding every block's fragments at once.
+// The accumulators start from the layer's bias (features 16 ob + 4 g .. +3 of
+// this lane), so the epilogue is only the ReLU and the rounding.
 template <int NT>
-__device__ __forceinline__ void layer_hidden_nt(const uint16_t *w, const bf16x8 (&b)[NT][4], f32x4 (&c)[NT][8],
-                                                int lane) {
+__device__ __forceinline__ void layer_hidden_nt(const uint16_t *w, const float *bias, const bf16x8 (&b)[NT][4],
+                                                f32x4 (&c)[NT][8], int lane) {
 #pragma unroll
     for (int ob = 0; ob < 8; ++ob) {
+        const float4 bv = *reinterpret_cast<const float4 *>(bias + 16 * ob + 4 * (lane >> 4));
         f32x4 acc[NT];
 #pragma unroll
-        for (int q = 0; q < NT; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int q = 0; q < NT; ++q) acc[q] = f32x4{bv.x, bv.y, bv.z, bv.w};
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) {
             const bf16x8 a = a_hidden(w, ob, kb, lane);
@@ -282,22 +291,21 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const float *__restrict__ P, 
 #pragma unroll
         for (int ob = 0; ob < 8; ++ob) {
             const bf16x8 a = a_first(L.w1, ob, lane);
+            const float4 bv = *reinterpret_cast<const float4 *>(L.b1 + 16 * ob + 4 * g);
 #pragma unroll
             for (int q = 0; q < NT; ++q)
-                c[q][ob] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[q][0], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+                c[q][ob] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[q][0], f32x4{bv.x, bv.y, bv.z, bv.w}, 0, 0, 0);
         }
         uint32_t hp[NT][8][2];
-        const float *bias[3] = {L.b1, L.b2, L.b3};
 #pragma unroll
         for (int layer = 0; layer < 3; ++layer) {
-            if (layer > 0) layer_hidden_nt<NT>(layer == 1 ? L.w2 : L.w3, b, c, lane);
+            if (layer > 0) layer_hidden_nt<NT>(layer == 1 ? L.w2 : L.w3, layer == 1 ? L.b2 : L.b3, b, c, lane);
 #pragma unroll
             for (int q = 0; q < NT; ++q) {
 #pragma unroll
                 for (int ob = 0; ob < 8; ++ob) {
-                    const float4 bv = *reinterpret_cast<const float4 *>(bias[layer] + 16 * ob + 4 * g);
-                    hp[q][ob][0] = bf16_pack(fmaxf(c[q][ob][0] + bv.x, 0.f), fmaxf(c[q][ob][1] + bv.y, 0.f));
-                    hp[q][ob][1] = bf16_pack(fmaxf(c[q][ob][2] + bv.z, 0.f), fmaxf(c[q][ob][3] + bv.w, 0.f));
+                    hp[q][ob][0] = bf16_pack(relu(c[q][ob][0]), relu(c[q][ob][1]));
+                    hp[q][ob][1] = bf16_pack(relu(c[q][ob][2]), relu(c[q][ob][3]));
                 }
 #pragma unroll
                 for (int kb = 0; kb < 4; ++kb)
