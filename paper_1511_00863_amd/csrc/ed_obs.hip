@@ -152,7 +152,9 @@ __device__ __forceinline__ uint64_t between_mask(int i, int j) {
     return ((1ull << hi) - 1ull) & ~((2ull << lo) - 1ull);
 }
 
-template <typename T>
+// NSM: a compile-time bound on the sites (16 or 32), so a 16-site lattice
+// keeps half the accumulators and loop trips
+template <typename T, int NSM>
 __global__ __launch_bounds__(256) void k_sflip(const T *__restrict__ psi, const uint64_t *__restrict__ st_up,
                                                const uint64_t *__restrict__ st_dn, int Ddn, int ns, int i,
                                                double *__restrict__ part) {
@@ -176,19 +178,19 @@ __global__ __launch_bounds__(256) void k_sflip(const T *__restrict__ psi, const 
         sgn_up[j] = (__popcll(su & between_mask(i, j)) & 1) ? -1.0 : 1.0;
     }
     __syncthreads();
-    double acc[kFlipSlots];
+    double acc[NSM + 1];   // row i of C for j < NSM, then |psi|^2
 #pragma unroll
-    for (int j = 0; j < kFlipSlots; ++j) acc[j] = 0.0;
+    for (int j = 0; j <= NSM; ++j) acc[j] = 0.0;
     const T *row = psi + (int64_t)r * Ddn;
     const bool up_hole = !(su & bi);
     for (int c = threadIdx.x; c < Ddn; c += blockDim.x) {
         const double x = (double)row[c];
         const uint64_t sd = st_dn[c];
-        acc[kObsMaxSites] += x * x;
+        acc[NSM] += x * x;
         if (up_hole) {
             if (sd & bi) {
 #pragma unroll
-                for (int j = 0; j < kObsMaxSites; ++j) {
+                for (int j = 0; j < NSM; ++j) {
                     if (row2[j] >= 0 && !((sd >> j) & 1ull)) {
                         const int64_t c2 = colex_rank_lds(sd ^ bi ^ (1ull << j), binom);
                         const double sd_sign = (__popcll(sd & between_mask(i, j)) & 1) ? -1.0 : 1.0;
@@ -198,14 +200,16 @@ __global__ __launch_bounds__(256) void k_sflip(const T *__restrict__ psi, const 
             }
         } else if (!(sd & bi)) {   // diagonal: n_i,up (1 - n_i,dn)
 #pragma unroll
-            for (int j = 0; j < kObsMaxSites; ++j)
+            for (int j = 0; j < NSM; ++j)
                 if (j == i) acc[j] += x * x;
         }
     }
-    double tot[kFlipSlots];
-    block_sum<kFlipSlots>(acc, tot);
-    if (threadIdx.x == 0)
-        for (int j = 0; j < kFlipSlots; ++j) part[(int64_t)r * kFlipSlots + j] = tot[j];
+    double tot[NSM + 1];
+    block_sum<NSM + 1>(acc, tot);
+    if (threadIdx.x == 0) {
+        for (int j = 0; j < NSM; ++j) part[(int64_t)r * kFlipSlots + j] = tot[j];
+        part[(int64_t)r * kFlipSlots + kObsMaxSites] = tot[NSM];
+    }
 }
 
 // row i of C: sums over the up rows in a fixed order (thread t adds the rows
@@ -247,8 +251,12 @@ static int flip_impl(const ed_ham *h, int ns, const T *psi, char *ws, hipStream_
     double *part = reinterpret_cast<double *>(ws);
     double *c = reinterpret_cast<double *>(ws + al(8 * kFlipSlots * h->dim_up));
     for (int i = 0; i < ns; ++i) {
-        hipLaunchKernelGGL(k_sflip<T>, dim3((unsigned)h->dim_up), dim3(256), 0, s, psi, h->st_up, h->st_dn,
-                           (int)h->dim_dn, ns, i, part);
+        if (ns <= 16)
+            hipLaunchKernelGGL((k_sflip<T, 16>), dim3((unsigned)h->dim_up), dim3(256), 0, s, psi, h->st_up, h->st_dn,
+                               (int)h->dim_dn, ns, i, part);
+        else
+            hipLaunchKernelGGL((k_sflip<T, kObsMaxSites>), dim3((unsigned)h->dim_up), dim3(256), 0, s, psi, h->st_up,
+                               h->st_dn, (int)h->dim_dn, ns, i, part);
         ED_LAUNCHED("k_sflip");
         hipLaunchKernelGGL(k_sflip_final, dim3(1), dim3(kFinalThreads), 0, s, part, (int)h->dim_up, ns, i, c);
         ED_LAUNCHED("k_sflip_final");
