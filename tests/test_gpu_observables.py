@@ -97,6 +97,7 @@ FLIP_CASES = [
     ("ring8_4x4", 8, ring_bonds(8), 4, 4),
     ("t32_3x2", 6, torus_bonds(3, 2), 3, 2),
     ("ring6_0x3", 6, ring_bonds(6), 0, 3),
+    ("ring18_2x2", 18, ring_bonds(18), 2, 2),     # more than 16 sites: the 32-site kernel variant
 ]
 
 
