@@ -672,6 +672,17 @@ int ed_ground_energy_batch(const ed_batch_item *items, int32_t n, int32_t max_st
     p += al(8 * (int64_t)n * (max_steps + 1));
     double *stage = reinterpret_cast<double *>(p);
 
+    // The kernel takes the instances largest first: every phase then ends on
+    // the small instances' tiles.  order[k] is the item at position k.
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return plan.inst[x].n > plan.inst[y].n; });
+    {
+        std::vector<BInst> sorted(n);
+        for (int k = 0; k < n; ++k) sorted[k] = plan.inst[order[k]];
+        plan.inst.swap(sorted);
+    }
+
     int grid = 0;
     rc = batch_grid(&grid);
     if (rc) return rc;
@@ -737,14 +748,15 @@ int ed_ground_energy_batch(const ed_batch_item *items, int32_t n, int32_t max_st
         for (int k = 0; k < 6; ++k) phase_ms[k] = khz > 0 ? (double)gbh.phase[k] / (double)khz : -1.0;
     }
     int result = ED_OK;
-    for (int i = 0; i < n; ++i) {
-        const BInst &I = out[i];
+    for (int pos = 0; pos < n; ++pos) {
+        const int i = order[pos];
+        const BInst &I = out[pos];
         if (I.status == kBadStart) return set_error(ED_EINVAL, "ed_ground_energy_batch: item %d has a zero start", i);
         const int k = I.j;
         steps[i] = k;
         status[i] = I.status == kConverged ? ED_OK : (I.status == ED_BREAKDOWN ? ED_BREAKDOWN : ED_NOT_CONVERGED);
         if (status[i] == ED_NOT_CONVERGED) result = ED_NOT_CONVERGED;
-        const double *a = staged.data() + (size_t)i * sst, *b = a + max_steps;
+        const double *a = staged.data() + (size_t)pos * sst, *b = a + max_steps;
         e0[i] = k > 0 ? tridiag_lowest(a, b + 1, k) : NAN;
         if (e0_device) e0_device[i] = k > 0 ? a[2 * max_steps + 1] : NAN;
     }
