@@ -261,9 +261,10 @@ __global__ __launch_bounds__(kBatchBlock, 3) void k_batch(BInst *__restrict__ in
         __syncthreads();
         if (!s_any) break;
 
-        // ---- up part (Eq. 4): T = t * up(F_j) into the next buffer.  Queue
-        // q = blockIdx % 8 holds the tiles of the stripes s = q (mod 8) of
-        // every live instance (so a stripe's tiles share one XCD's L2 when
+        // ---- up part (Eq. 4): T = t * up(F_j) into the next buffer.  The
+        // stripes of the live instances are numbered on from one instance to
+        // the next, and queue q = blockIdx % 8 holds the tiles of the stripes
+        // numbered q (mod 8) (so a stripe's tiles share one XCD's L2 when
         // workgroups are placed round-robin over the XCDs); its workgroups
         // take tiles in order from an atomic counter, which keeps the tiles
         // in flight within a narrow window of stripes, as in-order hardware
@@ -277,19 +278,26 @@ __global__ __launch_bounds__(kBatchBlock, 3) void k_batch(BInst *__restrict__ in
             __syncthreads();
             int64_t qi = s_tile;
             __syncthreads();
+            // stripes are numbered on across the live instances, and stripe
+            // number g goes to queue g mod 8: every queue gets the same share
+            // (to one stripe) and the queues move through the instances together
             int ci = 0;
             int64_t cb = 0;
+            int gcum = 0;      // stripes of the live instances before inst[ci]
+            int off = xq;      // first stripe of inst[ci] that falls to this queue
             while (true) {
                 bool found = false;
                 while (ci < ni) {
                     const BInst &I = inst[ci];
-                    const int cnt = b_live(I, max_steps) && xq < I.n_stripes
-                                        ? I.n_rc * ((I.n_stripes - xq + 7) >> 3) : 0;
+                    const bool live = b_live(I, max_steps);
+                    off = (xq - (gcum & 7) + 8) & 7;
+                    const int cnt = live && off < I.n_stripes ? I.n_rc * ((I.n_stripes - off + 7) >> 3) : 0;
                     if (qi < cb + cnt) {
                         found = true;
                         break;
                     }
                     cb += cnt;
+                    if (live) gcum += I.n_stripes;
                     ++ci;
                 }
                 if (!found) break;
@@ -298,7 +306,7 @@ __global__ __launch_bounds__(kBatchBlock, 3) void k_batch(BInst *__restrict__ in
                 const BInst &I = inst[ci];
                 const int local = (int)(qi - cb);
                 const int sl = local / I.n_rc, rci = local - sl * I.n_rc;
-                const int s = sl * 8 + xq;
+                const int s = sl * 8 + off;
                 const float *x = (const float *)I.vec[I.rot];
                 float *out = (float *)I.vec[(I.rot + 1) % 3];
                 const uint16_t *tab = (const uint16_t *)I.tab_up;
