@@ -82,44 +82,39 @@ __global__ __launch_bounds__(256) void k_obs_colsum(double *__restrict__ colpart
     colpart[c] = s;
 }
 
-// one workgroup: the (2 ns)^2 entries of G, normalised by sum_x |psi_x|^2
-__global__ __launch_bounds__(1024) void k_obs_final(const double *__restrict__ rowsum,
-                                                    const double *__restrict__ trow,
-                                                    const double *__restrict__ colsum,
-                                                    const uint64_t *__restrict__ st_up,
-                                                    const uint64_t *__restrict__ st_dn, int Dup, int Ddn, int ns,
-                                                    double *__restrict__ g) {
-    __shared__ double s_norm;
-    double p[1] = {0.0};
-    for (int r = threadIdx.x; r < Dup; r += blockDim.x) p[0] += rowsum[r];
-    double tot[1];
-    block_sum<1>(p, tot);
-    if (threadIdx.x == 0) s_norm = tot[0];
-    __syncthreads();
-    const double inv = s_norm > 0.0 ? 1.0 / s_norm : 0.0;
+// one workgroup per entry e = (a, b) of G: its sum and the norm sum_x |psi_x|^2,
+// each over the rows (or columns) strided by thread and then in the fixed
+// order of block_sum
+__global__ __launch_bounds__(256) void k_obs_final(const double *__restrict__ rowsum,
+                                                   const double *__restrict__ trow,
+                                                   const double *__restrict__ colsum,
+                                                   const uint64_t *__restrict__ st_up,
+                                                   const uint64_t *__restrict__ st_dn, int Dup, int Ddn, int ns,
+                                                   double *__restrict__ g) {
     const int n2 = 2 * ns;
-    for (int e = threadIdx.x; e < n2 * n2; e += blockDim.x) {
-        const int a = e / n2, b = e - a * n2;
-        double s = 0.0;
-        if (a < ns && b < ns) {          // up-up: sum_r rowsum[r] n_a n_b
-            const uint64_t m = (1ull << a) | (1ull << b);
-            for (int r = 0; r < Dup; ++r)
-                if ((st_up[r] & m) == m) s += rowsum[r];
-        } else if (a < ns) {             // up-down
-            const int j = b - ns;
-            for (int r = 0; r < Dup; ++r)
-                if ((st_up[r] >> a) & 1ull) s += trow[(int64_t)r * ns + j];
-        } else if (b < ns) {             // down-up: the transpose
-            const int j = a - ns;
-            for (int r = 0; r < Dup; ++r)
-                if ((st_up[r] >> b) & 1ull) s += trow[(int64_t)r * ns + j];
-        } else {                         // down-down: sum_c colsum[c] n_a n_b
-            const uint64_t m = (1ull << (a - ns)) | (1ull << (b - ns));
-            for (int c = 0; c < Ddn; ++c)
-                if ((st_dn[c] & m) == m) s += colsum[c];
-        }
-        g[e] = s * inv;
+    const int e = blockIdx.x, a = e / n2, b = e - a * n2;
+    double p[2] = {0.0, 0.0};   // norm, entry
+    for (int r = threadIdx.x; r < Dup; r += blockDim.x) p[0] += rowsum[r];
+    if (a < ns && b < ns) {          // up-up: sum_r rowsum[r] n_a n_b
+        const uint64_t m = (1ull << a) | (1ull << b);
+        for (int r = threadIdx.x; r < Dup; r += blockDim.x)
+            if ((st_up[r] & m) == m) p[1] += rowsum[r];
+    } else if (a < ns) {             // up-down
+        const int j = b - ns;
+        for (int r = threadIdx.x; r < Dup; r += blockDim.x)
+            if ((st_up[r] >> a) & 1ull) p[1] += trow[(int64_t)r * ns + j];
+    } else if (b < ns) {             // down-up: the transpose
+        const int j = a - ns;
+        for (int r = threadIdx.x; r < Dup; r += blockDim.x)
+            if ((st_up[r] >> b) & 1ull) p[1] += trow[(int64_t)r * ns + j];
+    } else {                         // down-down: sum_c colsum[c] n_a n_b
+        const uint64_t m = (1ull << (a - ns)) | (1ull << (b - ns));
+        for (int c = threadIdx.x; c < Ddn; c += blockDim.x)
+            if ((st_dn[c] & m) == m) p[1] += colsum[c];
     }
+    double tot[2];
+    block_sum<2>(p, tot);
+    if (threadIdx.x == 0) g[e] = tot[0] > 0.0 ? tot[1] / tot[0] : 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -424,7 +419,7 @@ static int obs_impl(const ed_ham *h, int ns, const T *psi, char *ws, hipStream_t
     ED_LAUNCHED("k_obs_cols");
     hipLaunchKernelGGL(k_obs_colsum, dim3((Ddn + 255) / 256), dim3(256), 0, s, colpart, nchunk, Ddn);
     ED_LAUNCHED("k_obs_colsum");
-    hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(1024), 0, s, rowsum, trow, colpart, h->st_up, h->st_dn, Dup, Ddn,
+    hipLaunchKernelGGL(k_obs_final, dim3(4 * ns * ns), dim3(256), 0, s, rowsum, trow, colpart, h->st_up, h->st_dn, Dup, Ddn,
                        ns, g);
     ED_LAUNCHED("k_obs_final");
     ED_HIP(hipMemcpyAsync(g_host, g, sizeof(double) * 4 * ns * ns, hipMemcpyDeviceToHost, s));
