@@ -45,20 +45,20 @@ __device__ __forceinline__ uint16_t bf16_bits(float f) {
     return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
 }
 __device__ __forceinline__ float bf16_val(uint16_t b) { return __builtin_bit_cast(float, (uint32_t)b << 16); }
+typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2;
 // two floats rounded to bfloat16 (nearest even, as bf16_bits for finite values) in one register, lo first:
 // the hardware conversion of gfx950
-typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2;
-// max(x, 0) in one integer max on the bits: a negative float (sign bit set) is a negative integer, a
-// non-negative one keeps its bits.  fmaxf of a raw accumulator value would canonicalise it first (two
-// instructions).
-__device__ __forceinline__ float relu(float x) {
-    return __builtin_bit_cast(float, max(__builtin_bit_cast(int, x), 0));
-}
 __device__ __forceinline__ uint32_t bf16_pack(float lo, float hi) {
     bf16x2 v;
     v[0] = (__bf16)lo;
     v[1] = (__bf16)hi;
     return __builtin_bit_cast(uint32_t, v);
+}
+// max(x, 0) in one integer max on the bits: a negative float (sign bit set) is a negative integer, a
+// non-negative one keeps its bits.  fmaxf of a raw accumulator value would canonicalise it first (two
+// instructions).
+__device__ __forceinline__ float relu(float x) {
+    return __builtin_bit_cast(float, max(__builtin_bit_cast(int, x), 0));
 }
 __device__ __forceinline__ __bf16 as_bf(uint16_t b) { return __builtin_bit_cast(__bf16, b); }
 
