@@ -147,12 +147,41 @@ __device__ __forceinline__ uint64_t between_mask(int i, int j) {
     return ((1ull << hi) - 1ull) & ~((2ull << lo) - 1ull);
 }
 
+// The down half of the flip for site i: tgt[j * Ddn + c] = (rank << 1) | sign
+// of the state c with the down particle moved i -> j (the sign of the occupied
+// sites strictly between), or all ones where column c has no particle at i or
+// one at j.  It depends on (c, j) only, so every row of psi shares it.
+constexpr uint32_t kNoFlip = 0xFFFFFFFFu;
+
+__global__ __launch_bounds__(256) void k_sflip_targets(const uint64_t *__restrict__ st_dn, int Ddn, int ns, int i,
+                                                       uint32_t *__restrict__ tgt) {
+    __shared__ int64_t binom[kObsMaxSites][kObsMaxSites + 1];   // C(n, k), n < 32
+    for (int e = threadIdx.x; e < kObsMaxSites * (kObsMaxSites + 1); e += blockDim.x) {
+        const int n = e / (kObsMaxSites + 1), k = e - n * (kObsMaxSites + 1);
+        int64_t c = k > n ? 0 : 1;
+        for (int m = 1; m <= k && k <= n; ++m) c = c * (n - k + m) / m;   // exact at every step
+        binom[n][k] = c;
+    }
+    __syncthreads();
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= Ddn) return;
+    const uint64_t sd = st_dn[c], bi = 1ull << i;
+    for (int j = 0; j < ns; ++j) {
+        uint32_t e = kNoFlip;
+        if ((sd & bi) && !((sd >> j) & 1ull)) {
+            const int64_t c2 = colex_rank_lds(sd ^ bi ^ (1ull << j), binom);
+            e = ((uint32_t)c2 << 1) | (uint32_t)(__popcll(sd & between_mask(i, j)) & 1);
+        }
+        tgt[(int64_t)j * Ddn + c] = e;
+    }
+}
+
 // NSM: a compile-time bound on the sites (16 or 32), so a 16-site lattice
 // keeps half the accumulators and loop trips
 template <typename T, int NSM>
 __global__ __launch_bounds__(256) void k_sflip(const T *__restrict__ psi, const uint64_t *__restrict__ st_up,
                                                const uint64_t *__restrict__ st_dn, int Ddn, int ns, int i,
-                                               double *__restrict__ part) {
+                                               const uint32_t *__restrict__ tgt, double *__restrict__ part) {
     __shared__ int64_t binom[kObsMaxSites][kObsMaxSites + 1];   // C(n, k), n < 32
     __shared__ int64_t row2[kObsMaxSites];                      // target up row of the hop j -> i, or -1
     __shared__ double sgn_up[kObsMaxSites];
@@ -186,10 +215,13 @@ __global__ __launch_bounds__(256) void k_sflip(const T *__restrict__ psi, const 
             if (sd & bi) {
 #pragma unroll
                 for (int j = 0; j < NSM; ++j) {
-                    if (row2[j] >= 0 && !((sd >> j) & 1ull)) {
-                        const int64_t c2 = colex_rank_lds(sd ^ bi ^ (1ull << j), binom);
-                        const double sd_sign = (__popcll(sd & between_mask(i, j)) & 1) ? -1.0 : 1.0;
-                        acc[j] -= sgn_up[j] * sd_sign * x * (double)psi[row2[j] * Ddn + c2];
+                    if (row2[j] >= 0) {
+                        const uint32_t e = tgt[(int64_t)j * Ddn + c];
+                        if (e != kNoFlip) {
+                            const int64_t c2 = (int64_t)(e >> 1);
+                            const double sd_sign = (e & 1u) ? -1.0 : 1.0;
+                            acc[j] -= sgn_up[j] * sd_sign * x * (double)psi[row2[j] * Ddn + c2];
+                        }
                     }
                 }
             }
@@ -237,7 +269,7 @@ __global__ __launch_bounds__(kFinalThreads) void k_sflip_final(const double *__r
 
 static int64_t flip_ws_bytes(const ed_ham *h) {
     auto al = [](int64_t b) { return (b + 255) & ~int64_t(255); };
-    return al(8 * kFlipSlots * h->dim_up) + al(8 * kObsMaxSites * kObsMaxSites);
+    return al(8 * kFlipSlots * h->dim_up) + al(8 * kObsMaxSites * kObsMaxSites) + al(4 * kObsMaxSites * h->dim_dn);
 }
 
 template <typename T>
@@ -245,13 +277,18 @@ static int flip_impl(const ed_ham *h, int ns, const T *psi, char *ws, hipStream_
     auto al = [](int64_t b) { return (b + 255) & ~int64_t(255); };
     double *part = reinterpret_cast<double *>(ws);
     double *c = reinterpret_cast<double *>(ws + al(8 * kFlipSlots * h->dim_up));
+    uint32_t *tgt = reinterpret_cast<uint32_t *>(ws + al(8 * kFlipSlots * h->dim_up) + al(8 * kObsMaxSites * kObsMaxSites));
+    const int Ddn = (int)h->dim_dn;
     for (int i = 0; i < ns; ++i) {
+        hipLaunchKernelGGL(k_sflip_targets, dim3((unsigned)((Ddn + 255) / 256)), dim3(256), 0, s, h->st_dn, Ddn, ns, i,
+                           tgt);
+        ED_LAUNCHED("k_sflip_targets");
         if (ns <= 16)
             hipLaunchKernelGGL((k_sflip<T, 16>), dim3((unsigned)h->dim_up), dim3(256), 0, s, psi, h->st_up, h->st_dn,
-                               (int)h->dim_dn, ns, i, part);
+                               Ddn, ns, i, (const uint32_t *)tgt, part);
         else
             hipLaunchKernelGGL((k_sflip<T, kObsMaxSites>), dim3((unsigned)h->dim_up), dim3(256), 0, s, psi, h->st_up,
-                               h->st_dn, (int)h->dim_dn, ns, i, part);
+                               h->st_dn, Ddn, ns, i, (const uint32_t *)tgt, part);
         ED_LAUNCHED("k_sflip");
         hipLaunchKernelGGL(k_sflip_final, dim3(1), dim3(kFinalThreads), 0, s, part, (int)h->dim_up, ns, i, c);
         ED_LAUNCHED("k_sflip_final");
