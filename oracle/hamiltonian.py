@@ -18,11 +18,16 @@ from .basis import basis_states
 from .hopping import hopping_matrix, hopping_matrix_complex
 
 
+# number of set bits of every 16-bit value, counted one by one
+_POP16 = np.array([bin(i).count("1") for i in range(1 << 16)], dtype=np.int64)
+
+
 def popcount_u64(a: np.ndarray) -> np.ndarray:
+    """Set bits of each 64-bit word: the sum over its four 16-bit quarters."""
     a = np.asarray(a, dtype=np.uint64)
     out = np.zeros(a.shape, dtype=np.int64)
-    for k in range(64):
-        out += ((a >> np.uint64(k)) & np.uint64(1)).astype(np.int64)
+    for k in range(4):
+        out += _POP16[((a >> np.uint64(16 * k)) & np.uint64(0xFFFF)).astype(np.int64)]
     return out
 
 

@@ -96,3 +96,12 @@ def test_u0_band_sum_complete_graph(n, nu, nd):
     m = Model(n, complete_bonds(n), nu, nd, t, 0.0)
     band = lambda N: 0.0 if N == 0 else -t * (n - 1) + (N - 1) * t
     assert abs(_e0_dense(m) - (band(nu) + band(nd))) < 1e-10
+
+
+def test_popcount_matches_bit_by_bit_count():
+    from oracle.hamiltonian import popcount_u64
+    rng = np.random.default_rng(3)
+    a = rng.integers(0, 2 ** 63, 2000, dtype=np.uint64) * np.uint64(2) + rng.integers(0, 2, 2000, dtype=np.uint64)
+    a = np.concatenate([a, np.array([0, 1, 2 ** 64 - 1, 2 ** 63, 0xFFFF0000FFFF0000], dtype=np.uint64)])
+    ref = np.array([bin(int(v)).count("1") for v in a])
+    assert np.array_equal(popcount_u64(a), ref)

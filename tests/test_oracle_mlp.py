@@ -105,3 +105,37 @@ def test_bf16_forward_close_to_exact():
     a, _ = mlp.forward(ws, bs, x, bf16=False)
     b, _ = mlp.forward(ws, bs, x, bf16=True)
     assert np.linalg.norm(a - b) <= 3e-2 * np.linalg.norm(a)
+
+
+def test_bf16_hand_computed_two_layer():
+    """A 2-2-1 network whose every bf16 rounding is worked out by hand (bf16 keeps 8 significant bits,
+    round to nearest, ties to even).  A rounding left out, or applied at a different place, moves the
+    output or a gradient away from these exact binary fractions.
+
+    Forward: z1 = r(x) r(W1)^T + b1, h1 = relu(z1), out = r(h1) r(W2)^T + b2.
+      r(1 + 2^-8 + 2^-12) = 1 + 2^-7 (above the half-way point), r(0.75) = 0.75,
+      r(0.5 + 2^-10) = 0.5 (a quarter spacing), r(-(1 + 3 2^-8)) = -(1 + 2^-6) (a tie: to the even 1 + 2^-6)
+      z1 = [1 + 2^-7 - 0.75 + 7 2^-11, 0.5 + 1 + 2^-6 + 0.2] = [535 2^-11, 1.715625]
+      r(535 2^-11 = 1000010111b 2^-11) = 536 2^-11 = 0.26171875 (above half), r(1.715625) = 220 2^-7 = 1.71875
+      r(0.5 + 3 2^-10) = 0.5 + 2^-8, r(-(0.25 + 2^-12)) = -0.25
+      out = 0.26171875 (0.5 + 2^-8) - 1.71875 / 4 + 0.1 = -0.1978057861328125 (+ the rounding of 0.1)
+    Backward, target 0.15: g2 = 2 (out - 0.15) = -0.695611572265625, r(g2) = -178 2^-8 = -0.6953125
+      dW2 = r(g2) r(h1) = [-0.181976318359375, -1.195068359375], db2 = g2
+      g1 = r(g2) r(W2) = [-0.350372314453125, 0.173828125] (both z1 > 0)
+      r(g1) = [-179 2^-9, 178 2^-10] = [-0.349609375, 0.173828125]
+      dW1 = r(g1)^T r(x) = [[-0.349609375, 0.349609375], [0.173828125, -0.173828125]], db1 = g1
+    """
+    x = np.array([[1.0, -1.0]])
+    ws = [np.array([[1 + 2 ** -8 + 2 ** -12, 0.75], [0.5 + 2 ** -10, -(1 + 3 * 2 ** -8)]]),
+          np.array([[0.5 + 3 * 2 ** -10, -(0.25 + 2 ** -12)]])]
+    bs = [np.array([7 * 2 ** -11, 0.2]), np.array([0.1])]
+    out, cache = mlp.forward(ws, bs, x, bf16=True)
+    assert abs(out[0] - (-0.1978057861328125)) <= 1e-15
+    gws, gbs = mlp.backward(ws, cache, out, np.array([0.15]), bf16=True)
+    assert np.allclose(gws[1], [[-0.181976318359375, -1.195068359375]], rtol=0, atol=1e-15)
+    assert abs(gbs[1][0] - (-0.695611572265625)) <= 1e-15
+    assert np.allclose(gws[0], [[-0.349609375, 0.349609375], [0.173828125, -0.173828125]], rtol=0, atol=1e-15)
+    assert np.allclose(gbs[0], [-0.350372314453125, 0.173828125], rtol=0, atol=1e-15)
+    # the same network without rounding gives other values (the pin can fail)
+    out_x, _ = mlp.forward(ws, bs, x, bf16=False)
+    assert abs(out_x[0] - out[0]) > 1e-4
