@@ -9,6 +9,7 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -23,7 +24,7 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-I", os.path.join(ROOT, "include")]
 
 HOST_SOURCES = ["ed_host.cpp"]
-DEVICE_SOURCES = ["ed_device.hip", "ed_batch.hip", "ed_mlp.hip", "ed_obs.hip", "ed_order.hip"]
+DEVICE_SOURCES = ["ed_device.hip", "ed_fused.hip", "ed_batch.hip", "ed_mlp.hip", "ed_obs.hip", "ed_order.hip"]
 
 
 def _run(cmd):
@@ -38,19 +39,22 @@ def _run(cmd):
 def build(verbose: bool = False) -> str:
     """Compile every source and link the library; always rebuilds.  Returns its path."""
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
+    cmds = []
     for src in HOST_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        out = _run(["g++"] + CXX_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj])
-        if verbose and out:
-            print(out)
-        objs.append(obj)
+        cmds.append((obj, ["g++"] + CXX_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]))
     for src in DEVICE_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        out = _run([HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj])
-        if verbose and out:
-            print(out)
-        objs.append(obj)
+        cmds.append((obj, [HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]))
+    # the sources compile independently: at most JOBS at a time (default 4)
+    jobs = max(1, int(os.environ.get("ED_BUILD_JOBS", "4")))
+    with ThreadPoolExecutor(max_workers=jobs) as pool:
+        outs = list(pool.map(lambda c: _run(c[1]), cmds))
+    if verbose:
+        for out in outs:
+            if out:
+                print(out)
+    objs = [obj for obj, _ in cmds]
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs)
     shutil.move(tmp, LIB)

@@ -17,7 +17,7 @@
 #include <vector>
 
 #include "../../include/ed.h"
-#include "ed_common.cuh"
+#include "ed_common.h"
 #include "ed_internal.h"
 #include "ed_launch.h"
 
@@ -726,12 +726,15 @@ int ed_ground_energy_batch(const ed_batch_item *items, int32_t n, int32_t max_st
             ok = false;
         }
         (void)hipGetLastError();   // a refused capture leaves no sticky error
-        if (!graphed && cs) (void)hipStreamSynchronize(cs);
+        // The graph's cooperative kernel may still be running: the executable
+        // graph, the graph, the event and the capture stream are released only
+        // after the capture stream (where the graph was launched) has drained.
+        const hipError_t se = cs ? hipStreamSynchronize(cs) : hipSuccess;
         if (ge) (void)hipGraphExecDestroy(ge);
         if (g) (void)hipGraphDestroy(g);
-        if (graphed) ED_HIP(hipStreamSynchronize(user));
         if (ev) (void)hipEventDestroy(ev);
         if (cs) (void)hipStreamDestroy(cs);
+        if (graphed) ED_HIP(se);
     }
     if (!graphed) {
         ED_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_batch), dim3(grid), dim3(kBatchBlock),

@@ -24,7 +24,7 @@
 #include <vector>
 
 #include "../../include/ed.h"
-#include "ed_common.cuh"
+#include "ed_common.h"
 #include "ed_internal.h"
 #include "ed_launch.h"
 

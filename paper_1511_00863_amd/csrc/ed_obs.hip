@@ -16,7 +16,7 @@
 #include <cstdint>
 
 #include "../../include/ed.h"
-#include "ed_common.cuh"
+#include "ed_common.h"
 #include "ed_internal.h"
 #include "ed_launch.h"
 
