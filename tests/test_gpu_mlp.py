@@ -39,9 +39,11 @@ def test_forward_parity(setup):
     announce("mlp forward n=%d" % S["n"])
     out = S["net"].forward(S["up"].dev_states, S["dn"].dev_states, S["idx"]).double().cpu().numpy()
     ref, _ = omlp.forward(S["ws"], S["bs"], S["x"], bf16=True)
-    assert _rel(out, ref) <= 1e-2
+    # measured 1.1e-4: float32 against float64 accumulation, and the bf16 rounding of an activation
+    # flipping where the two fall on either side of a rounding point
+    assert _rel(out, ref) <= 3.5e-4
     exact, _ = omlp.forward(S["ws"], S["bs"], S["x"], bf16=False)
-    assert _rel(out, exact) <= 3e-2
+    assert _rel(out, exact) <= 1e-2     # measured 2.5e-3: bf16 operands against exact ones
 
 
 def test_backward_parity(setup):
@@ -54,11 +56,11 @@ def test_backward_parity(setup):
     gw, gb = dmlp.unflatten(net.grad.double().cpu().numpy())
     ref_out, cache = omlp.forward(S["ws"], S["bs"], S["x"], bf16=True)
     rw, rb = omlp.backward(S["ws"], cache, ref_out, S["tgt"].astype(np.float32).astype(np.float64), bf16=True)
-    for l in range(4):
-        assert _rel(gw[l], rw[l]) <= 1e-2, ("W", l, _rel(gw[l], rw[l]))
-        assert _rel(gb[l], rb[l]) <= 1e-2, ("b", l, _rel(gb[l], rb[l]))
+    for l in range(4):   # measured at most 6.4e-5 (weights) and 3.2e-5 (biases)
+        assert _rel(gw[l], rw[l]) <= 2e-4, ("W", l, _rel(gw[l], rw[l]))
+        assert _rel(gb[l], rb[l]) <= 1e-4, ("b", l, _rel(gb[l], rb[l]))
     loss = float(net.loss.cpu()[0])
-    assert abs(loss - omlp.loss(ref_out, S["tgt"])) <= 1e-2 * omlp.loss(ref_out, S["tgt"])
+    assert abs(loss - omlp.loss(ref_out, S["tgt"])) <= 5e-5 * omlp.loss(ref_out, S["tgt"])   # measured 1.6e-5
 
 
 def test_adam_parity(setup):
@@ -88,7 +90,7 @@ def test_start_vector_over_all_states(setup):
     ks = rng.integers(0, h.dim, 700)
     x = omlp.features(S["up"].states[ks // h.dim_dn], S["dn"].states[ks % h.dim_dn])
     ref, _ = omlp.forward(S["ws"], S["bs"], x, bf16=True)
-    assert _rel(psi[ks], ref) <= 1e-2
+    assert _rel(psi[ks], ref) <= 7.5e-5     # measured 2.5e-5
     h64 = ed.Hamiltonian(S["up"], S["dn"], 1.0, 2.0, "f64")
     psi64 = S["net"].start_vector(h64).cpu().numpy()
     assert np.array_equal(psi64.astype(np.float32), psi.astype(np.float32))

@@ -13,7 +13,10 @@ pytestmark = pytest.mark.gpu
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("ns,bonds,nu,nd", [(16, torus_bonds(4, 4), 4, 4), (16, torus_bonds(4, 4), 3, 5),
-                                            (8, ring_bonds(8), 4, 4), (12, complete_bonds(12), 6, 6)])
+                                            (8, ring_bonds(8), 4, 4), (12, complete_bonds(12), 6, 6),
+                                            # up tables of 3 chunks (width 20) and of 4 chunks (width 32,
+                                            # the benchmark's shape)
+                                            (16, torus_bonds(4, 4), 5, 5), (16, torus_bonds(4, 4), 8, 8)])
 def test_every_tile_gives_identical_hv(ns, bonds, nu, nd, dtype):
     h = ham(ns, bonds, nu, nd, 1.0, 3.0, dtype)
     _, x = seeded_start(21, h.dim, dtype)
