@@ -343,6 +343,21 @@ int ed_ground_energy(const ed_ham *h, ed_lanczos *st, const void *f1, double tol
                      int32_t check_every, void *ws, void *stream, double *e0, int32_t *steps,
                      double *a_host, double *b_host);
 
+/* ed_ground_energy for callers that cannot allocate (code under stream
+ * capture, serving loops, harnesses that forbid hipMalloc): the same run and
+ * the same results, with no workspace argument, no captured graph and no
+ * stream of its own.  The run's workspace (header, partial sums, queue
+ * counters) is a 4 MiB array in device memory that the library holds on
+ * every GPU it runs on until the process ends; runs needing more than that
+ * (ed_workspace_size above 4 MiB: roughly dim_up + 2048 above 45,000 at
+ * max_steps 2048), or max_steps above 2048, return ED_ECAPACITY and launch
+ * nothing.  Steps are launched on `stream` `check_every` at a time.  Every
+ * call on a GPU shares that GPU's array: calls that overlap on one GPU race,
+ * whatever their streams.  Other arguments, results and errors as
+ * ed_ground_energy. */
+int ed_ground_energy_noalloc(const ed_ham *h, ed_lanczos *st, const void *f1, double tol, int32_t check_every,
+                             void *stream, double *e0, int32_t *steps, double *a_host, double *b_host);
+
 /* Ground-state vector by two passes: pass 1 runs m steps from f1 (as
  * ed_ground_energy with tol <= 0), the lowest eigenvector y of T_m is found on
  * the host, pass 2 replays the identical steps and accumulates

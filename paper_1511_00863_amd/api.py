@@ -562,6 +562,20 @@ class LanczosRun:
         k = steps.value
         return {"e0": e0.value, "steps": k, "status": rc, "a": a[:k], "b": b[:k + 1]}
 
+    def ground_energy_noalloc(self, f1, tol=0.0, check_every=10, stream=None):
+        """ed_ground_energy_noalloc: the run of ground_energy on the library's device scratch, no workspace."""
+        f1 = self.ham._vec(f1)
+        e0, steps = c_double(0), c_int32(0)
+        a = np.zeros(self.max_steps)
+        b = np.zeros(self.max_steps + 1)
+        if f1.data_ptr() == self.st.f_cur:
+            raise ValueError("f1 must not be the run's current vector")
+        rc = check(lib().ed_ground_energy_noalloc(byref(self._h), byref(self.st), _dptr(f1), float(tol),
+                                                  int(check_every), _stream(stream), byref(e0), byref(steps),
+                                                  _ptr(a, c_double), _ptr(b, c_double)))
+        k = steps.value
+        return {"e0": e0.value, "steps": k, "status": rc, "a": a[:k], "b": b[:k + 1]}
+
     def ground_state(self, f1, m, gauge_index=-1, stream=None):
         f1 = self.ham._vec(f1)
         v = self.ham.empty_vec()

@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 #include <vector>
@@ -1101,6 +1102,34 @@ static int tune_impl(const ed_ham *h, const T *x, T *y, const WsLayout &w, int r
     return ED_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Device scratch of the run that allocates nothing (ed_ground_energy_noalloc):
+// the workspace of a Lanczos run (header, partial sums, queue counters) in a
+// file-scope array of every GPU the library runs on, held until the process
+// ends.  Host code never passes the array's name to a kernel (on the host it
+// only stands for the symbol): it takes the array's address on each device
+// once, by hipGetSymbolAddress with that device current, and uses that.
+constexpr int64_t kScratchBytes = 4 << 20;
+constexpr int kScratchDevices = 64;
+constexpr int kNoallocMaxSteps = 2048;   // coefficients held on the host stack
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static std::atomic<void *> scratch_addr[kScratchDevices];
+
+static int scratch_on_current_device(void **out) {
+    int dev = 0;
+    ED_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kScratchDevices)
+        return set_error(ED_EINVAL, "device scratch: device %d beyond the %d the library tracks", dev, kScratchDevices);
+    void *p = scratch_addr[dev].load();
+    if (!p) {
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_check(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+        scratch_addr[dev].store(p);
+    }
+    *out = p;
+    return ED_OK;
+}
+
 }  // namespace ed
 
 using namespace ed;
@@ -1339,6 +1368,78 @@ int ed_ground_energy(const ed_ham *h, ed_lanczos *st, const void *f1, double tol
     if (b_host) std::copy(b.begin(), b.begin() + stop_at + 1, b_host);
     rc = ss.close();
     if (rc) return rc;
+    return result;
+}
+
+int ed_ground_energy_noalloc(const ed_ham *h, ed_lanczos *st, const void *f1, double tol, int32_t check_every,
+                             void *stream, double *e0, int32_t *steps, double *a_host, double *b_host) {
+    clear_error();
+    void *ws = nullptr;
+    int rc = scratch_on_current_device(&ws);
+    if (rc) return rc;
+    rc = check_lanczos(h, st, ws, "ed_ground_energy_noalloc");
+    if (rc) return rc;
+    if (!e0 || !steps) return set_error(ED_EINVAL, "ed_ground_energy_noalloc: e0/steps are NULL");
+    if (!f1 || f1 == st->f_cur)
+        return set_error(ED_EINVAL, "ed_ground_energy_noalloc: f1 must be a buffer other than f_cur");
+    const int max_steps = st->max_steps;
+    if (max_steps > kNoallocMaxSteps)
+        return set_error(ED_ECAPACITY, "ed_ground_energy_noalloc: max_steps %d above %d", max_steps, kNoallocMaxSteps);
+    if (ws_bytes(h, max_steps) > kScratchBytes)
+        return set_error(ED_ECAPACITY, "ed_ground_energy_noalloc: the run needs %lld bytes of scratch, above %lld",
+                         (long long)ws_bytes(h, max_steps), (long long)kScratchBytes);
+    rc = ensure_attrs();
+    if (rc) return rc;
+    const int chunk = std::max(1, check_every);
+    const Tile tl = resolve_tile(h);
+    const WsLayout w = ws_layout(h, ws, max_steps);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rc = init_impl(h, st, f1, w, s);
+    if (rc) return rc;
+    Hdr hh;
+    rc = read_hdr(w, &hh, s);
+    if (rc) return rc;
+    if (hh.status != 0) return set_error(ED_EINVAL, "ed_ground_energy_noalloc: start vector has zero or non-finite norm");
+    st->j = 0;
+    // the coefficients and Ritz values on the stack: no allocation on the host either
+    double a[kNoallocMaxSteps], b[kNoallocMaxSteps + 1], e[kNoallocMaxSteps + 1];
+    ed_lanczos cur = *st;
+    int have = 0, launched = 0, stop_at = -1, result = ED_NOT_CONVERGED;
+    while (true) {
+        for (int k = 0; k < chunk; ++k) {
+            rc = step_dispatch(h, tl, cur.f_prev, cur.f_cur, cur.f_next, cur.a, cur.b, nullptr, w, max_steps, s);
+            if (rc) return rc;
+            rotate(&cur);
+        }
+        launched += chunk;
+        rc = read_hdr(w, &hh, s);
+        if (rc) return rc;
+        const int jd = hh.jdev;
+        if (jd > have) {
+            ED_HIP(hipMemcpyAsync(a, st->a, 8 * (size_t)jd, hipMemcpyDeviceToHost, s));
+            ED_HIP(hipMemcpyAsync(b, st->b, 8 * (size_t)(jd + 1), hipMemcpyDeviceToHost, s));
+            ED_HIP(hipStreamSynchronize(s));
+            for (int j = have + 1; j <= jd; ++j) {
+                e[j] = tridiag_lowest(a, b + 1, j);
+                if (tol > 0 && j >= 3 && std::fabs(e[j] - e[j - 1]) < tol && std::fabs(e[j - 1] - e[j - 2]) < tol) {
+                    stop_at = j;
+                    break;
+                }
+            }
+            have = jd;
+        }
+        if (stop_at > 0) { result = ED_OK; break; }
+        if (hh.status == ED_BREAKDOWN) { result = ED_BREAKDOWN; stop_at = jd; break; }
+        if (jd >= max_steps) { result = tol > 0 ? ED_NOT_CONVERGED : ED_OK; stop_at = jd; break; }
+        if (launched > 4 * max_steps + 3 * chunk) return set_error(ED_EDEVICE, "ed_ground_energy_noalloc: no progress");
+    }
+    // steps launched beyond the device's count were no-ops: the vectors rotated jd times
+    for (int k = 0; k < hh.jdev; ++k) rotate(st);
+    st->j = hh.jdev;
+    *e0 = e[stop_at];
+    *steps = stop_at;
+    if (a_host) std::copy(a, a + stop_at, a_host);
+    if (b_host) std::copy(b, b + stop_at + 1, b_host);
     return result;
 }
 
