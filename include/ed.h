@@ -304,26 +304,6 @@ int ed_lanczos_step(const ed_ham *h, ed_lanczos *st, void *ws, void *stream);
  * (lines 7-8).  Synchronises on the last event.  ms: host, 5 doubles. */
 int ed_lanczos_step_timed(const ed_ham *h, ed_lanczos *st, void *ws, void *stream, double *ms);
 
-/* n iterations of Alg. 1 (n >= 1), asynchronous, with the state afterwards
- * exactly as after n calls of ed_lanczos_step (same coefficients up to the
- * order of additions inside H.v; f_cur = b_{j+1} f_{j+1}; the three pointers
- * rotate n times).  Where the instance allows it (real hopping, 16-bit or no
- * tables, a row of dim_dn elements of h->dtype within 152 KB of LDS) the run
- * takes the fused two-pass step: a down pass over the rows (Eq. 5 and the
- * on-site term) that also applies the previous step's update of Alg. 1 line 6
- * to the stored q, and an up pass over column stripes (Eq. 4) that completes
- * line 4 with the partial dot products of line 5; the last step's update is
- * applied at the end of the run.  Otherwise it makes n reference steps.
- * Arguments, ownership and freezing as ed_lanczos_step. */
-int ed_lanczos_steps(const ed_ham *h, ed_lanczos *st, int32_t n, void *ws, void *stream);
-
-/* ed_lanczos_steps on the fused step only (ED_EINVAL for instances it does
- * not take), with a HIP event recorded around every kernel on `stream`:
- * ms[0..3] = mean ms per step of the down pass, the b_{j+1} reduction (0 in
- * the first step), the up pass and the a_j reduction; ms[4], ms[5] = ms of
- * the closing update and of its norm.  Synchronises.  ms: host, 6 doubles. */
-int ed_lanczos_steps_timed(const ed_ham *h, ed_lanczos *st, int32_t n, void *ws, void *stream, double *ms);
-
 /* Synchronise `stream` and report the device-side state: *steps = number of
  * completed steps j, *status = ED_OK (running), ED_BREAKDOWN or
  * ED_NOT_CONVERGED (max_steps reached).  a_host (steps doubles) and b_host

@@ -89,9 +89,6 @@ _PROTOS = {
     "ed_lanczos_init": (c_int, [POINTER(EdHam), POINTER(EdLanczos), c_void_p, c_void_p, c_void_p]),
     "ed_lanczos_step": (c_int, [POINTER(EdHam), POINTER(EdLanczos), c_void_p, c_void_p]),
     "ed_lanczos_step_timed": (c_int, [POINTER(EdHam), POINTER(EdLanczos), c_void_p, c_void_p, POINTER(c_double)]),
-    "ed_lanczos_steps": (c_int, [POINTER(EdHam), POINTER(EdLanczos), c_int32, c_void_p, c_void_p]),
-    "ed_lanczos_steps_timed": (c_int, [POINTER(EdHam), POINTER(EdLanczos), c_int32, c_void_p, c_void_p,
-                                       POINTER(c_double)]),
     "ed_lanczos_read": (c_int, [POINTER(EdHam), POINTER(EdLanczos), c_void_p, c_void_p, POINTER(c_int32), POINTER(c_int32),
                                 POINTER(c_double), POINTER(c_double)]),
     "ed_ground_energy": (c_int, [POINTER(EdHam), POINTER(EdLanczos), c_void_p, c_double, c_int32, c_void_p,

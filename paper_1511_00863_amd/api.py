@@ -527,19 +527,6 @@ class LanczosRun:
                                           _ptr(ms, c_double)))
         return ms
 
-    def steps(self, n: int, stream=None):
-        """n Lanczos steps (Alg. 1) by the fused two-pass step where the instance allows it (else n reference
-        steps); the state afterwards is that of n calls of step()."""
-        check(lib().ed_lanczos_steps(byref(self._h), byref(self.st), int(n), _dptr(self.ws), _stream(stream)))
-
-    def steps_timed(self, n: int, stream=None):
-        """n fused steps with HIP events around every kernel: returns ms per step of the down pass, the b_{j+1}
-        reduction, the up pass and the a_j reduction, then ms of the closing update and its norm (6 values)."""
-        ms = np.zeros(6)
-        check(lib().ed_lanczos_steps_timed(byref(self._h), byref(self.st), int(n), _dptr(self.ws), _stream(stream),
-                                           _ptr(ms, c_double)))
-        return ms
-
     def read(self, stream=None):
         steps, status = c_int32(0), c_int32(0)
         a = np.zeros(self.max_steps)

@@ -24,7 +24,7 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-I", os.path.join(ROOT, "include")]
 
 HOST_SOURCES = ["ed_host.cpp"]
-DEVICE_SOURCES = ["ed_device.hip", "ed_fused.hip", "ed_batch.hip", "ed_mlp.hip", "ed_obs.hip", "ed_order.hip"]
+DEVICE_SOURCES = ["ed_device.hip", "ed_batch.hip", "ed_mlp.hip", "ed_obs.hip", "ed_order.hip"]
 
 
 def _run(cmd):

@@ -32,9 +32,79 @@
 #include "ed_common.h"
 #include "ed_internal.h"
 #include "ed_launch.h"
-#include "ed_state.h"
 
 namespace ed {
+
+// ---------------------------------------------------------------------------
+// Vectors are stored unnormalised ("deferred normalisation"): the buffer of
+// Lanczos vector f_j holds s_j f_j with s_1 = |f1| and s_j = b_j, and the
+// kernels apply sigma_j = 1/s_j on the fly.  A step is
+//   k_up     T  = t * up-part(F_j)                                   (Eq. 4)
+//   k_down   q  = sigma_j (T + down-part(F_j) + U Docc F_j) - b_j sigma_{j-1} F_{j-1}
+//               = H f_j - b_j f_{j-1}                  (Eq. 5, Alg. 1 line 4)
+//            + partial dots of q with F_j (and F_{j-1} in the mixed form)
+//   k_reduce a_j = q.f_j (Alg. 1 line 5); mixed form: q's projection onto
+//            span{f_j, f_{j-1}} from their 2x2 Gram matrix
+//   k_update F_{j+1} = q - a_j f_j (- beta f_{j-1})  in place (line 6)
+//            + partial sums of |F_{j+1}|^2 of the stored values
+//   k_norm   b_{j+1} = |F_{j+1}| (line 7), breakdown test (line 8)
+// so b_{j+1} is the norm of the vector actually stored, with no cancellation.
+//
+// workspace layout: [Hdr: 256 B][queue counters: 256 B][y: max_steps doubles]
+//                   [part: P x 8 doubles][part2: 8192 doubles]
+struct Hdr {
+    double sig_cur;    // 1 / s_j of the current vector
+    double sig_prev;   // 1 / s_{j-1}
+    double cx, cp;     // update coefficients on the stored F_j and F_{j-1}
+    double scale;      // max_k(|a_k|, b_k) so far (breakdown threshold)
+    double vinv;       // 1 / |v| for the two-pass ground state
+    double norm2;      // |f1|^2 of the last init
+    int32_t jdev;      // completed steps
+    int32_t status;    // 0 running, ED_BREAKDOWN, or kInitBad
+};
+static_assert(sizeof(Hdr) <= 256, "header too large");
+constexpr int32_t kInitBad = 100;
+constexpr int kPartStride = 8;    // doubles per partial-sum slot
+constexpr int kUpdBlocks = 8192;  // k_update / k_sumsq grid cap = part2 slots
+
+static inline int64_t align256(int64_t b) { return (b + 255) & ~int64_t(255); }
+
+struct WsLayout {
+    Hdr *hdr;
+    int *ctr;
+    double *y;
+    double *part;
+    double *part2;
+};
+
+// k_down partial-sum slots: one per workgroup.  Rows too long for LDS are split
+// into column blocks until the launch has kDownBlocks workgroups, so the grid
+// is at most dim_up + kDownBlocks.
+static int64_t n_partial_slots(const ed_ham *h) { return std::max<int64_t>(h->dim_up, 1) + kDownBlocks; }
+
+static int64_t ws_bytes(const ed_ham *h, int32_t max_steps) {
+    return 512 + align256(8 * (int64_t)std::max(max_steps, 1)) + align256(8 * kPartStride * n_partial_slots(h)) +
+           8 * kUpdBlocks;
+}
+
+static WsLayout ws_layout(const ed_ham *h, void *ws, int32_t max_steps) {
+    char *p = static_cast<char *>(ws);
+    WsLayout l;
+    l.hdr = reinterpret_cast<Hdr *>(p);
+    p += 256;
+    l.ctr = reinterpret_cast<int *>(p);
+    p += 256;
+    l.y = reinterpret_cast<double *>(p);
+    p += align256(8 * (int64_t)std::max(max_steps, 1));
+    l.part = reinterpret_cast<double *>(p);
+    p += align256(8 * kPartStride * n_partial_slots(h));
+    l.part2 = reinterpret_cast<double *>(p);
+    return l;
+}
+
+__device__ __forceinline__ bool frozen(const Hdr *hdr, int max_steps) {
+    return hdr->status != 0 || hdr->jdev >= max_steps;
+}
 
 // Which up-part tile a (R, NCH, E) variant runs: one row per wave with all
 // chunks in scalar registers, two rows per wave (16-bit tables of at most 4
@@ -520,7 +590,6 @@ __global__ __launch_bounds__(1024) void k_init_norm(const double *__restrict__ p
         hdr->scale = 0.0;
         hdr->jdev = 0;
         hdr->status = ok ? 0 : kInitBad;
-        hdr->pending = 0;
         b[0] = 0.0;
     } else {
         hdr->vinv = ok ? gauge_sign / sqrt(n2) : 0.0;
@@ -1013,33 +1082,6 @@ static int capture_steps(const ed_ham *h, const Tile &tl, ed_lanczos st_copy, co
     return ED_OK;
 }
 
-// Capture `nsteps` (a multiple of 3) pending fused steps starting from the
-// roles (fp, f, q); the roles rotate once per step, so a replay starts where
-// the last one ended.
-static int capture_fused(const ed_ham *h, void *fp, void *f, void *q, double *a, double *b, const WsLayout &w,
-                         int nsteps, int max_steps, hipStream_t s, StepGraph &sg) {
-    ED_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    int rc = ED_OK;
-    for (int k = 0; k < nsteps && rc == ED_OK; ++k) {
-        rc = fused_step(h, fp, f, q, true, a, b, nullptr, w, max_steps, s);
-        void *old = fp;
-        fp = f;
-        f = q;
-        q = old;
-    }
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(s, &g);
-    if (rc) {
-        if (g) (void)hipGraphDestroy(g);
-        return rc;
-    }
-    ED_HIP(e);
-    sg.g = g;
-    ED_HIP(hipGraphInstantiate(&sg.ge, g, nullptr, nullptr, 0));
-    sg.steps = nsteps;
-    return ED_OK;
-}
-
 template <typename T>
 static int tune_impl(const ed_ham *h, const T *x, T *y, const WsLayout &w, int reps, hipStream_t s, int32_t *tile,
                      double *ms_up, double *ms_dn) {
@@ -1288,16 +1330,6 @@ int ed_ground_energy(const ed_ham *h, ed_lanczos *st, const void *f1, double tol
     const Tile tl = resolve_tile(h);
     const WsLayout w = ws_layout(h, ws, max_steps);
 
-    // The run takes the reference step: on the instances measured so far the
-    // fused step (ed_lanczos_steps) is slower, its up pass bound by streaming
-    // its operands in narrow column stripes.  The fused branch below stays
-    // selectable by fused_for_runs().
-    const bool fused = fused_for_runs(h);
-    if (fused) {
-        rc = fused_prepare();
-        if (rc) return rc;
-    }
-
     SideStream ss;
     rc = ss.open(static_cast<hipStream_t>(stream));
     if (rc) return rc;
@@ -1309,19 +1341,10 @@ int ed_ground_energy(const ed_ham *h, ed_lanczos *st, const void *f1, double tol
     if (hh.status != 0) return set_error(ED_EINVAL, "ed_ground_energy: start vector has zero or non-finite norm");
     st->j = 0;
 
-    void *b0 = st->f_prev, *b1 = st->f_cur, *b2 = st->f_next;
     StepGraph sg;
-    int launched = 0;
-    if (fused) {
-        // the first step reads f_1 as stored; every later one is pending
-        rc = fused_step(h, b0, b1, b2, false, st->a, st->b, nullptr, w, max_steps, ss.own);
-        if (rc) return rc;
-        launched = 1;
-        rc = capture_fused(h, b0, b1, b2, st->a, st->b, w, chunk, max_steps, ss.own, sg);
-    } else {
-        rc = capture_steps(h, tl, *st, w, chunk, ss.own, sg);
-    }
+    rc = capture_steps(h, tl, *st, w, chunk, ss.own, sg);
     if (rc) return rc;
+    int launched = 0;
 
     std::vector<double> a(max_steps), b(max_steps + 1), e(max_steps + 1, 0.0);
     int have = 0;            // steps whose E0 is known
@@ -1350,13 +1373,6 @@ int ed_ground_energy(const ed_ham *h, ed_lanczos *st, const void *f1, double tol
         if (hh.status == ED_BREAKDOWN) { result = ED_BREAKDOWN; stop_at = jd; break; }
         if (jd >= max_steps) { result = tol > 0 ? ED_NOT_CONVERGED : ED_OK; stop_at = jd; break; }
         if (launched > 4 * max_steps + 3 * chunk) return set_error(ED_EDEVICE, "ed_ground_energy: no progress");
-    }
-    if (fused) {
-        // the last step's update of Alg. 1 line 6: F_{j+1} and b_{j+1}
-        rc = fused_flush(h, b0, b1, b2, st->a, st->b, w, max_steps, ss.own);
-        if (rc) return rc;
-        ED_HIP(hipMemcpyAsync(b.data(), st->b, 8 * (size_t)(hh.jdev + 1), hipMemcpyDeviceToHost, ss.own));
-        ED_HIP(hipStreamSynchronize(ss.own));
     }
     // Launched steps beyond the device's step count were no-ops (the state
     // froze at a breakdown or at max_steps): the vectors rotated jd times.
@@ -1480,39 +1496,11 @@ int ed_ground_state(const ed_ham *h, ed_lanczos *st, const void *f1, int32_t m, 
     else
         hipLaunchKernelGGL(k_fill0<float>, dim3(upd_grid(n)), dim3(256), 0, s, (float *)v, n);
     ED_LAUNCHED("k_fill0");
-    if (fused_for_runs(h)) {
-        // The fused step forms F_j in its down pass, before b_j is reduced, so
-        // the weights w_j = y_j / s_j come from pass 1's scales: s_1 = |f1|
-        // (the header after init) and s_j = b_j, the same float64 values.
-        Hdr hh;
-        rc = read_hdr(w, &hh, s);
+    const Tile tl = resolve_tile(h);
+    for (int j = 0; j < k; ++j) {
+        rc = step_dispatch(h, tl, s2.f_prev, s2.f_cur, s2.f_next, s2.a, s2.b, v, w, k, s);
         if (rc) return rc;
-        std::vector<double> wv(k);
-        for (int j = 0; j < k; ++j) wv[j] = y[j] * (j == 0 ? hh.sig_cur : 1.0 / b[j]);
-        ED_HIP(hipMemcpyAsync(w.y, wv.data(), 8 * (size_t)k, hipMemcpyHostToDevice, s));
-        ED_HIP(hipStreamSynchronize(s));
-        void *b0 = s2.f_prev, *b1 = s2.f_cur, *b2 = s2.f_next;
-        void *fp = b0, *f = b1, *q = b2;
-        for (int j = 0; j < k; ++j) {
-            rc = fused_step(h, fp, f, q, j > 0, s2.a, s2.b, v, w, k, s);
-            if (rc) return rc;
-            if (j > 0) {
-                void *old = fp;
-                fp = f;
-                f = q;
-                q = old;
-            }
-        }
-        rc = fused_flush(h, b0, b1, b2, s2.a, s2.b, w, k, s);
-        if (rc) return rc;
-        for (int j = 0; j < k; ++j) rotate(&s2);
-    } else {
-        const Tile tl = resolve_tile(h);
-        for (int j = 0; j < k; ++j) {
-            rc = step_dispatch(h, tl, s2.f_prev, s2.f_cur, s2.f_next, s2.a, s2.b, v, w, k, s);
-            if (rc) return rc;
-            rotate(&s2);
-        }
+        rotate(&s2);
     }
     double gsign = 1.0;
     if (gauge_index >= 0) {

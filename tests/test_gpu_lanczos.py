@@ -167,3 +167,22 @@ def test_two_pass_ground_state_c1(ring8, ring8_e0):
         assert abs(e0 - w[0]) <= 1e-10 * abs(w[0]) if dtype == "f64" else abs(e0 - w[0]) <= 1e-6 * abs(w[0])
         assert abs(np.linalg.norm(v) - 1.0) < (1e-12 if dtype == "f64" else 1e-6)
         assert abs(abs(v @ vecs[:, 0]) - 1.0) <= tol
+
+
+def test_ground_energy_newest_vector_after_partial_chunk():
+    """ed_ground_energy with max_steps not a multiple of its step chunk (steps launched past max_steps are
+    no-ops): afterwards f_cur holds b_{m+1} f_{m+1}, the same vector m single steps leave there."""
+    h = ham(16, torus_bonds(4, 4), 3, 3, 1.0, 4.0, "f64")
+    _, x = seeded_start(23, h.dim, "f64")
+    ra, rb = h.lanczos(100), h.lanczos(100)
+    announce("ground_energy f_cur after 100 steps in chunks of 12")
+    ra.ground_energy(x, tol=0.0, check_every=12)
+    rb.init(x)
+    for _ in range(100):
+        rb.step()
+    ga, gb = ra.read(), rb.read()
+    assert ga["steps"] == gb["steps"] == 100
+    assert np.array_equal(ga["a"], gb["a"]) and np.array_equal(ga["b"], gb["b"])
+    assert torch.equal(ra.f_cur, rb.f_cur) and torch.equal(ra.f_prev, rb.f_prev)
+    fa = ra.f_cur.cpu().numpy()
+    assert abs(np.linalg.norm(fa) - ga["b"][100]) <= 1e-12 * ga["b"][100]
