@@ -125,7 +125,7 @@ def start_in_order(h, x_host, dev):
 
 
 # the step kernels' sources: the traffic record is valid only for these exact bytes
-TRAFFIC_SOURCES = ("ed_device.hip", "ed_common.h", "ed_state.h")
+TRAFFIC_SOURCES = ("ed_device.hip", "ed_common.h")
 
 
 def measured_traffic(dtype, kernel, workload_name, basis_order):

@@ -1043,18 +1043,23 @@ struct SideStream {
         own = nullptr;
         return rc;
     }
-    ~SideStream() {
+    ~SideStream() {   // an early return: drain what was queued before releasing the stream
+        if (own) (void)hipStreamSynchronize(own);
         if (ev) (void)hipEventDestroy(ev);
         if (own) (void)hipStreamDestroy(own);
     }
 };
 
-// Launch `nsteps` steps as a replayed graph of 3*k steps (three-buffer rotation).
+// Launch `nsteps` steps as a replayed graph of 3*k steps (three-buffer rotation).  The stream the graph is
+// launched on must outlive this object: on an early return a launch may still be in flight, so the stream is
+// drained before the executable graph is released.
 struct StepGraph {
     hipGraph_t g = nullptr;
     hipGraphExec_t ge = nullptr;
+    hipStream_t s = nullptr;
     int steps = 0;
     ~StepGraph() {
+        if (s) (void)hipStreamSynchronize(s);
         if (ge) (void)hipGraphExecDestroy(ge);
         if (g) (void)hipGraphDestroy(g);
     }
@@ -1078,6 +1083,7 @@ static int capture_steps(const ed_ham *h, const Tile &tl, ed_lanczos st_copy, co
     ED_HIP(e);
     sg.g = g;
     ED_HIP(hipGraphInstantiate(&sg.ge, g, nullptr, nullptr, 0));
+    sg.s = s;
     sg.steps = nsteps;
     return ED_OK;
 }
