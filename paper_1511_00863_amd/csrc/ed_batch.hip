@@ -28,6 +28,7 @@ namespace ed {
 constexpr int kBatchBlock = 256;
 constexpr int kBatchUpRows = 64;            // rows per up tile at least: amortises the queue's atomic and barriers
 constexpr int kBatchLds = 40 * 1024;        // rows of up to 10240 floats; three workgroups per CU
+constexpr int kBatchShm = kBatchLds + 16;   // the rows and the zero after a single row
 constexpr int64_t kUpdChunk = 65536;         // elements per update tile
 constexpr int kConverged = 10;
 constexpr int kBadStart = 100;
@@ -352,6 +353,7 @@ __global__ __launch_bounds__(kBatchBlock, 3) void k_batch(BInst *__restrict__ in
                 const float *p = (const float *)I.vec[(I.rot + 2) % 3];
                 __syncthreads();
                 stage_rows<float>(x + base, xs, nr * I.Ddn);
+                if (I.rpb == 1 && threadIdx.x == 0) xs[I.Ddn] = 0.f;   // the target of padding entries
                 __syncthreads();
                 double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
                 const bool has_prev = I.j > 0;
@@ -367,8 +369,8 @@ __global__ __launch_bounds__(kBatchBlock, 3) void k_batch(BInst *__restrict__ in
                     down_rows<float, 2, 4, true>(xs, io, p, tdn, su, sd, I.Ddn, I.W8d, 0, nr * I.Ddn, base, tt, uu, sig, cprev,
                                                  has_prev, s);
                 else
-                    down_rows<float, 2, 4, false>(xs, io, p, tdn, su, sd, I.Ddn, I.W8d, 0, nr * I.Ddn, base, tt, uu, sig, cprev,
-                                                  has_prev, s);
+                    down_rows<float, 2, 4, false, true, true>(xs, io, p, tdn, su, sd, I.Ddn, I.W8d, 0, nr * I.Ddn, base, tt,
+                                                              uu, sig, cprev, has_prev, s);
                 double tot[5];
                 block_sum<5>(s, tot);
                 if (threadIdx.x == 0)
@@ -538,9 +540,9 @@ static int batch_grid(int *grid) {
         ED_HIP(hipGetDevice(&dev));
         ED_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
         ED_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k_batch),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, kBatchLds));
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, kBatchShm));
         ED_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void *>(k_batch),
-                                                            kBatchBlock, kBatchLds));
+                                                            kBatchBlock, kBatchShm));
         if (occ < 1) return set_error(ED_EDEVICE, "k_batch cannot be resident on a CU");
         cached = ncu * occ;
         if (cached < 8) return set_error(ED_EDEVICE, "k_batch needs at least 8 resident workgroups");
@@ -715,7 +717,7 @@ int ed_ground_energy_batch(const ed_batch_item *items, int32_t n, int32_t max_st
                   hipEventRecord(ev, user) == hipSuccess && hipStreamWaitEvent(cs, ev, 0) == hipSuccess;
         if (ok && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
             const hipError_t le = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_batch), dim3(grid),
-                                                             dim3(kBatchBlock), args, kBatchLds, cs);
+                                                             dim3(kBatchBlock), args, kBatchShm, cs);
             const hipError_t ee = hipStreamEndCapture(cs, &g);
             ok = le == hipSuccess && ee == hipSuccess && g != nullptr &&
                  hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) == hipSuccess;
@@ -738,7 +740,7 @@ int ed_ground_energy_batch(const ed_batch_item *items, int32_t n, int32_t max_st
     }
     if (!graphed) {
         ED_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_batch), dim3(grid), dim3(kBatchBlock),
-                                          args, kBatchLds, user));
+                                          args, kBatchShm, user));
     }
     if (graph_used) *graph_used = graphed ? 1 : 0;
     std::vector<BInst> out(n);

@@ -469,14 +469,102 @@ __device__ __forceinline__ void stage_rows(const T *__restrict__ src, T *__restr
     }
 }
 
+// The down-part sum of one column (Eq. 5): the row's elements at the column's
+// table entries times their signs, in two interleaved partial sums (even
+// entries in acc0, odd in acc1, each term added with one rounding).  Chunks
+// from nch on, and chunks that are padding for every lane of the wave, are
+// skipped.  Padding entries read element 0 and add it times zero.
+template <typename T, int NCH, typename E>
+__device__ __forceinline__ void down_gather(const T *__restrict__ xrow, const Chunk8<E> (&tq)[NCH > 0 ? NCH : 1],
+                                            int nch, T &acc0, T &acc1) {
+    acc0 = T(0);
+    acc1 = T(0);
+#pragma unroll
+    for (int k8 = 0; k8 < NCH; ++k8) {
+        if (k8 >= nch) break;
+        // a chunk whose first entry is padding is padding throughout; skip it
+        // when that holds for every lane of the wave
+        if (!__any(!is_pad<E>(entry(tq[k8], 0)))) break;
+        // likewise the chunk's second half (entries 4..7), in FP32: gather it only where some lane needs
+        // it (in FP64 the extra branch cost more than the skipped gathers saved)
+        bool upper = true;
+        if constexpr (sizeof(T) == 4) upper = __any(!is_pad<E>(entry(tq[k8], 4)));
+        T v[8], sg[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (k >= 4 && !upper) {
+                v[k] = T(0);
+                sg[k] = T(0);
+                continue;
+            }
+            const unsigned e = entry(tq[k8], k);
+            const bool pk = !is_pad<E>(e);
+            sg[k] = pk ? ((e & 1u) ? T(-1) : T(1)) : T(0);
+            v[k] = xrow[pk ? (int)(e >> 1) : 0];   // padding: one broadcast address
+        }
+#pragma unroll
+        for (int k = 0; k < 8; k += 2) {
+            acc0 += sg[k] * v[k];
+            acc1 += sg[k + 1] * v[k + 1];
+        }
+    }
+}
+
+// -v where the sign bit s31 (bit 31) is set, else v: one integer XOR on the
+// word holding the sign
+__device__ __forceinline__ double flip_sign(double v, unsigned s31) {
+    uint2 u = __builtin_bit_cast(uint2, v);
+    u.y ^= s31;
+    return __builtin_bit_cast(double, u);
+}
+__device__ __forceinline__ float flip_sign(float v, unsigned s31) {
+    return __builtin_bit_cast(float, __builtin_bit_cast(unsigned, v) ^ s31);
+}
+
+// down_gather for a row staged in LDS with a zero at index zslot (= the row
+// length): a padding entry's column (all ones) is clamped to zslot, so it adds
+// a zero, and an entry's sign flips the loaded value's sign bit, so each
+// entry costs a clamp, an address, a sign and an add instead of a selected
+// sign factor and a selected address.  The terms and their order are
+// down_gather's (x + (-v) is fma(-1, v, x)), so the results are the same bits.
+template <typename T, int NCH, typename E>
+__device__ __forceinline__ void down_gather_z(const T *__restrict__ xrow, const Chunk8<E> (&tq)[NCH > 0 ? NCH : 1],
+                                             int nch, unsigned zslot, T &acc0, T &acc1) {
+    acc0 = T(0);
+    acc1 = T(0);
+#pragma unroll
+    for (int k8 = 0; k8 < NCH; ++k8) {
+        if (k8 >= nch) break;
+        if (!__any(!is_pad<E>(entry(tq[k8], 0)))) break;
+        bool upper = true;
+        if constexpr (sizeof(T) == 4) upper = __any(!is_pad<E>(entry(tq[k8], 4)));
+        T v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (k >= 4 && !upper) {
+                v[k] = T(0);
+                continue;
+            }
+            const unsigned e = entry(tq[k8], k);
+            v[k] = flip_sign(xrow[min(e >> 1, zslot)], e << 31);
+        }
+#pragma unroll
+        for (int k = 0; k < 8; k += 2) {
+            acc0 += v[k];
+            acc1 += v[k + 1];
+        }
+    }
+}
+
 // Elements [i0, iend) of a block of rows starting at row r0 of one instance
 // (element i = row i / Ddn, column i % Ddn of the block): q = sig * (io + t *
 // down-part + U Docc x) - cprev * p, in place on io; per-thread partial sums
 // added to s[].  xrows: the rows (LDS copy or global); base: offset of row r0
 // in the global vectors.  A workgroup takes whole rows (i0 = 0, iend = rows *
 // Ddn) or, for one long row, a range of its columns.  IO = false: there is
-// no up part (the up species cannot hop); io is written but not read.
-template <typename T, int MODE, int NCH, bool MULTI, bool IO = true, typename E>
+// no up part (the up species cannot hop); io is written but not read.  ZS:
+// one row in LDS followed by a zero (down_gather_z).
+template <typename T, int MODE, int NCH, bool MULTI, bool IO = true, bool ZS = false, typename E>
 __device__ __forceinline__ void down_rows(const T *__restrict__ xrows, T *__restrict__ io, const T *__restrict__ p,
                                           const E *__restrict__ tab, const uint64_t *__restrict__ st_up_r0,
                                           const uint64_t *__restrict__ st_dn, int Ddn, int W8, int i0, int iend,
@@ -523,36 +611,11 @@ __device__ __forceinline__ void down_rows(const T *__restrict__ xrows, T *__rest
         uint64_t sun = su0;
         if constexpr (MULTI) sun = st_up_r0[rrn];
         const T *xrow = xrows + (int64_t)rr * Ddn;
-        T acc0 = T(0), acc1 = T(0);
-#pragma unroll
-        for (int k8 = 0; k8 < NCH; ++k8) {
-            if (k8 >= nch) break;
-            // a chunk whose first entry is padding is padding throughout; skip it
-            // when that holds for every lane of the wave
-            if (!__any(!is_pad<E>(entry(tq[k8], 0)))) break;
-            // likewise the chunk's second half (entries 4..7), in FP32: gather it only where some lane needs
-            // it (in FP64 the extra branch cost more than the skipped gathers saved)
-            bool upper = true;
-            if constexpr (sizeof(T) == 4) upper = __any(!is_pad<E>(entry(tq[k8], 4)));
-            T v[8], sg[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                if (k >= 4 && !upper) {
-                    v[k] = T(0);
-                    sg[k] = T(0);
-                    continue;
-                }
-                const unsigned e = entry(tq[k8], k);
-                const bool pk = !is_pad<E>(e);
-                sg[k] = pk ? ((e & 1u) ? T(-1) : T(1)) : T(0);
-                v[k] = xrow[pk ? (int)(e >> 1) : 0];   // padding: one broadcast address
-            }
-#pragma unroll
-            for (int k = 0; k < 8; k += 2) {
-                acc0 += sg[k] * v[k];
-                acc1 += sg[k + 1] * v[k + 1];
-            }
-        }
+        T acc0, acc1;
+        if constexpr (ZS)
+            down_gather_z<T, NCH, E>(xrow, tq, nch, (unsigned)Ddn, acc0, acc1);
+        else
+            down_gather<T, NCH, E>(xrow, tq, nch, acc0, acc1);
         const T xv = xrow[c];
         const T nd = static_cast<T>(__popcll(suv & sdv));
         T q = iov + t * (acc0 + acc1) + U * nd * xv;

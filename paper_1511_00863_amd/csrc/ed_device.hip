@@ -233,16 +233,19 @@ void k_down(const T *__restrict__ x, T *__restrict__ io, const T *__restrict__ p
     const int nr = min(rpb, Dup - r0);
     if constexpr (LDS) iend = nr * Ddn;
     const int64_t base = (int64_t)r0 * Ddn;
+    // one staged row is followed by a zero, the target of padding entries
+    constexpr bool ZS = LDS && !MULTI;
     if (LDS) {
         stage_rows<T>(x + base, xs, nr * Ddn);
+        if (ZS && threadIdx.x == 0) xs[Ddn] = T(0);
         __syncthreads();
     }
     constexpr int NV = MODE == 2 ? 5 : 1;
     double s[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) s[k] = 0.0;
-    down_rows<T, MODE, NCH, MULTI, IO>(LDS ? xs : x + base, io, p, tab, st_up + r0, st_dn, Ddn, W8, i0, iend, base, t,
-                                   U, sig, cprev, MODE != 0 && has_prev, s);
+    down_rows<T, MODE, NCH, MULTI, IO, ZS>(LDS ? xs : x + base, io, p, tab, st_up + r0, st_dn, Ddn, W8, i0, iend,
+                                           base, t, U, sig, cprev, MODE != 0 && has_prev, s);
     if (MODE != 0) {
         double tot[NV];
         block_sum<NV>(s, tot);
@@ -798,7 +801,8 @@ static int launch_down_e(const ed_ham *h, const Tile &tl, const T *x, T *io, con
     const DownShape d = down_shape(h, tl);
     const bool lds = d.lds;
     const int rpb = d.rpb, grid = d.grid, cs = d.csplit;
-    const size_t shm = lds ? (size_t)(h->dim_dn * (int64_t)sizeof(T) * rpb) : 0;
+    // rows plus one slot (the zero after a single row), 16-byte granular
+    const size_t shm = lds ? (size_t)(h->dim_dn * (int64_t)sizeof(T) * rpb) + 16 : 0;
     const int nch = h->w_dn >> 3;
     if (!lds && h->w_up == 0) {   // one species: no up part to add (launch_up wrote nothing)
         if (nch == 0) {
@@ -868,15 +872,15 @@ static int launch_down(const ed_ham *h, const Tile &tl, const T *x, T *io, const
 
 static int down_grid(const ed_ham *h, const Tile &tl) { return down_shape(h, tl).grid; }
 
-// Kernels staging rows in LDS may use up to kLdsBudget bytes of it; set once,
-// outside any stream capture.
+// Kernels staging rows in LDS may use up to kLdsBudget bytes of rows plus the
+// slot after them; set once, outside any stream capture.
 template <typename T, int MODE, int NCH, typename E>
 static hipError_t set_lds_attr_e() {
     const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_down<T, MODE, true, NCH, false, E>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget);
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget + 256);
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute(reinterpret_cast<const void *>(k_down<T, MODE, true, NCH, true, E>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget);
+                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget + 256);
 }
 
 template <typename T, int MODE, int NCH>
@@ -903,7 +907,7 @@ static hipError_t set_lds_attrs_c() {
                         reinterpret_cast<const void *>(k_downc<T, 1, true>),
                         reinterpret_cast<const void *>(k_downc<T, 2, true>)};
     for (const void *k : ks) {
-        const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget);
+        const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget + 256);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
