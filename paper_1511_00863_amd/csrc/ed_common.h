@@ -238,19 +238,20 @@ template <typename VT> __device__ __forceinline__ auto vcomp(const VT &v, int i)
     else return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
 }
 
-template <typename T, int V, int NL, int NCH, typename E>
+// One row of the vector up tile with exactly NE entries (a row's entries come
+// first, padding after them): every gather is a real row of x, then the
+// previous row's result is stored, then the row is summed in ascending column
+// order with one fused multiply-add per term.
+template <typename T, int V, int NE, int NCH, typename E>
 __device__ __forceinline__ void up_rowv(const T *__restrict__ xs, unsigned cc, int Ddn, const Chunk8<E> (&q)[NCH], T t,
                                         T (&pend)[V], T *&pend_ptr, T *row_out) {
     using VT = typename VecT<T, V>::type;
-    VT v[NL > 0 ? NL : 1][8];
+    VT v[NE > 0 ? NE : 1];
 #pragma unroll
-    for (int k8 = 0; k8 < NL; ++k8)
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const unsigned e = entry(q[k8], k);
-            const T *xr = xs + (int64_t)(!is_pad<E>(e) ? (e >> 1) : 0u) * Ddn;
-            v[k8][k] = *reinterpret_cast<const VT *>(xr + cc);
-        }
+    for (int j = 0; j < NE; ++j) {
+        const unsigned e = entry(q[j >> 3], j & 7);
+        v[j] = *reinterpret_cast<const VT *>(xs + (int64_t)(e >> 1) * Ddn + cc);
+    }
     if (pend_ptr) {
 #pragma unroll
         for (int i = 0; i < V; ++i) __builtin_nontemporal_store(pend[i], pend_ptr + i);
@@ -259,17 +260,28 @@ __device__ __forceinline__ void up_rowv(const T *__restrict__ xs, unsigned cc, i
 #pragma unroll
     for (int i = 0; i < V; ++i) a[i] = T(0);
 #pragma unroll
-    for (int k8 = 0; k8 < NL; ++k8)
+    for (int j = 0; j < NE; ++j) {
+        const unsigned e = entry(q[j >> 3], j & 7);
+        const T sg = (e & 1u) ? T(-1) : T(1);
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const unsigned e = entry(q[k8], k);
-            const T sg = is_pad<E>(e) ? T(0) : ((e & 1u) ? T(-1) : T(1));
-#pragma unroll
-            for (int i = 0; i < V; ++i) a[i] = fma_t(sg, vcomp(v[k8][k], i), a[i]);
-        }
+        for (int i = 0; i < V; ++i) a[i] = fma_t(sg, vcomp(v[j], i), a[i]);
+    }
 #pragma unroll
     for (int i = 0; i < V; ++i) pend[i] = t * a[i];
     pend_ptr = row_out;
+}
+
+// Dispatch a row with ne entries (wave-uniform) to its exact-count variant,
+// for tables of up to 8 * NCH <= 32 entries per row.
+template <typename T, int V, int NCH, typename E, int NE = 0>
+__device__ __forceinline__ void up_rowv_n(int ne, const T *__restrict__ xs, unsigned cc, int Ddn,
+                                          const Chunk8<E> (&q)[NCH], T t, T (&pend)[V], T *&pend_ptr, T *row_out) {
+    if constexpr (NE <= 8 * NCH) {
+        if (ne == NE)
+            up_rowv<T, V, NE, NCH, E>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out);
+        else
+            up_rowv_n<T, V, NCH, E, NE + 1>(ne, xs, cc, Ddn, q, t, pend, pend_ptr, row_out);
+    }
 }
 
 template <typename T, int V, int NCH, typename E>
@@ -293,19 +305,14 @@ __device__ __forceinline__ void up_tile_vec(const T *__restrict__ x, T *__restri
     for (int i = 0; i < V; ++i) pend[i] = T(0);
     T *pend_ptr = nullptr;
     for (; rb < r1; rb += nwave) {
-        int nl = 0;
+        // the row's entries: every entry of the row's chunks that is not padding (wave-uniform)
+        int ne = 0;
 #pragma unroll
-        for (int k8 = 0; k8 < NCH; ++k8) nl += !is_pad<E>(entry(q[k8], 0)) ? 1 : 0;
+        for (int j = 0; j < 8 * NCH; ++j) ne += !is_pad<E>(entry(q[j >> 3], j & 7)) ? 1 : 0;
         Chunk8<E> qn[NCH];
         row_chunks<NCH>(tab, min(rb + nwave, r1 - 1), W8, nch, qn);
         T *row_out = cok ? out + (int64_t)rb * Ddn + c : nullptr;
-        switch (nl) {
-        case 0: up_rowv<T, V, 0, NCH, E>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
-        case 1: up_rowv<T, V, 1, NCH, E>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
-        case 2: if constexpr (NCH >= 2) up_rowv<T, V, 2, NCH, E>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
-        case 3: if constexpr (NCH >= 4) up_rowv<T, V, 3, NCH, E>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
-        default: if constexpr (NCH >= 4) up_rowv<T, V, 4, NCH, E>(xs, cc, Ddn, q, t, pend, pend_ptr, row_out); break;
-        }
+        up_rowv_n<T, V, NCH, E>(ne, xs, cc, Ddn, q, t, pend, pend_ptr, row_out);
 #pragma unroll
         for (int k8 = 0; k8 < NCH; ++k8) q[k8] = qn[k8];
     }
