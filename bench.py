@@ -7,8 +7,10 @@ Hubbard model at half filling (8 up + 8 down, dim 165,636,900, t=1, U=4) from a
 seeded uniform(-1,1) start vector, float64 (the plain method); the mixed form
 (float32 vectors, float64 scalars) is timed beside it.  The down species' basis
 is taken in hop-count order (ed_hop_order; --basis-order ascending for the
-paper's order): the same H up to a permutation of the vector elements, with
-the start vector permuted alike, so the run has the same a_j, b_j and E0.
+paper's order) and the up species' in band order (ed_band_order; --up-order
+ascending for the paper's): the same H up to a permutation of the vector
+elements, with the start vector permuted alike, so the run has the same a_j,
+b_j and E0.
 Inputs are resident in HBM before the timed region; as in the paper's protocol
 no transfer is timed.
 
@@ -25,7 +27,8 @@ workloads beside its K40 times, and the oracle timed on the host cores.
 Prints ONE JSON line on stdout (progress lines go to stderr).  Options:
 --steps K --warmup W (timed / untimed steps), --gpus N (only 1 is supported:
 the method runs on one GPU), --no-cpu-baseline, --no-learned, --no-batch,
---no-scale, --no-single, --no-complex, --no-paper-shapes, --basis-order.
+--no-scale, --no-single, --no-complex, --no-paper-shapes, --basis-order,
+--up-order.
 """
 
 import argparse
@@ -128,9 +131,9 @@ def start_in_order(h, x_host, dev):
 TRAFFIC_SOURCES = ("ed_device.hip", "ed_common.h")
 
 
-def measured_traffic(dtype, kernel, workload_name, basis_order):
+def measured_traffic(dtype, kernel, workload_name, basis_order, up_order="ascending"):
     """HBM bytes per launch from the committed counter record, if it matches this kernel source, workload and
-    down-species basis order."""
+    the two species' basis orders."""
     import hashlib
     here = os.path.join(ROOT, "paper_1511_00863_amd")
     try:
@@ -139,7 +142,8 @@ def measured_traffic(dtype, kernel, workload_name, basis_order):
     except OSError:
         return None
     if (hashlib.sha256(src).hexdigest()[:16] != rec.get("source_sha256_prefix") or rec.get("workload") != workload_name
-            or rec.get("basis_order_down", "ascending") != basis_order):
+            or rec.get("basis_order_down", "ascending") != basis_order
+            or rec.get("basis_order_up", "ascending") != up_order):
         return None
     return rec["kernels"].get(dtype, {}).get(kernel)
 
@@ -504,7 +508,9 @@ def main():
     ap.add_argument("--single-steps", type=int, default=20)
     ap.add_argument("--scale-steps", type=int, default=6)
     ap.add_argument("--basis-order", choices=("hops", "ascending"), default="hops",
-                    help="basis order of the down species where its rows fit LDS (the up species stays ascending)")
+                    help="basis order of the down species where its rows fit LDS")
+    ap.add_argument("--up-order", choices=("band", "ascending"), default="band",
+                    help="basis order of the up species in the timed step")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this method runs on one GPU; --gpus %d is not supported (use --gpus 1)" % args.gpus,
@@ -522,14 +528,17 @@ def main():
     del x64
     up = ed.SpinTables(wl.n_sites, wl.bonds, wl.n_up, dev)
     dn = up if wl.n_dn == wl.n_up else ed.SpinTables(wl.n_sites, wl.bonds, wl.n_dn, dev)
-    # the timed step: down species in hop-count order (the same H up to a permutation of the elements)
+    # the timed step: down species in hop-count order, up species in band order (the same H up to a
+    # permutation of the elements)
     order = dn_order_for(args, dn.dim)
     dn_run = dn if order == "ascending" else ed.SpinTables(wl.n_sites, wl.bonds, wl.n_dn, dev, order=order)
+    up_run = up if args.up_order == "ascending" else ed.SpinTables(wl.n_sites, wl.bonds, wl.n_up, dev,
+                                                                   order=args.up_order)
     x_host = start_vector(wl.seed, up.dim * dn.dim)
 
     results = {}
     for dtype in (("f64",) if args.no_mixed else ("f64", "f32")):
-        h = ed.Hamiltonian(up, dn_run, wl.t, wl.U, dtype)
+        h = ed.Hamiltonian(up_run, dn_run, wl.t, wl.U, dtype)
         x = h.to_basis_order(torch.from_numpy(x_host).to(dev, h.torch_dtype))   # the same start, reordered
         tile_src = "default"
         if not args.no_tune:           # the project's autotuner (cached per shape); outside the timed region
@@ -552,7 +561,7 @@ def main():
     # the dominant kernel against the algorithmic bytes of one H.v (2pD + tables)
     achieved = r64["hv_bytes"] / (r64["kernel_ms"][dom] * 1e-3) / 1e9
     t_hv = (r64["kernel_ms"]["k_up"] + r64["kernel_ms"]["k_down"]) * 1e-3
-    traffic = {k: measured_traffic("f64", k, wl.name, dn_run.order) for k in ("k_up", "k_down")}
+    traffic = {k: measured_traffic("f64", k, wl.name, dn_run.order, up_run.order) for k in ("k_up", "k_down")}
     hv_counter = (traffic["k_up"] + traffic["k_down"]) if None not in traffic.values() else None
     line = {
         "metric": METRIC,
@@ -570,9 +579,10 @@ def main():
         "config": {"workload": wl.name, "lattice": "4x4 periodic square" if wl.n_sites == 16 else wl.name,
                    "n_up": wl.n_up, "n_dn": wl.n_dn, "dim": up.dim * dn.dim, "t": wl.t, "U": wl.U,
                    "start": "uniform(-1,1), seed %d" % wl.seed,
-                   "basis_order": {"up": "ascending", "down": dn_run.order}},
+                   "basis_order": {"up": up_run.order, "down": dn_run.order}},
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic("f64", dom, wl.name, dn_run.order),
+                     "frac": achieved / HBM_PEAK_GBPS,
+                     "traffic": measured_traffic("f64", dom, wl.name, dn_run.order, up_run.order),
                      "bytes": "one H.v's algorithmic bytes, 2pD + tables = %d, over this kernel's mean time"
                               % r64["hv_bytes"]},
         "hv_pair": {"ms": t_hv * 1e3, "alg_GBps": r64["hv_bytes"] / t_hv / 1e9,

@@ -152,6 +152,18 @@ int ed_pack_tables_complex(const int32_t *cols, const double *vals, const int32_
  * nnz: host, dim entries (>= 0); perm: host, dim entries. */
 int ed_hop_order(const int32_t *nnz, int64_t dim, int64_t *perm);
 
+/* ed_band_order: perm (position q holds state perm[q]) that numbers each
+ * state close to its hopping neighbours: reverse Cuthill-McKee on the graph
+ * whose edges are the table's nonzeros (a breadth-first sweep from a
+ * pseudo-peripheral state of fewest neighbours, each state's new neighbours
+ * taken fewest-neighbours first, then lowest index; one sweep per connected
+ * part; the whole order reversed).  The up-part kernel gathers, for a tile of
+ * consecutive rows, the rows of x at their neighbours; in this order those
+ * rows are fewer and closer together, so more of them are L2 hits.
+ * cols, nnz, width, layout: one species' ELL table as from ed_build_hopping
+ * (host); perm: host, dim entries.  nnz or a column out of range -> ED_EINVAL. */
+int ed_band_order(const int32_t *cols, const int32_t *nnz, int64_t dim, int32_t width, int layout, int64_t *perm);
+
 /* Reorder one species' basis and its exported ELL table (Fig. 2 format, as
  * from ed_build_hopping or ed_build_hopping_complex): position q of the
  * output is state perm[q] of the input, and each row's columns are renumbered

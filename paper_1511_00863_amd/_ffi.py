@@ -62,6 +62,7 @@ _PROTOS = {
                                        c_int, POINTER(c_uint32), POINTER(c_double), POINTER(c_int32)]),
     "ed_tridiag_lowest": (c_int, [POINTER(c_double), POINTER(c_double), c_int, POINTER(c_double)]),
     "ed_hop_order": (c_int, [POINTER(c_int32), c_int64, POINTER(c_int64)]),
+    "ed_band_order": (c_int, [POINTER(c_int32), POINTER(c_int32), c_int64, c_int32, c_int, POINTER(c_int64)]),
     "ed_permute_basis": (c_int, [POINTER(c_uint64), POINTER(c_int32), POINTER(c_double), POINTER(c_int32), c_int64,
                                  c_int32, c_int, c_int32, POINTER(c_int64), POINTER(c_uint64), POINTER(c_int32),
                                  POINTER(c_double), POINTER(c_int32)]),

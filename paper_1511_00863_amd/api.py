@@ -54,6 +54,16 @@ def hop_order(nnz) -> np.ndarray:
     return perm
 
 
+def band_order(table) -> np.ndarray:
+    """ed_band_order: reverse Cuthill-McKee positions of a basis from its ELL table (build_hopping output)."""
+    nnz = np.ascontiguousarray(table["nnz"], dtype=np.int32)
+    cols = np.ascontiguousarray(table["cols"], dtype=np.int32)
+    perm = np.zeros(nnz.size, dtype=np.int64)
+    check(lib().ed_band_order(_ptr(cols, c_int32), _ptr(nnz, c_int32), nnz.size, int(table["width"]),
+                              int(table["layout"]), _ptr(perm, c_int64)))
+    return perm
+
+
 def permute_basis(states, table, perm):
     """ed_permute_basis: (states, table) of a species in the order perm (real or complex exported tables)."""
     st = np.ascontiguousarray(states, dtype=np.uint64)
@@ -218,10 +228,11 @@ class SpinTables:
         """entry_bytes: 2 or 4 bytes per device table entry; by default 2 while dim <= 32767, else 4.
         amps: a complex amplitude per bond (term a c+_i c_j + h.c.); then the table is the complex format
         (32-bit entries indexing a table of at most 64 amplitudes) and the vectors are complex.
-        order: "ascending" (the basis of Sec. 2.1) or "hops" (sorted by hop count, ed_hop_order); then
-        position q holds ascending state perm[q], and vectors of this species follow that order."""
-        if order not in ("ascending", "hops"):
-            raise ValueError("order must be 'ascending' or 'hops'")
+        order: "ascending" (the basis of Sec. 2.1), "hops" (sorted by hop count, ed_hop_order) or "band"
+        (neighbours numbered close together, ed_band_order); then position q holds ascending state perm[q],
+        and vectors of this species follow that order."""
+        if order not in ("ascending", "hops", "band"):
+            raise ValueError("order must be 'ascending', 'hops' or 'band'")
         self.n_sites, self.n_part = n_sites, n_part
         self.bonds = [tuple(int(v) for v in b) for b in bonds]
         self.states = build_basis(n_sites, n_part)
@@ -234,8 +245,8 @@ class SpinTables:
         self._dev_perm = self._dev_inv = None
         if self.cplx:
             self.table = build_hopping_complex(n_sites, self.bonds, amps, self.states, ED_COL_MAJOR)
-            if order == "hops":
-                self.perm = hop_order(self.table["nnz"])
+            if order != "ascending":
+                self.perm = hop_order(self.table["nnz"]) if order == "hops" else band_order(self.table)
                 self.states, self.table = permute_basis(self.states, self.table, self.perm)
             self.width = self.table["width"]
             self.stride = table_stride(self.width)
@@ -244,8 +255,8 @@ class SpinTables:
             self.dev_amp = torch.from_numpy(self.amps.copy()).to(self.device)
         else:
             self.table = build_hopping(n_sites, self.bonds, self.states, ED_COL_MAJOR)
-            if order == "hops":
-                self.perm = hop_order(self.table["nnz"])
+            if order != "ascending":
+                self.perm = hop_order(self.table["nnz"]) if order == "hops" else band_order(self.table)
                 self.states, self.table = permute_basis(self.states, self.table, self.perm)
             self.width = self.table["width"]
             self.stride = table_stride(self.width)

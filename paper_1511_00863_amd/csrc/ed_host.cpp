@@ -368,6 +368,100 @@ int ed_hop_order(const int32_t *nnz, int64_t dim, int64_t *perm) {
     return ED_OK;
 }
 
+int ed_band_order(const int32_t *cols, const int32_t *nnz, int64_t dim, int32_t width, int layout, int64_t *perm) {
+    clear_error();
+    const char *who = "ed_band_order";
+    if (!nnz || !perm || dim < 1 || width < 0 || (width > 0 && !cols)) return set_error(ED_EINVAL, "%s: bad arguments", who);
+    if (layout != ED_ROW_MAJOR && layout != ED_COL_MAJOR) return set_error(ED_EINVAL, "%s: bad layout %d", who, layout);
+    if (dim > 0x7fffffffLL) return set_error(ED_EOVERFLOW, "%s: dim too large", who);
+    const int n = (int)dim;
+    // adjacency as compressed rows (the hopping graph is symmetric: a column of row r is a neighbour of r)
+    std::vector<int64_t> start(n + 1, 0);
+    for (int r = 0; r < n; ++r) {
+        if (nnz[r] < 0 || nnz[r] > width) return set_error(ED_EINVAL, "%s: nnz[%d] = %d", who, r, nnz[r]);
+        start[r + 1] = start[r] + nnz[r];
+    }
+    std::vector<int> adj(start[n]);
+    for (int r = 0; r < n; ++r)
+        for (int k = 0; k < nnz[r]; ++k) {
+            const int c = layout == ED_ROW_MAJOR ? cols[(int64_t)r * width + k] : cols[(int64_t)k * dim + r];
+            if (c < 0 || c >= n) return set_error(ED_EINVAL, "%s: column %d of row %d out of range", who, c, r);
+            adj[start[r] + k] = c;
+        }
+    // neighbours in the order the breadth-first sweep appends them: fewest neighbours first, then index
+    for (int r = 0; r < n; ++r)
+        std::sort(adj.begin() + start[r], adj.begin() + start[r + 1],
+                  [&](int a, int b) { return nnz[a] != nnz[b] ? nnz[a] < nnz[b] : a < b; });
+    std::vector<int> mark(n, -1), order;   // mark: the sweep that reached a vertex (-1: none yet)
+    order.reserve(n);
+    std::vector<int> level, next;
+    int sweep = 0;
+    // one breadth-first sweep over the unordered vertices from s: its levels, the last one kept in `level`;
+    // returns the number of levels.  Marks the vertices it reaches with `sweep`.
+    auto levels = [&](int s, std::vector<int> *out) {
+        ++sweep;
+        level.assign(1, s);
+        mark[s] = sweep;
+        if (out) out->push_back(s);
+        int depth = 1;
+        while (true) {
+            next.clear();
+            for (int v : level)
+                for (int64_t k = start[v]; k < start[v + 1]; ++k) {
+                    const int w = adj[k];
+                    if (mark[w] >= 0 && (mark[w] == sweep || mark[w] == 0)) continue;
+                    mark[w] = sweep;
+                    next.push_back(w);
+                    if (out) out->push_back(w);
+                }
+            if (next.empty()) return depth;
+            level.swap(next);
+            ++depth;
+        }
+    };
+    // mark 0: already placed in `order`.  Vertices of a sweep that were not placed get unmarked again.
+    std::vector<int> comp;
+    for (int seed = 0; seed < n; ++seed) {
+        if (mark[seed] == 0) continue;
+        // the component's vertices, and its vertex of fewest neighbours (lowest index among equals)
+        comp.clear();
+        levels(seed, &comp);
+        int s = seed;
+        for (int v : comp)
+            if (nnz[v] < nnz[s] || (nnz[v] == nnz[s] && v < s)) s = v;
+        // a pseudo-peripheral start (George and Liu): move to the last level's vertex of fewest neighbours
+        // while that lengthens the level structure
+        int depth = levels(s, nullptr);
+        for (int it = 0; it < 32; ++it) {
+            int c = level[0];
+            for (int v : level)
+                if (nnz[v] < nnz[c] || (nnz[v] == nnz[c] && v < c)) c = v;
+            const int d = levels(c, nullptr);
+            if (d <= depth) break;
+            s = c;
+            depth = d;
+        }
+        // Cuthill-McKee: breadth-first from s, each vertex's new neighbours in the sorted order
+        for (int v : comp) mark[v] = -1;
+        const size_t first = order.size();
+        order.push_back(s);
+        mark[s] = 0;
+        for (size_t i = first; i < order.size(); ++i) {
+            const int v = order[i];
+            for (int64_t k = start[v]; k < start[v + 1]; ++k) {
+                const int w = adj[k];
+                if (mark[w] == 0) continue;
+                mark[w] = 0;
+                order.push_back(w);
+            }
+        }
+    }
+    if ((int)order.size() != n) return set_error(ED_EINVAL, "%s: the table is not symmetric", who);
+    // reversed (reverse Cuthill-McKee)
+    for (int q = 0; q < n; ++q) perm[q] = order[n - 1 - q];
+    return ED_OK;
+}
+
 int ed_permute_basis(const uint64_t *states, const int32_t *cols, const double *vals, const int32_t *nnz,
                      int64_t dim, int32_t width, int layout, int32_t n_vals, const int64_t *perm,
                      uint64_t *states_out, int32_t *cols_out, double *vals_out, int32_t *nnz_out) {

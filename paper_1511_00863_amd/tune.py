@@ -1,7 +1,9 @@
 """Run the launch-configuration autotuner on the named workloads and record the
 chosen tiles in tune_cache.json (keyed by architecture, dims, table strides, dtype).
+The species' basis orders (up, down) are those the tuned runs use; a tile is
+correct in every order, only its speed depends on it.
 
-    python -m paper_1511_00863_amd.tune [--out PATH] torus4x4_8x8 torus4x4_5x5 ...
+    python -m paper_1511_00863_amd.tune [--out PATH] [--order UP,DOWN] torus4x4_8x8 torus4x4_5x5 ...
 """
 
 import json
@@ -13,21 +15,23 @@ from . import api
 from synth import start_vector, workload
 
 
-def tune_workloads(names, dtypes=("f64", "f32"), path=api.TUNE_CACHE):
+def tune_workloads(names, dtypes=("f64", "f32"), path=api.TUNE_CACHE, order=("ascending", "ascending")):
     cache = api.load_tune_cache(path)
     for name in names:
         wl = workload(name)
-        up = api.SpinTables(wl.n_sites, wl.bonds, wl.n_up, "cuda:0")
-        dn = up if wl.n_dn == wl.n_up else api.SpinTables(wl.n_sites, wl.bonds, wl.n_dn, "cuda:0")
+        up = api.SpinTables(wl.n_sites, wl.bonds, wl.n_up, "cuda:0", order=order[0])
+        dn = (up if wl.n_dn == wl.n_up and order[1] == order[0]
+              else api.SpinTables(wl.n_sites, wl.bonds, wl.n_dn, "cuda:0", order=order[1]))
         x_host = start_vector(wl.seed, up.dim * dn.dim)
         for dt in dtypes:
             h = api.Hamiltonian(up, dn, wl.t, wl.U, dt)
-            x = torch.from_numpy(x_host).to("cuda:0", h.torch_dtype)
+            x = h.to_basis_order(torch.from_numpy(x_host).to("cuda:0", h.torch_dtype))
             r = h.tune(x, reps=5)
             best_up = float(r["up_ms"][r["tile"] & 0xFF]) if r["tile"] & 0xFF else None
             best_dn = float(r["dn_ms"][r["tile"] >> 8]) if r["tile"] >> 8 else None
             cache[api.tune_key(h)] = {"tile": r["tile"], "params": h.tile_params(), "workload": name,
-                                      "up_ms": best_up, "dn_ms": best_dn}
+                                      "order": {"up": order[0], "down": order[1]}, "up_ms": best_up,
+                                      "dn_ms": best_dn}
             print("%s %s -> tile %d %s" % (name, dt, r["tile"], h.tile_params()), flush=True)
             del x, h
             torch.cuda.empty_cache()
@@ -38,7 +42,11 @@ def tune_workloads(names, dtypes=("f64", "f32"), path=api.TUNE_CACHE):
 
 if __name__ == "__main__":
     args = sys.argv[1:]
-    out = api.TUNE_CACHE
-    if args[:1] == ["--out"]:
-        out, args = args[1], args[2:]
-    tune_workloads(args or ["torus4x4_8x8"], path=out)
+    out, order = api.TUNE_CACHE, ("ascending", "ascending")
+    while args[:1] in (["--out"], ["--order"]):
+        if args[0] == "--out":
+            out = args[1]
+        else:
+            order = tuple(args[1].split(","))
+        args = args[2:]
+    tune_workloads(args or ["torus4x4_8x8"], path=out, order=order)

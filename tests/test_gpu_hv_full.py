@@ -1,7 +1,8 @@
 """The whole H x at the benchmark's size against the oracle's Eq. 4-5, element by element.
 
 4x4 periodic Hubbard at half filling, 8 + 8 (dim 165,636,900), U = 4, in the configuration the
-benchmark times: the down species in hop-count order and the tile from the tuning cache.  The device
+benchmark times: the up species in band order, the down species in hop-count order and the tile from the
+tuning cache.  The device
 result is mapped back to the ascending basis and compared with oracle.Model.hv over every element,
 float64 to 1e-12 and the float32 H.v to 2e-6 of max |H x| (float32 accumulation over up to 65 terms).
 """
@@ -29,7 +30,7 @@ def c5():
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 2e-6)])
 def test_c5_full_vector_tuned_tile_hop_order(c5, dtype, tol):
     w, m = c5
-    up = ed.SpinTables(w.n_sites, w.bonds, w.n_up, "cuda:0")
+    up = ed.SpinTables(w.n_sites, w.bonds, w.n_up, "cuda:0", order="band")
     dn = ed.SpinTables(w.n_sites, w.bonds, w.n_dn, "cuda:0", order="hops")
     h = ed.Hamiltonian(up, dn, w.t, w.U, dtype)
     src = ed.api.apply_tuned_tile(h, tune_if_missing=False)

@@ -1,5 +1,5 @@
 """Reordered bases on the device: H x, the Lanczos run and the vector permutation with a species in
-hop-count order, against the oracle in the ascending basis.
+hop-count order (ed_hop_order) or band order (ed_band_order), against the oracle in the ascending basis.
 
 In the order perm a species' hopping matrix is P H P^T, so for x_ordered = P x_ascending the result
 (H x)_ordered = P (H x)_ascending: element (p, q) of the reordered result is the oracle's element
@@ -29,7 +29,7 @@ CASES = [
     ("ring12_5x4", 12, ring_bonds(12), 5, 4),          # 792 x 495
     ("torus4x4_4x4", 16, torus_bonds(4, 4), 4, 4),     # 1820 x 1820: many tiles and workgroups
 ]
-ORDERS = [("ascending", "hops"), ("hops", "ascending"), ("hops", "hops")]
+ORDERS = [("ascending", "hops"), ("hops", "ascending"), ("hops", "hops"), ("band", "hops"), ("band", "band")]
 
 
 def _ham(ns, bonds, nu, nd, dtype, order, U=2.5, amps=None):
@@ -89,14 +89,15 @@ def test_every_down_tile_gives_the_same_bits_in_hop_order():
         assert torch.equal(h.hv(x), ref), (di, h.tile_params())
 
 
+@pytest.mark.parametrize("order", [("hops", "hops"), ("band", "hops")], ids=["hops-hops", "band-hops"])
 @pytest.mark.parametrize("case", CASES[:2], ids=[c[0] for c in CASES[:2]])
-def test_lanczos_in_hop_order_matches_oracle(case):
+def test_lanczos_in_hop_order_matches_oracle(case, order):
     """Alg. 1 from P f_1: the oracle's a_j, b_j on f_1, and E0 of the sector."""
     name, ns, bonds, nu, nd = case
     m = Model(ns, bonds, nu, nd, 1.0, 2.5)
-    h = _ham(ns, bonds, nu, nd, "f64", ("hops", "hops"))
+    h = _ham(ns, bonds, nu, nd, "f64", order)
     x_host, x = seeded_start(94, h.dim, "f64")
-    announce("lanczos hop order %s f64" % name)
+    announce("lanczos %s order %s f64" % ("-".join(order), name))
     r = h.ground_energy(h.to_basis_order(x), 40, tol=0.0)
     ref = lanczos(m.hv, x_host, 20)
     amax = np.max(np.abs(ref["a"]))
@@ -107,12 +108,13 @@ def test_lanczos_in_hop_order_matches_oracle(case):
     assert abs(rr["e0"] - e0) <= 1e-10 * abs(e0)
 
 
-def test_complex_hv_in_hop_order_matches_oracle():
+@pytest.mark.parametrize("order", [("hops", "hops"), ("band", "band")], ids=["hops-hops", "band-band"])
+def test_complex_hv_in_hop_order_matches_oracle(order):
     terms = checkerboard_terms(3, 3, 1.0, np.pi / 4, 0.3, 0.2)
     bonds, amps = [b for b, _ in terms], [a for _, a in terms]
     m = Model(18, bonds, 2, 2, 1.0, 2.5, amps)
     for dtype in ("f64", "f32"):
-        h = _ham(18, bonds, 2, 2, dtype, ("hops", "hops"), amps=amps)
+        h = _ham(18, bonds, 2, 2, dtype, order, amps=amps)
         x_host = start_vector_complex(95, h.dim)
         if dtype == "f32":
             x_host = x_host.astype(np.complex64).astype(np.complex128)
@@ -144,29 +146,31 @@ def test_batch_with_instances_in_hop_order():
     bonds = torus_bonds(4, 4)
     draws = batch_instances(6, 3000, fillings=(3, 4))
     res = {}
-    for order in ("ascending", "hops"):
+    for order in ("ascending", "hops", "band"):
         tabs = {n: ed.SpinTables(16, bonds, n, "cuda:0", order=order) for n in (3, 4)}
         hams = [ed.Hamiltonian(tabs[n], tabs[n], 1.0, U, "f32") for (U, n, s) in draws]
         f1s = []
         for h, (U, n, s) in zip(hams, draws):
             x = torch.from_numpy(start_vector(s, h.dim)).to("cuda:0", torch.float32)
-            f1s.append(h.to_basis_order(x) if order == "hops" else x)
+            f1s.append(h.to_basis_order(x) if order != "ascending" else x)
         announce("batch hop order %s" % order)
         r = ed.ground_energy_batch(hams, f1s, 400, tol=1e-7)
         assert np.all(r["status"] == 0)
         res[order] = r["e0"]
-    assert np.max(np.abs(res["hops"] - res["ascending"]) / np.abs(res["ascending"])) <= 1e-6
+    for order in ("hops", "band"):
+        assert np.max(np.abs(res[order] - res["ascending"]) / np.abs(res["ascending"])) <= 1e-6
 
 
+@pytest.mark.parametrize("up_order", ["ascending", "band"])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_full_size_half_filled_4x4_in_hop_order_sampled_elements(dtype):
+def test_full_size_half_filled_4x4_in_hop_order_sampled_elements(dtype, up_order):
     """4x4 torus, 8 + 8 (D = 165,636,900), down species in hop order, the tuned launch: elements of H x
     recomputed one by one by the oracle at the ascending positions they came from."""
     bonds = torus_bonds(4, 4)
-    h = ed.Hamiltonian.from_lattice(16, bonds, 8, 8, 1.0, 4.0, dtype, "cuda:0", order=("ascending", "hops"))
+    h = ed.Hamiltonian.from_lattice(16, bonds, 8, 8, 1.0, 4.0, dtype, "cuda:0", order=(up_order, "hops"))
     ed.api.apply_tuned_tile(h, tune_if_missing=False)
     x_host, x = seeded_start(5, h.dim, dtype)
-    announce("hv full torus4x4 8x8 hop order %s" % dtype)
+    announce("hv full torus4x4 8x8 %s/hop order %s" % (up_order, dtype))
     y = h.hv(h.to_basis_order(x)).double().cpu().numpy()
     del x
     rng = np.random.default_rng(97)

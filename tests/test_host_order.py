@@ -187,3 +187,109 @@ def test_spin_tables_order_option():
     assert h.order_bits == 3 and h.up is h.dn
     with pytest.raises(ValueError):
         ed.SpinTables(8, ring_bonds(8), 3, "cpu", order="random")
+
+
+def _cm_checks(adj, deg, perm):
+    """The order perm[::-1] is a Cuthill-McKee order of the graph adj: every connected part is contiguous
+    and starts at one vertex; every other vertex has an earlier neighbour, its parent (the earliest one);
+    parents never move back along the order (a breadth-first sweep); and the children of one parent come
+    fewest-neighbours first, then lowest index."""
+    n = len(adj)
+    order = perm[::-1]
+    pos = np.empty(n, dtype=np.int64)
+    pos[order] = np.arange(n)
+    last_parent = -1
+    for i, v in enumerate(order):
+        earlier = [pos[u] for u in adj[v] if pos[u] < i]
+        if not earlier:                      # the start of a connected part: nothing before it reaches it
+            assert all(pos[u] > i for u in adj[v])
+            last_parent = -1
+            continue
+        par = min(earlier)
+        assert par >= last_parent, (i, par, last_parent)
+        if par == last_parent:
+            prev = order[i - 1]
+            assert (deg[prev], prev) < (deg[v], v)
+        last_parent = par
+
+
+def _adjacency(h):
+    h = h.tocsr() if hasattr(h, "tocsr") else h
+    return [sorted(set(np.nonzero(np.asarray(h[r].todense() if hasattr(h[r], "todense") else h[r]).ravel())[0])
+                   - {r}) for r in range(h.shape[0])]
+
+
+def _bandwidth(adj, perm):
+    pos = np.empty(len(adj), dtype=np.int64)
+    pos[perm] = np.arange(len(adj))
+    return max((abs(int(pos[r]) - int(pos[c])) for r in range(len(adj)) for c in adj[r]), default=0)
+
+
+@pytest.mark.parametrize("layout", [ed.ED_ROW_MAJOR, ed.ED_COL_MAJOR])
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_band_order_is_reverse_cuthill_mckee_of_the_oracle_graph(case, layout):
+    """ed_band_order against the oracle's hopping matrix: a permutation, a Cuthill-McKee order reversed,
+    and no wider than the ascending order."""
+    _, ns, bonds, n = case
+    st = basis_states(ns, n)
+    adj = _adjacency(hopping_matrix(ns, bonds, st))
+    deg = np.array([len(a) for a in adj])
+    perm = ed.band_order(ed.build_hopping(ns, bonds, st, layout))
+    assert np.array_equal(np.sort(perm), np.arange(st.size))
+    _cm_checks(adj, deg, perm)
+    assert _bandwidth(adj, perm) <= _bandwidth(adj, np.arange(st.size))
+    # both layouts give the same order
+    other = ed.ED_COL_MAJOR if layout == ed.ED_ROW_MAJOR else ed.ED_ROW_MAJOR
+    assert np.array_equal(perm, ed.band_order(ed.build_hopping(ns, bonds, st, other)))
+
+
+def test_band_order_with_disconnected_parts():
+    """Two separate 4-site rings with two particles: three connected parts (2+0, 1+1, 0+2 particles), each
+    contiguous in the order."""
+    bonds = ring_bonds(4) + [(a + 4, b + 4) for a, b in ring_bonds(4)]
+    st = basis_states(8, 2)
+    adj = _adjacency(hopping_matrix(8, bonds, st))
+    deg = np.array([len(a) for a in adj])
+    perm = ed.band_order(ed.build_hopping(8, bonds, st))
+    assert np.array_equal(np.sort(perm), np.arange(st.size))
+    _cm_checks(adj, deg, perm)
+    left = np.array([bin(int(s) & 0xF).count("1") for s in st])   # particles on the first ring
+    runs = left[perm]
+    assert np.count_nonzero(np.diff(runs)) == 2                    # three contiguous parts
+
+
+def test_band_order_narrows_the_half_filled_4x4_up_graph():
+    """4x4 torus, 8 particles (12,870 states): the reordered graph's bandwidth is well below the
+    ascending order's."""
+    st = basis_states(16, 8)
+    tab = ed.build_hopping(16, torus_bonds(4, 4), st, ed.ED_ROW_MAJOR)
+    perm = ed.band_order(tab)
+    assert np.array_equal(np.sort(perm), np.arange(st.size))
+    cols = tab["cols"].reshape(st.size, tab["width"])
+    adj = [cols[r, :tab["nnz"][r]].tolist() for r in range(st.size)]
+    wa, wb = _bandwidth(adj, np.arange(st.size)), _bandwidth(adj, perm)
+    assert wb < 0.7 * wa, (wa, wb)
+
+
+def test_band_order_rejects_bad_tables():
+    lib = ed.lib()
+    p = lambda a, t: a.ctypes.data_as(ctypes.POINTER(t))  # noqa: E731
+    cols = np.array([1, 0], dtype=np.int32)
+    perm = np.zeros(2, dtype=np.int64)
+    assert lib.ed_band_order(p(cols, ctypes.c_int32), p(np.array([1, 2], dtype=np.int32), ctypes.c_int32), 2, 1,
+                             ed.ED_ROW_MAJOR, p(perm, ctypes.c_int64)) == _ffi.ED_EINVAL      # nnz above width
+    bad = np.array([1, 5], dtype=np.int32)
+    assert lib.ed_band_order(p(bad, ctypes.c_int32), p(np.array([1, 1], dtype=np.int32), ctypes.c_int32), 2, 1,
+                             ed.ED_ROW_MAJOR, p(perm, ctypes.c_int64)) == _ffi.ED_EINVAL      # column out of range
+    assert lib.ed_band_order(p(cols, ctypes.c_int32), p(np.array([1, 1], dtype=np.int32), ctypes.c_int32), 2, 1,
+                             ed.ED_ROW_MAJOR, p(perm, ctypes.c_int64)) == 0
+    assert sorted(perm.tolist()) == [0, 1]
+
+
+def test_spin_tables_band_order():
+    t = ed.SpinTables(16, torus_bonds(4, 4), 3, "cpu", order="band")
+    st = basis_states(16, 3)
+    assert np.array_equal(t.states, st[t.perm])
+    assert np.array_equal(t.perm, ed.band_order(ed.build_hopping(16, torus_bonds(4, 4), st)))
+    h = ed.Hamiltonian.from_lattice(16, torus_bonds(4, 4), 3, 3, 1.0, 4.0, "f64", "cpu", order=("band", "hops"))
+    assert h.order_bits == 3 and h.up is not h.dn
