@@ -112,10 +112,10 @@ def dn_order_for(args, dim_dn, cplx=False):
     return args.basis_order if dim_dn * (2 if cplx else 1) <= LDS_ROW_STATES else "ascending"
 
 
-def species_tables(ed, n_sites, bonds, n_up, n_dn, dev, dn_order, **kw):
-    """(up, down) SpinTables: the up species in ascending order, the down species in dn_order."""
-    up = ed.SpinTables(n_sites, bonds, n_up, dev, **kw)
-    if n_dn == n_up and dn_order == "ascending":
+def species_tables(ed, n_sites, bonds, n_up, n_dn, dev, dn_order, up_order="ascending", **kw):
+    """(up, down) SpinTables: the up species in up_order, the down species in dn_order."""
+    up = ed.SpinTables(n_sites, bonds, n_up, dev, order=up_order, **kw)
+    if n_dn == n_up and dn_order == up_order:
         return up, up
     return up, ed.SpinTables(n_sites, bonds, n_dn, dev, order=dn_order, **kw)
 
@@ -157,9 +157,10 @@ def scale_block(args):
     from synth import workload
     wl = workload("ring18_9x9")
     dev = "cuda:0"
-    tab, tdn = species_tables(ed, wl.n_sites, wl.bonds, wl.n_up, wl.n_dn, dev, "ascending")   # 48620-state rows
+    # 48620-state rows (beyond LDS: the down species stays ascending)
+    tab, tdn = species_tables(ed, wl.n_sites, wl.bonds, wl.n_up, wl.n_dn, dev, "ascending", args.up_order)
     out = {"workload": wl.name, "dim": tab.dim * tdn.dim, "U": wl.U, "table_entry_bytes": tab.entry_bytes,
-           "basis_order": {"up": "ascending", "down": tdn.order},
+           "basis_order": {"up": tab.order, "down": tdn.order},
            "start": "uniform(-1/2,1/2) from torch's device generator, seed %d, drawn in the run's order" % wl.seed}
     for dtype in ("f64", "f32"):
         h = ed.Hamiltonian(tab, tdn, wl.t, wl.U, dtype)
@@ -385,7 +386,8 @@ def batch_block(args):
     from synth import batch_instances, start_vector, torus_bonds
     bonds = torus_bonds(4, 4)
     draws = batch_instances(64, 1000)
-    tabs = {n: species_tables(ed, 16, bonds, n, n, "cuda:0", dn_order_for(args, comb(16, n))) for n in (3, 4, 5, 6)}
+    tabs = {n: species_tables(ed, 16, bonds, n, n, "cuda:0", dn_order_for(args, comb(16, n)), args.up_order)
+            for n in (3, 4, 5, 6)}
     hams = [ed.Hamiltonian(*tabs[n], 1.0, U, "f32") for (U, n, s) in draws]
     for h in hams:
         ed.api.apply_tuned_tile(h, tune_if_missing=False)
@@ -417,8 +419,9 @@ def batch_block(args):
         torch.cuda.synchronize()
         mix_ms += (time.perf_counter() - t0) * 1e3
         del x
-    small = small_batch(tabs_for=lambda n: species_tables(ed, 16, bonds, n, n, "cuda:0", dn_order_for(args, comb(16, n))))
-    return {"basis_order": {"up": "ascending", "down": args.basis_order}, "small_instances": small, "instances": 64, "total_dim": int(sum(h.dim for h in hams)), "wall_ms": r["wall_ms"],
+    small = small_batch(tabs_for=lambda n: species_tables(ed, 16, bonds, n, n, "cuda:0", dn_order_for(args, comb(16, n)),
+                                                          args.up_order))
+    return {"basis_order": {"up": args.up_order, "down": args.basis_order}, "small_instances": small, "instances": 64, "total_dim": int(sum(h.dim for h in hams)), "wall_ms": r["wall_ms"],
             "graph_used": r["graph_used"], "converged": int((r["status"] == 0).sum()),
             "max_steps_used": int(r["steps"].max()), "sequential_plain_f64_ms": seq_ms,
             "sequential_mixed_ms": mix_ms,
