@@ -45,14 +45,12 @@ __device__ __forceinline__ uint16_t bf16_bits(float f) {
     return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
 }
 __device__ __forceinline__ float bf16_val(uint16_t b) { return __builtin_bit_cast(float, (uint32_t)b << 16); }
-typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2;
 // two floats rounded to bfloat16 (nearest even, as bf16_bits for finite values) in one register, lo first:
 // the hardware conversion of gfx950
 __device__ __forceinline__ uint32_t bf16_pack(float lo, float hi) {
-    bf16x2 v;
-    v[0] = (__bf16)lo;
-    v[1] = (__bf16)hi;
-    return __builtin_bit_cast(uint32_t, v);
+    typedef float f32x2v __attribute__((ext_vector_type(2)));
+    typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2v{lo, hi}), bf16x2v));
 }
 // max(x, 0) in one integer max on the bits: a negative float (sign bit set) is a negative integer, a
 // non-negative one keeps its bits.  fmaxf of a raw accumulator value would canonicalise it first (two
@@ -62,7 +60,11 @@ __device__ __forceinline__ float relu(float x) {
 }
 __device__ __forceinline__ __bf16 as_bf(uint16_t b) { return __builtin_bit_cast(__bf16, b); }
 
-// LDS image of the weights (bfloat16) and biases (float32)
+// LDS image of the weights (bfloat16) and biases (float32).  The weight rows
+// are 256 (W2, W3) or 64 (W1) bytes long, so the 16 rows one A-operand read
+// touches would all start in the same LDS bank; each row's 8-byte (W2, W3) or
+// 16-byte (W1) pieces are therefore stored permuted by an XOR with the row
+// (w_at, w1_at), which puts the 16 rows of a read on distinct banks.
 struct MlpLds {
     uint16_t w1[kHid * kIn];      // [o][i]
     uint16_t w2[kHid * kHid];     // [o][i]   forward; transposed [i][o] in the backward kernel
@@ -71,11 +73,24 @@ struct MlpLds {
     float b4;
 };
 
+// LDS index of element (row, k) of a 128-column weight matrix: 4-element piece
+// k / 4 of the row XOR 2 (row % 16)
+__device__ __forceinline__ int w_at(int row, int k) {
+    return row * kHid + ((((k >> 2) ^ (2 * (row & 15))) << 2) | (k & 3));
+}
+// LDS index of element (row, k) of W1 (32 columns): 8-element piece k / 8 XOR (row / 4) % 4
+__device__ __forceinline__ int w1_at(int row, int k) {
+    return row * kIn + ((((k >> 3) ^ ((row >> 2) & 3)) << 3) | (k & 7));
+}
+
 __device__ void load_weights(const float *__restrict__ P, MlpLds &L, bool transpose) {
-    for (int k = threadIdx.x; k < kHid * kIn; k += blockDim.x) L.w1[k] = bf16_bits(P[oW1 + k]);
+    for (int k = threadIdx.x; k < kHid * kIn; k += blockDim.x) {
+        const int o = k / kIn, i = k - o * kIn;
+        L.w1[w1_at(o, i)] = bf16_bits(P[oW1 + k]);
+    }
     for (int k = threadIdx.x; k < kHid * kHid; k += blockDim.x) {
         const int o = k / kHid, i = k - o * kHid;
-        const int dst = transpose ? i * kHid + o : k;
+        const int dst = transpose ? w_at(i, o) : w_at(o, i);
         L.w2[dst] = bf16_bits(P[oW2 + k]);
         L.w3[dst] = bf16_bits(P[oW3 + k]);
     }
@@ -90,26 +105,18 @@ __device__ void load_weights(const float *__restrict__ P, MlpLds &L, bool transp
 }
 
 // A operand of a 128-wide layer: rows 16*ob + (lane % 16) of w ([row][col] with
-// 128 columns), virtual k block kb under the permuted map
+// 128 columns, stored by w_at), virtual k block kb under the permuted map
 __device__ __forceinline__ bf16x8 a_hidden(const uint16_t *w, int ob, int kb, int lane) {
     const int row = 16 * ob + (lane & 15), g = lane >> 4;
-    const uint16_t *p = w + row * kHid + 32 * kb + 4 * g;
-    const uint2 lo = *reinterpret_cast<const uint2 *>(p);        // features 32kb+4g .. +3
-    const uint2 hi = *reinterpret_cast<const uint2 *>(p + 16);   // features 32kb+16+4g .. +3
-    bf16x8 a;
-    a[0] = as_bf(lo.x & 0xFFFF); a[1] = as_bf(lo.x >> 16); a[2] = as_bf(lo.y & 0xFFFF); a[3] = as_bf(lo.y >> 16);
-    a[4] = as_bf(hi.x & 0xFFFF); a[5] = as_bf(hi.x >> 16); a[6] = as_bf(hi.y & 0xFFFF); a[7] = as_bf(hi.y >> 16);
-    return a;
+    const uint2 lo = *reinterpret_cast<const uint2 *>(w + w_at(row, 32 * kb + 4 * g));        // features 32kb+4g .. +3
+    const uint2 hi = *reinterpret_cast<const uint2 *>(w + w_at(row, 32 * kb + 16 + 4 * g));   // 32kb+16+4g .. +3
+    return __builtin_bit_cast(bf16x8, make_uint4(lo.x, lo.y, hi.x, hi.y));
 }
 
-// A operand of layer 1 (32 inputs, natural k order)
+// A operand of layer 1 (32 inputs, natural k order; W1 stored by w1_at)
 __device__ __forceinline__ bf16x8 a_first(const uint16_t *w1, int ob, int lane) {
     const int row = 16 * ob + (lane & 15), g = lane >> 4;
-    const uint4 q = *reinterpret_cast<const uint4 *>(w1 + row * kIn + 8 * g);
-    bf16x8 a;
-    a[0] = as_bf(q.x & 0xFFFF); a[1] = as_bf(q.x >> 16); a[2] = as_bf(q.y & 0xFFFF); a[3] = as_bf(q.y >> 16);
-    a[4] = as_bf(q.z & 0xFFFF); a[5] = as_bf(q.z >> 16); a[6] = as_bf(q.w & 0xFFFF); a[7] = as_bf(q.w >> 16);
-    return a;
+    return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(w1 + w1_at(row, 8 * g)));
 }
 
 // B operands of the next layer from eight 16x16 output tiles (bf16 bits)
@@ -263,12 +270,37 @@ __device__ __forceinline__ void layer_hidden_nt(const uint16_t *w, const float *
     }
 }
 
+// ReLU on two bfloat16 values in one register: a negative bfloat16 is a
+// negative 16-bit integer, so a packed integer max with zero clears it and keeps
+// the rest (the same bits as rounding the ReLU of the float32 values).
+__device__ __forceinline__ uint32_t relu_pk(uint32_t v) {
+    typedef short short2v __attribute__((ext_vector_type(2)));
+    const short2v r = __builtin_elementwise_max(__builtin_bit_cast(short2v, v), short2v{0, 0});
+    return __builtin_bit_cast(uint32_t, r);
+}
+
+// A operand of the output layer (128 -> 1) as a 16-row product whose row 0 is
+// W4 (bfloat16) and rows 1-15 are zero, under the permuted k map of a_hidden:
+// row 0 of the 16x16 result is psi of the tile's 16 samples.
+__device__ __forceinline__ bf16x8 a_out(const uint16_t *w4b, int kb, int lane) {
+    const int g = lane >> 4;
+    const uint2 lo = *reinterpret_cast<const uint2 *>(w4b + 32 * kb + 4 * g);
+    const uint2 hi = *reinterpret_cast<const uint2 *>(w4b + 32 * kb + 16 + 4 * g);
+    const uint32_t keep = (lane & 15) == 0 ? ~0u : 0u;
+    return __builtin_bit_cast(bf16x8, make_uint4(lo.x & keep, lo.y & keep, hi.x & keep, hi.y & keep));
+}
+
+// At most 256 VGPRs (two waves per SIMD, which is also what the weights' LDS
+// image allows: two workgroups per CU).
 template <typename OUT, int NT>
-__global__ __launch_bounds__(256) void k_mlp_infer(const float *__restrict__ P, const uint64_t *__restrict__ st_up,
-                                                   const uint64_t *__restrict__ st_dn, int64_t n, int dim_dn,
-                                                   OUT *__restrict__ out) {
+__global__ __launch_bounds__(256, 2) void k_mlp_infer(const float *__restrict__ P, const uint64_t *__restrict__ st_up,
+                                                      const uint64_t *__restrict__ st_dn, int64_t n, int dim_dn,
+                                                      OUT *__restrict__ out) {
     __shared__ MlpLds L;
+    __shared__ uint16_t w4b[kHid];
     load_weights(P, L, false);
+    for (int k = threadIdx.x; k < kHid; k += blockDim.x) w4b[k] = bf16_bits(P[oW4 + k]);
+    __syncthreads();
     const int lane = threadIdx.x & 63, g = lane >> 4, col = lane & 15;
     const int64_t ngroup = (n + 16 * NT - 1) / (16 * NT);
     const int64_t wstride = (int64_t)gridDim.x * (blockDim.x >> 6);
@@ -296,39 +328,35 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const float *__restrict__ P, 
             for (int q = 0; q < NT; ++q)
                 c[q][ob] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[q][0], f32x4{bv.x, bv.y, bv.z, bv.w}, 0, 0, 0);
         }
-        uint32_t hp[NT][8][2];
 #pragma unroll
         for (int layer = 0; layer < 3; ++layer) {
             if (layer > 0) layer_hidden_nt<NT>(layer == 1 ? L.w2 : L.w3, layer == 1 ? L.b2 : L.b3, b, c, lane);
+            // activations: bfloat16 pairs (rounded, then ReLU on the pair), which is also the register layout
+            // of the next layer's B operand
 #pragma unroll
-            for (int q = 0; q < NT; ++q) {
-#pragma unroll
-                for (int ob = 0; ob < 8; ++ob) {
-                    hp[q][ob][0] = bf16_pack(relu(c[q][ob][0]), relu(c[q][ob][1]));
-                    hp[q][ob][1] = bf16_pack(relu(c[q][ob][2]), relu(c[q][ob][3]));
-                }
+            for (int q = 0; q < NT; ++q)
 #pragma unroll
                 for (int kb = 0; kb < 4; ++kb)
-                    b[q][kb] = __builtin_bit_cast(bf16x8, make_uint4(hp[q][2 * kb][0], hp[q][2 * kb][1],
-                                                                     hp[q][2 * kb + 1][0], hp[q][2 * kb + 1][1]));
-            }
+                    b[q][kb] = __builtin_bit_cast(
+                        bf16x8, make_uint4(relu_pk(bf16_pack(c[q][2 * kb][0], c[q][2 * kb][1])),
+                                           relu_pk(bf16_pack(c[q][2 * kb][2], c[q][2 * kb][3])),
+                                           relu_pk(bf16_pack(c[q][2 * kb + 1][0], c[q][2 * kb + 1][1])),
+                                           relu_pk(bf16_pack(c[q][2 * kb + 1][2], c[q][2 * kb + 1][3]))));
         }
-        // layer 4 (128 -> 1): float32 dot of the bf16 activations with bf16 weights
+        // layer 4 (128 -> 1) on the matrix cores: row 0 of W4 times the tile, float32 accumulation
+        f32x4 o[NT];
+#pragma unroll
+        for (int q = 0; q < NT; ++q) o[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) {
+            const bf16x8 a = a_out(w4b, kb, lane);
+#pragma unroll
+            for (int q = 0; q < NT; ++q) o[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[q][kb], o[q], 0, 0, 0);
+        }
 #pragma unroll
         for (int q = 0; q < NT; ++q) {
-            float part = 0.f;
-#pragma unroll
-            for (int ob = 0; ob < 8; ++ob)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const uint32_t w = hp[q][ob][i >> 1];
-                    const float hv = __builtin_bit_cast(float, (i & 1) ? (w & 0xFFFF0000u) : (w << 16));
-                    part += hv * L.w4[16 * ob + 4 * g + i];
-                }
-            part += __shfl_xor(part, 16, 64);
-            part += __shfl_xor(part, 32, 64);
             const int64_t s = (grp * NT + q) * 16 + col;
-            if (g == 0 && s < n) out[s] = static_cast<OUT>(part + L.b4);
+            if (g == 0 && s < n) out[s] = static_cast<OUT>(o[q][0] + L.b4);
         }
     }
 }
