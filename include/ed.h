@@ -395,7 +395,7 @@ int ed_batch_workspace_size(const ed_batch_item *items, int32_t n, int32_t max_s
  * the steps, barrier waits included).  ws: ed_batch_workspace_size bytes,
  * 256-byte aligned.  Synchronises `stream`.  Returns ED_NOT_CONVERGED if any item
  * did not converge.  Limits: per-spin dims <= 32767, rows (dim_dn) of at
- * most 10240 floats, table strides <= 32 (both species), both species must
+ * most 8192 floats, table strides <= 32 (both species), both species must
  * hop. */
 int ed_ground_energy_batch(const ed_batch_item *items, int32_t n, int32_t max_steps, double tol, void *ws,
                            int64_t ws_bytes, void *stream, int32_t use_graph, double *e0, int32_t *steps,

@@ -27,7 +27,7 @@ namespace ed {
 
 constexpr int kBatchBlock = 256;
 constexpr int kBatchUpRows = 64;            // rows per up tile at least: amortises the queue's atomic and barriers
-constexpr int kBatchLds = 40 * 1024;        // rows of up to 10240 floats; three workgroups per CU
+constexpr int kBatchLds = 32 * 1024;        // rows of up to 8192 floats; four workgroups per CU
 constexpr int kBatchShm = kBatchLds + 16;   // the rows and the zero after a single row
 constexpr int64_t kUpdChunk = 65536;         // elements per update tile
 constexpr int kConverged = 10;
@@ -186,7 +186,7 @@ __device__ double ritz_lowest_wave(const double *a, const double *boff, int m) {
     return 0.5 * (lo + hi);
 }
 
-__global__ __launch_bounds__(kBatchBlock, 3) void k_batch(BInst *__restrict__ inst, int ni, double *__restrict__ part,
+__global__ __launch_bounds__(kBatchBlock, 4) void k_batch(BInst *__restrict__ inst, int ni, double *__restrict__ part,
                                                        double *__restrict__ part2, GridBar *gb, int max_steps,
                                                        double tol) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -569,7 +569,7 @@ static int plan_batch(const ed_batch_item *items, int n, int32_t max_steps, Batc
         // the persistent kernel's registers serve every phase: its tiles hold at most 4 table chunks
         if (h.w_dn > 32 || h.w_up > 32) return set_error(ED_EOVERFLOW, "ed_ground_energy_batch: table stride above 32");
         if (h.w_up == 0) return set_error(ED_EINVAL, "ed_ground_energy_batch: item %d has no up-spin hopping", i);
-        if (h.dim_dn * 4 > kBatchLds) return set_error(ED_EOVERFLOW, "ed_ground_energy_batch: rows above 40 KB");
+        if (h.dim_dn * 4 > kBatchLds) return set_error(ED_EOVERFLOW, "ed_ground_energy_batch: rows above 32 KB");
         if (fill_ptrs) {
             const ed_batch_item &it = items[i];
             if (!it.f1 || !it.vec[0] || !it.vec[1] || !it.vec[2] || !it.a || !it.b)
