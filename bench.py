@@ -232,13 +232,15 @@ def complex_block(args):
            "paper_k40_ms_per_step": {"f64": 712.0, "f32": 425.0}}
     for dtype in ("f64", "f32"):
         h = ed.Hamiltonian(tab, tdn, wl.t, wl.U, dtype)
+        src = ed.api.apply_tuned_tile(h, tune_if_missing=False)
         x = start_in_order(h, x_host, dev)
         ms, per, _ = time_run(h, x, 3, args.complex_steps, 3)
         es = 16 if dtype == "f64" else 8
         dn_bytes = 4 * es * h.dim + tdn.dim * tdn.stride * 4 + 8 * 2 * tdn.dim
         out[dtype] = {"steps_per_s": 1000.0 / ms, "ms_per_step": ms, "kernel_ms": per,
                       "k_down_alg_GBps": dn_bytes / (per["k_down"] * 1e-3) / 1e9,
-                      "up_alg_GBps": (2 * es * h.dim) / (per["k_up"] * 1e-3) / 1e9}
+                      "up_alg_GBps": (2 * es * h.dim) / (per["k_up"] * 1e-3) / 1e9,
+                      "tile": {"id": h.tile, "source": src, **h.tile_params()}}
         del x, h
         torch.cuda.empty_cache()
     return out

@@ -203,8 +203,8 @@ int ed_tridiag_lowest_vector(const double *a, const double *b, int m, double *e0
  * of the device calls holds dim_up*dim_dn complex numbers as interleaved
  * (re, im) pairs of dtype (so 2*dim_up*dim_dn reals).  a_j and b_j stay real
  * (H is Hermitian; a_j = Re f_j^dagger q).  Complex instances are accepted by
- * ed_hv, the Lanczos calls and ed_ground_state (gauge_index = -1 only);
- * ed_tune, the batch, the start-vector network and the observables return
+ * ed_hv, the Lanczos calls, ed_ground_state (gauge_index = -1 only) and
+ * ed_tune; the batch, the start-vector network and the observables return
  * ED_EINVAL for them.  cplx = 0: amp_up/amp_dn are ignored.
  * order: 0 when both bases are ascending (ed_build_basis); set bit 0 / bit 1
  * when the up / down tables and states come from ed_permute_basis.  Every
@@ -255,9 +255,13 @@ int ed_permute_vector(const ed_ham *h, const int64_t *perm_up, const int64_t *pe
  * after one warm-up, and returns in *tile the id of the fastest combination,
  * to be stored in ed_ham.tile.  The down-part kernel is timed as in a
  * Lanczos step.  x, y: as for ed_hv (y is overwritten); ws: device
- * workspace of ed_workspace_size(h, 2) bytes.
+ * workspace of ed_workspace_size(h, 2) bytes.  For complex instances the
+ * up-part kernel takes only the rows per tile and the down-part kernel only
+ * the workgroup size (one row per workgroup), so one candidate per distinct
+ * value is timed.
  * ms_up (n_up doubles) / ms_dn (n_dn doubles), may be NULL: average ms per
- * candidate index, -1 where a candidate does not apply (see ed_tile_count).
+ * candidate index, -1 where a candidate does not apply or repeats an earlier
+ * launch (see ed_tile_count).
  * Synchronises `stream`. */
 int ed_tune(const ed_ham *h, const void *x, void *y, void *ws, void *stream, int32_t reps, int32_t *tile,
             double *ms_up, double *ms_dn);

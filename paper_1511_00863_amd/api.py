@@ -477,8 +477,6 @@ def apply_tuned_tile(ham: "Hamiltonian", x=None, path: str = TUNE_CACHE, tune_if
     """Set ham.tile from the tuning cache, or run ed_tune when the key is absent.
 
     Returns "cache" or "tuned" (or "default" when missing and tune_if_missing is False)."""
-    if ham.cplx:   # complex amplitudes run a fixed launch shape (ed_tune takes real instances)
-        return "default"
     entry = load_tune_cache(path).get(tune_key(ham))
     if entry is not None:
         ham.tile = int(entry["tile"])

@@ -1101,10 +1101,19 @@ static int tune_impl(const ed_ham *h, const T *x, T *y, const WsLayout &w, int r
     int rc = ED_OK;
     double best_up = 1e300, best_dn = 1e300;
     int bu = 0, bd = 0;
+    // complex instances: k_upc takes only the rows per tile from a tile and
+    // k_downc only the workgroup size, so one candidate per distinct value
+    std::vector<int> seen_rc, seen_block;
+    auto first_of = [](std::vector<int> &seen, int v) {
+        if (std::find(seen.begin(), seen.end(), v) != seen.end()) return false;
+        seen.push_back(v);
+        return true;
+    };
     for (int ui = 1; ui < kNumUp && rc == ED_OK; ++ui) {
         const Tile tl = resolve_tile_id(h, ui);
         if (ms_up) ms_up[ui] = -1.0;
-        if (tl.up_wlog2 != kUpTiles[ui].wlog2) continue;   // clamped duplicate of a narrower stripe
+        if (h->cplx ? !first_of(seen_rc, tl.up_rc) : tl.up_wlog2 != kUpTiles[ui].wlog2)
+            continue;   // the same launch as an earlier candidate (a clamped stripe, or complex)
         rc = launch_up<T>(h, tl, x, y, w.ctr, nullptr, 0, 0, s);
         if (rc) break;
         rc = hip_check(hipEventRecord(e0, s), "hipEventRecord");
@@ -1132,9 +1141,14 @@ static int tune_impl(const ed_ham *h, const T *x, T *y, const WsLayout &w, int r
     for (int di = 1; di < kNumDn && rc == ED_OK; ++di) {
         const Tile tl = resolve_tile_id(h, di << 8);
         if (ms_dn) ms_dn[di] = -1.0;
-        if (kDnTiles[di].rpb > 0 && (int64_t)kDnTiles[di].rpb * h->dim_dn * (int64_t)sizeof(T) > kLdsBudget) continue;
-        if (kDnTiles[di].rpb > h->dim_up) continue;
-        if (tl.dn_block != kDnTiles[di].block) continue;   // clamped duplicate of a smaller workgroup
+        if (h->cplx) {
+            if (!first_of(seen_block, std::min(tl.dn_block, 1024))) continue;   // one row per workgroup
+        } else {
+            if (kDnTiles[di].rpb > 0 && (int64_t)kDnTiles[di].rpb * h->dim_dn * (int64_t)sizeof(T) > kLdsBudget)
+                continue;
+            if (kDnTiles[di].rpb > h->dim_up) continue;
+            if (tl.dn_block != kDnTiles[di].block) continue;   // clamped duplicate of a smaller workgroup
+        }
         rc = launch_down<T, SM>(h, tl, x, y, x, w.y, w.hdr, w.part, 2, s);
         if (rc) break;
         rc = hip_check(hipEventRecord(e0, s), "hipEventRecord");
@@ -1230,7 +1244,7 @@ int ed_tile_params(int32_t tile, const ed_ham *h, int32_t *params) {
 int ed_tune(const ed_ham *h, const void *x, void *y, void *ws, void *stream, int32_t reps, int32_t *tile,
             double *ms_up, double *ms_dn) {
     clear_error();
-    int rc = check_real(h, "ed_tune");
+    int rc = check_ham(h, "ed_tune");
     if (rc) return rc;
     rc = ensure_attrs();
     if (rc) return rc;

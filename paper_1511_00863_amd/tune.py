@@ -12,17 +12,18 @@ import sys
 import torch
 
 from . import api
-from synth import start_vector, workload
+from synth import start_vector, start_vector_complex, workload
 
 
 def tune_workloads(names, dtypes=("f64", "f32"), path=api.TUNE_CACHE, order=("ascending", "ascending")):
     cache = api.load_tune_cache(path)
     for name in names:
         wl = workload(name)
-        up = api.SpinTables(wl.n_sites, wl.bonds, wl.n_up, "cuda:0", order=order[0])
+        amps = list(wl.amps) if wl.amps else None
+        up = api.SpinTables(wl.n_sites, wl.bonds, wl.n_up, "cuda:0", order=order[0], amps=amps)
         dn = (up if wl.n_dn == wl.n_up and order[1] == order[0]
-              else api.SpinTables(wl.n_sites, wl.bonds, wl.n_dn, "cuda:0", order=order[1]))
-        x_host = start_vector(wl.seed, up.dim * dn.dim)
+              else api.SpinTables(wl.n_sites, wl.bonds, wl.n_dn, "cuda:0", order=order[1], amps=amps))
+        x_host = (start_vector_complex if amps else start_vector)(wl.seed, up.dim * dn.dim)
         for dt in dtypes:
             h = api.Hamiltonian(up, dn, wl.t, wl.U, dt)
             x = h.to_basis_order(torch.from_numpy(x_host).to("cuda:0", h.torch_dtype))

@@ -121,9 +121,31 @@ def test_real_only_calls_reject_complex_instances():
     _, x = _start(105, h.dim, "f64")
     announce("complex rejections")
     with pytest.raises(ed.EdError):
-        h.tune(x, reps=1)
-    with pytest.raises(ed.EdError):
         h.occupation_moments(x, 18)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_complex_tiles_give_the_same_bits_and_tune(dtype):
+    """Every tile the autotuner times on a complex instance (rows per up tile, down workgroup size) gives
+    the same H x bits as the default tile, and the tuner returns one of them."""
+    h = _ham(18, CB_BONDS, CB_AMPS, 3, 2, 4.0, dtype)
+    _, x = _start(106, h.dim, dtype)
+    announce("complex tiles checker18 3+2 %s" % dtype)
+    h.tile = 0
+    ref = h.hv(x).clone()
+    r = h.tune(x, reps=1, apply=False)
+    ups = [i for i, m in enumerate(r["up_ms"]) if m > 0]
+    dns = [i for i, m in enumerate(r["dn_ms"]) if m > 0]
+    assert ups and dns
+    rcs = [h.tile_params(ui)["up_rows"] for ui in ups]
+    assert len(set(rcs)) == len(rcs)                  # one candidate per distinct rows-per-tile
+    for ui in ups:
+        for di in dns:
+            h.tile = ui | (di << 8)
+            assert torch.equal(h.hv(x), ref), (ui, di, h.tile_params())
+    assert (r["tile"] & 0xFF) in ups and (r["tile"] >> 8) in dns
+    h.tile = 0
+    assert ed.api.tune_key(h).endswith("c128" if dtype == "f64" else "c64")
 
 
 # ---------------------------------------------------------------------------
