@@ -127,21 +127,38 @@ def start_in_order(h, x_host, dev):
     return h.to_basis_order(x) if h.order_bits else x
 
 
-# the step kernels' sources: the traffic record is valid only for these exact bytes
-TRAFFIC_SOURCES = ("ed_device.hip", "ed_common.h")
+# the step kernels' sources: the traffic record is valid only for these exact bytes (of ed_device.hip, the part
+# above the line that opens its host side: the step kernels and their launch shapes)
+TRAFFIC_SOURCES = ("ed_device.hip", "ed_common.h", "ed_launch.h")
+HOST_SIDE_MARK = b"// ---------------------------------------------------------------------------\n// Host side of the runs:"
+
+
+def traffic_source_hash():
+    """sha256 prefix of the step kernels' sources, as measured_traffic.json records it."""
+    import hashlib
+    here = os.path.join(ROOT, "paper_1511_00863_amd", "csrc")
+    parts = []
+    for f in TRAFFIC_SOURCES:
+        b = open(os.path.join(here, f), "rb").read()
+        if f == "ed_device.hip":
+            cut = b.find(HOST_SIDE_MARK)
+            if cut < 0:
+                raise OSError("ed_device.hip has no host-side mark")
+            b = b[:cut]
+        parts.append(b)
+    return hashlib.sha256(b"".join(parts)).hexdigest()[:16]
 
 
 def measured_traffic(dtype, kernel, workload_name, basis_order, up_order="ascending"):
     """HBM bytes per launch from the committed counter record, if it matches this kernel source, workload and
     the two species' basis orders."""
-    import hashlib
     here = os.path.join(ROOT, "paper_1511_00863_amd")
     try:
         rec = json.load(open(os.path.join(here, "measured_traffic.json")))
-        src = b"".join(open(os.path.join(here, "csrc", f), "rb").read() for f in TRAFFIC_SOURCES)
+        digest = traffic_source_hash()
     except OSError:
         return None
-    if (hashlib.sha256(src).hexdigest()[:16] != rec.get("source_sha256_prefix") or rec.get("workload") != workload_name
+    if (digest != rec.get("source_sha256_prefix") or rec.get("workload") != workload_name
             or rec.get("basis_order_down", "ascending") != basis_order
             or rec.get("basis_order_up", "ascending") != up_order):
         return None

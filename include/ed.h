@@ -359,9 +359,11 @@ int ed_ground_energy_noalloc(const ed_ham *h, ed_lanczos *st, const void *f1, do
  * the host, pass 2 replays the identical steps and accumulates
  * v = sum_k y_k f_k, then v is normalised (float64 norm).  v: device, h->dtype,
  * dim elements, distinct from the three Lanczos vectors.  gauge_index >= 0
- * fixes the arbitrary global sign: v[gauge_index] >= 0 afterwards (-1: no
- * gauge).  ws must hold ed_workspace_size(h, m).  *e0 = lowest eigenvalue
- * of T_m. */
+ * fixes the arbitrary global sign: v[gauge_index] >= 0 afterwards, or, when
+ * |v[gauge_index]| is below 1e-3 of max |v_i| (its sign then carries no
+ * information), the largest-magnitude element (the lowest index among equal
+ * magnitudes) is made positive instead; -1: no gauge.  ws must hold
+ * ed_workspace_size(h, m).  *e0 = lowest eigenvalue of T_m. */
 int ed_ground_state(const ed_ham *h, ed_lanczos *st, const void *f1, int32_t m, int64_t gauge_index, void *v,
                     void *ws, void *stream, double *e0, int32_t *steps);
 

@@ -452,7 +452,8 @@ class Hamiltonian:
         return run.ground_energy(f1, tol, check_every, stream)
 
     def ground_state(self, f1, m: int, gauge_index: int = -1, stream=None):
-        """Two-pass ground-state vector: returns (E0, steps, v) with |v| = 1 and v[gauge_index] >= 0."""
+        """Two-pass ground-state vector: returns (E0, steps, v) with |v| = 1 and v[gauge_index] >= 0 (or, where
+        that element is below 1e-3 of the largest magnitude, the largest-magnitude element positive)."""
         run = LanczosRun(self, m)
         return run.ground_state(f1, m, gauge_index, stream)
 

@@ -186,3 +186,22 @@ def test_ground_energy_newest_vector_after_partial_chunk():
     assert torch.equal(ra.f_cur, rb.f_cur) and torch.equal(ra.f_prev, rb.f_prev)
     fa = ra.f_cur.cpu().numpy()
     assert abs(np.linalg.norm(fa) - ga["b"][100]) <= 1e-12 * ga["b"][100]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_ground_state_gauge_follows_the_oracle_rule(dtype):
+    """The device's gauge against oracle.lanczos.fix_gauge on the device's own ungauged vector: at a reference
+    element of normal size, and at one below 1e-3 of the largest magnitude (the 8-ring's ground state has
+    symmetry zeros), where the largest-magnitude element decides."""
+    from oracle.lanczos import fix_gauge
+    h = ham(8, ring_bonds(8), 4, 4, 1.0, 4.0, dtype)
+    _, x = seeded_start(1, h.dim, dtype)
+    announce("ground state gauge ring8 4+4 %s" % dtype)
+    _, _, v0 = h.ground_state(x, 80, gauge_index=-1)
+    v0 = v0.double().cpu().numpy()
+    r = np.abs(v0) / np.abs(v0).max()
+    small = int(np.nonzero(r < 1e-4)[0][0])
+    big = int(np.argmax(r > 0.5))
+    for k in (big, small):
+        _, _, v = h.ground_state(x, 80, gauge_index=k)
+        assert np.array_equal(v.double().cpu().numpy(), fix_gauge(v0, k)), k

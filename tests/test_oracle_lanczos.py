@@ -123,3 +123,19 @@ def test_lowest_eigvec_T():
     y = lowest_eigvec_T(a, b)
     T = np.diag(a) + np.diag(b, 1) + np.diag(b, -1)
     assert np.linalg.norm(T @ y - tridiag_lowest(a, b) * y) < 1e-12
+
+
+def test_fix_gauge_follows_the_stated_reading():
+    """The eigenvector gauge: the reference amplitude is made positive; below 1e-3 of the largest magnitude
+    the largest-magnitude entry decides instead, the lowest index among equal magnitudes."""
+    g = fix_gauge(np.array([-0.5, 0.3, 0.8]), 0)
+    assert g.tolist() == [0.5, -0.3, -0.8]                       # negative reference: flipped
+    assert fix_gauge(np.array([0.5, -0.3]), 0).tolist() == [0.5, -0.3]   # positive reference: kept
+    g = fix_gauge(np.array([1e-4, 0.2, -0.9]), 0)                # reference too small: entry 2 decides
+    assert g.tolist() == [-1e-4, -0.2, 0.9]
+    g = fix_gauge(np.array([-1e-3, 1.0]), 0)                     # exactly 1e-3 of the largest: the reference decides
+    assert g.tolist() == [1e-3, -1.0]
+    g = fix_gauge(np.array([0.0, -0.7, 0.7]), 0)                 # tie in magnitude: the lower index decides
+    assert g.tolist() == [-0.0, 0.7, -0.7]
+    g = fix_gauge(np.array([0.25, -0.5, 0.75]), 2)               # any reference index
+    assert g.tolist() == [0.25, -0.5, 0.75]
