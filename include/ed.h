@@ -254,7 +254,10 @@ int ed_permute_vector(const ed_ham *h, const int64_t *perm_up, const int64_t *pe
  * rows per workgroup) on y = H x with h's sizes, `reps` timed launches each
  * after one warm-up, and returns in *tile the id of the fastest combination,
  * to be stored in ed_ham.tile.  The down-part kernel is timed as in a
- * Lanczos step.  x, y: as for ed_hv (y is overwritten); ws: device
+ * Lanczos step, each timed launch after an untimed up part.  x, y: as for
+ * ed_hv (y is overwritten); p: device vector of the same size standing in
+ * for f_{j-1} (read only; not y), or NULL to let x stand in (its reads then
+ * hit in cache and the down-part times come out short); ws: device
  * workspace of ed_workspace_size(h, 2) bytes.  For complex instances the
  * up-part kernel takes only the rows per tile and the down-part kernel only
  * the workgroup size (one row per workgroup), so one candidate per distinct
@@ -263,17 +266,19 @@ int ed_permute_vector(const ed_ham *h, const int64_t *perm_up, const int64_t *pe
  * candidate index, -1 where a candidate does not apply or repeats an earlier
  * launch (see ed_tile_count).
  * Synchronises `stream`. */
-int ed_tune(const ed_ham *h, const void *x, void *y, void *ws, void *stream, int32_t reps, int32_t *tile,
-            double *ms_up, double *ms_dn);
+int ed_tune(const ed_ham *h, const void *x, void *y, const void *p, void *ws, void *stream, int32_t reps,
+            int32_t *tile, double *ms_up, double *ms_dn);
 
 /* Number of up-part and down-part tile candidates; a tile id is
  * up_index | (down_index << 8), index 0 = built-in default. */
 int ed_tile_count(int32_t *n_up, int32_t *n_dn);
 
-/* The launch parameters a tile id resolves to for instance h: params[0..5] =
+/* The launch parameters a tile id resolves to for instance h: params[0..6] =
  * stripe width, rows per up tile, up workgroup size, up mapping (0 XCD
  * round-robin, 1 linear, 2 per-XCD work queues), down workgroup size, rows
- * per down workgroup.  params: host, 6 ints. */
+ * per down workgroup, and 1 when the down kernel takes two rows per
+ * workgroup that share each table chunk (both rows in LDS; else 0).
+ * params: host, 7 ints. */
 int ed_tile_params(int32_t tile, const ed_ham *h, int32_t *params);
 
 /* ---- device: the Lanczos iteration (Alg. 1) ---------------------------- */

@@ -83,8 +83,8 @@ _PROTOS = {
                                          POINTER(c_double)]),
     "ed_workspace_size": (c_int, [POINTER(EdHam), c_int32, POINTER(c_int64)]),
     "ed_hv": (c_int, [POINTER(EdHam), c_void_p, c_void_p, c_void_p, c_void_p]),
-    "ed_tune": (c_int, [POINTER(EdHam), c_void_p, c_void_p, c_void_p, c_void_p, c_int32, POINTER(c_int32),
-                        POINTER(c_double), POINTER(c_double)]),
+    "ed_tune": (c_int, [POINTER(EdHam), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int32,
+                        POINTER(c_int32), POINTER(c_double), POINTER(c_double)]),
     "ed_tile_count": (c_int, [POINTER(c_int32), POINTER(c_int32)]),
     "ed_tile_params": (c_int, [c_int32, POINTER(EdHam), POINTER(c_int32)]),
     "ed_lanczos_init": (c_int, [POINTER(EdHam), POINTER(EdLanczos), c_void_p, c_void_p, c_void_p]),

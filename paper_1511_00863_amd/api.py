@@ -380,10 +380,10 @@ class Hamiltonian:
         return y
 
     def tile_params(self, tile=None):
-        p = np.zeros(6, dtype=np.int32)
+        p = np.zeros(7, dtype=np.int32)
         h = self.c_struct()
         check(lib().ed_tile_params(self.tile if tile is None else int(tile), byref(h), _ptr(p, c_int32)))
-        keys = ("stripe_width", "up_rows", "up_block", "up_map", "dn_block", "dn_rows")
+        keys = ("stripe_width", "up_rows", "up_block", "up_map", "dn_block", "dn_rows", "dn_pair")
         return dict(zip(keys, p.tolist()))
 
     def tune(self, x=None, reps: int = 3, stream=None, apply: bool = True):
@@ -394,14 +394,16 @@ class Hamiltonian:
             x = torch.ones(self.dim, dtype=self.torch_dtype, device=self.device)
         x = self._vec(x)
         y = self.empty_vec()
+        p = x.clone()   # f_{j-1} of the timed down part: a vector of its own, as in a step
         ws = self.workspace(2)
         nu, nd = c_int32(0), c_int32(0)
         check(lib().ed_tile_count(byref(nu), byref(nd)))
         mu, md = np.full(nu.value, -1.0), np.full(nd.value, -1.0)
         tile = c_int32(0)
         h = self.c_struct()
-        check(lib().ed_tune(byref(h), _dptr(x), _dptr(y), _dptr(ws), _stream(stream), int(reps), byref(tile),
-                            _ptr(mu, c_double), _ptr(md, c_double)))
+        check(lib().ed_tune(byref(h), _dptr(x), _dptr(y), _dptr(p), _dptr(ws), _stream(stream), int(reps),
+                            byref(tile), _ptr(mu, c_double), _ptr(md, c_double)))
+        del p
         if apply:
             self.tile = tile.value
         return {"tile": tile.value, "up_ms": mu, "dn_ms": md}

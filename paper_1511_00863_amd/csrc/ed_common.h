@@ -238,17 +238,24 @@ template <typename VT> __device__ __forceinline__ auto vcomp(const VT &v, int i)
     else return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
 }
 
+// Gathers in flight per batch in up_rowv: a row's first 16 are issued
+// together, the rest (rows of up to 32 entries) after the first batch is
+// summed.  Holding all 32 in registers would cost the kernel a wave per SIMD.
+constexpr int kUpBatch = 16;
+
 // One row of the vector up tile with exactly NE entries (a row's entries come
 // first, padding after them): every gather is a real row of x, then the
 // previous row's result is stored, then the row is summed in ascending column
 // order with one fused multiply-add per term.
+
 template <typename T, int V, int NE, int NCH, typename E>
 __device__ __forceinline__ void up_rowv(const T *__restrict__ xs, unsigned cc, int Ddn, const Chunk8<E> (&q)[NCH], T t,
                                         T (&pend)[V], T *&pend_ptr, T *row_out) {
     using VT = typename VecT<T, V>::type;
-    VT v[NE > 0 ? NE : 1];
+    constexpr int B0 = NE < kUpBatch ? NE : kUpBatch;
+    VT v[B0 > 0 ? B0 : 1];
 #pragma unroll
-    for (int j = 0; j < NE; ++j) {
+    for (int j = 0; j < B0; ++j) {
         const unsigned e = entry(q[j >> 3], j & 7);
         v[j] = *reinterpret_cast<const VT *>(xs + (int64_t)(e >> 1) * Ddn + cc);
     }
@@ -260,11 +267,30 @@ __device__ __forceinline__ void up_rowv(const T *__restrict__ xs, unsigned cc, i
 #pragma unroll
     for (int i = 0; i < V; ++i) a[i] = T(0);
 #pragma unroll
-    for (int j = 0; j < NE; ++j) {
+    for (int j = 0; j < B0; ++j) {
         const unsigned e = entry(q[j >> 3], j & 7);
         const T sg = (e & 1u) ? T(-1) : T(1);
 #pragma unroll
         for (int i = 0; i < V; ++i) a[i] = fma_t(sg, vcomp(v[j], i), a[i]);
+    }
+    // later batches: the scheduling barrier keeps their loads after the sums
+    // above, so their registers reuse the first batch's
+#pragma unroll
+    for (int j0 = B0; j0 < NE; j0 += kUpBatch) {
+        __builtin_amdgcn_sched_barrier(0);
+        VT w[kUpBatch];
+#pragma unroll
+        for (int j = j0; j < NE && j < j0 + kUpBatch; ++j) {
+            const unsigned e = entry(q[j >> 3], j & 7);
+            w[j - j0] = *reinterpret_cast<const VT *>(xs + (int64_t)(e >> 1) * Ddn + cc);
+        }
+#pragma unroll
+        for (int j = j0; j < NE && j < j0 + kUpBatch; ++j) {
+            const unsigned e = entry(q[j >> 3], j & 7);
+            const T sg = (e & 1u) ? T(-1) : T(1);
+#pragma unroll
+            for (int i = 0; i < V; ++i) a[i] = fma_t(sg, vcomp(w[j - j0], i), a[i]);
+        }
     }
 #pragma unroll
     for (int i = 0; i < V; ++i) pend[i] = t * a[i];
@@ -452,7 +478,9 @@ __device__ __forceinline__ float keep_or_zero(float v, bool keep) {
 // NCH = largest number of table chunks per row (W8 / 8 <= NCH) handled.
 // MODE 0: plain H.v (sig = 1).  MODE 1: Lanczos, partial q.x.
 // MODE 2: Lanczos mixed form, partials (q.x, q.p, x.x, x.p, p.p).
-template <typename T>
+// P8: take 8-byte pieces where the source is 8- but not 16-byte aligned (the
+// second row of a pair of float rows of even length); else element by element.
+template <typename T, bool P8 = false>
 __device__ __forceinline__ void stage_rows(const T *__restrict__ src, T *__restrict__ dst, int n) {
     // 16-byte pieces, four in flight per thread; the tail element by element
     constexpr int V = 16 / sizeof(T);
@@ -471,6 +499,21 @@ __device__ __forceinline__ void stage_rows(const T *__restrict__ src, T *__restr
         }
         for (; i < nv; i += blockDim.x) d4[i] = s4[i];
         for (int k = nv * V + threadIdx.x; k < n; k += blockDim.x) dst[k] = src[k];
+    } else if (P8 && (reinterpret_cast<uintptr_t>(src) & 7) == 0 && (reinterpret_cast<uintptr_t>(dst) & 7) == 0) {
+        constexpr int V2 = 8 / sizeof(T);
+        const int n2 = n / V2;
+        const uint2 *s2 = reinterpret_cast<const uint2 *>(src);
+        uint2 *d2 = reinterpret_cast<uint2 *>(dst);
+        int i = threadIdx.x;
+        for (; i + 3 * (int)blockDim.x < n2; i += 4 * blockDim.x) {
+            const uint2 a = s2[i], b = s2[i + blockDim.x], c = s2[i + 2 * blockDim.x], d = s2[i + 3 * blockDim.x];
+            d2[i] = a;
+            d2[i + blockDim.x] = b;
+            d2[i + 2 * blockDim.x] = c;
+            d2[i + 3 * blockDim.x] = d;
+        }
+        for (; i < n2; i += blockDim.x) d2[i] = s2[i];
+        for (int k = n2 * V2 + threadIdx.x; k < n; k += blockDim.x) dst[k] = src[k];
     } else {
         for (int k = threadIdx.x; k < n; k += blockDim.x) dst[k] = src[k];
     }
@@ -653,4 +696,137 @@ __device__ __forceinline__ void down_rows(const T *__restrict__ xrows, T *__rest
     }
 }
 
+
+// down_gather_z for two rows staged in LDS (each followed by a zero at index
+// zslot): one table decode per entry serves both rows.  Each row's terms are
+// summed exactly as down_gather_z sums them.
+template <typename T, int NCH, typename E>
+__device__ __forceinline__ void down_gather_z2(const T *__restrict__ x0, const T *__restrict__ x1,
+                                               const Chunk8<E> (&tq)[NCH > 0 ? NCH : 1], int nch, unsigned zslot,
+                                               T &a00, T &a01, T &a10, T &a11) {
+    a00 = T(0);
+    a01 = T(0);
+    a10 = T(0);
+    a11 = T(0);
+#pragma unroll
+    for (int k8 = 0; k8 < NCH; ++k8) {
+        if (k8 >= nch) break;
+        if (!__any(!is_pad<E>(entry(tq[k8], 0)))) break;
+        bool upper = true;
+        if constexpr (sizeof(T) == 4) upper = __any(!is_pad<E>(entry(tq[k8], 4)));
+        T v0[8], v1[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (k >= 4 && !upper) {
+                v0[k] = T(0);
+                v1[k] = T(0);
+                continue;
+            }
+            const unsigned e = entry(tq[k8], k);
+            const unsigned at = min(e >> 1, zslot), sgn = e << 31;
+            v0[k] = flip_sign(x0[at], sgn);
+            v1[k] = flip_sign(x1[at], sgn);
+        }
+#pragma unroll
+        for (int k = 0; k < 8; k += 2) {
+            a00 += v0[k];
+            a01 += v0[k + 1];
+            a10 += v1[k];
+            a11 += v1[k + 1];
+        }
+    }
+}
+
+// down_rows for two rows r0, r0 + 1 of one workgroup, staged in LDS at x0 and
+// x1 (each followed by a zero): lane c takes column c of both rows, so each
+// table chunk is loaded once for the two.  Per row the arithmetic is
+// down_rows' (the same q bits); the partial sums take row 0's terms, then row
+// 1's, column by column.  two = false: only row 0 exists (x1 = x0, nothing of
+// row 1 is stored or summed).
+template <typename T, int MODE, int NCH, typename E>
+__device__ __forceinline__ void down_rows2(const T *__restrict__ x0, const T *__restrict__ x1, T *__restrict__ io,
+                                           const T *__restrict__ p, const E *__restrict__ tab, uint64_t su0,
+                                           uint64_t su1, bool two, const uint64_t *__restrict__ st_dn, int Ddn,
+                                           int W8, int64_t base, T t, T U, T sig, T cprev, bool use_p,
+                                           double (&s)[MODE == 2 ? 5 : 1]) {
+    const Chunk8<E> *til = reinterpret_cast<const Chunk8<E> *>(tab + (int64_t)Ddn * W8);
+    const int nch = W8 >> 3;
+    const int64_t base1 = base + (two ? Ddn : 0);
+    int c = threadIdx.x;
+    if (c >= Ddn) return;
+    Chunk8<E> tq[NCH > 0 ? NCH : 1];
+#pragma unroll
+    for (int k8 = 0; k8 < NCH; ++k8) tq[k8] = table_chunk<NCH, E>(til, k8, nch, Ddn, c);
+    T io0 = io[base + c], io1 = io[base1 + c];
+    T p0 = T(0), p1 = T(0);
+    if constexpr (MODE != 0) {
+        p0 = keep_or_zero(p[base + c], use_p);
+        p1 = keep_or_zero(p[base1 + c], use_p);
+    }
+    uint64_t sdv = st_dn[c];
+    for (; c < Ddn; c += blockDim.x) {
+        const int cn = min(c + (int)blockDim.x, Ddn - 1);
+        Chunk8<E> tqn[NCH > 0 ? NCH : 1];
+#pragma unroll
+        for (int k8 = 0; k8 < NCH; ++k8) tqn[k8] = table_chunk<NCH, E>(til, k8, nch, Ddn, cn);
+        const T io0n = io[base + cn], io1n = io[base1 + cn];
+        T p0n = T(0), p1n = T(0);
+        if constexpr (MODE != 0) {
+            p0n = keep_or_zero(p[base + cn], use_p);
+            p1n = keep_or_zero(p[base1 + cn], use_p);
+        }
+        const uint64_t sdn = st_dn[cn];
+        T a00, a01, a10, a11;
+        down_gather_z2<T, NCH, E>(x0, x1, tq, nch, (unsigned)Ddn, a00, a01, a10, a11);
+        {
+            const T xv = x0[c];
+            const T nd = static_cast<T>(__popcll(su0 & sdv));
+            T q = io0 + t * (a00 + a01) + U * nd * xv;
+            if (MODE != 0) {
+                q *= sig;
+                if (use_p) q -= cprev * p0;
+            }
+            io[base + c] = q;
+            if (MODE != 0) {
+                const double qd = q, xd = xv;
+                s[0] += qd * xd;
+                if constexpr (MODE == 2) {
+                    const double pd = p0;
+                    s[1] += qd * pd;
+                    s[2] += xd * xd;
+                    s[3] += xd * pd;
+                    s[4] += pd * pd;
+                }
+            }
+        }
+        if (two) {
+            const T xv = x1[c];
+            const T nd = static_cast<T>(__popcll(su1 & sdv));
+            T q = io1 + t * (a10 + a11) + U * nd * xv;
+            if (MODE != 0) {
+                q *= sig;
+                if (use_p) q -= cprev * p1;
+            }
+            io[base1 + c] = q;
+            if (MODE != 0) {
+                const double qd = q, xd = xv;
+                s[0] += qd * xd;
+                if constexpr (MODE == 2) {
+                    const double pd = p1;
+                    s[1] += qd * pd;
+                    s[2] += xd * xd;
+                    s[3] += xd * pd;
+                    s[4] += pd * pd;
+                }
+            }
+        }
+        io0 = io0n;
+        io1 = io1n;
+        p0 = p0n;
+        p1 = p1n;
+        sdv = sdn;
+#pragma unroll
+        for (int k8 = 0; k8 < NCH; ++k8) tq[k8] = tqn[k8];
+    }
+}
 }  // namespace ed

@@ -255,6 +255,52 @@ void k_down(const T *__restrict__ x, T *__restrict__ io, const T *__restrict__ p
     }
 }
 
+// k_down with two rows per workgroup (down_rows2): rows 2b and 2b + 1 staged
+// in LDS at 0 and S (S = the row length plus one, rounded up to 4 elements),
+// each followed by a zero.  One table chunk load per column serves both rows.
+template <typename T, int MODE, int NCH, typename E>
+__global__ __launch_bounds__(sizeof(E) == 4 ? 512 : 1024)
+void k_down2(const T *__restrict__ x, T *__restrict__ io, const T *__restrict__ p, const E *__restrict__ tab,
+             const uint64_t *__restrict__ st_up, const uint64_t *__restrict__ st_dn, int Dup, int Ddn, int W8, int S,
+             T t, T U, const double *__restrict__ bvec, const Hdr *__restrict__ hdr, double *__restrict__ partials,
+             int max_steps) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *x0 = reinterpret_cast<T *>(smem);
+    T *x1 = x0 + S;
+    bool has_prev = false;
+    T sig = T(1), cprev = T(0);
+    if (MODE != 0) {
+        if (frozen(hdr, max_steps)) return;
+        const int j = hdr->jdev;
+        has_prev = j > 0;
+        sig = static_cast<T>(hdr->sig_cur);
+        cprev = static_cast<T>(bvec[j] * hdr->sig_prev);
+    }
+    const int r0 = 2 * blockIdx.x;
+    const bool two = r0 + 1 < Dup;
+    const int64_t base = (int64_t)r0 * Ddn;
+    stage_rows<T, true>(x + base, x0, Ddn);
+    if (two) stage_rows<T, true>(x + base + Ddn, x1, Ddn);
+    if (threadIdx.x == 0) {
+        x0[Ddn] = T(0);
+        x1[Ddn] = T(0);
+    }
+    __syncthreads();
+    constexpr int NV = MODE == 2 ? 5 : 1;
+    double s[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) s[k] = 0.0;
+    down_rows2<T, MODE, NCH, E>(x0, two ? x1 : x0, io, p, tab, st_up[r0], two ? st_up[r0 + 1] : 0ull, two, st_dn, Ddn,
+                                W8, base, t, U, sig, cprev, MODE != 0 && has_prev, s);
+    if (MODE != 0) {
+        double tot[NV];
+        block_sum<NV>(s, tot);
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int k = 0; k < NV; ++k) partials[(int64_t)blockIdx.x * kPartStride + k] = tot[k];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Complex amplitudes.  Vectors are interleaved (re, im) pairs; every kernel of
 // the step other than these two treats them as real arrays of 2D values, which
@@ -623,13 +669,32 @@ static int grid_for(int64_t n, int block, int cap = 4096) {
 
 // Launch shape of k_down: rows per workgroup (LDS staging) or, for rows too
 // long for LDS, one row per workgroup split into csplit column blocks.
-struct DownShape { bool lds; int rpb, csplit, grid; };
+struct DownShape { bool lds; int rpb, csplit, grid; bool pair; };
 
 // LDS bytes of k_downc's amplitude table (kAmpSlots + 1 values, padded)
 static int64_t complex_amp_lds(const ed_ham *h) { return (int64_t)(kAmpSlots + 2) * 2 * elem_size(h); }
 
+// Row stride of the two-row down kernel in LDS: the row, its zero, rounded up
+// to 4 elements (16 bytes of float, 32 of double).
+static int64_t pair_stride(const ed_ham *h) { return (h->dim_dn + 1 + 3) & ~int64_t(3); }
+// The two-row down kernel: asked for by the tile, real instances where both
+// species hop, at least two rows, and both rows (with their zeros) in LDS.
+static bool pair_rows(const ed_ham *h, const Tile &tl) {
+    return tl.dn_pair && !h->cplx && h->w_up > 0 && h->w_dn > 0 && h->dim_up >= 2 &&
+           (pair_stride(h) + h->dim_dn + 1) * elem_size(h) <= kLdsBudget;
+}
+
 static DownShape down_shape(const ed_ham *h, const Tile &tl) {
     DownShape d;
+    d.pair = false;
+    if (pair_rows(h, tl)) {
+        d.pair = true;
+        d.lds = true;
+        d.rpb = 2;
+        d.csplit = 1;
+        d.grid = (int)((h->dim_up + 1) / 2);
+        return d;
+    }
     const int64_t row_bytes = h->dim_dn * (int64_t)elem_size(h) * (h->cplx ? 2 : 1);
     if (h->cplx) {   // one row per workgroup
         d.lds = row_bytes + complex_amp_lds(h) <= kLdsBudget;
@@ -804,6 +869,21 @@ static int launch_down_e(const ed_ham *h, const Tile &tl, const T *x, T *io, con
     // rows plus one slot (the zero after a single row), 16-byte granular
     const size_t shm = lds ? (size_t)(h->dim_dn * (int64_t)sizeof(T) * rpb) + 16 : 0;
     const int nch = h->w_dn >> 3;
+    if (d.pair) {
+        const int S = (int)pair_stride(h);
+        const size_t shm2 = (size_t)(S + h->dim_dn + 1) * sizeof(T);
+        const E *tab = static_cast<const E *>(h->tab_dn);
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3(grid), dim3(tl.dn_block), shm2, s, x, io, p, tab, h->st_up, h->st_dn,
+                               (int)h->dim_up, (int)h->dim_dn, h->w_dn, S, static_cast<T>(h->t),
+                               static_cast<T>(h->U), bvec, hdr, part, max_steps);
+        };
+        if (nch <= 2) go(k_down2<T, MODE, 2, E>);
+        else if (nch <= 4) go(k_down2<T, MODE, 4, E>);
+        else go(k_down2<T, MODE, 8, E>);
+        ED_LAUNCHED("k_down2");
+        return ED_OK;
+    }
     if (!lds && h->w_up == 0) {   // one species: no up part to add (launch_up wrote nothing)
         if (nch == 0) {
             launch_down_k<T, MODE, false, 0, E, false>(h, tl, grid, 1, cs, 0, x, io, p, bvec, hdr, part, max_steps, s);
@@ -885,9 +965,15 @@ static hipError_t set_lds_attr_e() {
 
 template <typename T, int MODE, int NCH>
 static hipError_t set_lds_attr() {
-    const hipError_t e = set_lds_attr_e<T, MODE, NCH, uint16_t>();
+    hipError_t e = set_lds_attr_e<T, MODE, NCH, uint16_t>();
     if (e != hipSuccess) return e;
-    return set_lds_attr_e<T, MODE, NCH, uint32_t>();
+    e = set_lds_attr_e<T, MODE, NCH, uint32_t>();
+    if (e != hipSuccess || NCH == 0) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_down2<T, MODE, NCH == 0 ? 2 : NCH, uint16_t>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget + 256);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(k_down2<T, MODE, NCH == 0 ? 2 : NCH, uint32_t>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget + 256);
 }
 
 template <typename T>
@@ -1136,8 +1222,8 @@ static int capture_steps(const ed_ham *h, const Tile &tl, ed_lanczos st_copy, co
 }
 
 template <typename T>
-static int tune_impl(const ed_ham *h, const T *x, T *y, const WsLayout &w, int reps, hipStream_t s, int32_t *tile,
-                     double *ms_up, double *ms_dn) {
+static int tune_impl(const ed_ham *h, const T *x, T *y, const T *p, const WsLayout &w, int reps, hipStream_t s,
+                     int32_t *tile, double *ms_up, double *ms_dn) {
     hipEvent_t e0, e1;
     ED_HIP(hipEventCreate(&e0));
     ED_HIP(hipEventCreate(&e1));
@@ -1170,7 +1256,9 @@ static int tune_impl(const ed_ham *h, const T *x, T *y, const WsLayout &w, int r
         if (m < best_up) { best_up = m; bu = ui; }
     }
     // k_down is timed as in a Lanczos step (second step: f_{j-1} read, partial
-    // sums written), from a synthetic header; x stands in for f_{j-1}.
+    // sums written), from a synthetic header; p stands in for f_{j-1}.  Each
+    // timed launch follows an untimed up part (the best tile's), as in a step,
+    // so the caches hold what they hold there.
     Hdr fake{};
     fake.sig_cur = 1.0;
     fake.sig_prev = 1.0;
@@ -1181,6 +1269,7 @@ static int tune_impl(const ed_ham *h, const T *x, T *y, const WsLayout &w, int r
     if (rc == ED_OK) rc = hip_check(hipMemcpyAsync(w.y, bfake, sizeof bfake, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
     if (rc == ED_OK) rc = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
     constexpr int SM = sizeof(T) == 8 ? 1 : 2;
+    const Tile tl_up = resolve_tile_id(h, bu);
     for (int di = 1; di < kNumDn && rc == ED_OK; ++di) {
         const Tile tl = resolve_tile_id(h, di << 8);
         if (ms_dn) ms_dn[di] = -1.0;
@@ -1190,17 +1279,23 @@ static int tune_impl(const ed_ham *h, const T *x, T *y, const WsLayout &w, int r
             if (kDnTiles[di].rpb > 0 && (int64_t)kDnTiles[di].rpb * h->dim_dn * (int64_t)sizeof(T) > kLdsBudget)
                 continue;
             if (kDnTiles[di].rpb > h->dim_up) continue;
+            if (kDnTiles[di].pair && !pair_rows(h, tl)) continue;   // would run as the one-row kernel
             if (tl.dn_block != kDnTiles[di].block) continue;   // clamped duplicate of a smaller workgroup
         }
-        rc = launch_down<T, SM>(h, tl, x, y, x, w.y, w.hdr, w.part, 2, s);
+        rc = launch_down<T, SM>(h, tl, x, y, p, w.y, w.hdr, w.part, 2, s);
         if (rc) break;
-        rc = hip_check(hipEventRecord(e0, s), "hipEventRecord");
-        for (int r = 0; r < reps && rc == ED_OK; ++r) rc = launch_down<T, SM>(h, tl, x, y, x, w.y, w.hdr, w.part, 2, s);
-        if (rc == ED_OK) rc = hip_check(hipEventRecord(e1, s), "hipEventRecord");
-        if (rc == ED_OK) rc = hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
-        float msf = 0.f;
-        if (rc == ED_OK) rc = hip_check(hipEventElapsedTime(&msf, e0, e1), "hipEventElapsedTime");
-        const double m = msf / reps;
+        double tot = 0.0;
+        for (int r = 0; r < reps && rc == ED_OK; ++r) {
+            rc = launch_up<T>(h, tl_up, x, y, w.ctr, nullptr, 0, 0, s);
+            if (rc == ED_OK) rc = hip_check(hipEventRecord(e0, s), "hipEventRecord");
+            if (rc == ED_OK) rc = launch_down<T, SM>(h, tl, x, y, p, w.y, w.hdr, w.part, 2, s);
+            if (rc == ED_OK) rc = hip_check(hipEventRecord(e1, s), "hipEventRecord");
+            if (rc == ED_OK) rc = hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+            float msf = 0.f;
+            if (rc == ED_OK) rc = hip_check(hipEventElapsedTime(&msf, e0, e1), "hipEventElapsedTime");
+            tot += msf;
+        }
+        const double m = tot / reps;
         if (ms_dn) ms_dn[di] = m;
         if (m < best_dn) { best_dn = m; bd = di; }
     }
@@ -1281,21 +1376,24 @@ int ed_tile_params(int32_t tile, const ed_ham *h, int32_t *params) {
     params[3] = t.up_map;
     params[4] = t.dn_block;
     params[5] = t.dn_rpb;
+    params[6] = pair_rows(h, t) ? 1 : 0;
     return ED_OK;
 }
 
-int ed_tune(const ed_ham *h, const void *x, void *y, void *ws, void *stream, int32_t reps, int32_t *tile,
-            double *ms_up, double *ms_dn) {
+int ed_tune(const ed_ham *h, const void *x, void *y, const void *p, void *ws, void *stream, int32_t reps,
+            int32_t *tile, double *ms_up, double *ms_dn) {
     clear_error();
     int rc = check_ham(h, "ed_tune");
     if (rc) return rc;
     rc = ensure_attrs();
     if (rc) return rc;
-    if (!x || !y || x == y || !ws || !tile || reps < 1) return set_error(ED_EINVAL, "ed_tune: bad arguments");
+    if (!x || !y || x == y || p == y || !ws || !tile || reps < 1) return set_error(ED_EINVAL, "ed_tune: bad arguments");
+    if (!p) p = x;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const WsLayout w = ws_layout(h, ws, 2);
-    if (h->dtype == ED_F64) return tune_impl<double>(h, (const double *)x, (double *)y, w, reps, s, tile, ms_up, ms_dn);
-    return tune_impl<float>(h, (const float *)x, (float *)y, w, reps, s, tile, ms_up, ms_dn);
+    if (h->dtype == ED_F64)
+        return tune_impl<double>(h, (const double *)x, (double *)y, (const double *)p, w, reps, s, tile, ms_up, ms_dn);
+    return tune_impl<float>(h, (const float *)x, (float *)y, (const float *)p, w, reps, s, tile, ms_up, ms_dn);
 }
 
 int ed_tile_count(int32_t *n_up, int32_t *n_dn) {

@@ -19,10 +19,11 @@ struct Tile {
     int up_map;     // 0 XCD round-robin remap, 1 linear, 2 per-XCD queues
     int dn_block;   // k_down threads per workgroup
     int dn_rpb;     // rows per k_down workgroup (0 = derive from LDS and block)
+    int dn_pair;    // 1: two rows per workgroup sharing each table chunk (k_down2), where both fit LDS
 };
 
 struct UpTile { int wlog2, rc, block, map; };
-struct DnTile { int block, rpb; };
+struct DnTile { int block, rpb, pair; };
 
 // Candidates searched by ed_tune.  A tile id is up_index | (dn_index << 8);
 // index 0 means "heuristic default" for that kernel.
@@ -42,7 +43,8 @@ static const UpTile kUpTiles[] = {
     {7, 8, 256, 0}, {7, 16, 512, 0}, {8, 8, 256, 0}, {8, 16, 256, 0}, {8, 32, 256, 0}, {8, 16, 512, 0},
 };
 static const DnTile kDnTiles[] = {
-    {0, 0}, {1024, 0}, {512, 0}, {256, 0}, {1024, 1}, {512, 1}, {256, 1}, {1024, 2}, {512, 2}, {256, 4},
+    {0, 0, 0}, {1024, 0, 0}, {512, 0, 0}, {256, 0, 0}, {1024, 1, 0}, {512, 1, 0}, {256, 1, 0}, {1024, 2, 0},
+    {512, 2, 0}, {256, 4, 0}, {1024, 2, 1}, {512, 2, 1}, {256, 2, 1},
 };
 constexpr int kNumUp = sizeof(kUpTiles) / sizeof(kUpTiles[0]);
 constexpr int kNumDn = sizeof(kDnTiles) / sizeof(kDnTiles[0]);
@@ -76,9 +78,11 @@ static inline Tile resolve_tile_id(const ed_ham *h, int id) {
     if (di > 0 && di < kNumDn) {
         t.dn_block = kDnTiles[di].block;
         t.dn_rpb = kDnTiles[di].rpb;
+        t.dn_pair = kDnTiles[di].pair;
     } else {
         t.dn_block = h->dim_dn >= 1024 ? 1024 : 256;
         t.dn_rpb = 0;
+        t.dn_pair = 0;
     }
     if (wide_dn(h)) t.dn_block = std::min(t.dn_block, 512);   // the 32-bit table variants' launch bound
     // V = 2 or 4 columns per lane need row starts aligned to V elements (a row
