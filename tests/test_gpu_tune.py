@@ -16,7 +16,9 @@ pytestmark = pytest.mark.gpu
                                             (8, ring_bonds(8), 4, 4), (12, complete_bonds(12), 6, 6),
                                             # up tables of 3 chunks (width 20) and of 4 chunks (width 32,
                                             # the benchmark's shape)
-                                            (16, torus_bonds(4, 4), 5, 5), (16, torus_bonds(4, 4), 8, 8)])
+                                            (16, torus_bonds(4, 4), 5, 5), (16, torus_bonds(4, 4), 8, 8),
+                                            # odd row counts (the two-row down kernel's last block has one row)
+                                            (11, ring_bonds(11), 3, 3), (15, ring_bonds(15), 7, 7)])
 def test_every_tile_gives_identical_hv(ns, bonds, nu, nd, dtype):
     h = ham(ns, bonds, nu, nd, 1.0, 3.0, dtype)
     _, x = seeded_start(21, h.dim, dtype)
@@ -51,3 +53,32 @@ def test_tuned_lanczos_matches_default():
     assert np.max(np.abs(r0["a"][:20] - r1["a"][:20])) <= 1e-12 * scale
     assert np.array_equal(r1["a"], r2["a"]) and np.array_equal(r1["b"], r2["b"])
     assert abs(r0["e0"] - r1["e0"]) <= 1e-12 * abs(r0["e0"])
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("ns,bonds,nu,nd", [(16, torus_bonds(4, 4), 4, 4), (11, ring_bonds(11), 3, 3),
+                                            (15, ring_bonds(15), 7, 7)])
+def test_two_row_down_kernel_in_lanczos(ns, bonds, nu, nd, dtype):
+    """The two-row down kernel (down tiles 10-12) in Lanczos runs, odd and even row counts: the same H x
+    bits as the one-row kernel, so a run differs from the default tile's only through the order of the
+    float64 partial sums (float64: coefficients to 1e-12; mixed form: E0 to 1e-6)."""
+    import ctypes
+    h = ham(ns, bonds, nu, nd, 1.0, 3.0, dtype)
+    _, x = seeded_start(23, h.dim, dtype)
+    nu_, nd_ = ctypes.c_int32(0), ctypes.c_int32(0)
+    ed.lib().ed_tile_count(ctypes.byref(nu_), ctypes.byref(nd_))
+    pairs = [di for di in range(nd_.value) if h.tile_params(di << 8)["dn_pair"]]
+    assert pairs, "no two-row tile applies"
+    announce("two-row down kernel, lanczos %d+%d on %d sites %s, tiles %s" % (nu, nd, ns, dtype, pairs))
+    h.tile = 0
+    r0 = h.ground_energy(x, 40, tol=0.0)
+    scale = np.max(np.abs(r0["a"]))
+    for di in pairs:
+        h.tile = di << 8
+        r1 = h.ground_energy(x, 40, tol=0.0)
+        assert r1["steps"] == r0["steps"]
+        if dtype == "f64":
+            assert np.max(np.abs(r0["a"][:20] - r1["a"][:20])) <= 1e-12 * scale, di
+            assert abs(r0["e0"] - r1["e0"]) <= 1e-12 * abs(r0["e0"]), di
+        else:
+            assert abs(r0["e0"] - r1["e0"]) <= 1e-6 * abs(r0["e0"]), di
