@@ -174,8 +174,9 @@ def scale_block(args):
     from synth import workload
     wl = workload("ring18_9x9")
     dev = "cuda:0"
-    # 48620-state rows (beyond LDS: the down species stays ascending)
-    tab, tdn = species_tables(ed, wl.n_sites, wl.bonds, wl.n_up, wl.n_dn, dev, "ascending", args.up_order)
+    # 48620-state rows, beyond LDS: the down species in band order, where the down part stages each
+    # 8192-state column block with its neighbours in LDS (k_down_win over the species' row windows)
+    tab, tdn = species_tables(ed, wl.n_sites, wl.bonds, wl.n_up, wl.n_dn, dev, "band", args.up_order)
     out = {"workload": wl.name, "dim": tab.dim * tdn.dim, "U": wl.U, "table_entry_bytes": tab.entry_bytes,
            "basis_order": {"up": tab.order, "down": tdn.order},
            "start": "uniform(-1/2,1/2) from torch's device generator, seed %d, drawn in the run's order" % wl.seed}

@@ -164,6 +164,19 @@ int ed_hop_order(const int32_t *nnz, int64_t dim, int64_t *perm);
  * (host); perm: host, dim entries.  nnz or a column out of range -> ED_EINVAL. */
 int ed_band_order(const int32_t *cols, const int32_t *nnz, int64_t dim, int32_t width, int layout, int64_t *perm);
 
+/* Neighbour windows of column blocks (for rows too long for LDS): for block
+ * b of block_cols consecutive states [b*block_cols, min((b+1)*block_cols,
+ * dim)), lo_hi[2b] and lo_hi[2b+1] bound every state of the block and every
+ * table column of its states, lo rounded down and hi up to multiples of 4
+ * (hi at most dim).  The down part can then stage x[r, lo..hi) of a row in
+ * LDS for that block (Eq. 5 reads a row only at the block's neighbours); in a
+ * band order (ed_band_order) the windows are narrow.  *max_window: the
+ * largest hi - lo.  cols, nnz, width, layout: one species' ELL table as from
+ * ed_build_hopping (host); block_cols > 0 and a multiple of 64; lo_hi: host,
+ * 2 * ceil(dim / block_cols) entries.  A column out of range -> ED_EINVAL. */
+int ed_row_windows(const int32_t *cols, const int32_t *nnz, int64_t dim, int32_t width, int layout,
+                   int32_t block_cols, int32_t *lo_hi, int32_t *max_window);
+
 /* Reorder one species' basis and its exported ELL table (Fig. 2 format, as
  * from ed_build_hopping or ed_build_hopping_complex): position q of the
  * output is state perm[q] of the input, and each row's columns are renumbered
@@ -210,7 +223,11 @@ int ed_tridiag_lowest_vector(const double *a, const double *b, int m, double *e0
  * when the up / down tables and states come from ed_permute_basis.  Every
  * call accepts reordered bases (tables and state arrays fix the order) except
  * ed_spin_flip_moments and ed_bond_moments, which find states by colex rank
- * and return ED_EINVAL unless order = 0; other values -> ED_EINVAL. */
+ * and return ED_EINVAL unless order = 0; other values -> ED_EINVAL.
+ * win_dn: NULL, or the down species' neighbour windows from ed_row_windows
+ * (device, 2 * ceil(dim_dn / win_cols) int32) for blocks of win_cols states,
+ * the largest win_max; the autotuner may then give rows too long for LDS a
+ * down-part kernel that stages each block's window (real instances). */
 typedef struct ed_ham {
     int64_t dim_up, dim_dn;
     int32_t w_up, w_dn;
@@ -223,6 +240,8 @@ typedef struct ed_ham {
     int32_t cplx;           /* 0: real hopping, 1: complex amplitudes and vectors */
     int32_t order;          /* bit 0 / bit 1: the up / down basis is not ascending (ed_permute_basis) */
     const double *amp_up, *amp_dn;
+    const int32_t *win_dn;
+    int32_t win_cols, win_max;
 } ed_ham;
 
 /* Bytes of device workspace (`ws` below) the calls on this instance need
@@ -276,9 +295,10 @@ int ed_tile_count(int32_t *n_up, int32_t *n_dn);
 /* The launch parameters a tile id resolves to for instance h: params[0..6] =
  * stripe width, rows per up tile, up workgroup size, up mapping (0 XCD
  * round-robin, 1 linear, 2 per-XCD work queues), down workgroup size, rows
- * per down workgroup, and 1 when the down kernel takes two rows per
- * workgroup that share each table chunk (both rows in LDS; else 0).
- * params: host, 7 ints. */
+ * per down workgroup, and the down kernel's form: 0 rows (or column blocks
+ * of long rows) per workgroup, 1 two rows per workgroup that share each
+ * table chunk (both in LDS), 2 column blocks of long rows with their
+ * neighbour windows in LDS (ed_ham.win_dn).  params: host, 7 ints. */
 int ed_tile_params(int32_t tile, const ed_ham *h, int32_t *params);
 
 /* ---- device: the Lanczos iteration (Alg. 1) ---------------------------- */

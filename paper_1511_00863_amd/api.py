@@ -64,6 +64,26 @@ def band_order(table) -> np.ndarray:
     return perm
 
 
+def row_windows(table, block_cols: int):
+    """ed_row_windows: (lo_hi, max_window) of the column blocks of block_cols states (ELL table from
+    build_hopping): lo_hi[2b], lo_hi[2b+1] bound block b's states and their table columns."""
+    nnz = np.ascontiguousarray(table["nnz"], dtype=np.int32)
+    cols = np.ascontiguousarray(table["cols"], dtype=np.int32)
+    nblk = (nnz.size + block_cols - 1) // block_cols
+    lo_hi = np.zeros(2 * nblk, dtype=np.int32)
+    widest = c_int32(0)
+    check(lib().ed_row_windows(_ptr(cols, c_int32), _ptr(nnz, c_int32), nnz.size, int(table["width"]),
+                               int(table["layout"]), int(block_cols), _ptr(lo_hi, c_int32), byref(widest)))
+    return lo_hi, int(widest.value)
+
+
+# Column blocks of the neighbour windows a down species carries (ed_ham.win_dn): rows longer than this
+# many states are the ones that do not fit LDS (19,456 FP64 states); a block's window holds its states and
+# their neighbours.
+WINDOW_COLS = 8192
+WINDOW_MIN_DIM = 16384
+
+
 def permute_basis(states, table, perm):
     """ed_permute_basis: (states, table) of a species in the order perm (real or complex exported tables)."""
     st = np.ascontiguousarray(states, dtype=np.uint64)
@@ -264,6 +284,12 @@ class SpinTables:
             self.entry_bytes = int(entry_bytes) if entry_bytes else (2 if self.dim <= NARROW_MAX_DIM else 4)
             self.packed = pack_tables(self.table, self.dim, self.entry_bytes)
         self.dev_states = torch.from_numpy(self.states.view(np.int64).copy()).to(self.device)
+        # neighbour windows of column blocks, for rows of this species too long for LDS (real tables)
+        self.win_cols, self.win_max, self.dev_win = 0, 0, None
+        if not self.cplx and self.width and self.dim >= WINDOW_MIN_DIM:
+            lo_hi, self.win_max = row_windows(self.table, WINDOW_COLS)
+            self.win_cols = WINDOW_COLS
+            self.dev_win = torch.from_numpy(lo_hi).to(self.device)
         signed = np.int16 if self.entry_bytes == 2 else np.int32
         self.dev_tab = (torch.from_numpy(self.packed.view(signed).copy()).to(self.device)
                         if self.width else torch.zeros(1, dtype=torch.int32, device=self.device))
@@ -328,7 +354,9 @@ class Hamiltonian:
                      self.t, self.U, self.dtype, self.tile, self.up.entry_bytes, self.dn.entry_bytes,
                      int(self.cplx), self.order_bits,
                      self.up.dev_amp.data_ptr() if self.up.dev_amp is not None else None,
-                     self.dn.dev_amp.data_ptr() if self.dn.dev_amp is not None else None)
+                     self.dn.dev_amp.data_ptr() if self.dn.dev_amp is not None else None,
+                     self.dn.dev_win.data_ptr() if self.dn.dev_win is not None else None,
+                     self.dn.win_cols, self.dn.win_max)
 
     @property
     def order_bits(self) -> int:
@@ -383,7 +411,7 @@ class Hamiltonian:
         p = np.zeros(7, dtype=np.int32)
         h = self.c_struct()
         check(lib().ed_tile_params(self.tile if tile is None else int(tile), byref(h), _ptr(p, c_int32)))
-        keys = ("stripe_width", "up_rows", "up_block", "up_map", "dn_block", "dn_rows", "dn_pair")
+        keys = ("stripe_width", "up_rows", "up_block", "up_map", "dn_block", "dn_rows", "dn_kind")
         return dict(zip(keys, p.tolist()))
 
     def tune(self, x=None, reps: int = 3, stream=None, apply: bool = True):

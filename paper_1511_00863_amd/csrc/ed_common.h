@@ -577,9 +577,10 @@ __device__ __forceinline__ float flip_sign(float v, unsigned s31) {
 // entry costs a clamp, an address, a sign and an add instead of a selected
 // sign factor and a selected address.  The terms and their order are
 // down_gather's (x + (-v) is fma(-1, v, x)), so the results are the same bits.
-template <typename T, int NCH, typename E>
+template <typename T, int NCH, typename E, bool WIN = false>
 __device__ __forceinline__ void down_gather_z(const T *__restrict__ xrow, const Chunk8<E> (&tq)[NCH > 0 ? NCH : 1],
-                                             int nch, unsigned zslot, T &acc0, T &acc1) {
+                                             int nch, unsigned zslot, T &acc0, T &acc1,
+                                             unsigned xlo = 0) {
     acc0 = T(0);
     acc1 = T(0);
 #pragma unroll
@@ -596,7 +597,10 @@ __device__ __forceinline__ void down_gather_z(const T *__restrict__ xrow, const 
                 continue;
             }
             const unsigned e = entry(tq[k8], k);
-            v[k] = flip_sign(xrow[min(e >> 1, zslot)], e << 31);
+            if constexpr (WIN)   // xrow holds the window from column xlo; padding clamps onto its zero
+                v[k] = flip_sign(xrow[min((e >> 1) - xlo, zslot)], e << 31);
+            else
+                v[k] = flip_sign(xrow[min(e >> 1, zslot)], e << 31);
         }
 #pragma unroll
         for (int k = 0; k < 8; k += 2) {
@@ -613,13 +617,15 @@ __device__ __forceinline__ void down_gather_z(const T *__restrict__ xrow, const 
 // in the global vectors.  A workgroup takes whole rows (i0 = 0, iend = rows *
 // Ddn) or, for one long row, a range of its columns.  IO = false: there is
 // no up part (the up species cannot hop); io is written but not read.  ZS:
-// one row in LDS followed by a zero (down_gather_z).
-template <typename T, int MODE, int NCH, bool MULTI, bool IO = true, bool ZS = false, typename E>
+// one row in LDS followed by a zero (down_gather_z).  WIN (with ZS, one
+// row): xrows is the window of the row from column xlo, its zero at index
+// zs_win, and [i0, iend) a block of columns inside it.
+template <typename T, int MODE, int NCH, bool MULTI, bool IO = true, bool ZS = false, typename E, bool WIN = false>
 __device__ __forceinline__ void down_rows(const T *__restrict__ xrows, T *__restrict__ io, const T *__restrict__ p,
                                           const E *__restrict__ tab, const uint64_t *__restrict__ st_up_r0,
                                           const uint64_t *__restrict__ st_dn, int Ddn, int W8, int i0, int iend,
                                           int64_t base, T t, T U, T sig, T cprev, bool use_p,
-                                          double (&s)[MODE == 2 ? 5 : 1]) {
+                                          double (&s)[MODE == 2 ? 5 : 1], unsigned xlo = 0, unsigned zs_win = 0) {
     const Chunk8<E> *til = reinterpret_cast<const Chunk8<E> *>(tab + (int64_t)Ddn * W8);   // 8-interleaved part
     const int nch = W8 >> 3;
     const int n = iend;
@@ -662,11 +668,14 @@ __device__ __forceinline__ void down_rows(const T *__restrict__ xrows, T *__rest
         if constexpr (MULTI) sun = st_up_r0[rrn];
         const T *xrow = xrows + (int64_t)rr * Ddn;
         T acc0, acc1;
-        if constexpr (ZS)
+        if constexpr (ZS && WIN)
+            down_gather_z<T, NCH, E, true>(xrow, tq, nch, zs_win, acc0, acc1, xlo);
+        else if constexpr (ZS)
             down_gather_z<T, NCH, E>(xrow, tq, nch, (unsigned)Ddn, acc0, acc1);
         else
             down_gather<T, NCH, E>(xrow, tq, nch, acc0, acc1);
-        const T xv = xrow[c];
+        T xv;
+        if constexpr (WIN) xv = xrow[c - (int)xlo]; else xv = xrow[c];
         const T nd = static_cast<T>(__popcll(suv & sdv));
         T q = iov + t * (acc0 + acc1) + U * nd * xv;
         if (MODE != 0) {

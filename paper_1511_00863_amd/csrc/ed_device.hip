@@ -80,7 +80,13 @@ struct WsLayout {
 // k_down partial-sum slots: one per workgroup.  Rows too long for LDS are split
 // into column blocks until the launch has kDownBlocks workgroups, so the grid
 // is at most dim_up + kDownBlocks.
-static int64_t n_partial_slots(const ed_ham *h) { return std::max<int64_t>(h->dim_up, 1) + kDownBlocks; }
+// partial-sum slots of the down part: one per workgroup (rows, column blocks
+// of long rows, or the windowed kernel's row-block pairs)
+static int64_t n_partial_slots(const ed_ham *h) {
+    const int64_t base = std::max<int64_t>(h->dim_up, 1) + kDownBlocks;
+    const int64_t nb = h->win_dn && h->win_cols > 0 ? (h->dim_dn + h->win_cols - 1) / h->win_cols : 0;
+    return std::max(base, h->dim_up * nb);
+}
 
 static int64_t ws_bytes(const ed_ham *h, int32_t max_steps) {
     return 512 + align256(8 * (int64_t)std::max(max_steps, 1)) + align256(8 * kPartStride * n_partial_slots(h)) +
@@ -292,6 +298,51 @@ void k_down2(const T *__restrict__ x, T *__restrict__ io, const T *__restrict__ 
     for (int k = 0; k < NV; ++k) s[k] = 0.0;
     down_rows2<T, MODE, NCH, E>(x0, two ? x1 : x0, io, p, tab, st_up[r0], two ? st_up[r0 + 1] : 0ull, two, st_dn, Ddn,
                                 W8, base, t, U, sig, cprev, MODE != 0 && has_prev, s);
+    if (MODE != 0) {
+        double tot[NV];
+        block_sum<NV>(s, tot);
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int k = 0; k < NV; ++k) partials[(int64_t)blockIdx.x * kPartStride + k] = tot[k];
+    }
+}
+
+// k_down for rows too long for LDS, by column blocks (ed_row_windows): the
+// workgroup of (row r, block b) stages x[r, lo_b..hi_b), the block's states
+// and all their neighbours, in LDS with a zero after it, and runs the block's
+// columns as the one-row kernel does (the same q bits).  win: the blocks'
+// (lo, hi) pairs; wcols: states per block; nblk blocks per row.
+template <typename T, int MODE, int NCH, typename E>
+__global__ __launch_bounds__(sizeof(E) == 4 ? 512 : 1024)
+void k_down_win(const T *__restrict__ x, T *__restrict__ io, const T *__restrict__ p, const E *__restrict__ tab,
+                const uint64_t *__restrict__ st_up, const uint64_t *__restrict__ st_dn, int Dup, int Ddn, int W8,
+                const int32_t *__restrict__ win, int wcols, int nblk, T t, T U, const double *__restrict__ bvec,
+                const Hdr *__restrict__ hdr, double *__restrict__ partials, int max_steps) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *xs = reinterpret_cast<T *>(smem);
+    bool has_prev = false;
+    T sig = T(1), cprev = T(0);
+    if (MODE != 0) {
+        if (frozen(hdr, max_steps)) return;
+        const int j = hdr->jdev;
+        has_prev = j > 0;
+        sig = static_cast<T>(hdr->sig_cur);
+        cprev = static_cast<T>(bvec[j] * hdr->sig_prev);
+    }
+    const int r = blockIdx.x / nblk, b = blockIdx.x - r * nblk;
+    const int lo = win[2 * b], hi = win[2 * b + 1];
+    const int c0 = b * wcols, c1 = min(Ddn, c0 + wcols);
+    const int64_t base = (int64_t)r * Ddn;
+    stage_rows<T>(x + base + lo, xs, hi - lo);
+    if (threadIdx.x == 0) xs[hi - lo] = T(0);
+    __syncthreads();
+    constexpr int NV = MODE == 2 ? 5 : 1;
+    double s[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) s[k] = 0.0;
+    down_rows<T, MODE, NCH, false, true, true, E, true>(xs, io, p, tab, st_up + r, st_dn, Ddn, W8, c0, c1, base, t, U,
+                                                        sig, cprev, MODE != 0 && has_prev, s, (unsigned)lo,
+                                                        (unsigned)(hi - lo));
     if (MODE != 0) {
         double tot[NV];
         block_sum<NV>(s, tot);
@@ -669,7 +720,7 @@ static int grid_for(int64_t n, int block, int cap = 4096) {
 
 // Launch shape of k_down: rows per workgroup (LDS staging) or, for rows too
 // long for LDS, one row per workgroup split into csplit column blocks.
-struct DownShape { bool lds; int rpb, csplit, grid; bool pair; };
+struct DownShape { bool lds; int rpb, csplit, grid; bool pair, win; };
 
 // LDS bytes of k_downc's amplitude table (kAmpSlots + 1 values, padded)
 static int64_t complex_amp_lds(const ed_ham *h) { return (int64_t)(kAmpSlots + 2) * 2 * elem_size(h); }
@@ -684,9 +735,32 @@ static bool pair_rows(const ed_ham *h, const Tile &tl) {
            (pair_stride(h) + h->dim_dn + 1) * elem_size(h) <= kLdsBudget;
 }
 
+// Column blocks of the down species' windows (0 without windows).
+static int64_t win_blocks(const ed_ham *h) {
+    return h->win_dn && h->win_cols > 0 ? (h->dim_dn + h->win_cols - 1) / h->win_cols : 0;
+}
+
+// The windowed down kernel: asked for by the tile, real instances where both
+// species hop, down tables of at most 4 chunks, rows too long for LDS and
+// every block's window (with its zero) in LDS.
+static bool win_rows(const ed_ham *h, const Tile &tl) {
+    return tl.dn_win && win_blocks(h) > 0 && !h->cplx && h->w_up > 0 && h->w_dn > 0 && (h->w_dn >> 3) <= 4 &&
+           h->dim_dn * elem_size(h) > kLdsBudget && h->win_max > 0 && h->win_max <= h->dim_dn &&
+           (h->win_max + 1) * elem_size(h) <= kLdsBudget;
+}
+
 static DownShape down_shape(const ed_ham *h, const Tile &tl) {
     DownShape d;
     d.pair = false;
+    d.win = false;
+    if (win_rows(h, tl)) {
+        d.win = true;
+        d.lds = false;
+        d.rpb = 1;
+        d.csplit = (int)win_blocks(h);
+        d.grid = (int)(h->dim_up * d.csplit);
+        return d;
+    }
     if (pair_rows(h, tl)) {
         d.pair = true;
         d.lds = true;
@@ -869,6 +943,19 @@ static int launch_down_e(const ed_ham *h, const Tile &tl, const T *x, T *io, con
     // rows plus one slot (the zero after a single row), 16-byte granular
     const size_t shm = lds ? (size_t)(h->dim_dn * (int64_t)sizeof(T) * rpb) + 16 : 0;
     const int nch = h->w_dn >> 3;
+    if (d.win) {
+        const size_t shmw = (size_t)((h->win_max + 1) * (int64_t)sizeof(T) + 15) & ~size_t(15);
+        const E *tab = static_cast<const E *>(h->tab_dn);
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3(grid), dim3(tl.dn_block), shmw, s, x, io, p, tab, h->st_up, h->st_dn,
+                               (int)h->dim_up, (int)h->dim_dn, h->w_dn, h->win_dn, h->win_cols, cs,
+                               static_cast<T>(h->t), static_cast<T>(h->U), bvec, hdr, part, max_steps);
+        };
+        if (nch <= 2) go(k_down_win<T, MODE, 2, E>);
+        else go(k_down_win<T, MODE, 4, E>);
+        ED_LAUNCHED("k_down_win");
+        return ED_OK;
+    }
     if (d.pair) {
         const int S = (int)pair_stride(h);
         const size_t shm2 = (size_t)(S + h->dim_dn + 1) * sizeof(T);
@@ -972,8 +1059,17 @@ static hipError_t set_lds_attr() {
     e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_down2<T, MODE, NCH == 0 ? 2 : NCH, uint16_t>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget + 256);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(k_down2<T, MODE, NCH == 0 ? 2 : NCH, uint32_t>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget + 256);
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_down2<T, MODE, NCH == 0 ? 2 : NCH, uint32_t>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget + 256);
+    if constexpr (NCH == 2 || NCH == 4) {
+        if (e != hipSuccess) return e;
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_down_win<T, MODE, NCH, uint16_t>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget + 256);
+        if (e != hipSuccess) return e;
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_down_win<T, MODE, NCH, uint32_t>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget + 256);
+    }
+    return e;
 }
 
 template <typename T>
@@ -1280,6 +1376,7 @@ static int tune_impl(const ed_ham *h, const T *x, T *y, const T *p, const WsLayo
                 continue;
             if (kDnTiles[di].rpb > h->dim_up) continue;
             if (kDnTiles[di].pair && !pair_rows(h, tl)) continue;   // would run as the one-row kernel
+            if (kDnTiles[di].win && !win_rows(h, tl)) continue;
             if (tl.dn_block != kDnTiles[di].block) continue;   // clamped duplicate of a smaller workgroup
         }
         rc = launch_down<T, SM>(h, tl, x, y, p, w.y, w.hdr, w.part, 2, s);
@@ -1376,7 +1473,7 @@ int ed_tile_params(int32_t tile, const ed_ham *h, int32_t *params) {
     params[3] = t.up_map;
     params[4] = t.dn_block;
     params[5] = t.dn_rpb;
-    params[6] = pair_rows(h, t) ? 1 : 0;
+    params[6] = pair_rows(h, t) ? 1 : (win_rows(h, t) ? 2 : 0);
     return ED_OK;
 }
 

@@ -368,6 +368,40 @@ int ed_hop_order(const int32_t *nnz, int64_t dim, int64_t *perm) {
     return ED_OK;
 }
 
+int ed_row_windows(const int32_t *cols, const int32_t *nnz, int64_t dim, int32_t width, int layout,
+                   int32_t block_cols, int32_t *lo_hi, int32_t *max_window) {
+    clear_error();
+    const char *who = "ed_row_windows";
+    if (!nnz || !lo_hi || !max_window || dim < 1 || width < 0 || (width > 0 && !cols) || block_cols <= 0 ||
+        (block_cols & 63))
+        return set_error(ED_EINVAL, "%s: bad arguments", who);
+    if (layout != ED_ROW_MAJOR && layout != ED_COL_MAJOR) return set_error(ED_EINVAL, "%s: bad layout %d", who, layout);
+    if (dim > 0x7fffffffLL) return set_error(ED_EOVERFLOW, "%s: dim too large", who);
+    const int64_t nblk = (dim + block_cols - 1) / block_cols;
+    int64_t widest = 0;
+    for (int64_t b = 0; b < nblk; ++b) {
+        const int64_t c0 = b * block_cols, c1 = std::min<int64_t>(dim, c0 + block_cols);
+        int64_t lo = c0, hi = c1;
+        for (int64_t r = c0; r < c1; ++r) {
+            if (nnz[r] < 0 || nnz[r] > width) return set_error(ED_EINVAL, "%s: nnz[%lld] = %d", who, (long long)r, nnz[r]);
+            for (int k = 0; k < nnz[r]; ++k) {
+                const int64_t c = layout == ED_ROW_MAJOR ? cols[r * width + k] : cols[(int64_t)k * dim + r];
+                if (c < 0 || c >= dim)
+                    return set_error(ED_EINVAL, "%s: column %lld of row %lld out of range", who, (long long)c, (long long)r);
+                lo = std::min(lo, c);
+                hi = std::max(hi, c + 1);
+            }
+        }
+        lo &= ~int64_t(3);
+        hi = std::min<int64_t>(dim, (hi + 3) & ~int64_t(3));
+        lo_hi[2 * b] = (int32_t)lo;
+        lo_hi[2 * b + 1] = (int32_t)hi;
+        widest = std::max(widest, hi - lo);
+    }
+    *max_window = (int32_t)widest;
+    return ED_OK;
+}
+
 int ed_band_order(const int32_t *cols, const int32_t *nnz, int64_t dim, int32_t width, int layout, int64_t *perm) {
     clear_error();
     const char *who = "ed_band_order";

@@ -20,10 +20,11 @@ struct Tile {
     int dn_block;   // k_down threads per workgroup
     int dn_rpb;     // rows per k_down workgroup (0 = derive from LDS and block)
     int dn_pair;    // 1: two rows per workgroup sharing each table chunk (k_down2), where both fit LDS
+    int dn_win;     // 1: rows too long for LDS by column blocks with their neighbour windows (k_down_win)
 };
 
 struct UpTile { int wlog2, rc, block, map; };
-struct DnTile { int block, rpb, pair; };
+struct DnTile { int block, rpb, pair, win; };
 
 // Candidates searched by ed_tune.  A tile id is up_index | (dn_index << 8);
 // index 0 means "heuristic default" for that kernel.
@@ -43,8 +44,9 @@ static const UpTile kUpTiles[] = {
     {7, 8, 256, 0}, {7, 16, 512, 0}, {8, 8, 256, 0}, {8, 16, 256, 0}, {8, 32, 256, 0}, {8, 16, 512, 0},
 };
 static const DnTile kDnTiles[] = {
-    {0, 0, 0}, {1024, 0, 0}, {512, 0, 0}, {256, 0, 0}, {1024, 1, 0}, {512, 1, 0}, {256, 1, 0}, {1024, 2, 0},
-    {512, 2, 0}, {256, 4, 0}, {1024, 2, 1}, {512, 2, 1}, {256, 2, 1},
+    {0, 0, 0, 0},    {1024, 0, 0, 0}, {512, 0, 0, 0}, {256, 0, 0, 0}, {1024, 1, 0, 0}, {512, 1, 0, 0},
+    {256, 1, 0, 0},  {1024, 2, 0, 0}, {512, 2, 0, 0}, {256, 4, 0, 0}, {1024, 2, 1, 0}, {512, 2, 1, 0},
+    {256, 2, 1, 0},  {1024, 0, 0, 1}, {512, 0, 0, 1}, {256, 0, 0, 1},
 };
 constexpr int kNumUp = sizeof(kUpTiles) / sizeof(kUpTiles[0]);
 constexpr int kNumDn = sizeof(kDnTiles) / sizeof(kDnTiles[0]);
@@ -79,10 +81,12 @@ static inline Tile resolve_tile_id(const ed_ham *h, int id) {
         t.dn_block = kDnTiles[di].block;
         t.dn_rpb = kDnTiles[di].rpb;
         t.dn_pair = kDnTiles[di].pair;
+        t.dn_win = kDnTiles[di].win;
     } else {
         t.dn_block = h->dim_dn >= 1024 ? 1024 : 256;
         t.dn_rpb = 0;
         t.dn_pair = 0;
+        t.dn_win = 0;
     }
     if (wide_dn(h)) t.dn_block = std::min(t.dn_block, 512);   // the 32-bit table variants' launch bound
     // V = 2 or 4 columns per lane need row starts aligned to V elements (a row
@@ -133,6 +137,8 @@ static inline int check_ham(const ed_ham *h, const char *who) {
             return set_error(ED_EOVERFLOW, "%s: per-spin dims above %d with complex tables", who, kComplexMaxDim);
     }
     if (!valid_tile_id(h->tile)) return set_error(ED_EINVAL, "%s: bad tile id %d", who, h->tile);
+    if (h->win_dn && (h->win_cols <= 0 || (h->win_cols & 63) || h->win_max <= 0 || h->win_max > h->dim_dn))
+        return set_error(ED_EINVAL, "%s: bad neighbour windows (win_cols %d, win_max %d)", who, h->win_cols, h->win_max);
     if (!std::isfinite(h->t) || !std::isfinite(h->U)) return set_error(ED_EINVAL, "%s: non-finite t or U", who);
     return ED_OK;
 }

@@ -67,7 +67,7 @@ def test_two_row_down_kernel_in_lanczos(ns, bonds, nu, nd, dtype):
     _, x = seeded_start(23, h.dim, dtype)
     nu_, nd_ = ctypes.c_int32(0), ctypes.c_int32(0)
     ed.lib().ed_tile_count(ctypes.byref(nu_), ctypes.byref(nd_))
-    pairs = [di for di in range(nd_.value) if h.tile_params(di << 8)["dn_pair"]]
+    pairs = [di for di in range(nd_.value) if h.tile_params(di << 8)["dn_kind"] == 1]
     assert pairs, "no two-row tile applies"
     announce("two-row down kernel, lanczos %d+%d on %d sites %s, tiles %s" % (nu, nd, ns, dtype, pairs))
     h.tile = 0

@@ -293,3 +293,37 @@ def test_spin_tables_band_order():
     assert np.array_equal(t.perm, ed.band_order(ed.build_hopping(16, torus_bonds(4, 4), st)))
     h = ed.Hamiltonian.from_lattice(16, torus_bonds(4, 4), 3, 3, 1.0, 4.0, "f64", "cpu", order=("band", "hops"))
     assert h.order_bits == 3 and h.up is not h.dn
+
+
+def test_row_windows_hold_each_block_and_its_neighbours():
+    """ed_row_windows against a brute-force scan: every state of a block and every table column of those
+    states lies in [lo, hi); lo and hi are multiples of 4 (hi capped at dim) and as tight as that allows;
+    max_window is the widest.  Both layouts, ascending and band order, a block size that leaves a ragged
+    last block."""
+    from paper_1511_00863_amd import api
+    from synth import ring_bonds, torus_bonds
+    for ns, bonds, n in ((16, torus_bonds(4, 4), 5), (12, ring_bonds(12), 6)):
+        st = api.build_basis(ns, n)
+        for layout in (api.ED_ROW_MAJOR, api.ED_COL_MAJOR):
+            tab = api.build_hopping(ns, bonds, st, layout=layout)
+            for order in ("ascending", "band"):
+                t = tab
+                if order == "band":
+                    _, t = api.permute_basis(st, tab, api.band_order(tab))
+                D, W = st.size, t["width"]
+                cols = t["cols"].reshape(D, W) if layout == api.ED_ROW_MAJOR else t["cols"].reshape(W, D).T
+                for bc in (64, 192):
+                    lo_hi, widest = api.row_windows(t, bc)
+                    nblk = (D + bc - 1) // bc
+                    assert lo_hi.size == 2 * nblk
+                    want_w = 0
+                    for b in range(nblk):
+                        c0, c1 = b * bc, min(D, (b + 1) * bc)
+                        nb = [int(c) for r in range(c0, c1) for c in cols[r, :t["nnz"][r]]]
+                        lo = min([c0] + nb) // 4 * 4
+                        hi = min(D, (max([c1 - 1] + nb) + 1 + 3) // 4 * 4)
+                        assert (lo_hi[2 * b], lo_hi[2 * b + 1]) == (lo, hi), (ns, n, layout, order, bc, b)
+                        want_w = max(want_w, hi - lo)
+                    assert widest == want_w
+    with pytest.raises(Exception):
+        api.row_windows(tab, 100)   # not a multiple of 64
