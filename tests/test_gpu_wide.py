@@ -156,3 +156,44 @@ def test_full_size_ring18_9x9_u0_closed_form(ring18_tables):
     torch.cuda.empty_cache()
     assert r["status"] == 0, (r["status"], r["steps"])
     assert abs(r["e0"] - exact) <= 1e-9 * abs(exact), (r["e0"], exact)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_full_size_ring18_9x9_band_order_windowed_rows(dtype):
+    """The bench's scale run: both species in band order, the cached tile, which stages each 8192-state
+    column block of a row with its neighbour window in LDS (k_down_win).  Five full rows of H x, carried
+    back to the ascending order, against the oracle."""
+    ns, bonds, n = RING18
+    announce("ring18 9+9 band-order tables")
+    tab = ed.SpinTables(ns, bonds, n, "cuda:0", order="band")
+    h = ed.Hamiltonian(tab, tab, 1.0, 4.0, dtype)
+    src = ed.api.apply_tuned_tile(h, tune_if_missing=False)
+    assert src == "cache" and h.tile_params()["dn_kind"] == 2, (src, h.tile_params())
+    x_host = start_vector(8, h.dim)
+    if dtype == "f32":
+        x32 = x_host.astype(np.float32)
+        del x_host
+        x = torch.from_numpy(x32).to("cuda:0")
+        x_host = x32.astype(np.float64)
+        del x32
+    else:
+        x = torch.from_numpy(x_host).to("cuda:0")
+    announce("hv full ring18 9+9 band order %s dim=%d, tile %d" % (dtype, h.dim, h.tile))
+    xo = h.to_basis_order(x)
+    del x
+    y = h.hv(xo)
+    del xo
+    ya = h.to_ascending(y)
+    del y
+    torch.cuda.synchronize()
+    got = ya.view(h.dim_up, h.dim_dn)[RING18_ROWS].double().cpu().numpy()
+    del ya, h, tab
+    torch.cuda.empty_cache()
+    ref = Model(ns, bonds, n, n, 1.0, 4.0).hv_rows(x_host, RING18_ROWS)
+    del x_host
+    scale = max(1.0, float(np.max(np.abs(ref))))
+    if dtype == "f64":
+        assert float(np.max(np.abs(got - ref))) <= 1e-12 * scale
+    else:
+        assert np.linalg.norm(got - ref) <= 2e-6 * np.linalg.norm(ref)
+        assert float(np.max(np.abs(got - ref))) <= 2e-5 * scale
