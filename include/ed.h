@@ -406,30 +406,40 @@ typedef struct ed_batch_item {
     double *a, *b;
 } ed_batch_item;
 
-/* Device workspace bytes for ed_ground_energy_batch on these items. */
-int ed_batch_workspace_size(const ed_batch_item *items, int32_t n, int32_t max_steps, int64_t *bytes);
+/* Device workspace bytes for ed_ground_energy_batch on these items with
+ * this solo_dim. */
+int ed_batch_workspace_size(const ed_batch_item *items, int32_t n, int32_t max_steps, int64_t solo_dim,
+                            int64_t *bytes);
 
 /* Run n independent Lanczos ground-state computations (Alg. 1 with the mixed
- * form of ed_lanczos_step) in ONE persistent cooperative kernel launch, which
+ * form of ed_lanczos_step).  The items below solo_dim states (all of them
+ * when solo_dim <= 0) run in ONE persistent cooperative kernel launch, which
  * is captured in a HIP graph when use_graph != 0 and the runtime accepts the
  * capture (*graph_used reports it; otherwise the kernel is launched
  * directly).  The instances may differ in U, t and fillings (uneven
  * dimensions).  Each instance stops on its own when |E0(j) - E0(j-1)| < tol
  * at two consecutive steps, E0(j) being the lowest eigenvalue of T_j found
  * on the device by Sturm-count multisection; or on breakdown; or at
- * max_steps.  Launch tiles follow each item's h.tile (see ed_tune).
+ * max_steps.  Launch tiles follow each item's h.tile (see ed_tune).  Items
+ * of at least solo_dim states (solo_dim > 0) then run one after another on
+ * `stream` through ed_ground_energy (the same stopping rule, checked every 9
+ * steps on the host, steps launched from a captured graph): one step of such
+ * an instance fills the GPU by itself, and its tuned one-instance kernels
+ * beat the persistent kernel's shared tiles.
  * Per item (host arrays of n): e0 = lowest eigenvalue of T at the stopping
  * step (host bisection of the returned coefficients), steps, status (ED_OK =
  * converged, ED_BREAKDOWN, ED_NOT_CONVERGED); e0_device (may be NULL) = the
- * device's value at that step.  phase_ms (6 doubles, may be NULL): time spent
- * in the phases start-up, up part, down part, a_j, update, b_j (summed over
- * the steps, barrier waits included).  ws: ed_batch_workspace_size bytes,
- * 256-byte aligned.  Synchronises `stream`.  Returns ED_NOT_CONVERGED if any item
- * did not converge.  Limits: per-spin dims <= 32767, rows (dim_dn) of at
- * most 8192 floats, table strides <= 32 (both species), both species must
- * hop. */
-int ed_ground_energy_batch(const ed_batch_item *items, int32_t n, int32_t max_steps, double tol, void *ws,
-                           int64_t ws_bytes, void *stream, int32_t use_graph, double *e0, int32_t *steps,
+ * device's value at that step (for an item run on its own, the host value).
+ * phase_ms (6 doubles, may be NULL): time the persistent launch spent in the
+ * phases start-up, up part, down part, a_j, update, b_j (summed over the
+ * steps, barrier waits included; zero without one).  ws:
+ * ed_batch_workspace_size bytes for the same solo_dim, 256-byte aligned.
+ * Synchronises `stream`.  Returns ED_NOT_CONVERGED if any item did not
+ * converge.  Limits (every item): per-spin dims <= 32767, rows (dim_dn) of
+ * at most 8192 floats, table strides <= 32 (both species), both species
+ * must hop. */
+int ed_ground_energy_batch(const ed_batch_item *items, int32_t n, int32_t max_steps, double tol, int64_t solo_dim,
+                           void *ws, int64_t ws_bytes, void *stream, int32_t use_graph, double *e0, int32_t *steps,
                            int32_t *status, double *e0_device, int32_t *graph_used, double *phase_ms);
 
 /* ---- device: observables of a state -------------------------------------- */

@@ -42,8 +42,8 @@ class EdLanczos(ctypes.Structure):
 
 
 _PROTOS = {
-    "ed_batch_workspace_size": (c_int, [POINTER(EdBatchItem), c_int32, c_int32, POINTER(c_int64)]),
-    "ed_ground_energy_batch": (c_int, [POINTER(EdBatchItem), c_int32, c_int32, c_double, c_void_p, c_int64,
+    "ed_batch_workspace_size": (c_int, [POINTER(EdBatchItem), c_int32, c_int32, c_int64, POINTER(c_int64)]),
+    "ed_ground_energy_batch": (c_int, [POINTER(EdBatchItem), c_int32, c_int32, c_double, c_int64, c_void_p, c_int64,
                                        c_void_p, c_int32, POINTER(c_double), POINTER(c_int32), POINTER(c_int32),
                                        POINTER(c_double), POINTER(c_int32), POINTER(c_double)]),
     "ed_last_error": (c_char_p, []),

@@ -614,7 +614,14 @@ class LanczosRun:
         return e0.value, steps.value, v
 
 
-def ground_energy_batch(hams, f1s, max_steps: int, tol: float = 1e-6, use_graph: bool = True, stream=None):
+# Instances of at least this many states in a batch run one by one through the one-instance path (a step of
+# theirs fills the GPU, and their tuned kernels beat the persistent launch's shared tiles); 0 puts every
+# instance in the persistent launch.
+BATCH_SOLO_DIM = 1 << 22
+
+
+def ground_energy_batch(hams, f1s, max_steps: int, tol: float = 1e-6, use_graph: bool = True, stream=None,
+                        solo_dim: int = BATCH_SOLO_DIM):
     """ed_ground_energy_batch over a list of float32 Hamiltonians and start vectors.
 
     Returns dict(e0, steps, status, e0_device, graph_used, wall_ms)."""
@@ -636,7 +643,7 @@ def ground_energy_batch(hams, f1s, max_steps: int, tol: float = 1e-6, use_graph:
         items[i].a = a.data_ptr()
         items[i].b = b.data_ptr()
     nb = c_int64(0)
-    check(lib().ed_batch_workspace_size(items, n, int(max_steps), byref(nb)))
+    check(lib().ed_batch_workspace_size(items, n, int(max_steps), int(solo_dim), byref(nb)))
     ws = torch.empty(nb.value, dtype=torch.uint8, device=hams[0].device)
     e0 = np.zeros(n)
     e0d = np.zeros(n)
@@ -647,7 +654,7 @@ def ground_energy_batch(hams, f1s, max_steps: int, tol: float = 1e-6, use_graph:
     torch.cuda.synchronize()
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     start.record()
-    rc = check(lib().ed_ground_energy_batch(items, n, int(max_steps), float(tol), _dptr(ws), nb.value,
+    rc = check(lib().ed_ground_energy_batch(items, n, int(max_steps), float(tol), int(solo_dim), _dptr(ws), nb.value,
                                             _stream(stream), 1 if use_graph else 0, _ptr(e0, c_double),
                                             _ptr(steps, c_int32), _ptr(status, c_int32), _ptr(e0d, c_double),
                                             byref(used), _ptr(phase, c_double)))

@@ -639,29 +639,66 @@ __global__ __launch_bounds__(256) void k_batch_collect(const BInst *__restrict__
     if (threadIdx.x == 0) o[2 * max_steps + 1] = k > 0 ? I.e[k] : 0.0;
 }
 
+// Steps between the host's convergence checks when a batch runs one of its
+// large instances on its own (ed_ground_energy).
+constexpr int kSoloCheck = 9;
+
 }  // namespace ed
+
+namespace {
 
 using namespace ed;
 
-extern "C" {
+// Instances of at least solo_dim states (solo_dim > 0) run one by one.
+bool solo_item(const ed_batch_item &it, int64_t solo_dim) {
+    return solo_dim > 0 && it.h.dim_up * it.h.dim_dn >= solo_dim;
+}
 
-int ed_batch_workspace_size(const ed_batch_item *items, int32_t n, int32_t max_steps, int64_t *bytes) {
-    clear_error();
-    if (!items || n < 1 || max_steps < 1 || !bytes) return set_error(ED_EINVAL, "ed_batch_workspace_size: bad arguments");
-    BatchPlan plan;
-    int rc = plan_batch(items, n, max_steps, plan, false);
-    if (rc) return rc;
-    *bytes = batch_ws_bytes(plan, n, max_steps);
+int64_t al256(int64_t b) { return (b + 255) & ~int64_t(255); }
+
+// Workspace of the persistent launch over `items` (0 for none) and of the
+// largest one-by-one run among `solo`.
+int batch_parts_bytes(const std::vector<ed_batch_item> &items, const std::vector<ed_batch_item> &solo,
+                      int32_t max_steps, int64_t *persist, int64_t *single) {
+    *persist = 0;
+    *single = 0;
+    if (!items.empty()) {
+        BatchPlan plan;
+        const int rc = plan_batch(items.data(), (int)items.size(), max_steps, plan, false);
+        if (rc) return rc;
+        *persist = batch_ws_bytes(plan, (int)items.size(), max_steps);
+    }
+    for (const ed_batch_item &it : solo) {
+        int64_t b = 0;
+        const int rc = ed_workspace_size(&it.h, max_steps, &b);
+        if (rc) return rc;
+        *single = std::max(*single, b);
+    }
     return ED_OK;
 }
 
-int ed_ground_energy_batch(const ed_batch_item *items, int32_t n, int32_t max_steps, double tol, void *ws,
-                           int64_t ws_bytes, void *stream, int32_t use_graph, double *e0, int32_t *steps,
-                           int32_t *status, double *e0_device, int32_t *graph_used, double *phase_ms) {
-    clear_error();
-    if (!items || n < 1 || max_steps < 1 || !ws || !e0 || !steps || !status || !(tol > 0))
-        return set_error(ED_EINVAL, "ed_ground_energy_batch: bad arguments");
-    if (reinterpret_cast<uintptr_t>(ws) & 255) return set_error(ED_EINVAL, "ed_ground_energy_batch: ws not aligned");
+void split_items(const ed_batch_item *items, int32_t n, int64_t solo_dim, std::vector<ed_batch_item> &group,
+                 std::vector<int> &gidx, std::vector<ed_batch_item> &solo, std::vector<int> &sidx) {
+    for (int i = 0; i < n; ++i) {
+        if (solo_item(items[i], solo_dim)) {
+            solo.push_back(items[i]);
+            sidx.push_back(i);
+        } else {
+            group.push_back(items[i]);
+            gidx.push_back(i);
+        }
+    }
+}
+
+}  // namespace
+
+namespace ed {
+
+// The persistent cooperative launch over n items (the whole of a batch, or
+// the part of it below solo_dim).
+static int persistent_run(const ed_batch_item *items, int32_t n, int32_t max_steps, double tol, void *ws,
+                          int64_t ws_bytes, void *stream, int32_t use_graph, double *e0, int32_t *steps,
+                          int32_t *status, double *e0_device, int32_t *graph_used, double *phase_ms) {
     BatchPlan plan;
     int rc = plan_batch(items, n, max_steps, plan, true);
     if (rc) return rc;
@@ -772,6 +809,93 @@ int ed_ground_energy_batch(const ed_batch_item *items, int32_t n, int32_t max_st
         const double *a = staged.data() + (size_t)pos * sst, *b = a + max_steps;
         e0[i] = k > 0 ? tridiag_lowest(a, b + 1, k) : NAN;
         if (e0_device) e0_device[i] = k > 0 ? a[2 * max_steps + 1] : NAN;
+    }
+    return result;
+}
+
+}  // namespace ed
+
+extern "C" {
+
+int ed_batch_workspace_size(const ed_batch_item *items, int32_t n, int32_t max_steps, int64_t solo_dim,
+                            int64_t *bytes) {
+    using namespace ed;
+    clear_error();
+    if (!items || n < 1 || max_steps < 1 || !bytes) return set_error(ED_EINVAL, "ed_batch_workspace_size: bad arguments");
+    BatchPlan all;
+    int rc = plan_batch(items, n, max_steps, all, false);   // every item meets the batch's limits
+    if (rc) return rc;
+    std::vector<ed_batch_item> group, solo;
+    std::vector<int> gidx, sidx;
+    split_items(items, n, solo_dim, group, gidx, solo, sidx);
+    int64_t persist = 0, single = 0;
+    rc = batch_parts_bytes(group, solo, max_steps, &persist, &single);
+    if (rc) return rc;
+    *bytes = al256(persist) + single;
+    return ED_OK;
+}
+
+int ed_ground_energy_batch(const ed_batch_item *items, int32_t n, int32_t max_steps, double tol, int64_t solo_dim,
+                           void *ws, int64_t ws_bytes, void *stream, int32_t use_graph, double *e0, int32_t *steps,
+                           int32_t *status, double *e0_device, int32_t *graph_used, double *phase_ms) {
+    using namespace ed;
+    clear_error();
+    if (!items || n < 1 || max_steps < 1 || !ws || !e0 || !steps || !status || !(tol > 0))
+        return set_error(ED_EINVAL, "ed_ground_energy_batch: bad arguments");
+    if (reinterpret_cast<uintptr_t>(ws) & 255) return set_error(ED_EINVAL, "ed_ground_energy_batch: ws not aligned");
+    BatchPlan all;
+    int rc = plan_batch(items, n, max_steps, all, true);   // limits and buffers of every item
+    if (rc) return rc;
+    std::vector<ed_batch_item> group, solo;
+    std::vector<int> gidx, sidx;
+    split_items(items, n, solo_dim, group, gidx, solo, sidx);
+    int64_t persist = 0, single = 0;
+    rc = batch_parts_bytes(group, solo, max_steps, &persist, &single);
+    if (rc) return rc;
+    if (ws_bytes < al256(persist) + single) return set_error(ED_ECAPACITY, "ed_ground_energy_batch: workspace too small");
+    if (graph_used) *graph_used = 0;
+    if (phase_ms)
+        for (int k = 0; k < 6; ++k) phase_ms[k] = 0.0;
+    int result = ED_OK;
+    if (!group.empty()) {
+        const int ng = (int)group.size();
+        std::vector<double> ge0(ng), ged(ng);
+        std::vector<int32_t> gst(ng), gss(ng);
+        rc = persistent_run(group.data(), ng, max_steps, tol, ws, al256(persist), stream, use_graph, ge0.data(),
+                            gst.data(), gss.data(), ged.data(), graph_used, phase_ms);
+        if (rc != ED_OK && rc != ED_NOT_CONVERGED) return rc;
+        result = rc;
+        for (int k = 0; k < ng; ++k) {
+            const int i = gidx[k];
+            e0[i] = ge0[k];
+            steps[i] = gst[k];
+            status[i] = gss[k];
+            if (e0_device) e0_device[i] = ged[k];
+        }
+    }
+    // the large instances, one after another on the same stream, through the
+    // one-instance run (the same stopping rule, checked every kSoloCheck steps)
+    void *ws_single = static_cast<char *>(ws) + al256(persist);
+    for (size_t k = 0; k < solo.size(); ++k) {
+        const ed_batch_item &it = solo[k];
+        const int i = sidx[k];
+        ed_lanczos st{};
+        st.f_prev = it.vec[0];
+        st.f_cur = it.vec[1];
+        st.f_next = it.vec[2];
+        st.a = it.a;
+        st.b = it.b;
+        st.j = 0;
+        st.max_steps = max_steps;
+        double e = NAN;
+        int32_t j = 0;
+        rc = ed_ground_energy(&it.h, &st, it.f1, tol, kSoloCheck, ws_single, stream, &e, &j, nullptr, nullptr);
+        if (rc != ED_OK && rc != ED_BREAKDOWN && rc != ED_NOT_CONVERGED) return rc;
+        e0[i] = e;
+        steps[i] = j;
+        status[i] = rc;
+        if (e0_device) e0_device[i] = e;
+        if (rc == ED_NOT_CONVERGED) result = ED_NOT_CONVERGED;
     }
     return result;
 }

@@ -40,8 +40,11 @@ def test_batch_mixed_shapes():
     assert abs(r["e0"][0] - (-16.0)) <= 1e-6 * 16
 
 
-def test_batch_64_uneven_fillings():
-    """64 instances, U ~ U[0,8], N_up = N_dn in {3,4,5,6}, one launch, |dE0| < 1e-6."""
+@pytest.mark.parametrize("solo_dim", [0, ed.api.BATCH_SOLO_DIM], ids=["persistent", "scheduled"])
+def test_batch_64_uneven_fillings(solo_dim):
+    """64 instances, U ~ U[0,8], N_up = N_dn in {3,4,5,6}, |dE0| < 1e-6: all in one persistent launch
+    (solo_dim 0), or with the instances of at least 2^22 states (5 and 6 per species) run one by one after
+    it."""
     bonds = torus_bonds(4, 4)
     draws = batch_instances(64, 1000)
     tabs = {n: ed.SpinTables(16, bonds, n, "cuda:0") for n in (3, 4, 5, 6)}
@@ -49,9 +52,13 @@ def test_batch_64_uneven_fillings():
     for h in hams:
         ed.api.apply_tuned_tile(h, tune_if_missing=False)
     f1s = [torch.from_numpy(start_vector(s, h.dim)).to("cuda:0", torch.float32) for h, (U, n, s) in zip(hams, draws)]
-    announce("batch 64 uneven, total dim %d" % sum(h.dim for h in hams))
-    r = ed.ground_energy_batch(hams, f1s, 500, tol=1e-6)
+    announce("batch 64 uneven, total dim %d, solo_dim %d" % (sum(h.dim for h in hams), solo_dim))
+    r = ed.ground_energy_batch(hams, f1s, 500, tol=1e-6, solo_dim=solo_dim)
     assert (r["status"] == ed.ED_OK).all(), r["status"]
+    solo = np.array([solo_dim > 0 and h.dim >= solo_dim for h in hams])
+    assert solo.sum() == (0 if solo_dim == 0 else sum(n >= 5 for (U, n, s) in draws))
+    assert np.array_equal(r["e0_device"][solo], r["e0"][solo])   # one-by-one items report the host value
+    assert (r["steps"] > 0).all()
     del f1s
     torch.cuda.empty_cache()
     # every instance against its solo float64 energy (sample 8 to bound the run time)
