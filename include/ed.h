@@ -227,7 +227,10 @@ int ed_tridiag_lowest_vector(const double *a, const double *b, int m, double *e0
  * win_dn: NULL, or the down species' neighbour windows from ed_row_windows
  * (device, 2 * ceil(dim_dn / win_cols) int32) for blocks of win_cols states,
  * the largest win_max; the autotuner may then give rows too long for LDS a
- * down-part kernel that stages each block's window (real instances). */
+ * down-part kernel that stages each block's window (real instances).  The
+ * windows must hold every block's table columns (they come from this
+ * species' table): a block whose pair is wider than win_max or does not
+ * cover the block is gathered from global memory instead. */
 typedef struct ed_ham {
     int64_t dim_up, dim_dn;
     int32_t w_up, w_dn;

@@ -311,13 +311,17 @@ void k_down2(const T *__restrict__ x, T *__restrict__ io, const T *__restrict__ 
 // workgroup of (row r, block b) stages x[r, lo_b..hi_b), the block's states
 // and all their neighbours, in LDS with a zero after it, and runs the block's
 // columns as the one-row kernel does (the same q bits).  win: the blocks'
-// (lo, hi) pairs; wcols: states per block; nblk blocks per row.
+// (lo, hi) pairs; wcols: states per block; nblk blocks per row; wmax: the
+// LDS room (elements) before the zero.  A pair that does not fit that room or
+// does not cover its block is not staged: that block gathers from global
+// memory as the kernel for long rows does (the same bits again).
 template <typename T, int MODE, int NCH, typename E>
 __global__ __launch_bounds__(sizeof(E) == 4 ? 512 : 1024)
 void k_down_win(const T *__restrict__ x, T *__restrict__ io, const T *__restrict__ p, const E *__restrict__ tab,
                 const uint64_t *__restrict__ st_up, const uint64_t *__restrict__ st_dn, int Dup, int Ddn, int W8,
-                const int32_t *__restrict__ win, int wcols, int nblk, T t, T U, const double *__restrict__ bvec,
-                const Hdr *__restrict__ hdr, double *__restrict__ partials, int max_steps) {
+                const int32_t *__restrict__ win, int wcols, int nblk, int wmax, T t, T U,
+                const double *__restrict__ bvec, const Hdr *__restrict__ hdr, double *__restrict__ partials,
+                int max_steps) {
     extern __shared__ __align__(16) unsigned char smem[];
     T *xs = reinterpret_cast<T *>(smem);
     bool has_prev = false;
@@ -333,16 +337,23 @@ void k_down_win(const T *__restrict__ x, T *__restrict__ io, const T *__restrict
     const int lo = win[2 * b], hi = win[2 * b + 1];
     const int c0 = b * wcols, c1 = min(Ddn, c0 + wcols);
     const int64_t base = (int64_t)r * Ddn;
-    stage_rows<T>(x + base + lo, xs, hi - lo);
-    if (threadIdx.x == 0) xs[hi - lo] = T(0);
-    __syncthreads();
+    const bool staged = lo >= 0 && lo <= c0 && hi >= c1 && hi <= Ddn && hi - lo <= wmax;
+    if (staged) {
+        stage_rows<T>(x + base + lo, xs, hi - lo);
+        if (threadIdx.x == 0) xs[hi - lo] = T(0);
+        __syncthreads();
+    }
     constexpr int NV = MODE == 2 ? 5 : 1;
     double s[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) s[k] = 0.0;
-    down_rows<T, MODE, NCH, false, true, true, E, true>(xs, io, p, tab, st_up + r, st_dn, Ddn, W8, c0, c1, base, t, U,
-                                                        sig, cprev, MODE != 0 && has_prev, s, (unsigned)lo,
-                                                        (unsigned)(hi - lo));
+    if (staged)
+        down_rows<T, MODE, NCH, false, true, true, E, true>(xs, io, p, tab, st_up + r, st_dn, Ddn, W8, c0, c1, base, t,
+                                                            U, sig, cprev, MODE != 0 && has_prev, s, (unsigned)lo,
+                                                            (unsigned)(hi - lo));
+    else
+        down_rows<T, MODE, NCH, false, true, false, E>(x + base, io, p, tab, st_up + r, st_dn, Ddn, W8, c0, c1, base, t,
+                                                       U, sig, cprev, MODE != 0 && has_prev, s);
     if (MODE != 0) {
         double tot[NV];
         block_sum<NV>(s, tot);
@@ -948,7 +959,7 @@ static int launch_down_e(const ed_ham *h, const Tile &tl, const T *x, T *io, con
         const E *tab = static_cast<const E *>(h->tab_dn);
         auto go = [&](auto kern) {
             hipLaunchKernelGGL(kern, dim3(grid), dim3(tl.dn_block), shmw, s, x, io, p, tab, h->st_up, h->st_dn,
-                               (int)h->dim_up, (int)h->dim_dn, h->w_dn, h->win_dn, h->win_cols, cs,
+                               (int)h->dim_up, (int)h->dim_dn, h->w_dn, h->win_dn, h->win_cols, cs, h->win_max,
                                static_cast<T>(h->t), static_cast<T>(h->U), bvec, hdr, part, max_steps);
         };
         if (nch <= 2) go(k_down_win<T, MODE, 2, E>);

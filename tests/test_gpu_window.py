@@ -88,3 +88,26 @@ def test_window_tile_mixed_form_energy(species):
     r = h.ground_energy(h.to_basis_order(x64.float()), 60, tol=0.0)
     assert r["steps"] == 60
     assert abs(r["e0"] - r64["e0"]) <= 1e-6 * abs(r64["e0"]), (r["e0"], r64["e0"])
+
+
+def test_window_wider_than_its_room_falls_back_to_global_rows(species):
+    """A window pair wider than win_max (here block 0 given the whole row) is not staged: that block is
+    gathered from global memory, and H x keeps the global-gather kernel's bits."""
+    bonds, up, dn = species
+    h = ed.Hamiltonian(up, dn, 1.0, 2.5, "f64")
+    di = _window_tiles(h)[0]
+    _, x = seeded_start(100, h.dim, "f64")
+    xo = h.to_basis_order(x)
+    h.tile = 0
+    ref = h.hv(xo).clone()
+    saved = dn.dev_win
+    try:
+        bad = saved.clone()
+        bad[0], bad[1] = 0, dn.dim
+        assert dn.dim > dn.win_max
+        dn.dev_win = bad
+        h.tile = di << 8
+        announce("windowed down rows, an over-wide window for block 0")
+        assert torch.equal(h.hv(xo), ref)
+    finally:
+        dn.dev_win = saved
