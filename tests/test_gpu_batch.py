@@ -66,3 +66,20 @@ def test_batch_64_uneven_fillings(solo_dim):
         U, n, s = draws[k]
         e64, _ = _solo_e0(tabs[n], tabs[n], U, s, "f64", 1e-11)
         assert abs(r["e0"][k] - e64) <= 1e-6 * abs(e64), (k, U, n, r["e0"][k], e64)
+
+
+def test_batch_every_item_one_by_one():
+    """solo_dim = 1 sends every item through the one-instance run (no persistent launch): the same E0 as the
+    persistent launch to 1e-6, coefficients written to each item's a and b, no phase times."""
+    bonds = torus_bonds(4, 4)
+    draws = batch_instances(6, 4000, fillings=(2, 3))
+    tabs = {n: ed.SpinTables(16, bonds, n, "cuda:0") for n in (2, 3)}
+    hams = [ed.Hamiltonian(tabs[n], tabs[n], 1.0, U, "f32") for (U, n, s) in draws]
+    f1s = [torch.from_numpy(start_vector(s, h.dim)).to("cuda:0", torch.float32) for h, (U, n, s) in zip(hams, draws)]
+    announce("batch, every item one by one")
+    ra = ed.ground_energy_batch(hams, f1s, 400, tol=1e-7, solo_dim=1)
+    rb = ed.ground_energy_batch(hams, f1s, 400, tol=1e-7, solo_dim=0)
+    assert (ra["status"] == ed.ED_OK).all() and (rb["status"] == ed.ED_OK).all(), (ra["status"], rb["status"])
+    assert not ra["graph_used"] and all(v == 0.0 for v in ra["phase_ms"].values())
+    assert np.max(np.abs(ra["e0"] - rb["e0"]) / np.abs(rb["e0"])) <= 1e-6
+    assert np.array_equal(ra["e0_device"], ra["e0"])
