@@ -383,17 +383,21 @@ int ed_ground_energy_noalloc(const ed_ham *h, ed_lanczos *st, const void *f1, do
                              void *stream, double *e0, int32_t *steps, double *a_host, double *b_host);
 
 /* Ground-state vector by two passes: pass 1 runs m steps from f1 (as
- * ed_ground_energy with tol <= 0), the lowest eigenvector y of T_m is found on
- * the host, pass 2 replays the identical steps and accumulates
- * v = sum_k y_k f_k, then v is normalised (float64 norm).  v: device, h->dtype,
+ * ed_ground_energy with tol <= 0) or, with tol > 0, the steps until
+ * |E0(j) - E0(j-1)| < tol at two consecutive j (ed_ground_energy's rule)
+ * plus `extra` (>= 0) more, at most m; the lowest eigenvector y of T_m (m
+ * the pass's step count) is found on the host, pass 2 replays the identical
+ * steps and accumulates v = sum_k y_k f_k, then v is normalised (float64
+ * norm).  A run to a tolerance therefore needs no separate ed_ground_energy
+ * call to fix m.  v: device, h->dtype,
  * dim elements, distinct from the three Lanczos vectors.  gauge_index >= 0
  * fixes the arbitrary global sign: v[gauge_index] >= 0 afterwards, or, when
  * |v[gauge_index]| is below 1e-3 of max |v_i| (its sign then carries no
  * information), the largest-magnitude element (the lowest index among equal
  * magnitudes) is made positive instead; -1: no gauge.  ws must hold
  * ed_workspace_size(h, m).  *e0 = lowest eigenvalue of T_m. */
-int ed_ground_state(const ed_ham *h, ed_lanczos *st, const void *f1, int32_t m, int64_t gauge_index, void *v,
-                    void *ws, void *stream, double *e0, int32_t *steps);
+int ed_ground_state(const ed_ham *h, ed_lanczos *st, const void *f1, int32_t m, double tol, int32_t extra,
+                    int64_t gauge_index, void *v, void *ws, void *stream, double *e0, int32_t *steps);
 
 /* ---- device: batched ground-state runs --------------------------------- */
 

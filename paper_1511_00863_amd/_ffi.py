@@ -101,8 +101,8 @@ _PROTOS = {
     "ed_ground_energy_noalloc": (c_int, [POINTER(EdHam), POINTER(EdLanczos), c_void_p, c_double, c_int32,
                                          c_void_p, POINTER(c_double), POINTER(c_int32), POINTER(c_double),
                                          POINTER(c_double)]),
-    "ed_ground_state": (c_int, [POINTER(EdHam), POINTER(EdLanczos), c_void_p, c_int32, c_int64, c_void_p,
-                                c_void_p, c_void_p, POINTER(c_double), POINTER(c_int32)]),
+    "ed_ground_state": (c_int, [POINTER(EdHam), POINTER(EdLanczos), c_void_p, c_int32, c_double, c_int32, c_int64,
+                                c_void_p, c_void_p, c_void_p, POINTER(c_double), POINTER(c_int32)]),
     "ed_mlp_workspace_size": (c_int, [c_int64, POINTER(c_int64)]),
     "ed_mlp_forward": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]),
     "ed_mlp_backward": (c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]),

@@ -481,11 +481,12 @@ class Hamiltonian:
         run = LanczosRun(self, max_steps)
         return run.ground_energy(f1, tol, check_every, stream)
 
-    def ground_state(self, f1, m: int, gauge_index: int = -1, stream=None):
+    def ground_state(self, f1, m: int, gauge_index: int = -1, stream=None, tol: float = 0.0, extra: int = 0):
         """Two-pass ground-state vector: returns (E0, steps, v) with |v| = 1 and v[gauge_index] >= 0 (or, where
-        that element is below 1e-3 of the largest magnitude, the largest-magnitude element positive)."""
+        that element is below 1e-3 of the largest magnitude, the largest-magnitude element positive).
+        tol > 0: pass 1 stops where E0 settles (ed_ground_energy's rule) plus `extra` steps, at most m."""
         run = LanczosRun(self, m)
-        return run.ground_state(f1, m, gauge_index, stream)
+        return run.ground_state(f1, m, gauge_index, stream, tol, extra)
 
 
 TUNE_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
@@ -603,14 +604,15 @@ class LanczosRun:
         k = steps.value
         return {"e0": e0.value, "steps": k, "status": rc, "a": a[:k], "b": b[:k + 1]}
 
-    def ground_state(self, f1, m, gauge_index=-1, stream=None):
+    def ground_state(self, f1, m, gauge_index=-1, stream=None, tol=0.0, extra=0):
         f1 = self.ham._vec(f1)
         v = self.ham.empty_vec()
         e0, steps = c_double(0), c_int32(0)
         if f1.data_ptr() == self.st.f_cur:
             raise ValueError("f1 must not be the run's current vector")
-        check(lib().ed_ground_state(byref(self._h), byref(self.st), _dptr(f1), int(m), int(gauge_index), _dptr(v),
-                                    _dptr(self.ws), _stream(stream), byref(e0), byref(steps)))
+        check(lib().ed_ground_state(byref(self._h), byref(self.st), _dptr(f1), int(m), float(tol), int(extra),
+                                    int(gauge_index), _dptr(v), _dptr(self.ws), _stream(stream), byref(e0),
+                                    byref(steps)))
         return e0.value, steps.value, v
 
 

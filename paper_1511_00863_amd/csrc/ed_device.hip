@@ -1732,27 +1732,45 @@ int ed_ground_energy_noalloc(const ed_ham *h, ed_lanczos *st, const void *f1, do
     return result;
 }
 
-int ed_ground_state(const ed_ham *h, ed_lanczos *st, const void *f1, int32_t m, int64_t gauge_index, void *v,
-                    void *ws, void *stream, double *e0, int32_t *steps) {
+int ed_ground_state(const ed_ham *h, ed_lanczos *st, const void *f1, int32_t m, double tol, int32_t extra,
+                    int64_t gauge_index, void *v, void *ws, void *stream, double *e0, int32_t *steps) {
     clear_error();
     int rc = check_lanczos(h, st, ws, "ed_ground_state");
     if (rc) return rc;
     rc = ensure_attrs();
     if (rc) return rc;
-    if (!v || !e0 || !steps || m < 1 || m > st->max_steps)
-        return set_error(ED_EINVAL, "ed_ground_state: bad arguments (need 1 <= m <= max_steps)");
+    if (!v || !e0 || !steps || m < 1 || m > st->max_steps || extra < 0)
+        return set_error(ED_EINVAL, "ed_ground_state: bad arguments (need 1 <= m <= max_steps, extra >= 0)");
     if (v == st->f_prev || v == st->f_cur || v == st->f_next || v == f1)
         return set_error(ED_EINVAL, "ed_ground_state: v must not alias f1 or the Lanczos vectors");
     if (h->cplx && gauge_index >= 0)
         return set_error(ED_EINVAL, "ed_ground_state: a complex state's phase is not fixed by an index (pass -1)");
-    // pass 1: m steps (fewer on breakdown)
+    // pass 1: m steps (fewer on breakdown); with tol > 0, up to m: the steps until E0 settles (the rule of
+    // ed_ground_energy), then `extra` more
     ed_lanczos s1 = *st;
     s1.max_steps = m;
     std::vector<double> a(m), b(m + 1);
     int32_t k = 0;
     double e;
-    rc = ed_ground_energy(h, &s1, f1, 0.0, 30, ws, stream, &e, &k, a.data(), b.data());
-    if (rc < 0) return rc;
+    if (tol > 0.0) {
+        rc = ed_ground_energy(h, &s1, f1, tol, 15, ws, stream, &e, &k, nullptr, nullptr);
+        if (rc < 0) return rc;
+        const int32_t want = (int32_t)std::min<int64_t>(m, (int64_t)k + extra);
+        // the device may be past k (steps go in chunks); step on to `want` unless frozen
+        int32_t done = 0, status = ED_OK;
+        rc = ed_lanczos_read(h, &s1, ws, stream, &done, &status, nullptr, nullptr);
+        if (rc) return rc;
+        for (int32_t j = done; j < want && status == ED_OK; ++j) {
+            rc = ed_lanczos_step(h, &s1, ws, stream);
+            if (rc) return rc;
+        }
+        rc = ed_lanczos_read(h, &s1, ws, stream, &done, &status, a.data(), b.data());
+        if (rc) return rc;
+        k = std::min(done, want);
+    } else {
+        rc = ed_ground_energy(h, &s1, f1, 0.0, 30, ws, stream, &e, &k, a.data(), b.data());
+        if (rc < 0) return rc;
+    }
     std::vector<double> y(k);
     rc = ed_tridiag_lowest_vector(a.data(), b.data() + 1, k, &e, y.data());
     if (rc) return rc;

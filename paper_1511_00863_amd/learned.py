@@ -34,16 +34,16 @@ def reference_energy(up, dn, t, U, seed, tol=1e-12, max_steps=800, tile=None):
 
 
 def training_data(up, dn, t, us, seed=100, dtype="f32", tol=1e-9, extra_steps=20, max_steps=800, gauge=None):
-    """(ham, psi, cdf) per training U: E0 run to find the step count, then the two-pass vector."""
+    """(ham, psi, cdf) per training U: the two-pass vector, pass 1 run until E0 settles to tol plus
+    extra_steps more (at most max_steps)."""
     out = []
     for k, U in enumerate(us):
         h = api.Hamiltonian(up, dn, t, U, dtype)
         api.apply_tuned_tile(h, tune_if_missing=False)
         x = _random_start(h, seed + k)
-        r = h.ground_energy(x, max_steps, tol=tol, check_every=15)
-        m = min(max_steps, r["steps"] + extra_steps)
         gi = mlp.neel_index(h) if gauge is None else gauge
-        e0, steps, psi = h.ground_state(x, m, gauge_index=gi)
+        # pass 1 runs until E0 settles to tol, then extra_steps more (at most max_steps); pass 2 builds psi
+        e0, steps, psi = h.ground_state(x, max_steps, gauge_index=gi, tol=tol, extra=extra_steps)
         del x
         out.append((h, psi, mlp.row_cdf(psi, h)))
     return out

@@ -205,3 +205,21 @@ def test_ground_state_gauge_follows_the_oracle_rule(dtype):
     for k in (big, small):
         _, _, v = h.ground_state(x, 80, gauge_index=k)
         assert np.array_equal(v.double().cpu().numpy(), fix_gauge(v0, k)), k
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_ground_state_to_a_tolerance_is_the_fixed_step_run(dtype):
+    """ed_ground_state with tol > 0 (pass 1 until E0 settles, then `extra` more steps) gives the same E0, step
+    count and vector bits as the fixed-m call with m = (ed_ground_energy's stopping step) + extra."""
+    h = ham(16, torus_bonds(4, 4), 4, 4, 1.0, 3.0, dtype)
+    _, x = seeded_start(31, h.dim, dtype)
+    tol, extra = (1e-10 if dtype == "f64" else 1e-7), 12
+    announce("ground state to a tolerance 4x4 4+4 %s" % dtype)
+    r = h.ground_energy(x, 400, tol=tol, check_every=15)
+    assert r["status"] == ed.ED_OK
+    m = r["steps"] + extra
+    e_a, k_a, v_a = h.ground_state(x, m, gauge_index=0)
+    e_b, k_b, v_b = h.ground_state(x, 400, gauge_index=0, tol=tol, extra=extra)
+    assert (k_a, k_b) == (m, m)
+    assert e_a == e_b
+    assert torch.equal(v_a, v_b)
