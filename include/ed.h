@@ -395,7 +395,9 @@ int ed_ground_energy_noalloc(const ed_ham *h, ed_lanczos *st, const void *f1, do
  * |v[gauge_index]| is below 1e-3 of max |v_i| (its sign then carries no
  * information), the largest-magnitude element (the lowest index among equal
  * magnitudes) is made positive instead; -1: no gauge.  ws must hold
- * ed_workspace_size(h, m).  *e0 = lowest eigenvalue of T_m. */
+ * ed_workspace_size(h, m).  *e0 = lowest eigenvalue of T_m, *steps = the
+ * pass's step count (fewer than asked on breakdown).  m outside
+ * [1, st->max_steps] or extra < 0 -> ED_EINVAL. */
 int ed_ground_state(const ed_ham *h, ed_lanczos *st, const void *f1, int32_t m, double tol, int32_t extra,
                     int64_t gauge_index, void *v, void *ws, void *stream, double *e0, int32_t *steps);
 
