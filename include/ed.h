@@ -177,6 +177,19 @@ int ed_band_order(const int32_t *cols, const int32_t *nnz, int64_t dim, int32_t 
 int ed_row_windows(const int32_t *cols, const int32_t *nnz, int64_t dim, int32_t width, int layout,
                    int32_t block_cols, int32_t *lo_hi, int32_t *max_window);
 
+/* The down part's table of a species with neighbour windows, columns
+ * relative to their block's window: the layout of ed_pack_tables (stride =
+ * width rounded up to 8; a row-major part, here all padding and unused, then
+ * the 8-interleaved part) with 16-bit entries ((col - lo_b) << 1) |
+ * negative, b = row / block_cols, padding 0xFFFF.  Windows of up to 32,767
+ * states thus take 16-bit entries at any species size.  cols, vals, nnz,
+ * width, layout: the species' ELL table (host, values +-1); lo_hi: its
+ * ed_row_windows output for block_cols; packed: host, 2 * stride * dim
+ * entries.  A window wider than 32,767 or not holding a row or its columns
+ * -> ED_EINVAL. */
+int ed_pack_tables_windowed(const int32_t *cols, const double *vals, const int32_t *nnz, int64_t dim, int32_t width,
+                            int layout, int32_t block_cols, const int32_t *lo_hi, uint16_t *packed);
+
 /* Reorder one species' basis and its exported ELL table (Fig. 2 format, as
  * from ed_build_hopping or ed_build_hopping_complex): position q of the
  * output is state perm[q] of the input, and each row's columns are renumbered
@@ -230,7 +243,10 @@ int ed_tridiag_lowest_vector(const double *a, const double *b, int m, double *e0
  * down-part kernel that stages each block's window (real instances).  The
  * windows must hold every block's table columns (they come from this
  * species' table): a block whose pair is wider than win_max or does not
- * cover the block is gathered from global memory instead. */
+ * cover the block is gathered from global memory instead.  win_tab: NULL,
+ * or the down table in the window-relative 16-bit form of
+ * ed_pack_tables_windowed (device, with win_dn), which that kernel then
+ * reads instead of tab_dn. */
 typedef struct ed_ham {
     int64_t dim_up, dim_dn;
     int32_t w_up, w_dn;
@@ -245,6 +261,7 @@ typedef struct ed_ham {
     const double *amp_up, *amp_dn;
     const int32_t *win_dn;
     int32_t win_cols, win_max;
+    const uint16_t *win_tab;
 } ed_ham;
 
 /* Bytes of device workspace (`ws` below) the calls on this instance need

@@ -77,6 +77,19 @@ def row_windows(table, block_cols: int):
     return lo_hi, int(widest.value)
 
 
+def pack_tables_windowed(table, dim: int, block_cols: int, lo_hi) -> np.ndarray:
+    """ed_pack_tables_windowed: the down table with columns relative to their block's window (uint16 entries,
+    the layout of pack_tables)."""
+    stride = table_stride(table["width"])
+    out = np.zeros(max(2 * stride * dim, 1), dtype=np.uint16)
+    vals = np.ascontiguousarray(table["vals"], dtype=np.float64)
+    lh = np.ascontiguousarray(lo_hi, dtype=np.int32)
+    check(lib().ed_pack_tables_windowed(_ptr(table["cols"], c_int32), _ptr(vals, c_double),
+                                        _ptr(table["nnz"], c_int32), dim, int(table["width"]), int(table["layout"]),
+                                        int(block_cols), _ptr(lh, c_int32), _ptr(out, c_uint16)))
+    return out
+
+
 # Column blocks of the neighbour windows a down species carries (ed_ham.win_dn): rows longer than this
 # many states are the ones that do not fit LDS (19,456 FP64 states); a block's window holds its states and
 # their neighbours.
@@ -285,11 +298,14 @@ class SpinTables:
             self.packed = pack_tables(self.table, self.dim, self.entry_bytes)
         self.dev_states = torch.from_numpy(self.states.view(np.int64).copy()).to(self.device)
         # neighbour windows of column blocks, for rows of this species too long for LDS (real tables)
-        self.win_cols, self.win_max, self.dev_win = 0, 0, None
+        self.win_cols, self.win_max, self.dev_win, self.dev_win_tab = 0, 0, None, None
         if not self.cplx and self.width and self.dim >= WINDOW_MIN_DIM:
             lo_hi, self.win_max = row_windows(self.table, WINDOW_COLS)
             self.win_cols = WINDOW_COLS
             self.dev_win = torch.from_numpy(lo_hi).to(self.device)
+            if self.win_max <= NARROW_MAX_DIM:   # the window-relative table takes 16-bit entries
+                rel = pack_tables_windowed(self.table, self.dim, WINDOW_COLS, lo_hi)
+                self.dev_win_tab = torch.from_numpy(rel.view(np.int16).copy()).to(self.device)
         signed = np.int16 if self.entry_bytes == 2 else np.int32
         self.dev_tab = (torch.from_numpy(self.packed.view(signed).copy()).to(self.device)
                         if self.width else torch.zeros(1, dtype=torch.int32, device=self.device))
@@ -356,7 +372,8 @@ class Hamiltonian:
                      self.up.dev_amp.data_ptr() if self.up.dev_amp is not None else None,
                      self.dn.dev_amp.data_ptr() if self.dn.dev_amp is not None else None,
                      self.dn.dev_win.data_ptr() if self.dn.dev_win is not None else None,
-                     self.dn.win_cols, self.dn.win_max)
+                     self.dn.win_cols, self.dn.win_max,
+                     self.dn.dev_win_tab.data_ptr() if self.dn.dev_win_tab is not None else None)
 
     @property
     def order_bits(self) -> int:

@@ -619,8 +619,9 @@ __device__ __forceinline__ void down_gather_z(const T *__restrict__ xrow, const 
 // no up part (the up species cannot hop); io is written but not read.  ZS:
 // one row in LDS followed by a zero (down_gather_z).  WIN (with ZS, one
 // row): xrows is the window of the row from column xlo, its zero at index
-// zs_win, and [i0, iend) a block of columns inside it.
-template <typename T, int MODE, int NCH, bool MULTI, bool IO = true, bool ZS = false, typename E, bool WIN = false>
+// zs_win, and [i0, iend) a block of columns inside it; the table's columns
+// are absolute (WIN 1) or relative to xlo already (WIN 2).
+template <typename T, int MODE, int NCH, bool MULTI, bool IO = true, bool ZS = false, typename E, int WIN = 0>
 __device__ __forceinline__ void down_rows(const T *__restrict__ xrows, T *__restrict__ io, const T *__restrict__ p,
                                           const E *__restrict__ tab, const uint64_t *__restrict__ st_up_r0,
                                           const uint64_t *__restrict__ st_dn, int Ddn, int W8, int i0, int iend,
@@ -668,8 +669,10 @@ __device__ __forceinline__ void down_rows(const T *__restrict__ xrows, T *__rest
         if constexpr (MULTI) sun = st_up_r0[rrn];
         const T *xrow = xrows + (int64_t)rr * Ddn;
         T acc0, acc1;
-        if constexpr (ZS && WIN)
+        if constexpr (ZS && WIN == 1)
             down_gather_z<T, NCH, E, true>(xrow, tq, nch, zs_win, acc0, acc1, xlo);
+        else if constexpr (ZS && WIN == 2)
+            down_gather_z<T, NCH, E>(xrow, tq, nch, zs_win, acc0, acc1);
         else if constexpr (ZS)
             down_gather_z<T, NCH, E>(xrow, tq, nch, (unsigned)Ddn, acc0, acc1);
         else

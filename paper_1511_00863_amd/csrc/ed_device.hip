@@ -314,14 +314,16 @@ void k_down2(const T *__restrict__ x, T *__restrict__ io, const T *__restrict__ 
 // (lo, hi) pairs; wcols: states per block; nblk blocks per row; wmax: the
 // LDS room (elements) before the zero.  A pair that does not fit that room or
 // does not cover its block is not staged: that block gathers from global
-// memory as the kernel for long rows does (the same bits again).
-template <typename T, int MODE, int NCH, typename E>
+// memory as the kernel for long rows does (the same bits again).  REL: a
+// staged block reads rtab, the table with 16-bit window-relative columns
+// (ed_pack_tables_windowed), instead of tab.
+template <typename T, int MODE, int NCH, typename E, bool REL = false>
 __global__ __launch_bounds__(sizeof(E) == 4 ? 512 : 1024)
 void k_down_win(const T *__restrict__ x, T *__restrict__ io, const T *__restrict__ p, const E *__restrict__ tab,
                 const uint64_t *__restrict__ st_up, const uint64_t *__restrict__ st_dn, int Dup, int Ddn, int W8,
                 const int32_t *__restrict__ win, int wcols, int nblk, int wmax, T t, T U,
                 const double *__restrict__ bvec, const Hdr *__restrict__ hdr, double *__restrict__ partials,
-                int max_steps) {
+                int max_steps, const uint16_t *__restrict__ rtab) {
     extern __shared__ __align__(16) unsigned char smem[];
     T *xs = reinterpret_cast<T *>(smem);
     bool has_prev = false;
@@ -347,10 +349,14 @@ void k_down_win(const T *__restrict__ x, T *__restrict__ io, const T *__restrict
     double s[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) s[k] = 0.0;
-    if (staged)
-        down_rows<T, MODE, NCH, false, true, true, E, true>(xs, io, p, tab, st_up + r, st_dn, Ddn, W8, c0, c1, base, t,
-                                                            U, sig, cprev, MODE != 0 && has_prev, s, (unsigned)lo,
-                                                            (unsigned)(hi - lo));
+    if (REL && staged)
+        down_rows<T, MODE, NCH, false, true, true, uint16_t, 2>(xs, io, p, rtab, st_up + r, st_dn, Ddn, W8, c0, c1,
+                                                                base, t, U, sig, cprev, MODE != 0 && has_prev, s,
+                                                                (unsigned)lo, (unsigned)(hi - lo));
+    else if (staged)
+        down_rows<T, MODE, NCH, false, true, true, E, 1>(xs, io, p, tab, st_up + r, st_dn, Ddn, W8, c0, c1, base, t,
+                                                         U, sig, cprev, MODE != 0 && has_prev, s, (unsigned)lo,
+                                                         (unsigned)(hi - lo));
     else
         down_rows<T, MODE, NCH, false, true, false, E>(x + base, io, p, tab, st_up + r, st_dn, Ddn, W8, c0, c1, base, t,
                                                        U, sig, cprev, MODE != 0 && has_prev, s);
@@ -960,10 +966,12 @@ static int launch_down_e(const ed_ham *h, const Tile &tl, const T *x, T *io, con
         auto go = [&](auto kern) {
             hipLaunchKernelGGL(kern, dim3(grid), dim3(tl.dn_block), shmw, s, x, io, p, tab, h->st_up, h->st_dn,
                                (int)h->dim_up, (int)h->dim_dn, h->w_dn, h->win_dn, h->win_cols, cs, h->win_max,
-                               static_cast<T>(h->t), static_cast<T>(h->U), bvec, hdr, part, max_steps);
+                               static_cast<T>(h->t), static_cast<T>(h->U), bvec, hdr, part, max_steps, h->win_tab);
         };
-        if (nch <= 2) go(k_down_win<T, MODE, 2, E>);
-        else go(k_down_win<T, MODE, 4, E>);
+        // a 32-bit table has a 16-bit window-relative copy when the windows allow it
+        const bool rel = sizeof(E) == 4 && h->win_tab != nullptr;
+        if (nch <= 2) rel ? go(k_down_win<T, MODE, 2, E, true>) : go(k_down_win<T, MODE, 2, E>);
+        else rel ? go(k_down_win<T, MODE, 4, E, true>) : go(k_down_win<T, MODE, 4, E>);
         ED_LAUNCHED("k_down_win");
         return ED_OK;
     }
@@ -1078,6 +1086,9 @@ static hipError_t set_lds_attr() {
                                 hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget + 256);
         if (e != hipSuccess) return e;
         e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_down_win<T, MODE, NCH, uint32_t>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget + 256);
+        if (e != hipSuccess) return e;
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_down_win<T, MODE, NCH, uint32_t, true>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget + 256);
     }
     return e;

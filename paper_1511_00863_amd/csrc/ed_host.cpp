@@ -368,6 +368,41 @@ int ed_hop_order(const int32_t *nnz, int64_t dim, int64_t *perm) {
     return ED_OK;
 }
 
+int ed_pack_tables_windowed(const int32_t *cols, const double *vals, const int32_t *nnz, int64_t dim, int32_t width,
+                            int layout, int32_t block_cols, const int32_t *lo_hi, uint16_t *packed) {
+    clear_error();
+    const char *who = "ed_pack_tables_windowed";
+    if (!cols || !vals || !nnz || !lo_hi || !packed || dim < 1 || width < 0 || block_cols <= 0 || (block_cols & 63))
+        return set_error(ED_EINVAL, "%s: bad arguments", who);
+    if (layout != ED_ROW_MAJOR && layout != ED_COL_MAJOR) return set_error(ED_EINVAL, "%s: bad layout %d", who, layout);
+    const int64_t stride = (width + 7) & ~7;
+    const uint16_t pad = 0xFFFFu;
+    for (int64_t r = 0; r < dim; ++r) {
+        if (nnz[r] < 0 || nnz[r] > width)
+            return set_error(ED_EINVAL, "%s: nnz[%lld] = %d out of range", who, (long long)r, nnz[r]);
+        const int64_t b = r / block_cols;
+        const int64_t lo = lo_hi[2 * b], hi = lo_hi[2 * b + 1];
+        if (lo < 0 || lo > r || hi <= r || hi > dim || hi - lo > 32767)
+            return set_error(ED_EINVAL, "%s: window %lld [%lld, %lld) does not hold row %lld in 15 bits", who,
+                             (long long)b, (long long)lo, (long long)hi, (long long)r);
+        for (int64_t k = 0; k < stride; ++k) {
+            uint16_t e = pad;
+            if (k < nnz[r]) {
+                const int64_t at = layout == ED_ROW_MAJOR ? r * width + k : k * dim + r;
+                const int64_t c = cols[at];
+                if (c < lo || c >= hi)
+                    return set_error(ED_EINVAL, "%s: column %lld of row %lld outside its window", who, (long long)c,
+                                     (long long)r);
+                if (vals[at] != 1.0 && vals[at] != -1.0) return set_error(ED_EINVAL, "%s: value %g is not +-1", who, vals[at]);
+                e = static_cast<uint16_t>(((uint32_t)(c - lo) << 1) | (vals[at] < 0 ? 1u : 0u));
+            }
+            packed[r * stride + k] = pad;                                   // row-major part: unused
+            packed[dim * stride + ((k >> 3) * dim + r) * 8 + (k & 7)] = e;  // 8-interleaved part
+        }
+    }
+    return ED_OK;
+}
+
 int ed_row_windows(const int32_t *cols, const int32_t *nnz, int64_t dim, int32_t width, int layout,
                    int32_t block_cols, int32_t *lo_hi, int32_t *max_window) {
     clear_error();

@@ -139,6 +139,8 @@ static inline int check_ham(const ed_ham *h, const char *who) {
     if (!valid_tile_id(h->tile)) return set_error(ED_EINVAL, "%s: bad tile id %d", who, h->tile);
     if (h->win_dn && (h->win_cols <= 0 || (h->win_cols & 63) || h->win_max <= 0 || h->win_max > h->dim_dn))
         return set_error(ED_EINVAL, "%s: bad neighbour windows (win_cols %d, win_max %d)", who, h->win_cols, h->win_max);
+    if (h->win_tab && (!h->win_dn || h->win_max > 32767))
+        return set_error(ED_EINVAL, "%s: a window-relative table needs windows of at most 32767 states", who);
     if (!std::isfinite(h->t) || !std::isfinite(h->U)) return set_error(ED_EINVAL, "%s: non-finite t or U", who);
     return ED_OK;
 }

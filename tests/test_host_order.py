@@ -327,3 +327,38 @@ def test_row_windows_hold_each_block_and_its_neighbours():
                     assert widest == want_w
     with pytest.raises(Exception):
         api.row_windows(tab, 100)   # not a multiple of 64
+
+
+def test_windowed_table_holds_window_relative_columns():
+    """ed_pack_tables_windowed against a decode by hand: in the 8-interleaved part, entry k of row r is
+    ((col - lo_b) << 1) | (value < 0) with b = r // block_cols, padding 0xFFFF after the row's nonzeros; the
+    row-major part is all padding.  Band order, both layouts; a window that leaves a column out is refused."""
+    from paper_1511_00863_amd import api
+    from synth import torus_bonds
+    st = api.build_basis(16, 5)
+    for layout in (api.ED_ROW_MAJOR, api.ED_COL_MAJOR):
+        tab = api.build_hopping(16, torus_bonds(4, 4), st, layout=layout)
+        _, t = api.permute_basis(st, tab, api.band_order(tab))
+        D, W = st.size, t["width"]
+        stride = api.table_stride(W)
+        bc = 512
+        lo_hi, _ = api.row_windows(t, bc)
+        packed = api.pack_tables_windowed(t, D, bc, lo_hi)
+        assert np.all(packed[:D * stride] == 0xFFFF)
+        inter = packed[D * stride:].reshape(stride // 8, D, 8)
+        if layout == api.ED_ROW_MAJOR:
+            cols, vals = t["cols"].reshape(D, W), t["vals"].reshape(D, W)
+        else:
+            cols, vals = t["cols"].reshape(W, D).T, t["vals"].reshape(W, D).T
+        for r in range(0, D, 37):
+            lo = lo_hi[2 * (r // bc)]
+            for k in range(stride):
+                e = int(inter[k // 8, r, k % 8])
+                if k < t["nnz"][r]:
+                    assert e == ((int(cols[r, k]) - lo) << 1) | (1 if vals[r, k] < 0 else 0), (r, k)
+                else:
+                    assert e == 0xFFFF
+    bad = lo_hi.copy()
+    bad[1] = bad[0] + 8   # block 0's window no longer holds its rows
+    with pytest.raises(Exception):
+        api.pack_tables_windowed(t, D, bc, bad)
