@@ -202,7 +202,10 @@ def single_block(args):
     particles (D = 10,400,600) and a 30-site periodic lattice with 9 (D = 14,307,150).  All particles
     in the down species, so H x is the down-part kernel over one row of length D, split into column
     blocks, with no up part.  Algorithmic bytes of that kernel per launch: the start vector, f_{j-1}
-    and q once each, the 8-interleaved table (D x W8 entries) and the states."""
+    and q once each, the table's nonzeros (entries of H) and the states.  Read bytes: the same with the
+    table chunks the kernel reads in place of the nonzeros: each wavefront's own chunk count
+    (ed_wave_chunks) where the kernel takes it, else every chunk of the padded ELL rows."""
+    import numpy as np
     import torch
     import paper_1511_00863_amd as ed
     from synth import start_vector, workload
@@ -220,9 +223,19 @@ def single_block(args):
             x = start_in_order(h, x_host, dev)
             ms, per, _ = time_run(h, x, 3, args.single_steps, 3)
             es = 8 if dtype == "f64" else 4
-            dn_bytes = 3 * es * h.dim + h.dim * dn.stride * dn.entry_bytes + 8 * h.dim
+            eb = dn.entry_bytes
+            nonzeros = int(dn.table["nnz"].sum())
+            # the chunk counts apply except in FP64 on 32-bit tables of more than 4 chunks
+            wch = dn.dev_wch is not None and not (es == 8 and eb == 4 and dn.stride > 32)
+            tab_read = (int(ed.wave_chunks(dn.table["nnz"]).astype(np.int64).sum()) * 64 * 8 * eb if wch
+                        else h.dim * dn.stride * eb)
+            vec_bytes = 3 * es * h.dim + 8 * h.dim
+            t_dn = per["k_down"] * 1e-3
             rec[dtype] = {"steps_per_s": 1000.0 / ms, "ms_per_step": ms, "kernel_ms": per,
-                          "k_down_alg_GBps": dn_bytes / (per["k_down"] * 1e-3) / 1e9,
+                          "k_down_alg_GBps": (vec_bytes + nonzeros * eb) / t_dn / 1e9,
+                          "k_down_read_GBps": (vec_bytes + tab_read) / t_dn / 1e9,
+                          "table_bytes_read": tab_read, "table_nonzero_bytes": nonzeros * eb,
+                          "wave_chunk_counts": wch,
                           "tile": {"id": h.tile, "source": src, **h.tile_params()}}
             del x, h
             torch.cuda.empty_cache()

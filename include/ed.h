@@ -152,6 +152,15 @@ int ed_pack_tables_complex(const int32_t *cols, const double *vals, const int32_
  * nnz: host, dim entries (>= 0); perm: host, dim entries. */
 int ed_hop_order(const int32_t *nnz, int64_t dim, int64_t *perm);
 
+/* ed_wave_chunks: for each group of 64 consecutive rows of an ELL table
+ * (nnz from ed_build_hopping, in the basis order the device sees), the number
+ * of 8-entry table chunks its widest row needs: out[g] = max over rows r in
+ * [64g, min(64g + 64, dim)) of ceil(nnz[r] / 8).  The chunks from out[g] on
+ * are padding for every row of the group (Fig. 2's ELL rows padded to the
+ * widest).  nnz: host, dim entries (>= 0); out: host, ceil(dim / 64)
+ * entries. */
+int ed_wave_chunks(const int32_t *nnz, int64_t dim, uint32_t *out);
+
 /* ed_band_order: perm (position q holds state perm[q]) that numbers each
  * state close to its hopping neighbours: reverse Cuthill-McKee on the graph
  * whose edges are the table's nonzeros (a breadth-first sweep from a
@@ -246,7 +255,15 @@ int ed_tridiag_lowest_vector(const double *a, const double *b, int m, double *e0
  * cover the block is gathered from global memory instead.  win_tab: NULL,
  * or the down table in the window-relative 16-bit form of
  * ed_pack_tables_windowed (device, with win_dn), which that kernel then
- * reads instead of tab_dn. */
+ * reads instead of tab_dn.
+ * wch_dn: NULL, or the down table's chunk count per 64 consecutive states
+ * from ed_wave_chunks (device, ceil(dim_dn / 64) uint32).  The down-part
+ * kernel that gathers from global memory for a species alone (w_up = 0, rows
+ * too long for LDS) then reads only those chunks of each wavefront's 64
+ * columns (in FP64 on 32-bit tables of more than 4 chunks it reads every
+ * chunk, which measured faster there); counts above w_dn / 8 are taken as
+ * w_dn / 8.  The results are the same bits as without it; a count below a
+ * column's true chunk count drops that column's later hops. */
 typedef struct ed_ham {
     int64_t dim_up, dim_dn;
     int32_t w_up, w_dn;
@@ -262,6 +279,7 @@ typedef struct ed_ham {
     const int32_t *win_dn;
     int32_t win_cols, win_max;
     const uint16_t *win_tab;
+    const uint32_t *wch_dn;
 } ed_ham;
 
 /* Bytes of device workspace (`ws` below) the calls on this instance need

@@ -10,10 +10,10 @@ from ._ffi import (ED_BREAKDOWN, ED_COL_MAJOR, ED_F32, ED_F64, ED_NOT_CONVERGED,
                    lib)
 from .api import (Hamiltonian, LanczosRun, SpinTables, band_order, build_basis, build_hopping, ground_energy_batch,
                   hop_order, occupation_correlations, pack_tables, permute_basis, row_windows, spin_correlations,
-                  state_rank, tridiag_lowest, tridiag_lowest_vector)
+                  state_rank, tridiag_lowest, tridiag_lowest_vector, wave_chunks)
 
 __all__ = ["Hamiltonian", "LanczosRun", "SpinTables", "build_basis", "build_hopping", "ground_energy_batch",
-           "hop_order", "band_order", "row_windows", "pack_tables", "permute_basis", "occupation_correlations",
-           "spin_correlations",
+           "hop_order", "band_order", "row_windows", "wave_chunks", "pack_tables", "permute_basis",
+           "occupation_correlations", "spin_correlations",
            "state_rank", "tridiag_lowest", "tridiag_lowest_vector", "EdError", "lib",
            "ED_OK", "ED_BREAKDOWN", "ED_NOT_CONVERGED", "ED_F64", "ED_F32", "ED_ROW_MAJOR", "ED_COL_MAJOR"]

@@ -29,7 +29,7 @@ class EdHam(ctypes.Structure):
                 ("t", c_double), ("U", c_double), ("dtype", c_int32), ("tile", c_int32),
                 ("eb_up", c_int32), ("eb_dn", c_int32), ("cplx", c_int32), ("order", c_int32),
                 ("amp_up", c_void_p), ("amp_dn", c_void_p), ("win_dn", c_void_p), ("win_cols", c_int32),
-                ("win_max", c_int32), ("win_tab", c_void_p)]
+                ("win_max", c_int32), ("win_tab", c_void_p), ("wch_dn", c_void_p)]
 
 
 class EdBatchItem(ctypes.Structure):
@@ -63,6 +63,7 @@ _PROTOS = {
                                        c_int, POINTER(c_uint32), POINTER(c_double), POINTER(c_int32)]),
     "ed_tridiag_lowest": (c_int, [POINTER(c_double), POINTER(c_double), c_int, POINTER(c_double)]),
     "ed_hop_order": (c_int, [POINTER(c_int32), c_int64, POINTER(c_int64)]),
+    "ed_wave_chunks": (c_int, [POINTER(c_int32), c_int64, POINTER(c_uint32)]),
     "ed_band_order": (c_int, [POINTER(c_int32), POINTER(c_int32), c_int64, c_int32, c_int, POINTER(c_int64)]),
     "ed_row_windows": (c_int, [POINTER(c_int32), POINTER(c_int32), c_int64, c_int32, c_int, c_int32,
                                POINTER(c_int32), POINTER(c_int32)]),

@@ -46,6 +46,14 @@ def state_rank(n_sites: int, n_part: int, states) -> np.ndarray:
     return out
 
 
+def wave_chunks(nnz) -> np.ndarray:
+    """ed_wave_chunks: per 64 consecutive rows, the 8-entry table chunks the widest of them needs."""
+    n = np.ascontiguousarray(nnz, dtype=np.int32)
+    out = np.zeros((n.size + 63) // 64, dtype=np.uint32)
+    check(lib().ed_wave_chunks(_ptr(n, c_int32), n.size, _ptr(out, c_uint32)))
+    return out
+
+
 def hop_order(nnz) -> np.ndarray:
     """ed_hop_order: positions of a basis sorted by hop count, most first, ties in their given order."""
     n = np.ascontiguousarray(nnz, dtype=np.int32)
@@ -299,6 +307,10 @@ class SpinTables:
         self.dev_states = torch.from_numpy(self.states.view(np.int64).copy()).to(self.device)
         # neighbour windows of column blocks, for rows of this species too long for LDS (real tables)
         self.win_cols, self.win_max, self.dev_win, self.dev_win_tab = 0, 0, None, None
+        # table chunks per 64 consecutive states (real tables): the down part of a species alone reads no more
+        self.dev_wch = None
+        if not self.cplx and self.width:
+            self.dev_wch = torch.from_numpy(wave_chunks(self.table["nnz"]).view(np.int32)).to(self.device)
         if not self.cplx and self.width and self.dim >= WINDOW_MIN_DIM:
             lo_hi, self.win_max = row_windows(self.table, WINDOW_COLS)
             self.win_cols = WINDOW_COLS
@@ -373,7 +385,8 @@ class Hamiltonian:
                      self.dn.dev_amp.data_ptr() if self.dn.dev_amp is not None else None,
                      self.dn.dev_win.data_ptr() if self.dn.dev_win is not None else None,
                      self.dn.win_cols, self.dn.win_max,
-                     self.dn.dev_win_tab.data_ptr() if self.dn.dev_win_tab is not None else None)
+                     self.dn.dev_win_tab.data_ptr() if self.dn.dev_win_tab is not None else None,
+                     self.dn.dev_wch.data_ptr() if self.dn.dev_wch is not None else None)
 
     @property
     def order_bits(self) -> int:

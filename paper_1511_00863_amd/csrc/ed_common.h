@@ -457,6 +457,20 @@ __device__ __forceinline__ Chunk8<E> table_chunk(const Chunk8<E> *__restrict__ t
     }
 }
 
+// table_chunk with the chunk's element offset (k8 * Ddn) precomputed and a
+// wave-uniform choice: chunk k8 when real, else padding read from chunk 0's
+// address (the per-wavefront chunk counts of the one-species down part)
+template <typename E>
+__device__ __forceinline__ Chunk8<E> table_chunk_off(const Chunk8<E> *__restrict__ til, int64_t off, bool real,
+                                                     int c) {
+    const unsigned m = real ? 0u : ~0u;
+    Chunk8<E> v = til[(real ? off : 0) + c];
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(E) / 2); ++i)
+        v.q[i] = make_uint4(v.q[i].x | m, v.q[i].y | m, v.q[i].z | m, v.q[i].w | m);
+    return v;
+}
+
 // v if keep, else +0, without a branch (the loaded value is always consumed)
 __device__ __forceinline__ double keep_or_zero(double v, bool keep) {
     return __longlong_as_double(__double_as_longlong(v) & (keep ? ~0ll : 0ll));
@@ -620,15 +634,29 @@ __device__ __forceinline__ void down_gather_z(const T *__restrict__ xrow, const 
 // one row in LDS followed by a zero (down_gather_z).  WIN (with ZS, one
 // row): xrows is the window of the row from column xlo, its zero at index
 // zs_win, and [i0, iend) a block of columns inside it; the table's columns
-// are absolute (WIN 1) or relative to xlo already (WIN 2).
-template <typename T, int MODE, int NCH, bool MULTI, bool IO = true, bool ZS = false, typename E, int WIN = 0>
+// are absolute (WIN 1) or relative to xlo already (WIN 2).  WCH (one row,
+// not staged, i0 a multiple of 64): wch holds the table's chunk count per 64
+// columns; a wavefront reads only its own count of chunks, the rest as
+// padding from chunk 0's address (the same bits: those chunks are padding for
+// all of its columns).
+template <typename T, int MODE, int NCH, bool MULTI, bool IO = true, bool ZS = false, typename E, int WIN = 0,
+          bool WCH = false>
 __device__ __forceinline__ void down_rows(const T *__restrict__ xrows, T *__restrict__ io, const T *__restrict__ p,
                                           const E *__restrict__ tab, const uint64_t *__restrict__ st_up_r0,
                                           const uint64_t *__restrict__ st_dn, int Ddn, int W8, int i0, int iend,
                                           int64_t base, T t, T U, T sig, T cprev, bool use_p,
-                                          double (&s)[MODE == 2 ? 5 : 1], unsigned xlo = 0, unsigned zs_win = 0) {
+                                          double (&s)[MODE == 2 ? 5 : 1], unsigned xlo = 0, unsigned zs_win = 0,
+                                          const uint32_t *__restrict__ wch = nullptr) {
     const Chunk8<E> *til = reinterpret_cast<const Chunk8<E> *>(tab + (int64_t)Ddn * W8);   // 8-interleaved part
     const int nch = W8 >> 3;
+    // the chunk count of column col's wavefront: one scalar load per wavefront
+    // (its 64 columns share col / 64, so the first lane's index is every lane's),
+    // issued a column ahead of its use: scalar loads complete on their own
+    // counter, so waiting for it never waits for the vector loads
+    auto chunks_of = [&](int col) -> int {
+        if constexpr (WCH) return min((int)wch[__builtin_amdgcn_readfirstlane(col >> 6)], nch);
+        else return nch;
+    };
     const int n = iend;
     // Every global operand of a column (table chunks, up part, f_{j-1}, the
     // down state) is fetched one column ahead, so that the wait for the
@@ -647,8 +675,18 @@ __device__ __forceinline__ void down_rows(const T *__restrict__ xrows, T *__rest
     uint64_t sdv, suv = su0;
     int c, rr;
     if constexpr (MULTI) { rr = i / Ddn; c = i - rr * Ddn; } else { rr = 0; c = i; }
+    int ncw = chunks_of(c), ncwn = nch;
+    int64_t koff[NCH > 0 ? NCH : 1];
+    if constexpr (WCH) {
+        ncwn = chunks_of(min(i + (int)blockDim.x, n - 1));
 #pragma unroll
-    for (int k8 = 0; k8 < NCH; ++k8) tq[k8] = table_chunk<NCH, E>(til, k8, nch, Ddn, c);
+        for (int k8 = 0; k8 < NCH; ++k8) koff[k8] = (int64_t)k8 * Ddn;
+#pragma unroll
+        for (int k8 = 0; k8 < NCH; ++k8) tq[k8] = table_chunk_off<E>(til, koff[k8], k8 < ncw, c);
+    } else {
+#pragma unroll
+        for (int k8 = 0; k8 < NCH; ++k8) tq[k8] = table_chunk<NCH, E>(til, k8, ncw, Ddn, c);
+    }
     if constexpr (IO) iov = io[base + i]; else iov = T(0);
     if constexpr (MODE != 0) pv = keep_or_zero(p[base + i], use_p); else pv = T(0);
     sdv = st_dn[c];
@@ -658,8 +696,15 @@ __device__ __forceinline__ void down_rows(const T *__restrict__ xrows, T *__rest
         int cn, rrn;
         if constexpr (MULTI) { rrn = in / Ddn; cn = in - rrn * Ddn; } else { rrn = 0; cn = in; }
         Chunk8<E> tqn[NCH > 0 ? NCH : 1];
+        int ncwn2 = nch;
+        if constexpr (WCH) {
+            ncwn2 = chunks_of(min(i + 2 * (int)blockDim.x, n - 1));
 #pragma unroll
-        for (int k8 = 0; k8 < NCH; ++k8) tqn[k8] = table_chunk<NCH, E>(til, k8, nch, Ddn, cn);
+            for (int k8 = 0; k8 < NCH; ++k8) tqn[k8] = table_chunk_off<E>(til, koff[k8], k8 < ncwn, cn);
+        } else {
+#pragma unroll
+            for (int k8 = 0; k8 < NCH; ++k8) tqn[k8] = table_chunk<NCH, E>(til, k8, ncwn, Ddn, cn);
+        }
         T iovn;
         if constexpr (IO) iovn = io[base + in]; else iovn = T(0);
         T pvn;
@@ -676,7 +721,7 @@ __device__ __forceinline__ void down_rows(const T *__restrict__ xrows, T *__rest
         else if constexpr (ZS)
             down_gather_z<T, NCH, E>(xrow, tq, nch, (unsigned)Ddn, acc0, acc1);
         else
-            down_gather<T, NCH, E>(xrow, tq, nch, acc0, acc1);
+            down_gather<T, NCH, E>(xrow, tq, ncw, acc0, acc1);
         T xv;
         if constexpr (WIN) xv = xrow[c - (int)xlo]; else xv = xrow[c];
         const T nd = static_cast<T>(__popcll(suv & sdv));
@@ -703,6 +748,8 @@ __device__ __forceinline__ void down_rows(const T *__restrict__ xrows, T *__rest
         pv = pvn;
         sdv = sdn;
         suv = sun;
+        ncw = ncwn;
+        ncwn = ncwn2;
 #pragma unroll
         for (int k8 = 0; k8 < NCH; ++k8) tq[k8] = tqn[k8];
     }

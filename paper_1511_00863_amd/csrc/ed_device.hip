@@ -24,6 +24,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <type_traits>
 #include <cmath>
 #include <cstdint>
 #include <vector>
@@ -204,7 +205,7 @@ __global__ void k_ctr_reset(int *ctr, const Hdr *hdr, int gate, int max_steps) {
 // which needs at most 80 VGPRs (6 waves per SIMD).  32-bit tables double the
 // registers of the prefetched table chunks: workgroups of at most 512 threads
 // (256 VGPRs) and no occupancy target.
-template <typename T, int MODE, bool LDS, int NCH, bool MULTI, typename E, bool IO = true>
+template <typename T, int MODE, bool LDS, int NCH, bool MULTI, typename E, bool IO = true, bool WCH = false>
 __global__ __launch_bounds__(sizeof(E) == 4 ? 512 : 1024)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NCH <= 4 && sizeof(E) == 2 ? 6 : 1)))
 void k_down(const T *__restrict__ x, T *__restrict__ io, const T *__restrict__ p,
@@ -213,7 +214,8 @@ void k_down(const T *__restrict__ x, T *__restrict__ io, const T *__restrict__ p
                                                const uint64_t *__restrict__ st_dn, int Dup, int Ddn, int W8,
                                                int rpb, int csplit, T t, T U, const double *__restrict__ bvec,
                                                const Hdr *__restrict__ hdr, double *__restrict__ partials,
-                                               int max_steps) {
+                                               int max_steps, const uint32_t *__restrict__ wch) {
+    static_assert(!WCH || (!LDS && !MULTI), "per-wavefront chunk counts: one unstaged row per workgroup");
     extern __shared__ __align__(16) unsigned char smem[];
     T *xs = reinterpret_cast<T *>(smem);
     bool has_prev = false;
@@ -250,8 +252,9 @@ void k_down(const T *__restrict__ x, T *__restrict__ io, const T *__restrict__ p
     double s[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) s[k] = 0.0;
-    down_rows<T, MODE, NCH, MULTI, IO, ZS>(LDS ? xs : x + base, io, p, tab, st_up + r0, st_dn, Ddn, W8, i0, iend,
-                                           base, t, U, sig, cprev, MODE != 0 && has_prev, s);
+    down_rows<T, MODE, NCH, MULTI, IO, ZS, E, 0, WCH>(LDS ? xs : x + base, io, p, tab, st_up + r0, st_dn, Ddn, W8,
+                                                      i0, iend, base, t, U, sig, cprev, MODE != 0 && has_prev, s,
+                                                      0u, 0u, wch);
     if (MODE != 0) {
         double tot[NV];
         block_sum<NV>(s, tot);
@@ -936,19 +939,23 @@ static int launch_up(const ed_ham *h, const Tile &tl, const T *x, T *out, int *c
     return launch_up_e<T, uint16_t>(h, tl, x, out, ctr, hdr, gate, max_steps, s);
 }
 
-template <typename T, int MODE, bool LDS, int NCH, typename E, bool IO = true>
+template <typename T, int MODE, bool LDS, int NCH, typename E, bool IO = true, bool WCH = false>
 static void launch_down_k(const ed_ham *h, const Tile &tl, int grid, int rpb, int csplit, size_t shm, const T *x,
                           T *io, const T *p, const double *bvec, const Hdr *hdr, double *part, int max_steps,
                           hipStream_t s) {
     const E *tab = static_cast<const E *>(h->tab_dn);
-    if (rpb > 1)
+    if constexpr (WCH)
+        hipLaunchKernelGGL((k_down<T, MODE, false, NCH, false, E, IO, true>), dim3(grid), dim3(tl.dn_block), shm, s,
+                           x, io, p, tab, h->st_up, h->st_dn, (int)h->dim_up, (int)h->dim_dn, h->w_dn, rpb, csplit,
+                           static_cast<T>(h->t), static_cast<T>(h->U), bvec, hdr, part, max_steps, h->wch_dn);
+    else if (rpb > 1)
         hipLaunchKernelGGL((k_down<T, MODE, LDS, NCH, true, E, IO>), dim3(grid), dim3(tl.dn_block), shm, s, x, io, p,
                            tab, h->st_up, h->st_dn, (int)h->dim_up, (int)h->dim_dn, h->w_dn, rpb, csplit,
-                           static_cast<T>(h->t), static_cast<T>(h->U), bvec, hdr, part, max_steps);
+                           static_cast<T>(h->t), static_cast<T>(h->U), bvec, hdr, part, max_steps, nullptr);
     else
         hipLaunchKernelGGL((k_down<T, MODE, LDS, NCH, false, E, IO>), dim3(grid), dim3(tl.dn_block), shm, s, x, io, p,
                            tab, h->st_up, h->st_dn, (int)h->dim_up, (int)h->dim_dn, h->w_dn, rpb, csplit,
-                           static_cast<T>(h->t), static_cast<T>(h->U), bvec, hdr, part, max_steps);
+                           static_cast<T>(h->t), static_cast<T>(h->U), bvec, hdr, part, max_steps, nullptr);
 }
 
 template <typename T, int MODE, typename E>
@@ -991,15 +998,25 @@ static int launch_down_e(const ed_ham *h, const Tile &tl, const T *x, T *io, con
         return ED_OK;
     }
     if (!lds && h->w_up == 0) {   // one species: no up part to add (launch_up wrote nothing)
+        // with per-wavefront chunk counts, each wavefront reads only the table chunks its columns need;
+        // not for FP64 on 32-bit tables of more than 4 chunks, where that variant (two waves per SIMD) ran
+        // slower although it read fewer bytes
+        auto one = [&](auto nc, auto wc) {
+            launch_down_k<T, MODE, false, decltype(nc)::value, E, false, decltype(wc)::value>(
+                h, tl, grid, 1, cs, 0, x, io, p, bvec, hdr, part, max_steps, s);
+        };
+        using W0 = std::false_type;
+        using W1 = std::true_type;
+        const bool wc = h->wch_dn != nullptr && !(sizeof(T) == 8 && sizeof(E) == 4 && nch > 4);
         if (nch == 0) {
-            launch_down_k<T, MODE, false, 0, E, false>(h, tl, grid, 1, cs, 0, x, io, p, bvec, hdr, part, max_steps, s);
+            one(std::integral_constant<int, 0>(), W0());
         } else {
             if constexpr (sizeof(E) == 4) {
-                if (nch <= 2) launch_down_k<T, MODE, false, 2, E, false>(h, tl, grid, 1, cs, 0, x, io, p, bvec, hdr, part, max_steps, s);
-                else if (nch <= 4) launch_down_k<T, MODE, false, 4, E, false>(h, tl, grid, 1, cs, 0, x, io, p, bvec, hdr, part, max_steps, s);
-                else launch_down_k<T, MODE, false, 8, E, false>(h, tl, grid, 1, cs, 0, x, io, p, bvec, hdr, part, max_steps, s);
+                if (nch <= 2) wc ? one(std::integral_constant<int, 2>(), W1()) : one(std::integral_constant<int, 2>(), W0());
+                else if (nch <= 4) wc ? one(std::integral_constant<int, 4>(), W1()) : one(std::integral_constant<int, 4>(), W0());
+                else wc ? one(std::integral_constant<int, 8>(), W1()) : one(std::integral_constant<int, 8>(), W0());
             } else {
-                launch_down_k<T, MODE, false, 8, E, false>(h, tl, grid, 1, cs, 0, x, io, p, bvec, hdr, part, max_steps, s);
+                wc ? one(std::integral_constant<int, 8>(), W1()) : one(std::integral_constant<int, 8>(), W0());
             }
         }
         ED_LAUNCHED("k_down");

@@ -368,6 +368,20 @@ int ed_hop_order(const int32_t *nnz, int64_t dim, int64_t *perm) {
     return ED_OK;
 }
 
+int ed_wave_chunks(const int32_t *nnz, int64_t dim, uint32_t *out) {
+    clear_error();
+    if (!nnz || !out || dim < 1) return set_error(ED_EINVAL, "ed_wave_chunks: bad arguments");
+    for (int64_t g = 0; g * 64 < dim; ++g) {
+        uint32_t most = 0;
+        for (int64_t r = g * 64; r < std::min(dim, g * 64 + 64); ++r) {
+            if (nnz[r] < 0) return set_error(ED_EINVAL, "ed_wave_chunks: nnz[%lld] = %d", (long long)r, nnz[r]);
+            most = std::max(most, (uint32_t)(nnz[r] + 7) / 8);
+        }
+        out[g] = most;
+    }
+    return ED_OK;
+}
+
 int ed_pack_tables_windowed(const int32_t *cols, const double *vals, const int32_t *nnz, int64_t dim, int32_t width,
                             int layout, int32_t block_cols, const int32_t *lo_hi, uint16_t *packed) {
     clear_error();

@@ -59,6 +59,32 @@ def test_long_rows_match_oracle_on_every_tile(case, dtype):
         assert torch.equal(h.hv(x), ref), (di, h.tile_params())
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_wavefront_chunk_counts_give_the_same_bits(dtype):
+    """With ed_ham.wch_dn the down part of a species alone reads only the table chunks of each wavefront's
+    widest column; H x and 30 Lanczos steps are the same bits as reading every chunk (16- and 32-bit
+    tables, every launch tile)."""
+    for name, ns, bonds, n in (("ring19_0x6", 19, ring_bonds(19), 6), ("ring20_0x7", 20, ring_bonds(20), 7),
+                               ("t45_0x6", 20, torus_bonds(4, 5), 6)):
+        h = ham(ns, bonds, 0, n, 1.0, 2.0, dtype)
+        assert h.dn.dev_wch is not None
+        _, x = seeded_start(85, h.dim, dtype)
+        announce("wavefront chunk counts %s %s dim=%d" % (name, dtype, h.dim))
+        wch = h.dn.dev_wch
+        _, n_dn = _tile_count()
+        for di in range(n_dn):
+            h.tile = di << 8
+            h.dn.dev_wch = wch
+            y1 = h.hv(x).clone()
+            r1 = h.ground_energy(x, 30, tol=0.0)
+            h.dn.dev_wch = None
+            y0 = h.hv(x).clone()
+            r0 = h.ground_energy(x, 30, tol=0.0)
+            assert torch.equal(y0, y1), (name, di)
+            assert np.array_equal(r0["a"], r1["a"]) and np.array_equal(r0["b"], r1["b"]), (name, di)
+        h.dn.dev_wch = wch
+
+
 def test_single_species_lanczos_matches_oracle():
     """Alg. 1 coefficients of a one-species float64 run against the oracle's Lanczos on the same start."""
     from oracle.lanczos import lanczos

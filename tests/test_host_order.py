@@ -362,3 +362,27 @@ def test_windowed_table_holds_window_relative_columns():
     bad[1] = bad[0] + 8   # block 0's window no longer holds its rows
     with pytest.raises(Exception):
         api.pack_tables_windowed(t, D, bc, bad)
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_wave_chunks_are_the_widest_row_of_each_64(case):
+    """ed_wave_chunks: per 64 consecutive rows (the last group ragged), the 8-entry chunks of the row with the
+    most hops, the hop counts taken from the oracle's matrix; ascending and hop-count order."""
+    _, ns, bonds, n = case
+    st = basis_states(ns, n)
+    hops = _oracle_hops(hopping_matrix(ns, bonds, st))
+    tab = ed.build_hopping(ns, bonds, st)
+    for order in ("ascending", "hops"):
+        perm = np.arange(st.size) if order == "ascending" else ed.hop_order(tab["nnz"])
+        t = tab if order == "ascending" else ed.permute_basis(st, tab, perm)[1]
+        got = ed.wave_chunks(t["nnz"])
+        h = hops[perm]
+        want = [max((int(v) + 7) // 8 for v in h[g:g + 64]) for g in range(0, st.size, 64)]
+        assert got.tolist() == want, (order,)
+
+
+def test_wave_chunks_errors():
+    with pytest.raises(ed.EdError):
+        ed.wave_chunks(np.array([3, -1, 2], dtype=np.int32))
+    with pytest.raises(ed.EdError):
+        ed.wave_chunks(np.zeros(0, dtype=np.int32))
