@@ -635,10 +635,10 @@ __device__ __forceinline__ void down_gather_z(const T *__restrict__ xrow, const 
 // row): xrows is the window of the row from column xlo, its zero at index
 // zs_win, and [i0, iend) a block of columns inside it; the table's columns
 // are absolute (WIN 1) or relative to xlo already (WIN 2).  WCH (one row,
-// not staged, i0 a multiple of 64): wch holds the table's chunk count per 64
-// columns; a wavefront reads only its own count of chunks, the rest as
-// padding from chunk 0's address (the same bits: those chunks are padding for
-// all of its columns).
+// i0 a multiple of 64): wch holds the table's chunk count per 64 columns; a
+// wavefront reads only its own count of chunks, the rest as padding from
+// chunk 0's address (the same bits: those chunks are padding for all of its
+// columns).
 template <typename T, int MODE, int NCH, bool MULTI, bool IO = true, bool ZS = false, typename E, int WIN = 0,
           bool WCH = false>
 __device__ __forceinline__ void down_rows(const T *__restrict__ xrows, T *__restrict__ io, const T *__restrict__ p,

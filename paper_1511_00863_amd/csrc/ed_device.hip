@@ -319,14 +319,16 @@ void k_down2(const T *__restrict__ x, T *__restrict__ io, const T *__restrict__ 
 // does not cover its block is not staged: that block gathers from global
 // memory as the kernel for long rows does (the same bits again).  REL: a
 // staged block reads rtab, the table with 16-bit window-relative columns
-// (ed_pack_tables_windowed), instead of tab.
-template <typename T, int MODE, int NCH, typename E, bool REL = false>
+// (ed_pack_tables_windowed), instead of tab; with WCH each of its wavefronts
+// reads only its own count of table chunks (wch, per 64 columns).
+template <typename T, int MODE, int NCH, typename E, bool REL = false, bool WCH = false>
 __global__ __launch_bounds__(sizeof(E) == 4 ? 512 : 1024)
 void k_down_win(const T *__restrict__ x, T *__restrict__ io, const T *__restrict__ p, const E *__restrict__ tab,
                 const uint64_t *__restrict__ st_up, const uint64_t *__restrict__ st_dn, int Dup, int Ddn, int W8,
                 const int32_t *__restrict__ win, int wcols, int nblk, int wmax, T t, T U,
                 const double *__restrict__ bvec, const Hdr *__restrict__ hdr, double *__restrict__ partials,
-                int max_steps, const uint16_t *__restrict__ rtab) {
+                int max_steps, const uint16_t *__restrict__ rtab, const uint32_t *__restrict__ wch) {
+    static_assert(!WCH || REL, "per-wavefront chunk counts: the window-relative table only");
     extern __shared__ __align__(16) unsigned char smem[];
     T *xs = reinterpret_cast<T *>(smem);
     bool has_prev = false;
@@ -353,9 +355,10 @@ void k_down_win(const T *__restrict__ x, T *__restrict__ io, const T *__restrict
 #pragma unroll
     for (int k = 0; k < NV; ++k) s[k] = 0.0;
     if (REL && staged)
-        down_rows<T, MODE, NCH, false, true, true, uint16_t, 2>(xs, io, p, rtab, st_up + r, st_dn, Ddn, W8, c0, c1,
-                                                                base, t, U, sig, cprev, MODE != 0 && has_prev, s,
-                                                                (unsigned)lo, (unsigned)(hi - lo));
+        down_rows<T, MODE, NCH, false, true, true, uint16_t, 2, WCH>(xs, io, p, rtab, st_up + r, st_dn, Ddn, W8, c0,
+                                                                     c1, base, t, U, sig, cprev,
+                                                                     MODE != 0 && has_prev, s, (unsigned)lo,
+                                                                     (unsigned)(hi - lo), wch);
     else if (staged)
         down_rows<T, MODE, NCH, false, true, true, E, 1>(xs, io, p, tab, st_up + r, st_dn, Ddn, W8, c0, c1, base, t,
                                                          U, sig, cprev, MODE != 0 && has_prev, s, (unsigned)lo,
@@ -973,12 +976,19 @@ static int launch_down_e(const ed_ham *h, const Tile &tl, const T *x, T *io, con
         auto go = [&](auto kern) {
             hipLaunchKernelGGL(kern, dim3(grid), dim3(tl.dn_block), shmw, s, x, io, p, tab, h->st_up, h->st_dn,
                                (int)h->dim_up, (int)h->dim_dn, h->w_dn, h->win_dn, h->win_cols, cs, h->win_max,
-                               static_cast<T>(h->t), static_cast<T>(h->U), bvec, hdr, part, max_steps, h->win_tab);
+                               static_cast<T>(h->t), static_cast<T>(h->U), bvec, hdr, part, max_steps, h->win_tab,
+                               h->wch_dn);
         };
-        // a 32-bit table has a 16-bit window-relative copy when the windows allow it
+        // a 32-bit table has a 16-bit window-relative copy when the windows allow it; on it a wavefront
+        // reads only its own count of table chunks when the species carries them
         const bool rel = sizeof(E) == 4 && h->win_tab != nullptr;
-        if (nch <= 2) rel ? go(k_down_win<T, MODE, 2, E, true>) : go(k_down_win<T, MODE, 2, E>);
-        else rel ? go(k_down_win<T, MODE, 4, E, true>) : go(k_down_win<T, MODE, 4, E>);
+        const bool wc = rel && h->wch_dn != nullptr;
+        if (nch <= 2)
+            wc ? go(k_down_win<T, MODE, 2, E, true, true>)
+               : (rel ? go(k_down_win<T, MODE, 2, E, true>) : go(k_down_win<T, MODE, 2, E>));
+        else
+            wc ? go(k_down_win<T, MODE, 4, E, true, true>)
+               : (rel ? go(k_down_win<T, MODE, 4, E, true>) : go(k_down_win<T, MODE, 4, E>));
         ED_LAUNCHED("k_down_win");
         return ED_OK;
     }
@@ -1106,6 +1116,9 @@ static hipError_t set_lds_attr() {
                                 hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget + 256);
         if (e != hipSuccess) return e;
         e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_down_win<T, MODE, NCH, uint32_t, true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget + 256);
+        if (e != hipSuccess) return e;
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_down_win<T, MODE, NCH, uint32_t, true, true>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget + 256);
     }
     return e;
