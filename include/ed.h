@@ -257,12 +257,13 @@ int ed_tridiag_lowest_vector(const double *a, const double *b, int m, double *e0
  * ed_pack_tables_windowed (device, with win_dn), which that kernel then
  * reads instead of tab_dn.
  * wch_dn: NULL, or the down table's chunk count per 64 consecutive states
- * from ed_wave_chunks (device, ceil(dim_dn / 64) uint32).  Two down-part
- * kernels then read only those chunks of each wavefront's 64 columns: the one
- * that gathers from global memory for a species alone (w_up = 0, rows too
- * long for LDS; in FP64 on 32-bit tables of more than 4 chunks it reads every
- * chunk, which measured faster there) and the windowed one on win_tab.
- * Counts above w_dn / 8 are taken as w_dn / 8.  The results are the same bits as without it; a count below a
+ * from ed_wave_chunks (device, ceil(dim_dn / 64) uint32).  These down-part
+ * kernels then read only those chunks of each wavefront's 64 columns: the
+ * one- and two-row kernels that stage rows in LDS (tables of 3 or 4 chunks),
+ * the windowed one on win_tab, and the one that gathers from global memory
+ * for a species alone (w_up = 0, rows too long for LDS; in FP64 on 32-bit
+ * tables of more than 4 chunks it reads every chunk, which measured faster
+ * there).  Counts above w_dn / 8 are taken as w_dn / 8.  The results are the same bits as without it; a count below a
  * column's true chunk count drops that column's later hops. */
 typedef struct ed_ham {
     int64_t dim_up, dim_dn;

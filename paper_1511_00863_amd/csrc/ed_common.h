@@ -801,21 +801,38 @@ __device__ __forceinline__ void down_gather_z2(const T *__restrict__ x0, const T
 // table chunk is loaded once for the two.  Per row the arithmetic is
 // down_rows' (the same q bits); the partial sums take row 0's terms, then row
 // 1's, column by column.  two = false: only row 0 exists (x1 = x0, nothing of
-// row 1 is stored or summed).
-template <typename T, int MODE, int NCH, typename E>
+// row 1 is stored or summed).  WCH: per-wavefront chunk counts, as in
+// down_rows.
+template <typename T, int MODE, int NCH, typename E, bool WCH = false>
 __device__ __forceinline__ void down_rows2(const T *__restrict__ x0, const T *__restrict__ x1, T *__restrict__ io,
                                            const T *__restrict__ p, const E *__restrict__ tab, uint64_t su0,
                                            uint64_t su1, bool two, const uint64_t *__restrict__ st_dn, int Ddn,
                                            int W8, int64_t base, T t, T U, T sig, T cprev, bool use_p,
-                                           double (&s)[MODE == 2 ? 5 : 1]) {
+                                           double (&s)[MODE == 2 ? 5 : 1],
+                                           const uint32_t *__restrict__ wch = nullptr) {
     const Chunk8<E> *til = reinterpret_cast<const Chunk8<E> *>(tab + (int64_t)Ddn * W8);
     const int nch = W8 >> 3;
     const int64_t base1 = base + (two ? Ddn : 0);
     int c = threadIdx.x;
     if (c >= Ddn) return;
+    auto chunks_of = [&](int col) -> int {
+        if constexpr (WCH) return min((int)wch[__builtin_amdgcn_readfirstlane(col >> 6)], nch);
+        else return nch;
+    };
     Chunk8<E> tq[NCH > 0 ? NCH : 1];
+    int ncwn = nch;
+    int64_t koff[NCH > 0 ? NCH : 1];
+    if constexpr (WCH) {
+        const int ncw = chunks_of(c);
+        ncwn = chunks_of(min(c + (int)blockDim.x, Ddn - 1));
 #pragma unroll
-    for (int k8 = 0; k8 < NCH; ++k8) tq[k8] = table_chunk<NCH, E>(til, k8, nch, Ddn, c);
+        for (int k8 = 0; k8 < NCH; ++k8) koff[k8] = (int64_t)k8 * Ddn;
+#pragma unroll
+        for (int k8 = 0; k8 < NCH; ++k8) tq[k8] = table_chunk_off<E>(til, koff[k8], k8 < ncw, c);
+    } else {
+#pragma unroll
+        for (int k8 = 0; k8 < NCH; ++k8) tq[k8] = table_chunk<NCH, E>(til, k8, nch, Ddn, c);
+    }
     T io0 = io[base + c], io1 = io[base1 + c];
     T p0 = T(0), p1 = T(0);
     if constexpr (MODE != 0) {
@@ -826,8 +843,15 @@ __device__ __forceinline__ void down_rows2(const T *__restrict__ x0, const T *__
     for (; c < Ddn; c += blockDim.x) {
         const int cn = min(c + (int)blockDim.x, Ddn - 1);
         Chunk8<E> tqn[NCH > 0 ? NCH : 1];
+        int ncwn2 = nch;
+        if constexpr (WCH) {
+            ncwn2 = chunks_of(min(c + 2 * (int)blockDim.x, Ddn - 1));
 #pragma unroll
-        for (int k8 = 0; k8 < NCH; ++k8) tqn[k8] = table_chunk<NCH, E>(til, k8, nch, Ddn, cn);
+            for (int k8 = 0; k8 < NCH; ++k8) tqn[k8] = table_chunk_off<E>(til, koff[k8], k8 < ncwn, cn);
+        } else {
+#pragma unroll
+            for (int k8 = 0; k8 < NCH; ++k8) tqn[k8] = table_chunk<NCH, E>(til, k8, nch, Ddn, cn);
+        }
         const T io0n = io[base + cn], io1n = io[base1 + cn];
         T p0n = T(0), p1n = T(0);
         if constexpr (MODE != 0) {
@@ -884,6 +908,7 @@ __device__ __forceinline__ void down_rows2(const T *__restrict__ x0, const T *__
         p0 = p0n;
         p1 = p1n;
         sdv = sdn;
+        ncwn = ncwn2;
 #pragma unroll
         for (int k8 = 0; k8 < NCH; ++k8) tq[k8] = tqn[k8];
     }

@@ -215,7 +215,7 @@ void k_down(const T *__restrict__ x, T *__restrict__ io, const T *__restrict__ p
                                                int rpb, int csplit, T t, T U, const double *__restrict__ bvec,
                                                const Hdr *__restrict__ hdr, double *__restrict__ partials,
                                                int max_steps, const uint32_t *__restrict__ wch) {
-    static_assert(!WCH || (!LDS && !MULTI), "per-wavefront chunk counts: one unstaged row per workgroup");
+    static_assert(!WCH || !MULTI, "per-wavefront chunk counts: one row per workgroup");
     extern __shared__ __align__(16) unsigned char smem[];
     T *xs = reinterpret_cast<T *>(smem);
     bool has_prev = false;
@@ -267,12 +267,13 @@ void k_down(const T *__restrict__ x, T *__restrict__ io, const T *__restrict__ p
 // k_down with two rows per workgroup (down_rows2): rows 2b and 2b + 1 staged
 // in LDS at 0 and S (S = the row length plus one, rounded up to 4 elements),
 // each followed by a zero.  One table chunk load per column serves both rows.
-template <typename T, int MODE, int NCH, typename E>
+// WCH: each wavefront reads only its own count of table chunks (wch).
+template <typename T, int MODE, int NCH, typename E, bool WCH = false>
 __global__ __launch_bounds__(sizeof(E) == 4 ? 512 : 1024)
 void k_down2(const T *__restrict__ x, T *__restrict__ io, const T *__restrict__ p, const E *__restrict__ tab,
              const uint64_t *__restrict__ st_up, const uint64_t *__restrict__ st_dn, int Dup, int Ddn, int W8, int S,
              T t, T U, const double *__restrict__ bvec, const Hdr *__restrict__ hdr, double *__restrict__ partials,
-             int max_steps) {
+             int max_steps, const uint32_t *__restrict__ wch) {
     extern __shared__ __align__(16) unsigned char smem[];
     T *x0 = reinterpret_cast<T *>(smem);
     T *x1 = x0 + S;
@@ -299,8 +300,8 @@ void k_down2(const T *__restrict__ x, T *__restrict__ io, const T *__restrict__ 
     double s[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) s[k] = 0.0;
-    down_rows2<T, MODE, NCH, E>(x0, two ? x1 : x0, io, p, tab, st_up[r0], two ? st_up[r0 + 1] : 0ull, two, st_dn, Ddn,
-                                W8, base, t, U, sig, cprev, MODE != 0 && has_prev, s);
+    down_rows2<T, MODE, NCH, E, WCH>(x0, two ? x1 : x0, io, p, tab, st_up[r0], two ? st_up[r0 + 1] : 0ull, two, st_dn,
+                                     Ddn, W8, base, t, U, sig, cprev, MODE != 0 && has_prev, s, wch);
     if (MODE != 0) {
         double tot[NV];
         block_sum<NV>(s, tot);
@@ -948,7 +949,7 @@ static void launch_down_k(const ed_ham *h, const Tile &tl, int grid, int rpb, in
                           hipStream_t s) {
     const E *tab = static_cast<const E *>(h->tab_dn);
     if constexpr (WCH)
-        hipLaunchKernelGGL((k_down<T, MODE, false, NCH, false, E, IO, true>), dim3(grid), dim3(tl.dn_block), shm, s,
+        hipLaunchKernelGGL((k_down<T, MODE, LDS, NCH, false, E, IO, true>), dim3(grid), dim3(tl.dn_block), shm, s,
                            x, io, p, tab, h->st_up, h->st_dn, (int)h->dim_up, (int)h->dim_dn, h->w_dn, rpb, csplit,
                            static_cast<T>(h->t), static_cast<T>(h->U), bvec, hdr, part, max_steps, h->wch_dn);
     else if (rpb > 1)
@@ -999,10 +1000,10 @@ static int launch_down_e(const ed_ham *h, const Tile &tl, const T *x, T *io, con
         auto go = [&](auto kern) {
             hipLaunchKernelGGL(kern, dim3(grid), dim3(tl.dn_block), shm2, s, x, io, p, tab, h->st_up, h->st_dn,
                                (int)h->dim_up, (int)h->dim_dn, h->w_dn, S, static_cast<T>(h->t),
-                               static_cast<T>(h->U), bvec, hdr, part, max_steps);
+                               static_cast<T>(h->U), bvec, hdr, part, max_steps, h->wch_dn);
         };
         if (nch <= 2) go(k_down2<T, MODE, 2, E>);
-        else if (nch <= 4) go(k_down2<T, MODE, 4, E>);
+        else if (nch <= 4) h->wch_dn && nch > 2 ? go(k_down2<T, MODE, 4, E, true>) : go(k_down2<T, MODE, 4, E>);
         else go(k_down2<T, MODE, 8, E>);
         ED_LAUNCHED("k_down2");
         return ED_OK;
@@ -1042,7 +1043,9 @@ static int launch_down_e(const ed_ham *h, const Tile &tl, const T *x, T *io, con
         else if (nch <= 4) launch_down_k<T, MODE, true, 4, E>(h, tl, grid, rpb, 1, shm, x, io, p, bvec, hdr, part, max_steps, s);
         else launch_down_k<T, MODE, true, 8, E>(h, tl, grid, rpb, 1, shm, x, io, p, bvec, hdr, part, max_steps, s);
     } else {
-        if (!lds && nch == 0) launch_down_k<T, MODE, false, 0, E>(h, tl, grid, 1, cs, 0, x, io, p, bvec, hdr, part, max_steps, s);
+        if (lds && rpb == 1 && nch > 2 && nch <= 4 && h->wch_dn != nullptr)
+            launch_down_k<T, MODE, true, 4, E, true, true>(h, tl, grid, 1, 1, shm, x, io, p, bvec, hdr, part, max_steps, s);
+        else if (!lds && nch == 0) launch_down_k<T, MODE, false, 0, E>(h, tl, grid, 1, cs, 0, x, io, p, bvec, hdr, part, max_steps, s);
         else if (!lds) launch_down_k<T, MODE, false, 8, E>(h, tl, grid, 1, cs, 0, x, io, p, bvec, hdr, part, max_steps, s);
         else if (nch == 0) launch_down_k<T, MODE, true, 0, E>(h, tl, grid, rpb, 1, shm, x, io, p, bvec, hdr, part, max_steps, s);
         else if (nch <= 2) launch_down_k<T, MODE, true, 2, E>(h, tl, grid, rpb, 1, shm, x, io, p, bvec, hdr, part, max_steps, s);
@@ -1092,6 +1095,12 @@ static hipError_t set_lds_attr_e() {
     const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_down<T, MODE, true, NCH, false, E>),
                                              hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget + 256);
     if (e != hipSuccess) return e;
+    if constexpr (NCH == 4 && sizeof(E) == 2) {
+        const hipError_t e2 =
+            hipFuncSetAttribute(reinterpret_cast<const void *>(k_down<T, MODE, true, NCH, false, E, true, true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget + 256);
+        if (e2 != hipSuccess) return e2;
+    }
     return hipFuncSetAttribute(reinterpret_cast<const void *>(k_down<T, MODE, true, NCH, true, E>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget + 256);
 }
@@ -1107,6 +1116,14 @@ static hipError_t set_lds_attr() {
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_down2<T, MODE, NCH == 0 ? 2 : NCH, uint32_t>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget + 256);
+    if constexpr (NCH == 4) {
+        if (e != hipSuccess) return e;
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_down2<T, MODE, 4, uint16_t, true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget + 256);
+        if (e != hipSuccess) return e;
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_down2<T, MODE, 4, uint32_t, true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBudget + 256);
+    }
     if constexpr (NCH == 2 || NCH == 4) {
         if (e != hipSuccess) return e;
         e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_down_win<T, MODE, NCH, uint16_t>),
